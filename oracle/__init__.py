@@ -1,0 +1,251 @@
+"""Python access to the FP64 EMPC oracle (C, single-threaded).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg are the only callers.  Nothing here is shared
+with, or imported by, the HIP library or its binding.
+
+The oracle follows the paper (Hyatt, Williams, Killpack 2020): eq. 2 for the
+linear step, eq. 3 for the cost, Sec. IV-D for the knot interpolation,
+Sec. V / Alg. 1 for the evolutionary step.  See empc_oracle.h for how each
+function is pinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "empc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math) into liboracle.so."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-o", tmp, _SRC,
+                        "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _OrProblem(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int), ("n", ctypes.c_int), ("m", ctypes.c_int),
+                ("T", ctypes.c_int), ("p", ctypes.c_int),
+                ("Ad", _dp), ("Bd", _dp), ("wd", _dp),
+                ("stiff", _dp), ("damp", _dp), ("mass", _dp), ("len", _dp),
+                ("gravity", ctypes.c_double), ("dt", ctypes.c_double),
+                ("q", _dp), ("r", _dp), ("qf", _dp), ("x_goal", _dp), ("u_goal", _dp),
+                ("u_min", _dp), ("u_max", _dp)]
+
+
+class _OrGA(ctypes.Structure):
+    _fields_ = [("pop", ctypes.c_int), ("n_elite", ctypes.c_int),
+                ("generations", ctypes.c_int), ("elitism", ctypes.c_int),
+                ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.or_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.or_knot_weights.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      _dp]
+        L.or_step.argtypes = [ctypes.POINTER(_OrProblem), _dp, _dp, _dp]
+        L.or_plant_step.argtypes = [ctypes.POINTER(_OrProblem), _dp, _dp, _dp, _dp]
+        L.or_rollout_one.argtypes = [ctypes.POINTER(_OrProblem), _dp, _dp, ctypes.c_int64,
+                                     ctypes.c_int64, _dp]
+        L.or_rollout_one.restype = ctypes.c_double
+        L.or_rollout_cost.argtypes = [ctypes.POINTER(_OrProblem), _dp, _dp, ctypes.c_int64,
+                                      ctypes.c_int64, _dp]
+        L.or_select.argtypes = [_dp, ctypes.c_int64, ctypes.c_int, _i64p, _i64p]
+        L.or_next_population.argtypes = [ctypes.POINTER(_OrProblem), ctypes.POINTER(_OrGA), _dp,
+                                         ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, _dp,
+                                         ctypes.c_int64]
+        L.or_solve.argtypes = [ctypes.POINTER(_OrProblem), ctypes.POINTER(_OrGA), _dp,
+                               ctypes.POINTER(ctypes.c_int), _dp, ctypes.c_uint32, _dp, _dp, _dp,
+                               _dp, _dp, _i64p, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        L.or_solve.restype = ctypes.c_int
+        L.or_grad.argtypes = [ctypes.POINTER(_OrProblem), _dp, _dp, ctypes.c_int64,
+                              ctypes.c_int64, _dp, _dp]
+        L.or_refine.argtypes = [ctypes.POINTER(_OrProblem), _dp, _dp, ctypes.c_int64,
+                                ctypes.c_int64, _dp, ctypes.c_double, ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+class OracleProblem:
+    """Holds float64 copies of a workloads.Problem and the C struct over them."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        self._keep = {}
+        s = _OrProblem()
+        s.model, s.n, s.m, s.T, s.p = prob.model, prob.n, prob.m, prob.T, prob.p
+        for name, cname in (("Ad", "Ad"), ("Bd", "Bd"), ("wd", "wd"), ("stiffness", "stiff"),
+                            ("damping", "damp"), ("mass", "mass"), ("length", "len"),
+                            ("q", "q"), ("r", "r"), ("qf", "qf"), ("x_goal", "x_goal"),
+                            ("u_goal", "u_goal"), ("u_min", "u_min"), ("u_max", "u_max")):
+            v = getattr(prob, name)
+            if v is not None:
+                v = _f64(v)
+                self._keep[name] = v
+                setattr(s, cname, _ptr(v))
+        s.gravity = float(prob.gravity)
+        s.dt = float(prob.dt)
+        self.s = s
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def _ga_struct(ga, pop=None):
+    g = _OrGA()
+    g.pop = ga.pop if pop is None else pop
+    g.n_elite, g.generations = ga.n_elite, ga.generations
+    g.elitism = 1 if ga.elitism else 0
+    g.sigma = float(ga.sigma)
+    g.seed = int(ga.seed)
+    return g
+
+
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().or_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def knot_weights(T, p, k):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    lib().or_knot_weights(T, p, k, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return a.value, b.value, c.value
+
+
+def step(prob, x, u, noise=None):
+    P = OracleProblem(prob)
+    x, u = _f64(x), _f64(u)
+    out = np.zeros(prob.n)
+    nz = None if noise is None else _f64(noise)
+    lib().or_plant_step(P.ref, _ptr(x), _ptr(u), _ptr(nz), _ptr(out))
+    return out
+
+
+def rollout_one(prob, x0, knots, cand=0):
+    """Cost of one candidate and its trajectory x_0..x_T, shape (T+1, n)."""
+    P = OracleProblem(prob)
+    x0, knots = _f64(x0), _f64(knots)
+    ld = knots.shape[1]
+    traj = np.zeros((prob.T + 1, prob.n))
+    J = lib().or_rollout_one(P.ref, _ptr(x0), _ptr(knots), ld, cand, _ptr(traj))
+    return J, traj
+
+
+def rollout_cost(prob, x0, knots, ncand=None):
+    """Costs of candidates 0..ncand-1; knots SoA [p*m][ld]."""
+    P = OracleProblem(prob)
+    x0, knots = _f64(x0), _f64(knots)
+    ld = knots.shape[1]
+    ncand = ld if ncand is None else ncand
+    cost = np.zeros(ncand)
+    lib().or_rollout_cost(P.ref, _ptr(x0), _ptr(knots), ncand, ld, _ptr(cost))
+    return cost
+
+
+def select(cost, k):
+    """(elite indices ascending, best index) of the k lowest (J, index)."""
+    cost = _f64(cost)
+    idx = np.zeros(k, dtype=np.int64)
+    best = ctypes.c_int64()
+    lib().or_select(_ptr(cost), cost.shape[0], k, idx.ctypes.data_as(_i64p), ctypes.byref(best))
+    return idx, best.value
+
+
+def next_population(prob, ga, elite_knots, cold, tick, gen, pop=None):
+    """Next population [p*m][pop] from elite rows [k][p*m]."""
+    P = OracleProblem(prob)
+    G = _ga_struct(ga, pop)
+    pm = prob.p * prob.m
+    ek = _f64(elite_knots if elite_knots is not None else np.zeros((ga.n_elite, pm)))
+    out = np.zeros((pm, G.pop))
+    lib().or_next_population(P.ref, ctypes.byref(G), _ptr(ek), 1 if cold else 0, tick, gen,
+                             _ptr(out), G.pop)
+    return out
+
+
+def grad(prob, x0, knots, ncand=None):
+    """(dJ/dknots [p*m][ld], cost [ncand]) by the adjoint, full storage."""
+    P = OracleProblem(prob)
+    x0, knots = _f64(x0), _f64(knots)
+    ld = knots.shape[1]
+    ncand = ld if ncand is None else ncand
+    dJ = np.zeros_like(knots)
+    cost = np.zeros(ncand)
+    lib().or_grad(P.ref, _ptr(x0), _ptr(knots), ncand, ld, _ptr(dJ), _ptr(cost))
+    return dJ, cost
+
+
+def refine(prob, x0, knots, cost, lr=0.01, steps=5):
+    """Adam refinement of candidates in place of copies; returns (knots, cost)."""
+    P = OracleProblem(prob)
+    x0 = _f64(x0)
+    knots = _f64(knots).copy()
+    cost = _f64(cost).copy()
+    lib().or_refine(P.ref, _ptr(x0), _ptr(knots), knots.shape[1], knots.shape[1], _ptr(cost),
+                    lr, steps)
+    return knots, cost
+
+
+class Solver:
+    """Warm-started EMPC controller state for one problem (oracle side)."""
+
+    def __init__(self, prob, ga, refine=False, lr=0.01, adam_steps=5):
+        self.prob, self.ga = prob, ga
+        self.P = OracleProblem(prob)
+        self.G = _ga_struct(ga)
+        pm = prob.p * prob.m
+        self.elite_knots = np.zeros((ga.n_elite, pm))
+        self.has_elites = ctypes.c_int(0)
+        self.knots_ws = np.zeros((pm, ga.pop))
+        self.cost_ws = np.zeros(ga.pop)
+        self.idx_ws = np.zeros(ga.n_elite, dtype=np.int64)
+        self.refine, self.lr, self.adam_steps = refine, lr, adam_steps
+        self.best_slot = 0
+
+    def solve(self, x0, tick):
+        """Returns (u*, best cost, per-generation best costs)."""
+        x0 = _f64(x0)
+        u = np.zeros(self.prob.m)
+        best = ctypes.c_double()
+        gen_best = np.zeros(self.ga.generations)
+        self.best_slot = lib().or_solve(self.P.ref, ctypes.byref(self.G), _ptr(self.elite_knots),
+                                        ctypes.byref(self.has_elites), _ptr(x0), tick, _ptr(u),
+                                        ctypes.byref(best), _ptr(gen_best), _ptr(self.knots_ws),
+                                        _ptr(self.cost_ws),
+                                        self.idx_ws.ctypes.data_as(_i64p),
+                                        1 if self.refine else 0, self.lr, self.adam_steps)
+        return u, best.value, gen_best

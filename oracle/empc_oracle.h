@@ -1,0 +1,94 @@
+/*
+ * EMPC oracle: plain, slow, single-threaded FP64 reference of the
+ * parameterized Evolutionary MPC hot path (Hyatt, Williams, Killpack,
+ * "Parameterized and GPU-Parallelized Real-Time Model Predictive Control for
+ * High Degree of Freedom Robots", 2020).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path
+ * (the HIP library) shares no code, header or constant with it.
+ *
+ * Parity status per function (what pins it, see the tests):
+ *   or_philox4x32_10   pinned: published Philox known-answer vectors and an
+ *                      independent library implementation.
+ *   or_knot_weights    pinned: worked example T=5, p=3 of Sec. IV-F.
+ *   or_rollout_cost    linear: pinned by the small-matrix closed form
+ *                      (Sec. IV-C) and the quadratic form of J;
+ *                      pendulum chain: pinned by energy / equilibrium /
+ *                      single-pendulum (eq. 7) special cases and the
+ *                      gravity-torque finite-difference check.
+ *   or_select          pinned: a library sort on (J, index).
+ *   or_next_population pinned: statistics of the draws, bounds, elitism.
+ *   or_solve           pinned: brute-force box-QP bound on tiny problems;
+ *                      multi-generation trajectories beyond one generation
+ *                      are parity unpinned against the paper (the paper gives
+ *                      no numbers for them).
+ *   or_grad            pinned: central finite differences, and 2 P U + 2 q
+ *                      of the small-matrix form for linear models.
+ *   or_refine          follows Adam (Kingma & Ba 2015); pinned only through
+ *                      or_grad and a monotone-acceptance invariant.
+ */
+#ifndef EMPC_ORACLE_H
+#define EMPC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_LINEAR = 0, OR_PENDULUM_CHAIN = 1 };
+
+/* Problem statement of eq. 3 with the knot parameterization of Sec. III-B.
+ * All arrays are host memory, float64, owned by the caller. */
+typedef struct {
+    int model;              /* OR_LINEAR or OR_PENDULUM_CHAIN                  */
+    int n, m, T, p;         /* states, inputs, horizon steps, knots per input  */
+    const double *Ad;       /* linear: n*n row-major                           */
+    const double *Bd;       /* linear: n*m row-major                           */
+    const double *wd;       /* linear: n, may be NULL (= 0)                    */
+    const double *stiff;    /* chain (d = m, n = 2d): joint stiffness, d       */
+    const double *damp;     /* chain: joint viscous damping, d                 */
+    const double *mass;     /* chain: link point mass, d                       */
+    const double *len;      /* chain: link length, d                           */
+    double gravity, dt;     /* chain: gravity and integration step             */
+    const double *q, *r;    /* diagonal stage weights: n, m                    */
+    const double *qf;       /* diagonal terminal weight: n, may be NULL (= 0)  */
+    const double *x_goal;   /* n, may be NULL (= 0)                            */
+    const double *u_goal;   /* m, may be NULL (= 0)                            */
+    const double *u_min, *u_max; /* m                                          */
+} or_problem;
+
+/* Tunables of Alg. 1: numSims (pop), numParents (n_elite), sigma_noise. */
+typedef struct {
+    int pop, n_elite, generations, elitism;
+    double sigma;
+    uint64_t seed;
+} or_ga;
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void or_knot_weights(int T, int p, int k, int *a, int *b, double *c);
+void or_input_at(const or_problem *P, const double *knots, int64_t ld, int64_t cand, int k,
+                 double *u);
+void or_step(const or_problem *P, const double *x, const double *u, double *x_next);
+double or_rollout_one(const or_problem *P, const double *x0, const double *knots, int64_t ld,
+                      int64_t cand, double *traj);
+void or_rollout_cost(const or_problem *P, const double *x0, const double *knots, int64_t ncand,
+                     int64_t ld, double *cost);
+void or_select(const double *cost, int64_t pop, int k, int64_t *elite_idx, int64_t *best);
+void or_next_population(const or_problem *P, const or_ga *G, const double *elite_knots, int cold,
+                        uint32_t tick, uint32_t gen, double *knots, int64_t ld);
+int or_solve(const or_problem *P, const or_ga *G, double *elite_knots, int *has_elites,
+             const double *x0, uint32_t tick, double *u_star, double *best_cost,
+             double *gen_best, double *knots_ws, double *cost_ws, int64_t *idx_ws, int refine,
+             double lr, int adam_steps);
+void or_grad(const or_problem *P, const double *x0, const double *knots, int64_t ncand,
+             int64_t ld, double *dJ, double *cost);
+void or_refine(const or_problem *P, const double *x0, double *knots, int64_t ncand, int64_t ld,
+               double *cost, double lr, int steps);
+void or_plant_step(const or_problem *P, const double *x, const double *u, const double *noise,
+                   double *x_next);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,585 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every check here compares the oracle with something other than itself: the
+paper's worked examples (Sec. IV-E/F), its small-matrix closed form
+(Sec. IV-C), published Philox known-answer vectors, an independent Philox
+implementation, library sorts, brute force over tiny problems, invariants of
+the dynamics, and finite differences.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.stats
+
+import workloads as W
+from conftest import load_golden
+
+# ---------------------------------------------------------------------------
+# helpers that build the paper's small-matrix closed form independently of
+# the oracle's step-by-step simulation
+
+
+def hat_weights(T, p):
+    """W[k, j]: weight of knot j at step k, from the hat functions of
+    piecewise-linear interpolation with knots at k = j (T-1)/(p-1)."""
+    Wt = np.zeros((T, p))
+    if p == 1:
+        Wt[:, 0] = 1.0
+        return Wt
+    for k in range(T):
+        for j in range(p):
+            Wt[k, j] = max(0.0, 1.0 - abs(k * (p - 1) - j * (T - 1)) / (T - 1))
+    return Wt
+
+
+def small_matrix(A, B, w, x0, T, p):
+    """S (nT x pm), v (nT), Phi (Tm x pm) with [x_1..x_T] = S z + v and
+    [u_0..u_{T-1}] = Phi z, z[j*m + i] = knot j of input i (Sec. IV-C/F)."""
+    n, m = B.shape
+    Wt = hat_weights(T, p)
+    powers = [np.eye(n)]
+    for _ in range(T):
+        powers.append(A @ powers[-1])
+    S = np.zeros((n * T, p * m))
+    v = np.zeros(n * T)
+    for k in range(1, T + 1):
+        blk = np.zeros((n, p * m))
+        for j in range(k):
+            for kn in range(p):
+                blk[:, kn * m:(kn + 1) * m] += Wt[j, kn] * powers[k - 1 - j] @ B
+        S[(k - 1) * n:k * n] = blk
+        v[(k - 1) * n:k * n] = powers[k] @ x0 + sum(powers[i] @ w for i in range(k))
+    Phi = np.zeros((T * m, p * m))
+    for k in range(T):
+        for kn in range(p):
+            Phi[k * m:(k + 1) * m, kn * m:(kn + 1) * m] = Wt[k, kn] * np.eye(m)
+    return S, v, Phi
+
+
+def quadratic_form(prob, x0):
+    """P, q, c with J(z) = z'Pz + 2q'z + c (small-matrix form with the
+    constant term written out; terminal weight on the last block)."""
+    T, n, m = prob.T, prob.n, prob.m
+    S, v, Phi = small_matrix(prob.Ad, prob.Bd, prob.wd, x0, T, prob.p)
+    qdiag = np.tile(prob.q, T)
+    qdiag[-n:] += prob.qf
+    Qb = np.diag(qdiag)
+    Rb = np.diag(np.tile(prob.r, T))
+    Xg = np.tile(prob.x_goal, T)
+    Ug = np.tile(prob.u_goal, T)
+    P = S.T @ Qb @ S + Phi.T @ Rb @ Phi
+    q = S.T @ Qb @ (v - Xg) - Phi.T @ Rb @ Ug
+    c = (v - Xg) @ Qb @ (v - Xg) + Ug @ Rb @ Ug
+    return P, q, c
+
+
+def random_linear(n, m, T, p, seed, goal=True):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(0, 1, (n, n))
+    A *= 0.95 / max(abs(np.linalg.eigvals(A)))
+    B = rng.normal(0, 1, (n, m))
+    prob = W.Problem(model=W.LINEAR, n=n, m=m, T=T, p=p, Ad=A, Bd=B, wd=rng.normal(0, 0.1, n),
+                     q=rng.uniform(0.5, 2, n), r=rng.uniform(0.01, 0.1, m),
+                     qf=rng.uniform(0, 1, n),
+                     x_goal=rng.normal(0, 1, n) if goal else np.zeros(n),
+                     u_goal=rng.normal(0, 0.2, m) if goal else np.zeros(m),
+                     u_min=-np.ones(m), u_max=np.ones(m))
+    return prob
+
+
+def knots_to_z(knots, cand):
+    return knots[:, cand].copy()
+
+
+# ---------------------------------------------------------------------------
+# Philox
+
+
+def test_philox_known_answers(oracle_lib):
+    for row in load_golden("philox4x32_10_kat.txt"):
+        vals = [int(x, 16) for x in row]
+        assert oracle_lib.philox4x32_10(vals[0:4], vals[4:6]) == vals[6:10]
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
+def test_philox_matches_rocrand(oracle_lib, tmp_path):
+    src = os.path.join(os.path.dirname(__file__), "rocrand_philox_probe.cpp")
+    exe = str(tmp_path / "probe")
+    subprocess.run(["hipcc", "-x", "hip", "--offload-arch=gfx950", "-O1", src, "-o", exe],
+                   check=True, capture_output=True)
+    rng = np.random.default_rng(11)
+    cases = rng.integers(0, 2**32, (64, 6), dtype=np.uint64)
+    text = "\n".join(" ".join("%08x" % v for v in row) for row in cases) + "\n"
+    out = subprocess.run([exe], input=text, capture_output=True, text=True, check=True).stdout
+    got = [[int(x, 16) for x in line.split()] for line in out.strip().splitlines()]
+    for row, ref in zip(cases, got):
+        assert oracle_lib.philox4x32_10([int(v) for v in row[:4]], [int(v) for v in row[4:]]) == ref
+
+
+# ---------------------------------------------------------------------------
+# knot interpolation and the parameterized matrices (Sec. IV-D/E/F)
+
+
+def test_knot_weights_worked_example(oracle_lib):
+    for row in load_golden("knot_weights_T5_p3.txt"):
+        k = int(row[0])
+        want = np.array([float(x) for x in row[1:]])
+        a, b, c = oracle_lib.knot_weights(5, 3, k)
+        got = np.zeros(3)
+        got[a] += 1.0 - c
+        got[b] += c
+        np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("T,p", [(5, 3), (50, 10), (100, 10), (20, 5), (37, 6), (7, 7), (9, 1),
+                                 (1, 1), (2, 2), (100, 3)])
+def test_knot_weights_match_hat_functions(oracle_lib, T, p):
+    Wt = hat_weights(T, p)
+    for k in range(T):
+        a, b, c = oracle_lib.knot_weights(T, p, k)
+        got = np.zeros(p)
+        got[a] += 1.0 - c
+        got[b] += c
+        np.testing.assert_allclose(got, Wt[k], rtol=0, atol=1e-15)
+        assert 0 <= a <= b <= p - 1 and 0.0 <= c < 1.0
+
+
+def test_knot_count_equal_horizon_is_traditional_mpc(oracle_lib):
+    # p = T: every step applies its own knot exactly (Sec. III-C)
+    for T in (1, 2, 5, 50):
+        for k in range(T):
+            a, b, c = oracle_lib.knot_weights(T, T, k)
+            assert a == k and c == 0.0
+
+
+def test_parameterized_S_worked_example(oracle_lib):
+    rng = np.random.default_rng(3)
+    n, m, T, p = 4, 2, 5, 3
+    A = rng.normal(0, 0.5, (n, n))
+    B = rng.normal(0, 1, (n, m))
+    prob = W.Problem(model=W.LINEAR, n=n, m=m, T=T, p=p, Ad=A, Bd=B, wd=np.zeros(n),
+                     q=np.ones(n), r=np.ones(m), qf=np.zeros(n), x_goal=np.zeros(n),
+                     u_goal=np.zeros(m), u_min=-np.ones(m) * 10, u_max=np.ones(m) * 10)
+    pw = [np.linalg.matrix_power(A, e) for e in range(5)]
+    # S columns from unit-knot rollouts from x0 = 0
+    S = np.zeros((n * T, p * m))
+    for col in range(p * m):
+        knots = np.zeros((p * m, 1))
+        knots[col, 0] = 1.0
+        _, traj = oracle_lib.rollout_one(prob, np.zeros(n), knots)
+        S[:, col] = traj[1:].reshape(-1)
+    for row in load_golden("param_S_T5_p3.txt"):
+        i, j = int(row[0]), int(row[1])
+        coef = [float(x) for x in row[2:]]
+        blk = sum(c * pw[e] for e, c in enumerate(coef)) @ B
+        np.testing.assert_allclose(S[(i - 1) * n:i * n, j * m:(j + 1) * m], blk, rtol=0,
+                                   atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# linear rollout and cost against the closed forms of Sec. IV-C
+
+
+@pytest.mark.parametrize("n,m,T,p", [(5, 3, 12, 4), (4, 2, 20, 5), (6, 6, 9, 9), (3, 1, 7, 1),
+                                     (8, 3, 30, 30)])
+def test_linear_rollout_closed_form(oracle_lib, n, m, T, p):
+    prob = random_linear(n, m, T, p, seed=n * 100 + T)
+    rng = np.random.default_rng(5)
+    x0 = rng.normal(0, 1, n)
+    knots = rng.uniform(-1, 1, (p * m, 3))
+    S, v, Phi = small_matrix(prob.Ad, prob.Bd, prob.wd, x0, T, p)
+    for cand in range(3):
+        _, traj = oracle_lib.rollout_one(prob, x0, knots, cand)
+        want = S @ knots[:, cand] + v
+        np.testing.assert_allclose(traj[1:].reshape(-1), want, rtol=1e-12, atol=1e-12)
+        np.testing.assert_array_equal(traj[0], x0)
+
+
+@pytest.mark.parametrize("n,m,T,p", [(5, 3, 12, 4), (4, 2, 20, 5), (6, 2, 15, 15), (3, 1, 10, 1)])
+def test_linear_cost_quadratic_form(oracle_lib, n, m, T, p):
+    prob = random_linear(n, m, T, p, seed=7 + n + T)
+    rng = np.random.default_rng(9)
+    x0 = rng.normal(0, 1, n)
+    knots = rng.uniform(-1, 1, (p * m, 16))
+    P, q, c = quadratic_form(prob, x0)
+    J = oracle_lib.rollout_cost(prob, x0, knots)
+    for cand in range(16):
+        z = knots[:, cand]
+        np.testing.assert_allclose(J[cand], z @ P @ z + 2 * q @ z + c, rtol=1e-10)
+
+
+def test_linear_trajectory_with_linear_knots(oracle_lib):
+    # knots on a line are reproduced exactly at every step by linear
+    # interpolation: u_k = alpha + beta * k (p-1)/(T-1)
+    n, m, T, p = 3, 2, 17, 5
+    prob = random_linear(n, m, T, p, seed=1)
+    alpha, beta = np.array([0.2, -0.3]), np.array([0.1, 0.05])
+    knots = np.array([[alpha[i] + beta[i] * j] for j in range(p) for i in range(m)])
+    x = np.zeros(n)
+    _, traj = oracle_lib.rollout_one(prob, x, knots)
+    for k in range(T):
+        u = alpha + beta * k * (p - 1) / (T - 1)
+        x = prob.Ad @ x + prob.Bd @ u + prob.wd
+        np.testing.assert_allclose(traj[k + 1], x, rtol=1e-13, atol=1e-14)
+
+
+def test_equilibrium_stays(oracle_lib):
+    lin = W.linear_chain(3, 25, 5, seed=2)
+    ch = W.pendulum_chain(5, 40, 6, seed=2)
+    for prob in (lin, ch):
+        knots = np.zeros((prob.p * prob.m, 2))
+        J, traj = oracle_lib.rollout_one(prob, np.zeros(prob.n), knots)
+        assert J == 0.0
+        assert np.all(traj == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# pendulum chain: reductions and invariants
+
+
+def chain_positions(prob, q):
+    """Planar positions of the point masses, angles from the downward vertical."""
+    phi = np.cumsum(q)
+    x = np.cumsum(prob.length * np.sin(phi))
+    y = -np.cumsum(prob.length * np.cos(phi))
+    return x, y
+
+
+def test_chain_single_link_is_eq7(oracle_lib):
+    # one link: m l^2 qdd + b qd + m g l sin q + k q = tau, semi-implicit Euler
+    prob = W.pendulum_chain(1, 10, 2, seed=4)
+    ml2 = prob.mass[0] * prob.length[0] ** 2
+    x = np.array([0.7, -0.3])
+    u = np.array([0.4])
+    qdd = (u[0] - prob.damping[0] * x[1] - prob.mass[0] * prob.gravity * prob.length[0] *
+           np.sin(x[0]) - prob.stiffness[0] * x[0]) / ml2
+    qd = x[1] + prob.dt * qdd
+    want = np.array([x[0] + prob.dt * qd, qd])
+    np.testing.assert_allclose(oracle_lib.step(prob, x, u), want, rtol=1e-14)
+
+
+def test_chain_gravity_torque_is_potential_gradient(oracle_lib):
+    # with k = b = 0 and qd = 0, applying u = dV/dq (central differences of
+    # V = g sum m_i y_i) holds the chain still for one step
+    prob = W.pendulum_chain(7, 10, 2, seed=5)
+    prob.stiffness[:] = 0.0
+    prob.damping[:] = 0.0
+    rng = np.random.default_rng(1)
+    q = rng.normal(0, 0.6, 7)
+
+    def V(qq):
+        _, y = chain_positions(prob, qq)
+        return prob.gravity * np.sum(prob.mass * y)
+
+    h = 1e-5
+    grad = np.array([(V(q + h * e) - V(q - h * e)) / (2 * h) for e in np.eye(7)])
+    x = np.concatenate([q, np.zeros(7)])
+    xn = oracle_lib.step(prob, x, grad)
+    assert np.max(np.abs(xn[7:])) < 1e-6
+    # and without the compensating torque the chain does move
+    xn0 = oracle_lib.step(prob, x, np.zeros(7))
+    assert np.max(np.abs(xn0[7:])) > 1e-3
+
+
+def test_chain_inertia_is_mass_matrix_diagonal(oracle_lib):
+    # g = k = b = 0 and a unit torque at joint j from rest, straight chain:
+    # qd_j' = dt / M_jj(0), with M_jj = sum_i m_i |d p_i / d q_j|^2 by
+    # finite differences of the forward kinematics
+    d = 6
+    prob = W.pendulum_chain(d, 10, 2, seed=6)
+    prob.stiffness[:] = 0.0
+    prob.damping[:] = 0.0
+    prob.gravity = 0.0
+    h = 1e-6
+    for j in range(d):
+        e = np.zeros(d)
+        e[j] = h
+        xp, yp = chain_positions(prob, e)
+        xm, ym = chain_positions(prob, -e)
+        Mjj = np.sum(prob.mass * (((xp - xm) / (2 * h)) ** 2 + ((yp - ym) / (2 * h)) ** 2))
+        u = np.zeros(d)
+        u[j] = 1.0
+        xn = oracle_lib.step(prob, np.zeros(2 * d), u)
+        np.testing.assert_allclose(xn[d + j], prob.dt / Mjj, rtol=1e-8)
+
+
+def test_chain_energy_bounded(oracle_lib):
+    # undamped, unforced: semi-implicit Euler keeps the energy
+    # 1/2 sum I_j qd_j^2 + V(q) from drifting (it oscillates about its start)
+    d = 4
+    prob = W.pendulum_chain(d, 10, 2, seed=8)
+    prob.damping[:] = 0.0
+    inertia = np.array([prob.dt / oracle_lib.step(
+        W.dataclasses.replace(prob, gravity=0.0, stiffness=np.zeros(d)), np.zeros(2 * d),
+        np.eye(d)[j])[d + j] for j in range(d)])
+
+    def energy(x):
+        _, y = chain_positions(prob, x[:d])
+        return (0.5 * np.sum(inertia * x[d:] ** 2) + prob.gravity * np.sum(prob.mass * y) +
+                0.5 * np.sum(prob.stiffness * x[:d] ** 2))
+
+    x = np.concatenate([np.full(d, 0.3), np.zeros(d)])
+    E0 = energy(x)
+    Es = []
+    for _ in range(4000):
+        x = oracle_lib.step(prob, x, np.zeros(d))
+        Es.append(energy(x))
+    Es = np.array(Es)
+    scale = abs(E0 - prob.gravity * np.sum(prob.mass * chain_positions(prob, np.zeros(d))[1]))
+    assert np.max(np.abs(Es - E0)) < 0.1 * scale
+    # no secular drift: first and last quarter average the same
+    assert abs(Es[-1000:].mean() - Es[:1000].mean()) < 0.02 * scale
+
+
+def test_chain_c3_instance_is_stable(oracle_lib):
+    # the configuration's 36-link chain stays finite over the horizon from
+    # x0 ~ N(0, 0.5^2) under bounded random inputs
+    prob = W.pendulum_chain(36, 100, 10, seed=0)
+    x0 = W.draw_x0(prob.n, 0)
+    knots = W.draw_knots(prob, 8, seed=1)
+    J = oracle_lib.rollout_cost(prob, x0, knots)
+    assert np.all(np.isfinite(J))
+    _, traj = oracle_lib.rollout_one(prob, x0, knots, 0)
+    assert np.max(np.abs(traj)) < 1e3
+
+
+# ---------------------------------------------------------------------------
+# selection
+
+
+def test_select_matches_library_sort(oracle_lib):
+    rng = np.random.default_rng(4)
+    for trial in range(20):
+        pop = int(rng.integers(1, 400))
+        k = int(rng.integers(1, pop + 1))
+        cost = np.round(rng.normal(0, 1, pop), 1)  # many exact ties
+        cost[rng.random(pop) < 0.05] = np.nan
+        cost[rng.random(pop) < 0.02] = np.inf
+        key = np.where(np.isnan(cost), np.inf, cost)
+        order = np.lexsort((np.arange(pop), key))
+        idx, best = oracle_lib.select(cost, k)
+        np.testing.assert_array_equal(idx, np.sort(order[:k]))
+        assert best == order[0]
+
+
+# ---------------------------------------------------------------------------
+# evolutionary step: distributions, bounds, elitism
+
+
+def _ga_problem(m=6, p=5):
+    return W.linear_chain(m, 20, p, seed=1)
+
+
+def test_cold_start_uniform(oracle_lib):
+    prob = _ga_problem()
+    prob.u_min = np.linspace(-2, -0.5, prob.m)
+    prob.u_max = np.linspace(0.5, 3, prob.m)
+    ga = W.GA(pop=4000, n_elite=8, generations=1, sigma=0.1, seed=3)
+    K = oracle_lib.next_population(prob, ga, None, cold=True, tick=0, gen=0)
+    for j in range(prob.p * prob.m):
+        i = j % prob.m
+        z = (K[j] - prob.u_min[i]) / (prob.u_max[i] - prob.u_min[i])
+        assert z.min() > 0 and z.max() < 1
+        assert scipy.stats.kstest(z, "uniform").pvalue > 1e-4
+
+
+def test_elites_kept_and_children_in_bounds(oracle_lib):
+    prob = _ga_problem()
+    rng = np.random.default_rng(2)
+    k = 8
+    E = rng.uniform(-1, 1, (k, prob.p * prob.m))
+    ga = W.GA(pop=512, n_elite=k, generations=1, sigma=3.0, seed=5)
+    K = oracle_lib.next_population(prob, ga, E, cold=False, tick=4, gen=2)
+    np.testing.assert_array_equal(K[:, :k].T, E)
+    assert K.min() >= -1.0 and K.max() <= 1.0
+    assert np.mean(np.abs(K[:, k:]) == 1.0) > 0.2  # heavy noise does clamp
+    ga2 = W.dataclasses.replace(ga, elitism=False)
+    K2 = oracle_lib.next_population(prob, ga2, E, cold=False, tick=4, gen=2)
+    assert not np.array_equal(K2[:, :k].T, E)
+
+
+def test_crossover_parents_and_mutation_statistics(oracle_lib):
+    prob = _ga_problem(m=6, p=5)
+    pm = prob.p * prob.m
+    k = 16
+    # elite s holds the constant value v_s everywhere
+    vals = np.linspace(-0.75, 0.75, k)
+    E = np.repeat(vals[:, None], pm, axis=1)
+    pop = 20000
+    ga0 = W.GA(pop=pop, n_elite=k, generations=1, sigma=0.0, seed=9)
+    K = oracle_lib.next_population(prob, ga0, E, cold=False, tick=1, gen=0)[:, k:]
+    # sigma = 0: every parameter is one of the two parents' values
+    ids = np.rint((K + 0.75) / 1.5 * (k - 1)).astype(int)
+    np.testing.assert_allclose(K, vals[ids], atol=1e-15)
+    # each child draws from at most 2 parents; parents uniform over k
+    nuniq = np.array([len(np.unique(ids[:, c])) for c in range(ids.shape[1])])
+    assert nuniq.max() <= 2
+    first = ids.min(axis=0)
+    second = ids.max(axis=0)
+    counts = np.bincount(np.concatenate([first, second]), minlength=k)
+    assert scipy.stats.chisquare(counts).pvalue > 1e-4
+    # crossover: among children with two distinct parents, each parameter
+    # comes from either with probability 1/2
+    two = nuniq == 2
+    frac = np.mean(ids[:, two] == first[two])
+    assert abs(frac - 0.5) < 0.01
+    # mutation: elites at 0, sigma 0.1, far from the bounds
+    E0 = np.zeros((k, pm))
+    ga1 = W.GA(pop=pop, n_elite=k, generations=1, sigma=0.1, seed=10)
+    K1 = oracle_lib.next_population(prob, ga1, E0, cold=False, tick=1, gen=3)[:, k:]
+    mutated = K1 != 0.0  # (pm, children)
+    per_input = mutated.reshape(prob.p, prob.m, -1)
+    # a flagged input has all of its knots perturbed, an unflagged one none
+    assert np.all(per_input.all(axis=0) == per_input.any(axis=0))
+    assert abs(per_input[0].mean() - 0.5) < 0.01
+    z = K1[mutated] / 0.1
+    assert abs(z.mean()) < 0.01 and abs(z.std() - 1.0) < 0.01
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-4
+
+
+# ---------------------------------------------------------------------------
+# solve: brute force on tiny problems, elitism invariant
+
+
+def box_qp_min(P, q, c, lo, hi):
+    """Exact minimum of z'Pz + 2q'z + c over a 2-D box by active sets."""
+    best = np.inf
+    for s0 in ("f", "l", "u"):
+        for s1 in ("f", "l", "u"):
+            z = np.zeros(2)
+            free = []
+            for i, s in enumerate((s0, s1)):
+                if s == "l":
+                    z[i] = lo
+                elif s == "u":
+                    z[i] = hi
+                else:
+                    free.append(i)
+            if free:
+                fixed = [i for i in range(2) if i not in free]
+                rhs = -q[free] - P[np.ix_(free, fixed)] @ z[fixed]
+                z[free] = np.linalg.solve(P[np.ix_(free, free)], rhs)
+            if np.all(z >= lo - 1e-12) and np.all(z <= hi + 1e-12):
+                best = min(best, z @ P @ z + 2 * q @ z + c)
+    return best
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_empc_brute_force_tiny(oracle_lib, seed):
+    prob = W.linear_chain(1, 10, 2, seed=seed)
+    x0 = np.array([0.8, -0.5]) * (1 + seed)
+    P, q, c = quadratic_form(prob, x0)
+    Jbox = box_qp_min(P, q, c, -1.0, 1.0)
+    g = np.linspace(-1, 1, 201)
+    Z = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    Jgrid = np.einsum("ki,ij,kj->k", Z, P, Z) + 2 * Z @ q + c
+    L = 2 * np.linalg.norm(P, 2) * np.sqrt(2) + 2 * np.linalg.norm(q)
+    assert Jbox <= Jgrid.min() + 1e-12
+    assert Jgrid.min() <= Jbox + L * 0.01
+    # grid values agree with the oracle's simulation
+    Kg = Z[::97].T.copy()
+    np.testing.assert_allclose(oracle_lib.rollout_cost(prob, x0, Kg), Jgrid[::97], rtol=1e-10)
+    ga = W.GA(pop=256, n_elite=16, generations=50, sigma=0.1, seed=seed)
+    s = oracle_lib.Solver(prob, ga)
+    u, Jbest, gen_best = s.solve(x0, tick=0)
+    assert Jbox - 1e-12 <= Jbest <= Jgrid.min() + 1e-9
+    assert np.all(np.diff(gen_best) <= 0)
+    assert np.all(np.abs(s.elite_knots) <= 1.0)
+    # u* is knot 0 of the best candidate
+    assert u[0] == s.elite_knots[s.best_slot, 0]
+
+
+def test_solve_warm_start_and_elitism_over_ticks(oracle_lib):
+    prob, ga = W.config_c1(0)
+    ga = W.dataclasses.replace(ga, generations=4)
+    s = oracle_lib.Solver(prob, ga)
+    x = W.draw_x0(prob.n, 0)
+    for tick in range(3):
+        u, J, gb = s.solve(x, tick)
+        assert np.all(np.diff(gb) <= 0)
+        assert np.all(np.abs(u) <= 1.0)
+        x = oracle_lib.step(prob, x, u)
+    # a second solver run with the same seed repeats bit for bit
+    s2 = oracle_lib.Solver(prob, ga)
+    x = W.draw_x0(prob.n, 0)
+    u1, J1, _ = s2.solve(x, 0)
+    s3 = oracle_lib.Solver(prob, ga)
+    u2, J2, _ = s3.solve(x, 0)
+    assert J1 == J2 and np.array_equal(u1, u2)
+
+
+# ---------------------------------------------------------------------------
+# adjoint gradient
+
+
+@pytest.mark.parametrize("n,m,T,p", [(5, 3, 12, 4), (4, 2, 20, 5), (6, 2, 9, 9)])
+def test_grad_linear_matches_quadratic_form(oracle_lib, n, m, T, p):
+    prob = random_linear(n, m, T, p, seed=21 + n)
+    rng = np.random.default_rng(2)
+    x0 = rng.normal(0, 1, n)
+    knots = rng.uniform(-1, 1, (p * m, 5))
+    P, q, c = quadratic_form(prob, x0)
+    dJ, cost = oracle_lib.grad(prob, x0, knots)
+    for cand in range(5):
+        z = knots[:, cand]
+        want = 2 * P @ z + 2 * q
+        np.testing.assert_allclose(dJ[:, cand], want, rtol=1e-9, atol=1e-10 * np.abs(want).max())
+        np.testing.assert_allclose(cost[cand], z @ P @ z + 2 * q @ z + c, rtol=1e-10)
+
+
+def test_grad_chain_central_differences(oracle_lib):
+    prob = W.pendulum_chain(5, 30, 4, seed=3)
+    prob.qf = np.full(prob.n, 0.5)
+    x0 = W.draw_x0(prob.n, 3)
+    knots = W.draw_knots(prob, 2, seed=3)
+    dJ, cost = oracle_lib.grad(prob, x0, knots)
+    h = 1e-3
+    for cand in range(2):
+        fd = np.zeros(prob.p * prob.m)
+        for j in range(prob.p * prob.m):
+            kp = knots[:, cand:cand + 1].copy()
+            km = kp.copy()
+            kp[j] += h
+            km[j] -= h
+            fd[j] = (oracle_lib.rollout_cost(prob, x0, kp)[0] -
+                     oracle_lib.rollout_cost(prob, x0, km)[0]) / (2 * h)
+        np.testing.assert_allclose(dJ[:, cand], fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
+
+
+def test_refine_never_increases_cost(oracle_lib):
+    prob = W.linear_chain(3, 20, 4, seed=1)
+    x0 = W.draw_x0(prob.n, 1)
+    knots = W.draw_knots(prob, 6, seed=2)
+    cost = oracle_lib.rollout_cost(prob, x0, knots)
+    k2, c2 = oracle_lib.refine(prob, x0, knots, cost, lr=0.01, steps=5)
+    assert np.all(c2 <= cost)
+    assert np.sum(c2 < cost) >= 4  # convex problem: Adam makes progress
+    np.testing.assert_allclose(oracle_lib.rollout_cost(prob, x0, k2), c2, rtol=1e-12)
+    assert np.all(np.abs(k2) <= 1.0)
+
+
+# ---------------------------------------------------------------------------
+# input generator sanity (zero-order hold)
+
+
+def test_zoh_matches_closed_form_oscillator():
+    # 1-DoF mass-spring-damper: A_d = expm(A dt) checked against the closed
+    # form of an underdamped oscillator; A_d ~ I + A dt for small dt
+    mass, k, c = 1.3, 40.0, 1.2
+    A, B = W.chain_continuous(np.array([mass]), np.array([k]), np.array([c]))
+    dt = 0.01
+    Ad, Bd = W.zoh(A, B, dt)
+    wn = np.sqrt(k / mass)
+    zeta = c / (2 * np.sqrt(k * mass))
+    wd = wn * np.sqrt(1 - zeta ** 2)
+    e = np.exp(-zeta * wn * dt)
+    x_free = e * (np.cos(wd * dt) + zeta * wn / wd * np.sin(wd * dt))
+    v_free = -e * wn ** 2 / wd * np.sin(wd * dt)
+    np.testing.assert_allclose(Ad[:, 0], [x_free, v_free], rtol=1e-12)
+    # B_d = A^{-1}(A_d - I) B for invertible A
+    np.testing.assert_allclose(Bd, np.linalg.solve(A, (Ad - np.eye(2)) @ B), rtol=1e-10)
+    Ad2, _ = W.zoh(A, B, 1e-6)
+    np.testing.assert_allclose(Ad2, np.eye(2) + A * 1e-6, atol=1e-10)
