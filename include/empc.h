@@ -1,0 +1,175 @@
+/*
+ * empc.h — C ABI of the MI355X (gfx950) EMPC library, libempc.so.
+ *
+ * Parameterized Evolutionary Model Predictive Control, after Hyatt,
+ * Williams, Killpack, "Parameterized and GPU-Parallelized Real-Time Model
+ * Predictive Control for High Degree of Freedom Robots" (2020): a population
+ * of candidate input trajectories, each described by p knots per input
+ * (Sec. III-B, interpolation of Sec. IV-D), is simulated through the discrete
+ * model (eq. 2), scored by the quadratic cost of eq. 3, and evolved by
+ * selection, crossover and mutation (Sec. V, Alg. 1).
+ *
+ * Conventions shared by every entry point
+ *  - Memory: every array argument is a DEVICE pointer owned by the caller,
+ *    unless a comment says "host".  The library never frees caller memory.
+ *  - Precision: problem->dtype (EMPC_F32 or EMPC_F64) is the element type of
+ *    every floating-point array of the problem and of x0, knots, costs,
+ *    gradients, u* and noise.  Index outputs are int64.
+ *  - Knot layout: structure of arrays.  Parameter j = knot * m + input of
+ *    candidate c lives at knots[j * ld + c], ld >= number of candidates.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
+ *    are asynchronous; results are valid once the stream has synchronised.
+ *  - Errors: arguments are validated on the host before anything is
+ *    launched; a bad argument returns EMPC_EINVAL and launches nothing.  A
+ *    HIP launch error, or an asynchronous fault of earlier work, returns
+ *    EMPC_EDEVICE.  empc_last_error() describes the last failure of the
+ *    calling thread.  Nothing throws across this ABI.
+ *  - Costs that are NaN rank after every finite or infinite cost.
+ *  - Limits of this build: n <= 80, m <= 40 for LINEAR; d = m <= 40 joints
+ *    (n = 2d) for PENDULUM_CHAIN; 1 <= p <= T; n_elite <= 256;
+ *    pop <= 2^24.  Larger problems return EMPC_EUNSUPPORTED.
+ */
+#ifndef EMPC_H
+#define EMPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EMPC_OK = 0,
+    EMPC_EINVAL = 1,       /* invalid argument; nothing was launched             */
+    EMPC_EDEVICE = 2,      /* HIP runtime error or earlier asynchronous fault    */
+    EMPC_EUNSUPPORTED = 3, /* valid problem outside this build's limits          */
+    EMPC_EWORKSPACE = 4    /* workspace NULL or smaller than required            */
+} empc_status;
+
+typedef enum { EMPC_F32 = 0, EMPC_F64 = 1 } empc_dtype;
+
+/* EMPC_LINEAR: x_{k+1} = A_d x_k + B_d u_k + w_d (eq. 2).
+ * EMPC_PENDULUM_CHAIN: d = m joints, state x = [q; qd] (n = 2d), relative
+ *   angles from the downward vertical; the single pendulum of eq. 7 extended
+ *   joint by joint with joint stiffness, gravity torque of the cumulative
+ *   angles G_j = g sum_{r>=j} l_r (sum_{i>=r} m_i) sin(q_0 + ... + q_r), and
+ *   the constant diagonal inertia of the straight chain
+ *   I_j = sum_{i>=j} m_i (l_j + ... + l_i)^2;
+ *   qdd = (u - k q - b qd - G) / I, semi-implicit Euler with step dt. */
+typedef enum { EMPC_LINEAR = 0, EMPC_PENDULUM_CHAIN = 1 } empc_model;
+
+/* The MPC problem of eq. 3 with diagonal weights.  Pointers are device
+ * pointers of problem->dtype elements. */
+typedef struct {
+    int32_t n, m;          /* states, inputs                                     */
+    int32_t T;             /* horizon steps                                      */
+    int32_t p;             /* knots per input, 1 <= p <= T                       */
+    int32_t dtype;         /* empc_dtype                                         */
+    int32_t model;         /* empc_model                                         */
+    const void *Ad;        /* LINEAR: n*n row-major                              */
+    const void *Bd;        /* LINEAR: n*m row-major                              */
+    const void *wd;        /* LINEAR: n; NULL = 0                                */
+    const void *stiffness; /* CHAIN: d joint stiffness                           */
+    const void *damping;   /* CHAIN: d joint damping                             */
+    const void *mass;      /* CHAIN: d link point masses                         */
+    const void *length;    /* CHAIN: d link lengths                              */
+    double gravity;        /* CHAIN: gravitational acceleration                  */
+    double dt;             /* CHAIN: integration step                            */
+    const void *q;         /* n  stage state weight (diagonal of Q)              */
+    const void *r;         /* m  stage input weight (diagonal of R)              */
+    const void *qf;        /* n  terminal state weight; NULL = 0                 */
+    const void *x_goal;    /* n; NULL = 0                                        */
+    const void *u_goal;    /* m; NULL = 0                                        */
+    const void *u_min;     /* m  input lower bounds                              */
+    const void *u_max;     /* m  input upper bounds                              */
+} empc_problem;
+
+/* Tunables of Alg. 1: numSims = pop, numParents = n_elite, sigma_noise. */
+typedef struct {
+    int32_t pop;         /* candidates per generation                            */
+    int32_t n_elite;     /* parents kept by selection, 1 <= n_elite <= pop       */
+    int32_t generations; /* generations per solve (one control tick)             */
+    int32_t elitism;     /* 1: parents re-enter the next generation in slots     */
+                         /*    0..n_elite-1; 0: every slot is a child            */
+    double sigma;        /* standard deviation of the mutation noise             */
+    uint64_t seed;       /* key of the counter-based random streams              */
+} empc_ga;
+
+/* Human-readable name of a status code (static string). */
+const char *empc_status_str(empc_status s);
+
+/* Message describing the last failure on the calling thread (static
+ * thread-local buffer; "" if none). */
+const char *empc_last_error(void);
+
+/* Rollout and cost (Alg. 1 simulation loop; cost of eq. 3 charged on
+ * x_1..x_T and u_0..u_{T-1}, plus the terminal weight on x_T).
+ * x0: n.  knots: [p*m][ld].  cost: ncand outputs.  ncand >= 0; ncand = 0 is
+ * a no-op.  Candidates' knots are used as given (no clamping). */
+empc_status empc_rollout_cost(const empc_problem *prob, const void *x0, const void *knots,
+                              int64_t ncand, int64_t ld, void *cost, void *stream);
+
+/* One evolutionary step (Sec. V): select the n_elite lowest (cost, index)
+ * candidates of knots_in / cost_in (ga->pop candidates, leading dimension
+ * ld_in) and write the next population to knots_out ([p*m][ld_out]): parents
+ * in slots 0..n_elite-1 when ga->elitism, children elsewhere (two parents
+ * drawn uniformly with replacement, one crossover bit per parameter, one
+ * mutation flag per input with N(0, sigma^2) noise on each knot of a flagged
+ * input, clamp to [u_min, u_max]).  knots_in = NULL and cost_in = NULL give a
+ * cold start (every knot uniform in its bounds).  elite_idx (n_elite
+ * outputs, ascending index order) is required for a warm start and unused by
+ * a cold start; best_idx (1 output) may be NULL.  knots_out must not overlap
+ * knots_in.  (tick, gen) select the random stream. */
+empc_status empc_generation(const empc_problem *prob, const empc_ga *ga, const void *knots_in,
+                            int64_t ld_in, const void *cost_in, void *knots_out, int64_t ld_out,
+                            int64_t *elite_idx, int64_t *best_idx, uint32_t tick, uint32_t gen,
+                            void *stream);
+
+/* Bytes of the workspace that empc_solve needs for (prob, ga). */
+size_t empc_workspace_bytes(const empc_problem *prob, const empc_ga *ga);
+
+/* One control tick of EMPC: ga->generations rounds of {population, rollout
+ * and cost, selection}, then u* = knot 0 of the best candidate (Alg. 1,
+ * u* = get_u_from_U(U_best, 0)).  The workspace (device, ws_bytes >=
+ * empc_workspace_bytes) carries the parents from tick to tick (warm start,
+ * Sec. V); a zero-filled workspace cold-starts.  x0: n.  u_star: m.
+ * best_cost: 1.  Consecutive ticks must use the same prob shape and ga. */
+empc_status empc_solve(const empc_problem *prob, const empc_ga *ga, void *workspace,
+                       size_t ws_bytes, const void *x0, uint32_t tick, void *u_star,
+                       void *best_cost, void *stream);
+
+/* Gradient of the rollout cost with respect to the knots by a hand-written
+ * adjoint pass (states recomputed from checkpoints every ceil(sqrt(T))
+ * steps).  dJ: [p*m][ld].  cost: ncand (may be NULL). */
+empc_status empc_grad(const empc_problem *prob, const void *x0, const void *knots, int64_t ncand,
+                      int64_t ld, void *dJ, void *cost, void *stream);
+
+/* Gradient refinement: `steps` Adam updates (beta1 0.9, beta2 0.999, eps
+ * 1e-8, learning rate lr) of each candidate's knots, each followed by a clamp
+ * to [u_min, u_max]; a refined candidate replaces the original only if its
+ * cost is lower.  knots [p*m][ld] and cost (ncand, the current costs on
+ * entry) are updated in place. */
+empc_status empc_refine(const empc_problem *prob, const void *x0, void *knots, int64_t ncand,
+                        int64_t ld, void *cost, double lr, int32_t steps, void *stream);
+
+/* One step of the model, x_next = f(x, u) + noise (noise may be NULL):
+ * the simulated plant of a closed-loop run.  x, x_next: n.  u: m. */
+empc_status empc_plant_step(const empc_problem *prob, const void *x, const void *u,
+                            const void *noise, void *x_next, void *stream);
+
+/* Kernel timing.  empc_profile_begin(max_launches) creates a pool of HIP
+ * event pairs (host call, may allocate); until empc_profile_end, every
+ * rollout launch made by empc_rollout_cost and empc_solve (at most
+ * max_launches of them) is bracketed by an event pair on its stream.
+ * empc_profile_end waits for the recorded events and returns the number of
+ * timed launches and their summed duration in milliseconds, then stops
+ * timing.  Not thread-safe: one profiling session per process. */
+empc_status empc_profile_begin(int32_t max_launches);
+empc_status empc_profile_end(int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMPC_H */

@@ -1,0 +1,266 @@
+"""ctypes binding of libempc.so (include/empc.h), argument marshalling only.
+
+Every function named like the C entry point takes torch tensors that live on
+the GPU, passes their device pointers and the current HIP stream to the
+library, and raises EmpcError on a non-OK status.  All arithmetic happens in
+the library's HIP kernels; there is no host fallback: a missing library is an
+error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libempc.so")
+
+EMPC_OK, EMPC_EINVAL, EMPC_EDEVICE, EMPC_EUNSUPPORTED, EMPC_EWORKSPACE = range(5)
+EMPC_F32, EMPC_F64 = 0, 1
+EMPC_LINEAR, EMPC_PENDULUM_CHAIN = 0, 1
+
+_vp = ctypes.c_void_p
+
+
+class EmpcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("empc status %d: %s" % (status, message))
+        self.status = status
+
+
+class EmpcProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("T", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("dtype", ctypes.c_int32), ("model", ctypes.c_int32),
+                ("Ad", _vp), ("Bd", _vp), ("wd", _vp),
+                ("stiffness", _vp), ("damping", _vp), ("mass", _vp), ("length", _vp),
+                ("gravity", ctypes.c_double), ("dt", ctypes.c_double),
+                ("q", _vp), ("r", _vp), ("qf", _vp), ("x_goal", _vp), ("u_goal", _vp),
+                ("u_min", _vp), ("u_max", _vp)]
+
+
+class EmpcGA(ctypes.Structure):
+    _fields_ = [("pop", ctypes.c_int32), ("n_elite", ctypes.c_int32),
+                ("generations", ctypes.c_int32), ("elitism", ctypes.c_int32),
+                ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libempc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libempc.so is not built (python -m paper_2001_04931_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, G = ctypes.POINTER(EmpcProblem), ctypes.POINTER(EmpcGA)
+        i64, u32, sz = ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+        sigs = {
+            "empc_status_str": ([ctypes.c_int], ctypes.c_char_p),
+            "empc_last_error": ([], ctypes.c_char_p),
+            "empc_rollout_cost": ([P, _vp, _vp, i64, i64, _vp, _vp], ctypes.c_int),
+            "empc_generation": ([P, G, _vp, i64, _vp, _vp, i64, _vp, _vp, u32, u32, _vp],
+                                ctypes.c_int),
+            "empc_workspace_bytes": ([P, G], sz),
+            "empc_solve": ([P, G, _vp, sz, _vp, u32, _vp, _vp, _vp], ctypes.c_int),
+            "empc_grad": ([P, _vp, _vp, i64, i64, _vp, _vp, _vp], ctypes.c_int),
+            "empc_refine": ([P, _vp, _vp, i64, i64, _vp, ctypes.c_double, ctypes.c_int32, _vp],
+                            ctypes.c_int),
+            "empc_plant_step": ([P, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+            "empc_profile_begin": ([ctypes.c_int32], ctypes.c_int),
+            "empc_profile_end": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+                                 ctypes.c_int),
+        }
+        for name, (args, res) in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ["empc_status_str", "empc_last_error", "empc_rollout_cost", "empc_generation",
+            "empc_workspace_bytes", "empc_solve", "empc_grad", "empc_refine", "empc_plant_step",
+            "empc_profile_begin", "empc_profile_end"]
+
+
+def _check(status: int):
+    if status != EMPC_OK:
+        msg = lib().empc_last_error().decode()
+        raise EmpcError(status, msg or lib().empc_status_str(status).decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _cprob(prob):
+    return ctypes.byref(prob.c if hasattr(prob, "c") else prob)
+
+
+def _cga(ga):
+    return ctypes.byref(ga.c if hasattr(ga, "c") else ga)
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+
+
+def empc_rollout_cost(prob, x0, knots, ncand, ld, cost, stream=None):
+    _check(lib().empc_rollout_cost(_cprob(prob), _ptr(x0), _ptr(knots), int(ncand), int(ld),
+                                   _ptr(cost), _stream(stream)))
+
+
+def empc_generation(prob, ga, knots_in, ld_in, cost_in, knots_out, ld_out, elite_idx, best_idx,
+                    tick, gen, stream=None):
+    _check(lib().empc_generation(_cprob(prob), _cga(ga), _ptr(knots_in), int(ld_in),
+                                 _ptr(cost_in), _ptr(knots_out), int(ld_out), _ptr(elite_idx),
+                                 _ptr(best_idx), int(tick), int(gen), _stream(stream)))
+
+
+def empc_workspace_bytes(prob, ga) -> int:
+    return int(lib().empc_workspace_bytes(_cprob(prob), _cga(ga)))
+
+
+def empc_solve(prob, ga, workspace, x0, tick, u_star, best_cost, stream=None):
+    _check(lib().empc_solve(_cprob(prob), _cga(ga), _ptr(workspace), workspace.numel(),
+                            _ptr(x0), int(tick), _ptr(u_star), _ptr(best_cost), _stream(stream)))
+
+
+def empc_grad(prob, x0, knots, ncand, ld, dJ, cost, stream=None):
+    _check(lib().empc_grad(_cprob(prob), _ptr(x0), _ptr(knots), int(ncand), int(ld), _ptr(dJ),
+                           _ptr(cost), _stream(stream)))
+
+
+def empc_refine(prob, x0, knots, ncand, ld, cost, lr, steps, stream=None):
+    _check(lib().empc_refine(_cprob(prob), _ptr(x0), _ptr(knots), int(ncand), int(ld),
+                             _ptr(cost), float(lr), int(steps), _stream(stream)))
+
+
+def empc_plant_step(prob, x, u, noise, x_next, stream=None):
+    _check(lib().empc_plant_step(_cprob(prob), _ptr(x), _ptr(u), _ptr(noise), _ptr(x_next),
+                                 _stream(stream)))
+
+
+def empc_profile_begin(max_launches):
+    _check(lib().empc_profile_begin(int(max_launches)))
+
+
+def empc_profile_end():
+    """(number of timed rollout launches, their summed duration in ms)."""
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(lib().empc_profile_end(ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
+
+
+# ---------------------------------------------------------------------------
+# device-side problem description
+
+
+class DeviceProblem:
+    """A problem's arrays copied to the GPU, plus the C struct pointing at them.
+
+    `prob` is any object with the fields of the C struct: model, n, m, T, p,
+    Ad, Bd, wd (linear) or stiffness, damping, mass, length, gravity, dt
+    (chain), and q, r, qf, x_goal, u_goal, u_min, u_max (host arrays).
+    """
+
+    _ARRAYS = ("Ad", "Bd", "wd", "stiffness", "damping", "mass", "length", "q", "r", "qf",
+               "x_goal", "u_goal", "u_min", "u_max")
+
+    def __init__(self, prob, dtype=torch.float32, device="cuda"):
+        self.prob, self.dtype, self.device = prob, dtype, torch.device(device)
+        self.tensors = {}
+        c = EmpcProblem()
+        c.n, c.m, c.T, c.p = int(prob.n), int(prob.m), int(prob.T), int(prob.p)
+        c.dtype = EMPC_F64 if dtype == torch.float64 else EMPC_F32
+        c.model = int(prob.model)
+        for name in self._ARRAYS:
+            v = getattr(prob, name, None)
+            if v is None:
+                setattr(c, name, None)
+                continue
+            t = torch.as_tensor(v, dtype=dtype).contiguous().to(self.device)
+            self.tensors[name] = t
+            setattr(c, name, t.data_ptr())
+        c.gravity = float(getattr(prob, "gravity", 0.0) or 0.0)
+        c.dt = float(getattr(prob, "dt", 0.0) or 0.0)
+        self.c = c
+
+    @property
+    def n(self):
+        return self.c.n
+
+    @property
+    def m(self):
+        return self.c.m
+
+    @property
+    def pm(self):
+        return self.c.p * self.c.m
+
+
+def make_ga(ga) -> EmpcGA:
+    g = EmpcGA()
+    g.pop, g.n_elite, g.generations = int(ga.pop), int(ga.n_elite), int(ga.generations)
+    g.elitism = 1 if getattr(ga, "elitism", True) else 0
+    g.sigma, g.seed = float(ga.sigma), int(ga.seed)
+    return g
+
+
+class Solver:
+    """Warm-started EMPC controller for one problem: owns the workspace."""
+
+    def __init__(self, dprob: DeviceProblem, ga):
+        self.dprob = dprob
+        self.ga = make_ga(ga)
+        nbytes = empc_workspace_bytes(dprob, self.ga)
+        if nbytes == 0:
+            _check(EMPC_EINVAL)
+        self.workspace = torch.zeros(nbytes, dtype=torch.uint8, device=dprob.device)
+        self.u_star = torch.zeros(dprob.m, dtype=dprob.dtype, device=dprob.device)
+        self.best_cost = torch.zeros(1, dtype=dprob.dtype, device=dprob.device)
+
+    def reset(self):
+        self.workspace.zero_()
+
+    def solve(self, x0: torch.Tensor, tick: int, stream=None):
+        """Runs one tick; returns (u*, best cost) device tensors (asynchronous)."""
+        empc_solve(self.dprob, self.ga, self.workspace, x0, tick, self.u_star, self.best_cost,
+                   stream)
+        return self.u_star, self.best_cost
+
+
+class EmpcCost(torch.autograd.Function):
+    """cost[c] = J(knots[:, c]) with the hand-written adjoint as backward.
+
+    forward(knots [p*m, ncand] GPU tensor, x0 [n], dprob) -> cost [ncand]
+    """
+
+    @staticmethod
+    def forward(ctx, knots, x0, dprob):
+        knots = knots.contiguous()
+        ncand = knots.shape[1]
+        cost = torch.empty(ncand, dtype=knots.dtype, device=knots.device)
+        dJ = torch.empty_like(knots)
+        empc_grad(dprob, x0.contiguous(), knots, ncand, ncand, dJ, cost)
+        ctx.save_for_backward(dJ)
+        return cost
+
+    @staticmethod
+    def backward(ctx, grad_cost):
+        (dJ,) = ctx.saved_tensors
+        return dJ * grad_cost.unsqueeze(0), None, None

@@ -1,0 +1,364 @@
+// C ABI of libempc.so: argument validation, dispatch and the solve loop.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace empc;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+empc_status fail(empc_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+empc_status device_status(hipError_t e, const char *where) {
+    if (e == hipSuccess) return EMPC_OK;
+    return fail(EMPC_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// An asynchronous fault of earlier work is reported by the next call.
+empc_status check_prior() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(EMPC_EDEVICE, "earlier device error: %s", hipGetErrorString(e));
+    return EMPC_OK;
+}
+
+size_t esize(const empc_problem *P) { return P->dtype == EMPC_F64 ? 8 : 4; }
+
+empc_status validate_problem(const empc_problem *P) {
+    if (!P) return fail(EMPC_EINVAL, "problem is NULL");
+    if (P->dtype != EMPC_F32 && P->dtype != EMPC_F64)
+        return fail(EMPC_EINVAL, "unknown dtype %d", P->dtype);
+    if (P->model != EMPC_LINEAR && P->model != EMPC_PENDULUM_CHAIN)
+        return fail(EMPC_EINVAL, "unknown model %d", P->model);
+    if (P->n < 1 || P->m < 1) return fail(EMPC_EINVAL, "n=%d, m=%d must be >= 1", P->n, P->m);
+    if (P->T < 1 || P->T > 100000) return fail(EMPC_EINVAL, "T=%d outside [1, 100000]", P->T);
+    if (P->p < 1 || P->p > P->T) return fail(EMPC_EINVAL, "p=%d outside [1, T=%d]", P->p, P->T);
+    if (!P->q || !P->r || !P->u_min || !P->u_max)
+        return fail(EMPC_EINVAL, "q, r, u_min and u_max are required");
+    if (P->model == EMPC_LINEAR) {
+        if (!P->Ad || !P->Bd) return fail(EMPC_EINVAL, "linear model needs Ad and Bd");
+        if (P->n > Limits::MAX_N_LINEAR || P->m > Limits::MAX_M_LINEAR)
+            return fail(EMPC_EUNSUPPORTED, "linear n=%d, m=%d above %d, %d", P->n, P->m,
+                        Limits::MAX_N_LINEAR, Limits::MAX_M_LINEAR);
+    } else {
+        if (P->n != 2 * P->m) return fail(EMPC_EINVAL, "chain needs n = 2m (n=%d, m=%d)", P->n, P->m);
+        if (!P->stiffness || !P->damping || !P->mass || !P->length)
+            return fail(EMPC_EINVAL, "chain needs stiffness, damping, mass and length");
+        if (!(P->dt > 0.0) || !isfinite(P->dt) || !isfinite(P->gravity))
+            return fail(EMPC_EINVAL, "chain needs a finite dt > 0 and finite gravity");
+        if (P->m > Limits::MAX_D_CHAIN)
+            return fail(EMPC_EUNSUPPORTED, "chain d=%d above %d", P->m, Limits::MAX_D_CHAIN);
+    }
+    return EMPC_OK;
+}
+
+empc_status validate_grad(const empc_problem *P) {
+    if (P->model == EMPC_LINEAR ? P->n > 64 : P->m > 64)
+        return fail(EMPC_EUNSUPPORTED, "adjoint supports n <= 64 (linear) or d <= 64 (chain)");
+    const size_t b = grad_smem_bytes(P->model, P->n, P->m, P->T, P->p, esize(P));
+    if (b > MAX_GRAD_LDS)
+        return fail(EMPC_EUNSUPPORTED, "adjoint needs %zu bytes of LDS, above %zu", b, MAX_GRAD_LDS);
+    return EMPC_OK;
+}
+
+empc_status validate_ga(const empc_ga *G) {
+    if (!G) return fail(EMPC_EINVAL, "ga is NULL");
+    if (G->pop < 1 || G->pop > (1 << 24)) return fail(EMPC_EINVAL, "pop=%d outside [1, 2^24]", G->pop);
+    if (G->n_elite < 1 || G->n_elite > G->pop)
+        return fail(EMPC_EINVAL, "n_elite=%d outside [1, pop=%d]", G->n_elite, G->pop);
+    if (G->n_elite > Limits::MAX_ELITE)
+        return fail(EMPC_EUNSUPPORTED, "n_elite=%d above %d", G->n_elite, Limits::MAX_ELITE);
+    if (G->generations < 1) return fail(EMPC_EINVAL, "generations=%d must be >= 1", G->generations);
+    if (!(G->sigma >= 0.0) || !isfinite(G->sigma)) return fail(EMPC_EINVAL, "sigma must be finite, >= 0");
+    return EMPC_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workspace of empc_solve, in order: header (has_elites, best_slot),
+// population knots [pm][pop], costs [pop], elite rows [k][pm], elite costs
+// [k], elite indices [k] (int64), best index (int64).
+struct Workspace {
+    int *has_elites, *best_slot;
+    void *knots, *cost, *elite_rows, *elite_cost;
+    int64_t *elite_idx, *best_idx;
+    size_t bytes;
+};
+
+Workspace layout(const empc_problem *P, const empc_ga *G, void *base) {
+    const size_t es = esize(P), pm = (size_t)P->p * P->m, pop = G->pop, k = G->n_elite;
+    char *b = (char *)base;
+    size_t off = 0;
+    Workspace w;
+    w.has_elites = (int *)(b + off);
+    w.best_slot = (int *)(b + off + sizeof(int));
+    off += 256;
+    w.knots = b + off; off += align256(pm * pop * es);
+    w.cost = b + off; off += align256(pop * es);
+    w.elite_rows = b + off; off += align256(k * pm * es);
+    w.elite_cost = b + off; off += align256(k * es);
+    w.elite_idx = (int64_t *)(b + off); off += align256(k * sizeof(int64_t));
+    w.best_idx = (int64_t *)(b + off); off += 256;
+    w.bytes = off;
+    return w;
+}
+
+// Rollout timing with HIP events (empc_profile_begin / _end).
+struct Profile {
+    bool on = false;
+    int used = 0;
+    std::vector<hipEvent_t> start, stop;
+};
+Profile g_prof;
+
+template <typename T>
+hipError_t timed_rollout(const ProbView<T> &V, int model, const T *x0, const T *knots,
+                         int64_t ncand, int64_t ld, T *cost, hipStream_t s) {
+    const bool rec = g_prof.on && g_prof.used < (int)g_prof.start.size();
+    if (rec) {
+        hipError_t e = hipEventRecord(g_prof.start[g_prof.used], s);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_rollout<T>(V, model, x0, knots, ncand, ld, cost, s);
+    if (e != hipSuccess) return e;
+    if (rec) {
+        e = hipEventRecord(g_prof.stop[g_prof.used], s);
+        ++g_prof.used;
+    }
+    return e;
+}
+
+template <typename T>
+empc_status solve_t(const empc_problem *P, const empc_ga *G, const Workspace &w, const void *x0,
+                    uint32_t tick, void *u_star, void *best_cost, hipStream_t s) {
+    const ProbView<T> V = view_of<T>(*P);
+    const int64_t pop = G->pop;
+    for (int g = 0; g < G->generations; ++g) {
+        const bool last = g == G->generations - 1;
+        hipError_t e = launch_population<T>(V, *G, nullptr, 0, nullptr, (const T *)w.elite_rows,
+                                            w.has_elites, 2, (T *)w.knots, pop, tick, (uint32_t)g, s);
+        if (e != hipSuccess) return device_status(e, "population launch");
+        e = timed_rollout<T>(V, P->model, (const T *)x0, (const T *)w.knots, pop, pop, (T *)w.cost, s);
+        if (e != hipSuccess) return device_status(e, "rollout launch");
+        e = launch_select<T>(V, (const T *)w.cost, (const T *)w.knots, pop, pop, G->n_elite,
+                             w.elite_idx, w.best_idx, (T *)w.elite_rows, (T *)w.elite_cost,
+                             w.has_elites, w.best_slot, last ? (T *)u_star : nullptr,
+                             last ? (T *)best_cost : nullptr, s);
+        if (e != hipSuccess) return device_status(e, "select launch");
+    }
+    return EMPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *empc_status_str(empc_status s) {
+    switch (s) {
+        case EMPC_OK: return "ok";
+        case EMPC_EINVAL: return "invalid argument";
+        case EMPC_EDEVICE: return "device error";
+        case EMPC_EUNSUPPORTED: return "unsupported problem size";
+        case EMPC_EWORKSPACE: return "workspace too small";
+    }
+    return "unknown status";
+}
+
+const char *empc_last_error(void) { return g_err; }
+
+empc_status empc_rollout_cost(const empc_problem *prob, const void *x0, const void *knots,
+                              int64_t ncand, int64_t ld, void *cost, void *stream) {
+    empc_status st = validate_problem(prob);
+    if (st) return st;
+    if (ncand < 0 || ld < ncand) return fail(EMPC_EINVAL, "need 0 <= ncand <= ld (ncand=%lld, ld=%lld)",
+                                             (long long)ncand, (long long)ld);
+    if (ncand == 0) return EMPC_OK;
+    if (!x0 || !knots || !cost) return fail(EMPC_EINVAL, "x0, knots and cost are required");
+    if ((st = check_prior())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = prob->dtype == EMPC_F32
+                       ? timed_rollout<float>(view_of<float>(*prob), prob->model, (const float *)x0,
+                                              (const float *)knots, ncand, ld, (float *)cost, s)
+                       : timed_rollout<double>(view_of<double>(*prob), prob->model,
+                                                (const double *)x0, (const double *)knots, ncand, ld,
+                                                (double *)cost, s);
+    return device_status(e, "rollout launch");
+}
+
+empc_status empc_generation(const empc_problem *prob, const empc_ga *ga, const void *knots_in,
+                            int64_t ld_in, const void *cost_in, void *knots_out, int64_t ld_out,
+                            int64_t *elite_idx, int64_t *best_idx, uint32_t tick, uint32_t gen,
+                            void *stream) {
+    empc_status st = validate_problem(prob);
+    if (st) return st;
+    if ((st = validate_ga(ga))) return st;
+    const bool cold = knots_in == nullptr && cost_in == nullptr;
+    if (!knots_out) return fail(EMPC_EINVAL, "knots_out is required");
+    if (ld_out < ga->pop) return fail(EMPC_EINVAL, "ld_out=%lld < pop=%d", (long long)ld_out, ga->pop);
+    if (!cold) {
+        if (!knots_in || !cost_in) return fail(EMPC_EINVAL, "knots_in and cost_in go together");
+        if (!elite_idx) return fail(EMPC_EINVAL, "elite_idx is required for a warm start");
+        if (ld_in < ga->pop) return fail(EMPC_EINVAL, "ld_in=%lld < pop=%d", (long long)ld_in, ga->pop);
+        const size_t es = esize(prob), pm = (size_t)prob->p * prob->m;
+        const char *a0 = (const char *)knots_in, *a1 = a0 + ((pm - 1) * ld_in + ga->pop) * es;
+        const char *b0 = (const char *)knots_out, *b1 = b0 + ((pm - 1) * ld_out + ga->pop) * es;
+        if (a0 < b1 && b0 < a1) return fail(EMPC_EINVAL, "knots_out overlaps knots_in");
+    }
+    if ((st = check_prior())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (prob->dtype == EMPC_F32) {
+        const ProbView<float> V = view_of<float>(*prob);
+        if (!cold) {
+            e = launch_select<float>(V, (const float *)cost_in, (const float *)knots_in, ld_in,
+                                     ga->pop, ga->n_elite, elite_idx, best_idx, nullptr, nullptr,
+                                     nullptr, nullptr, nullptr, nullptr, s);
+            if (e != hipSuccess) return device_status(e, "select launch");
+        }
+        e = launch_population<float>(V, *ga, (const float *)knots_in, ld_in, elite_idx, nullptr,
+                                     nullptr, cold ? 1 : 0, (float *)knots_out, ld_out, tick, gen, s);
+    } else {
+        const ProbView<double> V = view_of<double>(*prob);
+        if (!cold) {
+            e = launch_select<double>(V, (const double *)cost_in, (const double *)knots_in, ld_in,
+                                      ga->pop, ga->n_elite, elite_idx, best_idx, nullptr, nullptr,
+                                      nullptr, nullptr, nullptr, nullptr, s);
+            if (e != hipSuccess) return device_status(e, "select launch");
+        }
+        e = launch_population<double>(V, *ga, (const double *)knots_in, ld_in, elite_idx, nullptr,
+                                      nullptr, cold ? 1 : 0, (double *)knots_out, ld_out, tick, gen,
+                                      s);
+    }
+    return device_status(e, "population launch");
+}
+
+size_t empc_workspace_bytes(const empc_problem *prob, const empc_ga *ga) {
+    if (validate_problem(prob) || validate_ga(ga)) return 0;
+    return layout(prob, ga, nullptr).bytes;
+}
+
+empc_status empc_solve(const empc_problem *prob, const empc_ga *ga, void *workspace,
+                       size_t ws_bytes, const void *x0, uint32_t tick, void *u_star,
+                       void *best_cost, void *stream) {
+    empc_status st = validate_problem(prob);
+    if (st) return st;
+    if ((st = validate_ga(ga))) return st;
+    if (!x0 || !u_star || !best_cost) return fail(EMPC_EINVAL, "x0, u_star and best_cost are required");
+    const Workspace w = layout(prob, ga, workspace);
+    if (!workspace || ws_bytes < w.bytes)
+        return fail(EMPC_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, w.bytes);
+    if ((st = check_prior())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    return prob->dtype == EMPC_F32 ? solve_t<float>(prob, ga, w, x0, tick, u_star, best_cost, s)
+                                   : solve_t<double>(prob, ga, w, x0, tick, u_star, best_cost, s);
+}
+
+empc_status empc_grad(const empc_problem *prob, const void *x0, const void *knots, int64_t ncand,
+                      int64_t ld, void *dJ, void *cost, void *stream) {
+    empc_status st = validate_problem(prob);
+    if (st) return st;
+    if (ncand < 0 || ld < ncand) return fail(EMPC_EINVAL, "need 0 <= ncand <= ld");
+    if (ncand == 0) return EMPC_OK;
+    if (!x0 || !knots || !dJ) return fail(EMPC_EINVAL, "x0, knots and dJ are required");
+    if ((st = validate_grad(prob))) return st;
+    if ((st = check_prior())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = prob->dtype == EMPC_F32
+                       ? launch_grad<float>(view_of<float>(*prob), prob->model, (const float *)x0,
+                                            (const float *)knots, ncand, ld, (float *)dJ,
+                                            (float *)cost, 0, 0.f, nullptr, nullptr, s)
+                       : launch_grad<double>(view_of<double>(*prob), prob->model,
+                                             (const double *)x0, (const double *)knots, ncand, ld,
+                                             (double *)dJ, (double *)cost, 0, 0.0, nullptr, nullptr,
+                                             s);
+    return device_status(e, "grad launch");
+}
+
+empc_status empc_refine(const empc_problem *prob, const void *x0, void *knots, int64_t ncand,
+                        int64_t ld, void *cost, double lr, int32_t steps, void *stream) {
+    empc_status st = validate_problem(prob);
+    if (st) return st;
+    if (ncand < 0 || ld < ncand) return fail(EMPC_EINVAL, "need 0 <= ncand <= ld");
+    if (steps < 0 || !(lr >= 0.0) || !isfinite(lr)) return fail(EMPC_EINVAL, "need steps >= 0, finite lr >= 0");
+    if (ncand == 0 || steps == 0) return EMPC_OK;
+    if (!x0 || !knots || !cost) return fail(EMPC_EINVAL, "x0, knots and cost are required");
+    if ((st = validate_grad(prob))) return st;
+    if ((st = check_prior())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = prob->dtype == EMPC_F32
+                       ? launch_grad<float>(view_of<float>(*prob), prob->model, (const float *)x0,
+                                            nullptr, ncand, ld, nullptr, nullptr, steps, (float)lr,
+                                            (float *)knots, (float *)cost, s)
+                       : launch_grad<double>(view_of<double>(*prob), prob->model,
+                                             (const double *)x0, nullptr, ncand, ld, nullptr,
+                                             nullptr, steps, lr, (double *)knots, (double *)cost, s);
+    return device_status(e, "refine launch");
+}
+
+empc_status empc_plant_step(const empc_problem *prob, const void *x, const void *u,
+                            const void *noise, void *x_next, void *stream) {
+    empc_status st = validate_problem(prob);
+    if (st) return st;
+    if (!x || !u || !x_next) return fail(EMPC_EINVAL, "x, u and x_next are required");
+    if ((st = check_prior())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = prob->dtype == EMPC_F32
+                       ? launch_plant<float>(view_of<float>(*prob), prob->model, (const float *)x,
+                                             (const float *)u, (const float *)noise,
+                                             (float *)x_next, s)
+                       : launch_plant<double>(view_of<double>(*prob), prob->model,
+                                              (const double *)x, (const double *)u,
+                                              (const double *)noise, (double *)x_next, s);
+    return device_status(e, "plant launch");
+}
+
+empc_status empc_profile_begin(int32_t max_launches) {
+    if (max_launches < 1) return fail(EMPC_EINVAL, "max_launches must be >= 1");
+    if (g_prof.on) return fail(EMPC_EINVAL, "a profiling session is already open");
+    while ((int)g_prof.start.size() < max_launches) {
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return device_status(e, "hipEventCreate");
+        e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return device_status(e, "hipEventCreate");
+        }
+        g_prof.start.push_back(a);
+        g_prof.stop.push_back(b);
+    }
+    g_prof.used = 0;
+    g_prof.on = true;
+    return EMPC_OK;
+}
+
+empc_status empc_profile_end(int64_t *launches, double *total_ms) {
+    if (!g_prof.on) return fail(EMPC_EINVAL, "no profiling session is open");
+    g_prof.on = false;
+    double tot = 0.0;
+    for (int i = 0; i < g_prof.used; ++i) {
+        hipError_t e = hipEventSynchronize(g_prof.stop[i]);
+        if (e != hipSuccess) return device_status(e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, g_prof.start[i], g_prof.stop[i]);
+        if (e != hipSuccess) return device_status(e, "hipEventElapsedTime");
+        tot += ms;
+    }
+    if (launches) *launches = g_prof.used;
+    if (total_ms) *total_ms = tot;
+    return EMPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Internal declarations of the EMPC HIP library (gfx950).  Not installed;
+// the public interface is include/empc.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "../../include/empc.h"
+
+namespace empc {
+
+// ---------------------------------------------------------------------------
+// Problem view handed to kernels by value.  Pointers are device pointers of
+// element type T (the problem dtype).
+template <typename T>
+struct ProbView {
+    int n, m, Tn, p;
+    const T *Ad, *Bd, *wd;
+    const T *stiff, *damp, *mass, *len;
+    T gravity, dt;
+    const T *q, *r, *qf, *xg, *ug, *umin, *umax;
+};
+
+template <typename T>
+inline ProbView<T> view_of(const empc_problem &P) {
+    ProbView<T> v;
+    v.n = P.n; v.m = P.m; v.Tn = P.T; v.p = P.p;
+    v.Ad = (const T *)P.Ad; v.Bd = (const T *)P.Bd; v.wd = (const T *)P.wd;
+    v.stiff = (const T *)P.stiffness; v.damp = (const T *)P.damping;
+    v.mass = (const T *)P.mass; v.len = (const T *)P.length;
+    v.gravity = (T)P.gravity; v.dt = (T)P.dt;
+    v.q = (const T *)P.q; v.r = (const T *)P.r; v.qf = (const T *)P.qf;
+    v.xg = (const T *)P.x_goal; v.ug = (const T *)P.u_goal;
+    v.umin = (const T *)P.u_min; v.umax = (const T *)P.u_max;
+    return v;
+}
+
+// Knot interpolation of Sec. IV-D in exact integers: with num = k (p-1) and
+// den = T-1, idx1 = num / den, c = (num mod den) / den, idx2 = min(idx1+1, p-1).
+struct Knot {
+    int a, b;
+    int rem, den;
+};
+__host__ __device__ inline Knot knot_at(int T, int p, int k) {
+    Knot s;
+    if (p == 1 || T == 1) {
+        s.a = 0; s.b = 0; s.rem = 0; s.den = 1;
+        return s;
+    }
+    int num = k * (p - 1);
+    s.den = T - 1;
+    s.a = num / s.den;
+    s.rem = num - s.a * s.den;
+    s.b = s.a + 1 < p ? s.a + 1 : p - 1;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: Philox4x32-10 (Salmon et al., SC'11).
+struct U4 {
+    uint32_t x, y, z, w;
+};
+__device__ inline U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+__device__ inline uint32_t word_of(const U4 &v, int i) {
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+// Stream layout of the evolutionary draws (counter = (slot, gen, tick,
+// stream << 24 | block), key = seed): warm start (stream 0) uses block 0 for
+// the two parent draws, blocks 1.. for mutation flags (input i: block
+// 1 + i/128, bit i%128), blocks XB.. for crossover bits (parameter j: block
+// XB + j/128, bit j%128), blocks NB.. for normals (parameter j: block NB + j/4,
+// Box-Muller pair (0,1) or (2,3)); cold start (stream 1): parameter j uses
+// block j/4, word j%4.
+struct GaStreams {
+    uint32_t k0, k1;
+    int XB, NB;
+};
+inline GaStreams ga_streams(uint64_t seed, int m, int pm) {
+    GaStreams s;
+    s.k0 = (uint32_t)seed;
+    s.k1 = (uint32_t)(seed >> 32);
+    s.XB = 1 + (m + 127) / 128;
+    s.NB = s.XB + (pm + 127) / 128;
+    return s;
+}
+__device__ inline U4 ga_draw(const GaStreams &g, uint32_t slot, uint32_t gen, uint32_t tick,
+                             uint32_t stream, uint32_t block) {
+    return philox10(U4{slot, gen, tick, (stream << 24) | block}, g.k0, g.k1);
+}
+// Open-interval uniform (2 (w >> 9) + 1) 2^-24, exact in float and double.
+template <typename T>
+__device__ inline T uni23(uint32_t w) {
+    return ((T)(w >> 9) + (T)0.5) * (T)(1.0 / 8388608.0);
+}
+
+// ---------------------------------------------------------------------------
+// Totally ordered unsigned keys of costs: NaN maps above +inf and -0 to the
+// key of +0, so that key order is the numeric order of the costs.
+__device__ inline uint32_t sort_key(float v) {
+    if (v != v) return 0xFFFFFFFFu;
+    const uint32_t b = v == 0.0f ? 0u : __float_as_uint(v);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline uint64_t sort_key(double v) {
+    if (v != v) return ~0ull;
+    const uint64_t b = v == 0.0 ? 0ull : (uint64_t)__double_as_longlong(v);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (one per kernel family), defined in the .hip files.
+// All return a hipError_t from the launch.
+struct Limits {
+    static constexpr int MAX_N_LINEAR = 80;
+    static constexpr int MAX_M_LINEAR = 40;
+    static constexpr int MAX_D_CHAIN = 40;
+    static constexpr int MAX_ELITE = 256;
+};
+
+template <typename T>
+hipError_t launch_rollout(const ProbView<T> &P, int model, const T *x0, const T *knots,
+                          int64_t ncand, int64_t ld, T *cost, hipStream_t s);
+
+template <typename T>
+hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *knots_in,
+                             int64_t ld_in, const int64_t *elite_idx, const T *elite_rows,
+                             const int *has_elites, int cold_mode, T *knots_out, int64_t ld_out,
+                             uint32_t tick, uint32_t gen, hipStream_t s);
+
+// Selection writes elite indices (ascending), best index, and optionally the
+// elite knot rows [k][pm], elite costs [k], the warm-start flag, u* and the
+// best cost.
+template <typename T>
+hipError_t launch_select(const ProbView<T> &P, const T *cost, const T *knots, int64_t ld,
+                         int64_t pop, int k, int64_t *elite_idx, int64_t *best_idx, T *elite_rows,
+                         T *elite_cost, int *has_elites, int *best_slot, T *u_star, T *best_cost,
+                         hipStream_t s);
+
+template <typename T>
+hipError_t launch_grad(const ProbView<T> &P, int model, const T *x0, const T *knots, int64_t ncand,
+                       int64_t ld, T *dJ, T *cost, int refine_steps, T lr, T *knots_io,
+                       T *cost_io, hipStream_t s);
+
+// LDS bytes of the adjoint kernel; the kernel needs n <= 64 (linear) or
+// d <= 64 (chain) and at most MAX_GRAD_LDS bytes.
+size_t grad_smem_bytes(int model, int n, int m, int T, int p, size_t esize);
+constexpr size_t MAX_GRAD_LDS = 160 * 1024;
+
+template <typename T>
+hipError_t launch_plant(const ProbView<T> &P, int model, const T *x, const T *u, const T *noise,
+                        T *x_next, hipStream_t s);
+
+}  // namespace empc

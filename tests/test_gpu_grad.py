@@ -1,0 +1,147 @@
+"""GPU adjoint (empc_grad), Adam refinement (empc_refine) and the autograd
+wrapper, against the FP64 oracle's adjoint and Adam, and against central
+finite differences of the GPU's own FP64 rollout cost (h = 1e-3)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = torch.float32, torch.float64
+
+
+@pytest.fixture(scope="module")
+def E():
+    import paper_2001_04931_amd as E
+
+    assert torch.cuda.is_available()
+    E.lib()
+    return E
+
+
+def npdt(dtype):
+    return np.float32 if dtype == F32 else np.float64
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def setup(prob, ncand, dtype, seed=0, ld=None):
+    prob = prob.cast(npdt(dtype))
+    x0 = W.draw_x0(prob.n, seed).astype(npdt(dtype)).astype(np.float64)
+    knots = W.draw_knots(prob, ncand, seed + 3, ld=ld).astype(npdt(dtype)).astype(np.float64)
+    return prob, x0, knots
+
+
+def gpu_grad(E, prob, x0, knots, ncand, dtype):
+    dp = E.DeviceProblem(prob, dtype)
+    K = dev(knots, dtype)
+    dJ = torch.full_like(K, float("nan"))
+    cost = torch.zeros(ncand, dtype=dtype, device="cuda")
+    E.empc_grad(dp, dev(x0, dtype), K, ncand, knots.shape[1], dJ, cost)
+    torch.cuda.synchronize()
+    return dJ.cpu().numpy().astype(np.float64), cost.cpu().numpy().astype(np.float64)
+
+
+def rel_err_cols(got, want):
+    scale = np.maximum(np.abs(want).max(axis=0), 1e-30)
+    return (np.abs(got - want).max(axis=0) / scale).max()
+
+
+CASES = [
+    ("linear", 2, 20, 5), ("linear", 14, 50, 10), ("linear", 7, 33, 33), ("linear", 5, 17, 1),
+    ("linear", 21, 40, 6), ("chain", 3, 30, 4), ("chain", 36, 100, 10), ("chain", 9, 50, 50),
+]
+
+
+def make(kind, d, T, p, seed=0):
+    prob = (W.linear_chain if kind == "linear" else W.pendulum_chain)(d, T, p, seed=seed)
+    prob.qf = np.linspace(0.2, 1.0, prob.n)
+    prob.x_goal = np.linspace(-0.1, 0.2, prob.n)
+    return prob
+
+
+@pytest.mark.parametrize("kind,d,T,p", CASES)
+def test_grad_fp64_matches_oracle(oracle_lib, E, kind, d, T, p):
+    prob, x0, knots = setup(make(kind, d, T, p), 9, F64, ld=12)
+    dJ, cost = gpu_grad(E, prob, x0, knots, 9, F64)
+    want, wcost = oracle_lib.grad(prob, x0, knots, 9)
+    assert rel_err_cols(dJ[:, :9], want[:, :9]) < 1e-9
+    np.testing.assert_allclose(cost, wcost, rtol=1e-10)
+
+
+@pytest.mark.parametrize("kind,d,T,p", CASES)
+def test_grad_fp32_matches_oracle(oracle_lib, E, kind, d, T, p):
+    prob, x0, knots = setup(make(kind, d, T, p), 64, F32)
+    dJ, cost = gpu_grad(E, prob, x0, knots, 64, F32)
+    want, wcost = oracle_lib.grad(prob, x0, knots, 64)
+    assert rel_err_cols(dJ, want) < 2e-3
+    np.testing.assert_allclose(cost, wcost, rtol=1e-4)
+
+
+@pytest.mark.parametrize("kind,d,T,p", [("linear", 14, 50, 10), ("chain", 6, 40, 5)])
+def test_grad_fp64_central_differences(E, kind, d, T, p):
+    prob, x0, knots = setup(make(kind, d, T, p), 2, F64)
+    dJ, _ = gpu_grad(E, prob, x0, knots, 2, F64)
+    pm = prob.p * prob.m
+    h = 1e-3
+    # all perturbed candidates in one rollout launch
+    plus = np.repeat(knots[:, :1], pm, axis=1) + h * np.eye(pm)
+    minus = np.repeat(knots[:, :1], pm, axis=1) - h * np.eye(pm)
+    dp = E.DeviceProblem(prob, F64)
+    cost = torch.zeros(2 * pm, dtype=F64, device="cuda")
+    E.empc_rollout_cost(dp, dev(x0, F64), dev(np.hstack([plus, minus]), F64), 2 * pm, 2 * pm,
+                        cost)
+    c = cost.cpu().numpy()
+    fd = (c[:pm] - c[pm:]) / (2 * h)
+    tol = 1e-8 if kind == "linear" else 1e-5  # linear J is quadratic: FD is exact
+    np.testing.assert_allclose(dJ[:, 0], fd, rtol=tol, atol=tol * np.abs(fd).max())
+
+
+@pytest.mark.parametrize("kind,d,T,p", [("linear", 14, 50, 10), ("chain", 5, 30, 4)])
+def test_refine_fp64_matches_oracle(oracle_lib, E, kind, d, T, p):
+    prob, x0, knots = setup(make(kind, d, T, p), 16, F64)
+    cost = oracle_lib.rollout_cost(prob, x0, knots)
+    wk, wc = oracle_lib.refine(prob, x0, knots, cost, lr=0.01, steps=5)
+    dp = E.DeviceProblem(prob, F64)
+    K, C = dev(knots, F64), dev(cost, F64)
+    E.empc_refine(dp, dev(x0, F64), K, 16, 16, C, 0.01, 5)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(C.cpu().numpy(), wc, rtol=1e-9)
+    np.testing.assert_allclose(K.cpu().numpy(), wk, rtol=0, atol=1e-10)
+    assert np.all(wc <= cost) and np.any(wc < cost)
+
+
+def test_refine_fp32_c2_elites(oracle_lib, E):
+    prob, _ = W.config_c2(0)
+    prob, x0, knots = setup(prob, 64, F32)
+    dp = E.DeviceProblem(prob, F32)
+    K = dev(knots, F32)
+    C = torch.zeros(64, dtype=F32, device="cuda")
+    E.empc_rollout_cost(dp, dev(x0, F32), K, 64, 64, C)
+    c0 = C.clone()
+    E.empc_refine(dp, dev(x0, F32), K, 64, 64, C, 0.01, 5)
+    C2 = torch.zeros_like(C)
+    E.empc_rollout_cost(dp, dev(x0, F32), K, 64, 64, C2)
+    torch.cuda.synchronize()
+    assert torch.all(C <= c0) and torch.sum(C < c0) > 32
+    np.testing.assert_allclose(C2.cpu().numpy(), C.cpu().numpy(), rtol=1e-5)
+    assert float(K.abs().max()) <= 1.0
+    cost64 = oracle_lib.rollout_cost(prob, x0, knots)
+    _, wc = oracle_lib.refine(prob, x0, knots, cost64, lr=0.01, steps=5)
+    np.testing.assert_allclose(C.cpu().numpy(), wc, rtol=1e-3)
+
+
+def test_autograd_function(E):
+    prob, x0, knots = setup(make("linear", 4, 20, 5), 8, F64)
+    dp = E.DeviceProblem(prob, F64)
+    K = dev(knots, F64).requires_grad_(True)
+    w = torch.linspace(0.5, 2.0, 8, dtype=F64, device="cuda")
+    cost = E.EmpcCost.apply(K, dev(x0, F64), dp)
+    (cost * w).sum().backward()
+    dJ, c = gpu_grad(E, prob, x0, knots, 8, F64)
+    np.testing.assert_allclose(cost.detach().cpu().numpy(), c, rtol=1e-12)
+    np.testing.assert_allclose(K.grad.cpu().numpy(), dJ * w.cpu().numpy()[None, :], rtol=1e-12)

@@ -1,0 +1,302 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Inputs are seeded synthetic instances from workloads/; for FP32 runs every
+input is rounded to float32 first and the same rounded values go to the
+oracle.  Tolerances: costs 1e-4 relative in FP32 and 1e-9 relative in FP64
+(the bar the method's configuration states); integer decisions (elite sets,
+parent picks, crossover bits, mutation flags) bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = torch.float32, torch.float64
+RTOL = {F32: 1e-4, F64: 1e-9}
+
+
+@pytest.fixture(scope="module")
+def E():
+    import paper_2001_04931_amd as E
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    E.lib()
+    return E
+
+
+def npdt(dtype):
+    return np.float32 if dtype == F32 else np.float64
+
+
+def as_dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def rounded(prob, dtype):
+    return prob.cast(npdt(dtype))
+
+
+def gpu_costs(E, prob, x0, knots, ncand, dtype):
+    dp = E.DeviceProblem(prob, dtype)
+    K = as_dev(knots, dtype)
+    cost = torch.full((ncand,), float("nan"), dtype=dtype, device="cuda")
+    E.empc_rollout_cost(dp, as_dev(x0, dtype), K, ncand, knots.shape[1], cost)
+    torch.cuda.synchronize()
+    return cost.cpu().numpy().astype(np.float64)
+
+
+def check_costs(oracle_lib, E, prob, ncand, ld, dtype, seed=0, spread=1.0):
+    prob = rounded(prob, dtype)
+    x0 = W.draw_x0(prob.n, seed).astype(npdt(dtype)).astype(np.float64)
+    knots = W.draw_knots(prob, ncand, seed + 1, ld=ld, spread=spread)
+    knots = knots.astype(npdt(dtype)).astype(np.float64)
+    got = gpu_costs(E, prob, x0, knots, ncand, dtype)
+    want = oracle_lib.rollout_cost(prob, x0, knots, ncand)
+    np.testing.assert_allclose(got, want, rtol=RTOL[dtype], atol=0)
+    return got, want
+
+
+# ---------------------------------------------------------------------------
+# rollout + cost
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("d", [2, 7, 14, 21, 36])
+def test_rollout_linear_chain_shapes(oracle_lib, E, dtype, d):
+    # several 16-candidate tiles plus a ragged tail, ld > ncand
+    prob = W.linear_chain(d, 37, 6, seed=d)
+    check_costs(oracle_lib, E, prob, ncand=16 * 5 + 7, ld=100, dtype=dtype, seed=d)
+
+
+def test_rollout_linear_c2_shape(oracle_lib, E):
+    prob, _ = W.config_c2(0)
+    check_costs(oracle_lib, E, prob, ncand=131, ld=131, dtype=F32)
+
+
+def test_rollout_linear_c1_shape_fp64(oracle_lib, E):
+    prob, _ = W.config_c1(0)
+    check_costs(oracle_lib, E, prob, ncand=300, ld=301, dtype=F64)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("d", [2, 7, 14, 21, 36])
+def test_rollout_pendulum_chain_shapes(oracle_lib, E, dtype, d):
+    prob = W.pendulum_chain(d, 60, 7, seed=d)
+    check_costs(oracle_lib, E, prob, ncand=300, ld=301, dtype=dtype, seed=d)
+
+
+def test_rollout_pendulum_c3_shape(oracle_lib, E):
+    prob, _ = W.config_c3(0)
+    check_costs(oracle_lib, E, prob, ncand=70, ld=70, dtype=F32)
+
+
+@pytest.mark.parametrize("model", ["linear", "chain"])
+@pytest.mark.parametrize("T,p", [(1, 1), (9, 1), (12, 12), (50, 2), (2, 2)])
+def test_rollout_knot_edge_cases(oracle_lib, E, model, T, p):
+    mk = W.linear_chain if model == "linear" else W.pendulum_chain
+    prob = mk(3, T, p, seed=1)
+    prob.qf = np.linspace(0.1, 1.0, prob.n)
+    prob.x_goal = np.linspace(-0.2, 0.3, prob.n)
+    prob.u_goal = np.linspace(0.1, -0.1, prob.m)
+    check_costs(oracle_lib, E, prob, ncand=33, ld=40, dtype=F64, seed=T)
+
+
+def test_rollout_out_of_bounds_knots_used_as_given(oracle_lib, E):
+    prob = W.linear_chain(4, 20, 5, seed=3)
+    check_costs(oracle_lib, E, prob, ncand=50, ld=50, dtype=F64, spread=3.0)
+
+
+def test_rollout_zero_and_single_candidate(oracle_lib, E):
+    prob = W.linear_chain(2, 10, 3, seed=0)
+    dp = E.DeviceProblem(prob, F64)
+    cost = torch.full((4,), -7.0, dtype=F64, device="cuda")
+    x0 = as_dev(np.zeros(prob.n), F64)
+    K = as_dev(np.zeros((prob.p * prob.m, 4)), F64)
+    E.empc_rollout_cost(dp, x0, K, 0, 4, cost)
+    torch.cuda.synchronize()
+    assert torch.all(cost == -7.0)  # ncand = 0 writes nothing
+    check_costs(oracle_lib, E, prob, ncand=1, ld=1, dtype=F64)
+
+
+def test_rollout_full_c2_population_sampled(oracle_lib, E):
+    # the benchmark's launch: 4096 candidates in one call; sampled check
+    prob, ga = W.config_c2(0)
+    prob = rounded(prob, F32)
+    x0 = W.draw_x0(prob.n, 0).astype(np.float32).astype(np.float64)
+    knots = W.draw_knots(prob, ga.pop, 2).astype(np.float32).astype(np.float64)
+    got = gpu_costs(E, prob, x0, knots, ga.pop, F32)
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([rng.choice(ga.pop, 40, replace=False), [0, ga.pop - 1]])
+    want = oracle_lib.rollout_cost(prob, x0, np.ascontiguousarray(knots[:, idx]))
+    np.testing.assert_allclose(got[idx], want, rtol=1e-4)
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+
+
+def test_rollout_equilibrium_is_zero(E):
+    for mk in (W.linear_chain, W.pendulum_chain):
+        prob = mk(5, 30, 5, seed=0)
+        got = gpu_costs(E, prob, np.zeros(prob.n), np.zeros((prob.p * prob.m, 20)), 20, F32)
+        assert np.all(got == 0.0)
+
+
+def test_rollout_deterministic(E):
+    prob, ga = W.config_c2(0)
+    knots = W.draw_knots(prob, 1000, 4)
+    a = gpu_costs(E, prob, W.draw_x0(prob.n, 0), knots, 1000, F32)
+    b = gpu_costs(E, prob, W.draw_x0(prob.n, 0), knots, 1000, F32)
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# selection and next population
+
+
+def gpu_generation(E, prob, ga, knots_in, cost_in, tick, gen, dtype):
+    dp = E.DeviceProblem(prob, dtype)
+    g = E.make_ga(ga)
+    pm = prob.p * prob.m
+    out = torch.full((pm, ga.pop), float("nan"), dtype=dtype, device="cuda")
+    eidx = torch.full((ga.n_elite,), -1, dtype=torch.int64, device="cuda")
+    best = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    if knots_in is None:
+        E.empc_generation(dp, g, None, 0, None, out, ga.pop, None, None, tick, gen)
+    else:
+        E.empc_generation(dp, g, as_dev(knots_in, dtype), knots_in.shape[1],
+                          as_dev(cost_in, dtype), out, ga.pop, eidx, best, tick, gen)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64), eidx.cpu().numpy(), int(best.item())
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_cold_start_population(oracle_lib, E, dtype):
+    prob, ga = W.config_c2(0)
+    prob = rounded(prob, dtype)
+    ga = W.dataclasses.replace(ga, pop=1000)
+    got, _, _ = gpu_generation(E, prob, ga, None, None, tick=3, gen=1, dtype=dtype)
+    want = oracle_lib.next_population(prob, ga, None, cold=True, tick=3, gen=1)
+    np.testing.assert_allclose(got, want, rtol=0, atol=2e-7 if dtype == F32 else 1e-15)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("elitism", [True, False])
+def test_warm_generation_matches_oracle(oracle_lib, E, dtype, elitism):
+    prob, ga = W.config_c2(0)
+    prob = rounded(prob, dtype)
+    ga = W.dataclasses.replace(ga, pop=777, n_elite=40, elitism=elitism, seed=12345678901)
+    rng = np.random.default_rng(1)
+    knots = W.draw_knots(prob, ga.pop, 5).astype(npdt(dtype)).astype(np.float64)
+    cost = rng.uniform(0, 10, ga.pop).astype(npdt(dtype)).astype(np.float64)
+    got, eidx, best = gpu_generation(E, prob, ga, knots, cost, tick=7, gen=2, dtype=dtype)
+    want_idx, want_best = oracle_lib.select(cost, ga.n_elite)
+    np.testing.assert_array_equal(eidx, want_idx)
+    assert best == want_best
+    elite_rows = knots[:, want_idx].T.copy()
+    want = oracle_lib.next_population(prob, ga, elite_rows, cold=False, tick=7, gen=2)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-6 if dtype == F32 else 1e-14)
+    # integer decisions are exact: un-mutated, unclamped children equal a parent
+    assert np.mean(got == want) > 0.4
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_selection_ties_nan_inf(oracle_lib, E, dtype):
+    prob = W.linear_chain(2, 10, 3, seed=0)
+    rng = np.random.default_rng(7)
+    for pop, k in [(1, 1), (5, 5), (300, 17), (4096, 64), (5000, 256), (1025, 1)]:
+        ga = W.GA(pop=pop, n_elite=k, generations=1, sigma=0.1, seed=1)
+        cost = np.round(rng.normal(0, 1, pop), 1)
+        cost[rng.random(pop) < 0.05] = np.nan
+        cost[rng.random(pop) < 0.03] = np.inf
+        cost[rng.random(pop) < 0.03] = -np.inf
+        cost[rng.random(pop) < 0.02] = 0.0
+        cost[rng.random(pop) < 0.02] = -0.0
+        knots = W.draw_knots(prob, pop, 1)
+        _, eidx, best = gpu_generation(E, prob, ga, knots, cost, 0, 0, dtype)
+        want_idx, want_best = oracle_lib.select(cost, k)
+        np.testing.assert_array_equal(eidx, want_idx)
+        assert best == want_best
+
+
+# ---------------------------------------------------------------------------
+# solve
+
+
+def test_solve_fp64_matches_oracle_over_ticks(oracle_lib, E):
+    # FP64 keeps every elite set identical to the oracle's, so whole
+    # multi-generation, multi-tick trajectories agree
+    prob, ga = W.config_c1(0)
+    dp = E.DeviceProblem(prob, F64)
+    solver = E.Solver(dp, ga)
+    osolver = oracle_lib.Solver(prob, ga)
+    x = W.draw_x0(prob.n, 0)
+    noise = W.process_noise(prob.n, 5, 0)
+    for tick in range(5):
+        u, J = solver.solve(as_dev(x, F64), tick)
+        u = u.cpu().numpy()
+        J = float(J.item())
+        uo, Jo, _ = osolver.solve(x, tick)
+        np.testing.assert_allclose(u, uo, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(J, Jo, rtol=1e-9)
+        x = oracle_lib.step(prob, x, uo, noise[tick])
+
+
+def test_solve_fp32_one_generation_matches_oracle(oracle_lib, E):
+    prob, ga = W.config_c2(0)
+    prob = rounded(prob, F32)
+    ga = W.dataclasses.replace(ga, generations=1)
+    x0 = W.draw_x0(prob.n, 0).astype(np.float32).astype(np.float64)
+    solver = E.Solver(E.DeviceProblem(prob, F32), ga)
+    u, J = solver.solve(as_dev(x0, F32), 0)
+    uo, Jo, _ = oracle_lib.Solver(prob, ga).solve(x0, 0)
+    np.testing.assert_allclose(float(J.item()), Jo, rtol=1e-4)
+    np.testing.assert_allclose(u.cpu().numpy(), uo, atol=1e-6)
+
+
+def test_solve_fp32_c2_tick_quality(oracle_lib, E):
+    # full C2 tick: the best cost is the cost of the returned knots, it is
+    # non-increasing over generations, and it is close to the FP64 oracle's
+    prob, ga = W.config_c2(0)
+    prob = rounded(prob, F32)
+    x0 = W.draw_x0(prob.n, 0).astype(np.float32).astype(np.float64)
+    dp = E.DeviceProblem(prob, F32)
+    bests = []
+    for G in (1, 5, 20):
+        s = E.Solver(dp, W.dataclasses.replace(ga, generations=G))
+        _, J = s.solve(as_dev(x0, F32), 0)
+        bests.append(float(J.item()))
+    assert bests[0] >= bests[1] >= bests[2]
+    _, Jo, gb = oracle_lib.Solver(prob, W.dataclasses.replace(ga, generations=5)).solve(x0, 0)
+    np.testing.assert_allclose(bests[1], Jo, rtol=1e-3)
+
+
+def test_solve_workspace_errors(E):
+    prob, ga = W.config_c1(0)
+    dp = E.DeviceProblem(prob, F64)
+    g = E.make_ga(ga)
+    ws = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    u = torch.zeros(prob.m, dtype=F64, device="cuda")
+    b = torch.zeros(1, dtype=F64, device="cuda")
+    with pytest.raises(E.EmpcError) as ei:
+        E.empc_solve(dp, g, ws, as_dev(np.zeros(prob.n), F64), 0, u, b)
+    assert ei.value.status == 4
+
+
+# ---------------------------------------------------------------------------
+# plant step
+
+
+@pytest.mark.parametrize("mk", [W.linear_chain, W.pendulum_chain])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_plant_step(oracle_lib, E, mk, dtype):
+    prob = rounded(mk(6, 10, 3, seed=2), dtype)
+    dp = E.DeviceProblem(prob, dtype)
+    x = W.draw_x0(prob.n, 1).astype(npdt(dtype)).astype(np.float64)
+    u = np.linspace(-0.5, 0.7, prob.m).astype(npdt(dtype)).astype(np.float64)
+    nz = W.process_noise(prob.n, 1, 0)[0].astype(npdt(dtype)).astype(np.float64)
+    out = torch.zeros(prob.n, dtype=dtype, device="cuda")
+    E.empc_plant_step(dp, as_dev(x, dtype), as_dev(u, dtype), as_dev(nz, dtype), out)
+    want = oracle_lib.step(prob, x, u, nz)
+    np.testing.assert_allclose(out.cpu().numpy(), want, rtol=1e-5 if dtype == F32 else 1e-12,
+                               atol=1e-6 if dtype == F32 else 1e-14)

@@ -1,0 +1,149 @@
+"""Host-side checks of libempc.so that need no GPU: every symbol declared in
+include/empc.h is exported, and argument validation rejects bad calls before
+anything reaches the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "empc.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(empc_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def E():
+    import paper_2001_04931_amd as E
+
+    if not os.path.exists(E.binding.LIB_PATH):
+        pytest.skip("libempc.so not built")
+    E.lib()
+    return E
+
+
+def test_header_symbols_exported(E):
+    names = header_functions()
+    assert len(names) >= 10
+    L = ctypes.CDLL(E.binding.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(E.binding.exported_symbols()) == names
+
+
+def _problem(E, **over):
+    c = E.EmpcProblem()
+    c.n, c.m, c.T, c.p, c.dtype, c.model = 4, 2, 10, 3, 0, 0
+    fake = ctypes.c_void_p(0x1000)
+    for f in ("Ad", "Bd", "q", "r", "u_min", "u_max"):
+        setattr(c, f, fake)
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c
+
+
+def _call_rollout(E, c, ncand=8, ld=8):
+    fake = ctypes.c_void_p(0x2000)
+    return E.lib().empc_rollout_cost(ctypes.byref(c), fake, fake, ncand, ld, fake, None)
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(p=11), 1), (dict(p=0), 1), (dict(T=0), 1), (dict(n=0), 1), (dict(dtype=7), 1),
+    (dict(model=5), 1), (dict(Ad=None), 1), (dict(u_max=None), 1),
+    (dict(n=81), 3), (dict(m=41), 3),
+    (dict(model=1, n=6, m=3), 1),                       # chain without its parameters
+])
+def test_rollout_validation(E, over, status):
+    st = _call_rollout(E, _problem(E, **over))
+    assert st == status
+    assert E.lib().empc_last_error().decode() != ""
+
+
+def test_rollout_bad_sizes(E):
+    assert _call_rollout(E, _problem(E), ncand=9, ld=8) == 1
+    assert _call_rollout(E, _problem(E), ncand=-1, ld=8) == 1
+    assert E.lib().empc_rollout_cost(None, None, None, 1, 1, None, None) == 1
+
+
+def test_chain_validation(E):
+    fake = ctypes.c_void_p(0x1000)
+    c = _problem(E, model=1, n=6, m=3, stiffness=fake, damping=fake, mass=fake, length=fake)
+    c.dt = 0.0
+    assert _call_rollout(E, c) == 1
+    c.dt = 0.005
+    c.n = 7
+    assert _call_rollout(E, c) == 1
+    c.n, c.m = 82, 41
+    assert _call_rollout(E, c) == 3
+
+
+def test_ga_validation_and_workspace_size(E):
+    c = _problem(E)
+    g = E.EmpcGA()
+    g.pop, g.n_elite, g.generations, g.elitism, g.sigma, g.seed = 100, 10, 2, 1, 0.1, 0
+    nb = E.lib().empc_workspace_bytes(ctypes.byref(c), ctypes.byref(g))
+    assert nb >= 4 * (c.p * c.m * 100 + 100 + 10 * c.p * c.m)
+    for field, val in (("n_elite", 101), ("n_elite", 0), ("pop", 0), ("generations", 0),
+                       ("n_elite", 300), ("sigma", -1.0)):
+        g2 = E.EmpcGA.from_buffer_copy(g)
+        setattr(g2, field, val)
+        if field == "n_elite" and val == 300:
+            g2.pop = 1000
+        assert E.lib().empc_workspace_bytes(ctypes.byref(c), ctypes.byref(g2)) == 0
+    fake = ctypes.c_void_p(0x3000)
+    st = E.lib().empc_solve(ctypes.byref(c), ctypes.byref(g), fake, nb - 1, fake, 0, fake, fake,
+                            None)
+    assert st == 4
+    st = E.lib().empc_solve(ctypes.byref(c), ctypes.byref(g), None, nb, fake, 0, fake, fake, None)
+    assert st == 4
+
+
+def test_generation_validation(E):
+    c = _problem(E)
+    g = E.EmpcGA()
+    g.pop, g.n_elite, g.generations, g.elitism, g.sigma, g.seed = 64, 8, 1, 1, 0.1, 0
+    L = E.lib()
+    fake = ctypes.c_void_p(0x10000)
+    # warm start without elite_idx
+    assert L.empc_generation(ctypes.byref(c), ctypes.byref(g), fake, 64, fake,
+                             ctypes.c_void_p(0x900000), 64, None, None, 0, 0, None) == 1
+    # overlapping in / out populations
+    assert L.empc_generation(ctypes.byref(c), ctypes.byref(g), fake, 64, fake, fake, 64,
+                             fake, None, 0, 0, None) == 1
+    # ld_out below pop
+    assert L.empc_generation(ctypes.byref(c), ctypes.byref(g), None, 0, None, fake, 63,
+                             None, None, 0, 0, None) == 1
+
+
+def test_grad_limits(E):
+    c = _problem(E, n=70, m=10)
+    fake = ctypes.c_void_p(0x1000)
+    assert E.lib().empc_grad(ctypes.byref(c), fake, fake, 4, 4, fake, None, None) == 3
+    c = _problem(E)
+    assert E.lib().empc_refine(ctypes.byref(c), fake, fake, 4, 4, fake, -1.0, 5, None) == 1
+
+
+def test_profile_session_errors(E):
+    L = E.lib()
+    assert L.empc_profile_end(None, None) == 1
+    assert L.empc_profile_begin(0) == 1
+
+
+def test_status_strings(E):
+    for s in range(5):
+        assert E.lib().empc_status_str(s).decode()
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
