@@ -13,7 +13,11 @@ plant step.  Printed as one JSON line:
   roofline    rollout kernel: algorithmic FLOP per launch over the mean
               launch time from HIP events recorded around every rollout
               launch of the timed ticks, against the FP32 matrix-core peak;
-  cpu_baseline the FP64 oracle on a bounded sample of the same workload.
+  cpu_baseline the FP64 oracle on a bounded sample of the same workload;
+  workloads   the other configurations measured the same way: 2-DoF chain
+              in FP64, 36-link pendulum chain, the gradient-refined form of
+              the 14-DoF run beside plain EMPC, and 512 uneven problems
+              solved together, one HIP-graph replay per tick.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -34,12 +38,15 @@ sys.path.insert(0, ROOT)
 METRIC = ("candidate rollouts/sec and EMPC solve latency p50/p99 (ms) at fixed DoF/horizon")
 PEAK_FP32_MFMA = 157.3e12  # MI355X dense FP32 matrix peak, FLOP/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rollout_linear_c2_traffic.json")
-ROLLOUT_SRC = os.path.join(ROOT, "paper_2001_04931_amd", "csrc", "rollout.hip")
+ROLLOUT_SRC = os.path.join(ROOT, "paper_2001_04931_amd", "csrc", "rollout_linear.hpp")
 
 
-def linear_flop_per_step(n, m):
-    # knot interpolation 3m, A_d x 2n^2, B_d u 2nm, stage cost 3n + 3m
-    return 2 * n * n + 2 * n * m + 3 * n + 6 * m
+def linear_flop_per_candidate(n, m, T, p):
+    """Algorithmic FLOP of one linear rollout with the knot precompute
+    (V_j = B_d U_j once per knot): per step A_d x (2n^2), the knot blend and
+    the state cost (6n), the input blend and cost (6m); per candidate the p
+    knot responses B_d U_j (2pnm)."""
+    return T * (2 * n * n + 6 * n + 6 * m) + 2 * p * n * m
 
 
 def traffic_entry():
@@ -77,6 +84,109 @@ def cpu_baseline(prob, ga, ticks):
                       "each), FP64, one thread, %.1f s" % (ticks, ga.generations, ga.pop, dt)}
 
 
+def closed_loop(E, W, prob, ga, dtype, ticks, warmup, noise_std=0.0, refine_steps=0):
+    """Closed-loop ticks on one problem: solve, u* and best cost to the host,
+    plant step.  Returns (rollouts/s, per-tick latencies in ms, best costs)."""
+    import torch
+
+    dp = E.DeviceProblem(prob, dtype)
+    solver = E.Solver(dp, ga)
+    total = warmup + ticks
+    x = torch.tensor(W.draw_x0(prob.n, 0), dtype=dtype, device="cuda")
+    x_next = torch.empty_like(x)
+    noise = None
+    if noise_std > 0:
+        noise = torch.tensor(W.process_noise(prob.n, total, 0, noise_std), dtype=dtype,
+                             device="cuda")
+    u_host = torch.empty(prob.m, dtype=dtype).pin_memory()
+    j_host = torch.empty(1, dtype=dtype).pin_memory()
+    done = torch.cuda.Event()
+    lats, costs = [], []
+    t_start = None
+    for t in range(total):
+        if t == warmup:
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+        t0 = time.perf_counter()
+        u, J = solver.solve(x, t, refine_steps=refine_steps)
+        u_host.copy_(u, non_blocking=True)
+        j_host.copy_(J, non_blocking=True)
+        done.record()
+        done.synchronize()
+        if t >= warmup:
+            lats.append((time.perf_counter() - t0) * 1e3)
+            costs.append(float(j_host.item()))
+        E.empc_plant_step(dp, x, u, None if noise is None else noise[t], x_next)
+        x, x_next = x_next, x
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    return ga.pop * ga.generations * ticks / wall, np.array(lats), costs
+
+
+def summary(rate, lats, **extra):
+    d = {"rollouts_per_s": rate, "latency_ms": {"p50": float(np.percentile(lats, 50)),
+                                                "p99": float(np.percentile(lats, 99))}}
+    d.update(extra)
+    return d
+
+
+def other_workloads(E, W):
+    """The remaining benchmark configurations, measured the same way."""
+    import torch
+
+    out = {}
+    prob, ga = W.config_c1(0)
+    rate, lats, _ = closed_loop(E, W, prob, ga, torch.float64, 100, 5)
+    out["c1_fp64_2dof"] = summary(rate, lats, ticks=100, dtype="f64")
+
+    prob, ga = W.config_c3(0)
+    rate, lats, _ = closed_loop(E, W, prob, ga, torch.float32, 10, 2)
+    out["c3_fp32_36link_chain"] = summary(rate, lats, ticks=10, dtype="f32")
+
+    # gradient-refined form beside plain EMPC on the same ticks
+    prob, ga = W.config_c2(0)
+    rate_p, lats_p, costs_p = closed_loop(E, W, prob, ga, torch.float32, 10, 1, noise_std=1e-3)
+    rate_r, lats_r, costs_r = closed_loop(E, W, prob, ga, torch.float32, 10, 1, noise_std=1e-3,
+                                          refine_steps=5)
+    out["c4_fp32_14dof_refined"] = summary(
+        rate_r, lats_r, ticks=10, dtype="f32", adam_steps_per_generation=5, elites_refined=64,
+        plain_rollouts_per_s=rate_p,
+        first_tick_best_cost={"plain": costs_p[0], "refined": costs_r[0]})
+
+    # 512 uneven problems, one tick per HIP-graph replay
+    probs, ga = W.config_c5(512, 0)
+    dps = [E.DeviceProblem(p.cast(np.float32), torch.float32) for p in probs]
+    bs = E.BatchSolver(dps, ga)
+    for i, p in enumerate(probs):
+        bs.set_x0(i, W.draw_x0(p.n, i))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bs.solve()
+    u_host = torch.empty(bs.u_star.numel(), dtype=torch.float32).pin_memory()
+    done = torch.cuda.Event()
+    ticks, warm = 200, 10
+    lats = []
+    for t in range(warm + ticks):
+        if t == warm:
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+        t0 = time.perf_counter()
+        g.replay()
+        u_host.copy_(bs.u_star, non_blocking=True)
+        done.record()
+        done.synchronize()
+        if t >= warm:
+            lats.append((time.perf_counter() - t0) * 1e3)
+    wall = time.perf_counter() - t_start
+    lats = np.array(lats)
+    out["c5_fp32_512_problems"] = summary(
+        len(probs) * ga.pop * ga.generations * ticks / wall, lats, ticks=ticks, dtype="f32",
+        problems=len(probs), within_2ms=float(np.mean(lats <= 2.0)))
+    bs.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +194,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5, help="untimed control ticks")
     ap.add_argument("--cpu-ticks", type=int, default=4, help="oracle ticks for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the other configurations (C1, C3, C4, C5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the EMPC hot path here is a single-GPU "
@@ -138,7 +250,7 @@ def main():
 
     rollouts = ga.pop * ga.generations * args.steps
     lat_ms = np.array(lats) * 1e3
-    flop_launch = ga.pop * prob.T * linear_flop_per_step(prob.n, prob.m)
+    flop_launch = ga.pop * linear_flop_per_candidate(prob.n, prob.m, prob.T, prob.p)
     avg_launch_s = kernel_ms * 1e-3 / max(launches, 1)
     achieved = flop_launch / avg_launch_s
     traffic = traffic_entry()
@@ -172,6 +284,8 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic},
         "final_best_cost": final_cost,
     }
+    if not args.no_workloads:
+        out["workloads"] = other_workloads(E, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, ga, args.cpu_ticks)
     print(json.dumps(out), flush=True)

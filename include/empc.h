@@ -139,6 +139,14 @@ empc_status empc_solve(const empc_problem *prob, const empc_ga *ga, void *worksp
                        size_t ws_bytes, const void *x0, uint32_t tick, void *u_star,
                        void *best_cost, void *stream);
 
+/* Gradient-refined tick: as empc_solve, but after every selection the
+ * parents are refined by `adam_steps` Adam updates (empc_refine semantics,
+ * learning rate lr) before they breed the next generation; u* and the best
+ * cost come from the best refined parent.  Same workspace as empc_solve. */
+empc_status empc_solve_refined(const empc_problem *prob, const empc_ga *ga, void *workspace,
+                               size_t ws_bytes, const void *x0, uint32_t tick, double lr,
+                               int32_t adam_steps, void *u_star, void *best_cost, void *stream);
+
 /* Gradient of the rollout cost with respect to the knots by a hand-written
  * adjoint pass (states recomputed from checkpoints every ceil(sqrt(T))
  * steps).  dJ: [p*m][ld].  cost: ncand (may be NULL). */
@@ -158,10 +166,38 @@ empc_status empc_refine(const empc_problem *prob, const void *x0, void *knots, i
 empc_status empc_plant_step(const empc_problem *prob, const void *x, const void *u,
                             const void *noise, void *x_next, void *stream);
 
+/* Batched solve: many independent problems (each its own empc_problem, all
+ * FP32, possibly of different model, size, horizon and knot count) advance
+ * one control tick together under one empc_ga.  Problem i draws from the
+ * Philox key (seed low word, seed high word XOR i), so it evolves exactly as
+ * empc_solve would with that seed.
+ *
+ * empc_batch_workspace_bytes(probs (host array), nprob, ga) -> bytes of
+ *   device workspace (0 if an argument is invalid).
+ * empc_batch_create binds the problems, the workspace (device, zero-filled
+ *   for a cold start; it also holds the tick counter, starting at 0), the
+ *   packed initial states x0_packed (device, sum of n, problem after
+ *   problem; the caller may rewrite them between ticks), the packed outputs
+ *   u_star_packed (device, sum of m) and best_cost (device, nprob) into a
+ *   plan.  Host call; allocates the plan's small device tables.
+ * empc_solve_batched(plan, stream) runs one tick: ga->generations x
+ *   {population, rollout + cost, selection} for every problem, then
+ *   increments the device tick counter, so that a HIP graph captured from
+ *   one call replays tick after tick.  Allocates nothing.
+ * empc_batch_destroy frees the plan (not the caller's buffers). */
+typedef struct empc_batch empc_batch;
+size_t empc_batch_workspace_bytes(const empc_problem *probs, int32_t nprob, const empc_ga *ga);
+empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const empc_ga *ga,
+                              void *workspace, size_t ws_bytes, const void *x0_packed,
+                              void *u_star_packed, void *best_cost, empc_batch **out);
+empc_status empc_solve_batched(empc_batch *plan, void *stream);
+empc_status empc_batch_destroy(empc_batch *plan);
+
 /* Kernel timing.  empc_profile_begin(max_launches) creates a pool of HIP
  * event pairs (host call, may allocate); until empc_profile_end, every
  * rollout launch made by empc_rollout_cost and empc_solve (at most
- * max_launches of them) is bracketed by an event pair on its stream.
+ * max_launches of them) carries an event pair stamped at the start and end
+ * of the kernel's own dispatch (no extra packets on the stream).
  * empc_profile_end waits for the recorded events and returns the number of
  * timed launches and their summed duration in milliseconds, then stops
  * timing.  Not thread-safe: one profiling session per process. */

@@ -12,6 +12,7 @@ import ctypes
 import os
 from typing import Optional
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -66,10 +67,17 @@ def lib() -> ctypes.CDLL:
                                 ctypes.c_int),
             "empc_workspace_bytes": ([P, G], sz),
             "empc_solve": ([P, G, _vp, sz, _vp, u32, _vp, _vp, _vp], ctypes.c_int),
+            "empc_solve_refined": ([P, G, _vp, sz, _vp, u32, ctypes.c_double, ctypes.c_int32, _vp,
+                                    _vp, _vp], ctypes.c_int),
             "empc_grad": ([P, _vp, _vp, i64, i64, _vp, _vp, _vp], ctypes.c_int),
             "empc_refine": ([P, _vp, _vp, i64, i64, _vp, ctypes.c_double, ctypes.c_int32, _vp],
                             ctypes.c_int),
             "empc_plant_step": ([P, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+            "empc_batch_workspace_bytes": ([P, ctypes.c_int32, G], sz),
+            "empc_batch_create": ([P, ctypes.c_int32, G, _vp, sz, _vp, _vp, _vp,
+                                   ctypes.POINTER(_vp)], ctypes.c_int),
+            "empc_solve_batched": ([_vp, _vp], ctypes.c_int),
+            "empc_batch_destroy": ([_vp], ctypes.c_int),
             "empc_profile_begin": ([ctypes.c_int32], ctypes.c_int),
             "empc_profile_end": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
                                  ctypes.c_int),
@@ -84,8 +92,9 @@ def lib() -> ctypes.CDLL:
 
 def exported_symbols():
     return ["empc_status_str", "empc_last_error", "empc_rollout_cost", "empc_generation",
-            "empc_workspace_bytes", "empc_solve", "empc_grad", "empc_refine", "empc_plant_step",
-            "empc_profile_begin", "empc_profile_end"]
+            "empc_workspace_bytes", "empc_solve", "empc_solve_refined", "empc_grad", "empc_refine", "empc_plant_step",
+            "empc_batch_workspace_bytes", "empc_batch_create", "empc_solve_batched",
+            "empc_batch_destroy", "empc_profile_begin", "empc_profile_end"]
 
 
 def _check(status: int):
@@ -140,6 +149,13 @@ def empc_solve(prob, ga, workspace, x0, tick, u_star, best_cost, stream=None):
                             _ptr(x0), int(tick), _ptr(u_star), _ptr(best_cost), _stream(stream)))
 
 
+def empc_solve_refined(prob, ga, workspace, x0, tick, lr, adam_steps, u_star, best_cost,
+                       stream=None):
+    _check(lib().empc_solve_refined(_cprob(prob), _cga(ga), _ptr(workspace), workspace.numel(),
+                                    _ptr(x0), int(tick), float(lr), int(adam_steps), _ptr(u_star),
+                                    _ptr(best_cost), _stream(stream)))
+
+
 def empc_grad(prob, x0, knots, ncand, ld, dJ, cost, stream=None):
     _check(lib().empc_grad(_cprob(prob), _ptr(x0), _ptr(knots), int(ncand), int(ld), _ptr(dJ),
                            _ptr(cost), _stream(stream)))
@@ -153,6 +169,26 @@ def empc_refine(prob, x0, knots, ncand, ld, cost, lr, steps, stream=None):
 def empc_plant_step(prob, x, u, noise, x_next, stream=None):
     _check(lib().empc_plant_step(_cprob(prob), _ptr(x), _ptr(u), _ptr(noise), _ptr(x_next),
                                  _stream(stream)))
+
+
+def empc_batch_workspace_bytes(cprobs, nprob, ga) -> int:
+    return int(lib().empc_batch_workspace_bytes(cprobs, int(nprob), _cga(ga)))
+
+
+def empc_batch_create(cprobs, nprob, ga, workspace, x0_packed, u_star_packed, best_cost):
+    plan = ctypes.c_void_p()
+    _check(lib().empc_batch_create(cprobs, int(nprob), _cga(ga), _ptr(workspace),
+                                   workspace.numel(), _ptr(x0_packed), _ptr(u_star_packed),
+                                   _ptr(best_cost), ctypes.byref(plan)))
+    return plan
+
+
+def empc_solve_batched(plan, stream=None):
+    _check(lib().empc_solve_batched(plan, _stream(stream)))
+
+
+def empc_batch_destroy(plan):
+    _check(lib().empc_batch_destroy(plan))
 
 
 def empc_profile_begin(max_launches):
@@ -180,6 +216,7 @@ class DeviceProblem:
 
     _ARRAYS = ("Ad", "Bd", "wd", "stiffness", "damping", "mass", "length", "q", "r", "qf",
                "x_goal", "u_goal", "u_min", "u_max")
+    _OPTIONAL = ("wd", "qf", "x_goal", "u_goal")
 
     def __init__(self, prob, dtype=torch.float32, device="cuda"):
         self.prob, self.dtype, self.device = prob, dtype, torch.device(device)
@@ -190,7 +227,9 @@ class DeviceProblem:
         c.model = int(prob.model)
         for name in self._ARRAYS:
             v = getattr(prob, name, None)
-            if v is None:
+            # optional arrays that are all zero are passed as NULL (= 0 by the
+            # ABI), which lets the kernels skip them
+            if v is None or (name in self._OPTIONAL and not np.any(np.asarray(v))):
                 setattr(c, name, None)
                 continue
             t = torch.as_tensor(v, dtype=dtype).contiguous().to(self.device)
@@ -237,10 +276,16 @@ class Solver:
     def reset(self):
         self.workspace.zero_()
 
-    def solve(self, x0: torch.Tensor, tick: int, stream=None):
-        """Runs one tick; returns (u*, best cost) device tensors (asynchronous)."""
-        empc_solve(self.dprob, self.ga, self.workspace, x0, tick, self.u_star, self.best_cost,
-                   stream)
+    def solve(self, x0: torch.Tensor, tick: int, stream=None, refine_steps: int = 0,
+              lr: float = 0.01):
+        """Runs one tick; returns (u*, best cost) device tensors (asynchronous).
+        refine_steps > 0 refines the parents of every generation by Adam."""
+        if refine_steps > 0:
+            empc_solve_refined(self.dprob, self.ga, self.workspace, x0, tick, lr, refine_steps,
+                               self.u_star, self.best_cost, stream)
+        else:
+            empc_solve(self.dprob, self.ga, self.workspace, x0, tick, self.u_star,
+                       self.best_cost, stream)
         return self.u_star, self.best_cost
 
 
@@ -264,3 +309,53 @@ class EmpcCost(torch.autograd.Function):
     def backward(ctx, grad_cost):
         (dJ,) = ctx.saved_tensors
         return dJ * grad_cost.unsqueeze(0), None, None
+
+
+class BatchSolver:
+    """Warm-started EMPC for many independent FP32 problems, one tick per call.
+
+    dprobs: DeviceProblem list (float32).  x0 is the packed device tensor of
+    initial states (problem after problem); u_star and best_cost are the
+    packed outputs.  The device tick counter starts at 0 and advances by one
+    per solve()."""
+
+    def __init__(self, dprobs, ga):
+        self.dprobs = list(dprobs)
+        self.ga = make_ga(ga)
+        n = len(self.dprobs)
+        arr = (EmpcProblem * n)(*[d.c for d in self.dprobs])
+        self._arr = arr
+        nbytes = empc_batch_workspace_bytes(arr, n, self.ga)
+        if nbytes == 0:
+            _check(EMPC_EINVAL)
+        dev = self.dprobs[0].device
+        self.workspace = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        self.x_off = np.concatenate([[0], np.cumsum([d.n for d in self.dprobs])])
+        self.u_off = np.concatenate([[0], np.cumsum([d.m for d in self.dprobs])])
+        self.x0 = torch.zeros(int(self.x_off[-1]), dtype=torch.float32, device=dev)
+        self.u_star = torch.zeros(int(self.u_off[-1]), dtype=torch.float32, device=dev)
+        self.best_cost = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.plan = empc_batch_create(arr, n, self.ga, self.workspace, self.x0, self.u_star,
+                                      self.best_cost)
+
+    def set_x0(self, i, x):
+        self.x0[int(self.x_off[i]):int(self.x_off[i + 1])] = torch.as_tensor(
+            x, dtype=torch.float32, device=self.x0.device)
+
+    def solve(self, stream=None):
+        empc_solve_batched(self.plan, stream)
+        return self.u_star, self.best_cost
+
+    def u_of(self, i):
+        return self.u_star[int(self.u_off[i]):int(self.u_off[i + 1])]
+
+    def close(self):
+        if self.plan is not None:
+            empc_batch_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -22,6 +22,12 @@ LIB = os.path.join(HERE, "libempc.so")
 ARCH = "gfx950"
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-file device options.  The rollout kernels keep MFMA accumulators in
+# ordinary VGPRs: the state the matrix cores produce is read back by the
+# next step's MFMAs and by VALU cost code, and the AGPR form would force
+# copies between the two register files on every step.
+FILE_FLAGS = {"rollout_linear_f32.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+              "batched.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Wno-unused-function", "-Wno-unused-result"]
 
@@ -35,8 +41,8 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), "-c", *COMMON, *DEVICE_FLAGS, "-I", os.path.join(HERE, "..", "include"),
-           src, "-o", obj]
+    cmd = [hipcc(), "-c", *COMMON, *DEVICE_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []),
+           "-I", os.path.join(HERE, "..", "include"), src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed on %s:\n%s" % (src, r.stderr[-8000:]))

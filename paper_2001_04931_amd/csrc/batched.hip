@@ -1,0 +1,323 @@
+// Problem-batched EMPC tick (gfx950): many independent problems of different
+// sizes advance one control tick together.  Per generation: one population
+// launch over all problems, one rollout launch per kernel shape class (the
+// problems whose state and input counts select the same register tiling),
+// one selection launch over all problems; then one tiny launch advances the
+// device tick counter, so the same launch sequence, captured once as a HIP
+// graph, replays tick after tick.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <vector>
+
+#include "evolve_body.hpp"
+#include "rollout_chain.hpp"
+#include "rollout_linear.hpp"
+
+namespace empc {
+
+template <typename T>
+__global__ __launch_bounds__(256) void batch_population(const BatchSlot<T> *__restrict__ slots,
+                                                        int64_t pop, int k, int elitism, T sigma,
+                                                        uint32_t seed_lo, int g,
+                                                        const uint32_t *__restrict__ tick) {
+    const BatchSlot<T> &S = slots[blockIdx.y];
+    const ProbView<T> P = S.P;
+    GaStreams gs;
+    gs.k0 = seed_lo;
+    gs.k1 = S.key_hi;
+    gs.XB = 1 + (P.m + 127) / 128;
+    gs.NB = gs.XB + (P.p * P.m + 127) / 128;
+    const bool first = g == 0;
+    const bool cold = first && *S.has_elites == 0;
+    population_body<T>(P, gs, pop, k, elitism, sigma, first ? nullptr : S.knots[(g + 1) & 1], pop,
+                       first ? nullptr : S.elite_idx, first ? S.elite_rows : nullptr, cold,
+                       S.knots[g & 1], pop, *tick, (uint32_t)g,
+                       (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <typename T, int NT, int NU, int WPB>
+__global__ __launch_bounds__(64 * WPB) void batch_roll_linear(const BatchSlot<T> *__restrict__ slots,
+                                                              const int *__restrict__ items,
+                                                              int64_t pop, int g) {
+    const BatchSlot<T> &S = slots[items[blockIdx.y]];
+    linear_tile<T, NT, NU, true>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
+                                 (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6));
+}
+
+template <typename T, int DMAX>
+__global__ __launch_bounds__(256) void batch_roll_chain(const BatchSlot<T> *__restrict__ slots,
+                                                        const int *__restrict__ items, int64_t pop,
+                                                        int g) {
+    __shared__ JointConst<T> jc[DMAX];
+    const BatchSlot<T> &S = slots[items[blockIdx.y]];
+    chain_constants_lds(S.P, jc);
+    __syncthreads();
+    const int64_t cand = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cand >= pop) return;
+    chain_candidate<T, DMAX>(S.P, jc, S.x0, S.knots[g & 1], pop, S.cost, cand);
+}
+
+template <typename T, typename K, int CACHE>
+__global__ __launch_bounds__(SEL_THREADS) void batch_select(const BatchSlot<T> *__restrict__ slots,
+                                                            int64_t pop, int k, int g, int last) {
+    const BatchSlot<T> &S = slots[blockIdx.x];
+    select_body<T, K, CACHE>(S.cost, pop, k, S.knots[g & 1], pop, S.P.p * S.P.m, S.P.m,
+                             S.elite_idx, S.best_idx, last ? S.elite_rows : nullptr, S.elite_cost,
+                             S.has_elites, nullptr, last ? S.u_star : nullptr,
+                             last ? S.best_cost : nullptr);
+}
+
+__global__ void batch_tick_advance(uint32_t *tick) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *tick += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+struct BatchClass {
+    int model;   // EMPC_LINEAR / EMPC_PENDULUM_CHAIN
+    int a, b;    // linear: (NT, NU bucket); chain: (DMAX, 0)
+    int first;   // offset in the device item list
+    int count;
+};
+
+int nu_bucket(int m) {
+    const int nu = (m + 3) / 4;
+    if (nu <= 1) return 1;
+    if (nu <= 2) return 2;
+    if (nu <= 4) return 4;
+    if (nu <= 6) return 6;
+    if (nu <= 8) return 8;
+    return 10;
+}
+int dmax_bucket(int d) {
+    if (d <= 4) return 4;
+    if (d <= 8) return 8;
+    if (d <= 16) return 16;
+    if (d <= 24) return 24;
+    return 40;
+}
+
+template <int NT, int NU>
+static void go_batch_linear(const BatchSlot<float> *slots, const int *items, int count,
+                            int64_t pop, int g, hipStream_t s) {
+    constexpr int WPB = 4;
+    const int64_t tiles = (pop + 15) / 16;
+    hipLaunchKernelGGL((batch_roll_linear<float, NT, NU, WPB>),
+                       dim3((unsigned)((tiles + WPB - 1) / WPB), (unsigned)count), dim3(64 * WPB), 0,
+                       s, slots, items, pop, g);
+}
+template <int NT>
+static void go_batch_linear_nu(int nu, const BatchSlot<float> *slots, const int *items, int count,
+                               int64_t pop, int g, hipStream_t s) {
+    switch (nu) {
+        case 1: go_batch_linear<NT, 1>(slots, items, count, pop, g, s); break;
+        case 2: go_batch_linear<NT, 2>(slots, items, count, pop, g, s); break;
+        case 4: go_batch_linear<NT, 4>(slots, items, count, pop, g, s); break;
+        case 6: go_batch_linear<NT, 6>(slots, items, count, pop, g, s); break;
+        case 8: go_batch_linear<NT, 8>(slots, items, count, pop, g, s); break;
+        default: go_batch_linear<NT, 10>(slots, items, count, pop, g, s); break;
+    }
+}
+template <int DMAX>
+static void go_batch_chain(const BatchSlot<float> *slots, const int *items, int count, int64_t pop,
+                           int g, hipStream_t s) {
+    hipLaunchKernelGGL((batch_roll_chain<float, DMAX>),
+                       dim3((unsigned)((pop + 255) / 256), (unsigned)count), dim3(256), 0, s, slots,
+                       items, pop, g);
+}
+
+}  // namespace empc
+
+using namespace empc;
+
+struct empc_batch {
+    int nprob = 0;
+    empc_ga ga{};
+    int64_t pop = 0;
+    int ngmax = 0;
+    std::vector<BatchClass> classes;
+    BatchSlot<float> *d_slots = nullptr;
+    int *d_items = nullptr;
+    uint32_t *d_tick = nullptr;
+};
+
+namespace {
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Per-problem workspace, after a 256-byte header holding the tick counter:
+// flag (256 B), two populations [pm][pop], costs [pop], parent rows [k][pm],
+// parent costs [k], parent indices [k], best index.
+size_t slot_bytes(const empc_problem &P, const empc_ga &G) {
+    const size_t pm = (size_t)P.p * P.m, pop = G.pop, k = G.n_elite;
+    return 256 + 2 * al256(pm * pop * 4) + al256(pop * 4) + al256(k * pm * 4) + al256(k * 4) +
+           al256(k * 8) + 256;
+}
+
+}  // namespace
+
+// Validation shared with the single-problem entry points lives in capi.hip.
+empc_status empc_validate_problem_internal(const empc_problem *P);
+empc_status empc_validate_ga_internal(const empc_ga *G);
+empc_status empc_fail_internal(empc_status s, const char *msg);
+
+extern "C" {
+
+size_t empc_batch_workspace_bytes(const empc_problem *probs, int32_t nprob, const empc_ga *ga) {
+    if (!probs || nprob < 1 || empc_validate_ga_internal(ga)) return 0;
+    size_t b = 256;
+    for (int i = 0; i < nprob; ++i) {
+        if (empc_validate_problem_internal(&probs[i]) || probs[i].dtype != EMPC_F32) return 0;
+        b += slot_bytes(probs[i], *ga);
+    }
+    return b;
+}
+
+empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const empc_ga *ga,
+                              void *workspace, size_t ws_bytes, const void *x0_packed,
+                              void *u_star_packed, void *best_cost, empc_batch **out) {
+    if (!out) return empc_fail_internal(EMPC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!probs || nprob < 1) return empc_fail_internal(EMPC_EINVAL, "need nprob >= 1 problems");
+    empc_status st = empc_validate_ga_internal(ga);
+    if (st) return st;
+    for (int i = 0; i < nprob; ++i) {
+        if ((st = empc_validate_problem_internal(&probs[i]))) return st;
+        if (probs[i].dtype != EMPC_F32)
+            return empc_fail_internal(EMPC_EUNSUPPORTED, "batched solves run in FP32");
+    }
+    if (!x0_packed || !u_star_packed || !best_cost)
+        return empc_fail_internal(EMPC_EINVAL, "x0_packed, u_star_packed and best_cost are required");
+    const size_t need = empc_batch_workspace_bytes(probs, nprob, ga);
+    if (!workspace || ws_bytes < need) return empc_fail_internal(EMPC_EWORKSPACE, "batch workspace too small");
+
+    empc_batch *b = new empc_batch();
+    b->nprob = nprob;
+    b->ga = *ga;
+    b->pop = ga->pop;
+    std::vector<BatchSlot<float>> slots(nprob);
+    char *base = (char *)workspace;
+    size_t off = 256;
+    const float *x0 = (const float *)x0_packed;
+    float *us = (float *)u_star_packed;
+    int64_t xo = 0, uo = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const empc_problem &P = probs[i];
+        const size_t pm = (size_t)P.p * P.m, pop = ga->pop, k = ga->n_elite;
+        BatchSlot<float> &S = slots[i];
+        S.P = view_of<float>(P);
+        S.model = P.model;
+        S.key_hi = (uint32_t)(ga->seed >> 32) ^ (uint32_t)i;
+        S.x0 = x0 + xo;
+        S.u_star = us + uo;
+        S.best_cost = (float *)best_cost + i;
+        xo += P.n;
+        uo += P.m;
+        S.has_elites = (int *)(base + off); off += 256;
+        S.knots[0] = (float *)(base + off); off += al256(pm * pop * 4);
+        S.knots[1] = (float *)(base + off); off += al256(pm * pop * 4);
+        S.cost = (float *)(base + off); off += al256(pop * 4);
+        S.elite_rows = (float *)(base + off); off += al256(k * pm * 4);
+        S.elite_cost = (float *)(base + off); off += al256(k * 4);
+        S.elite_idx = (int64_t *)(base + off); off += al256(k * 8);
+        S.best_idx = (int64_t *)(base + off); off += 256;
+        b->ngmax = std::max(b->ngmax, (int)((pm + 3) / 4));
+    }
+    // group problems by kernel shape class
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    for (int i = 0; i < nprob; ++i) {
+        const empc_problem &P = probs[i];
+        if (P.model == EMPC_LINEAR)
+            groups[std::make_tuple(0, (P.n + 15) / 16, nu_bucket(P.m))].push_back(i);
+        else
+            groups[std::make_tuple(1, dmax_bucket(P.m), 0)].push_back(i);
+    }
+    std::vector<int> items;
+    for (auto &kv : groups) {
+        BatchClass c;
+        c.model = std::get<0>(kv.first) == 0 ? EMPC_LINEAR : EMPC_PENDULUM_CHAIN;
+        c.a = std::get<1>(kv.first);
+        c.b = std::get<2>(kv.first);
+        c.first = (int)items.size();
+        c.count = (int)kv.second.size();
+        items.insert(items.end(), kv.second.begin(), kv.second.end());
+        b->classes.push_back(c);
+    }
+    b->d_tick = (uint32_t *)base;
+    hipError_t e = hipMalloc(&b->d_slots, sizeof(BatchSlot<float>) * nprob);
+    if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(int) * items.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_slots, slots.data(), sizeof(BatchSlot<float>) * nprob, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_items, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(b->d_slots);
+        (void)hipFree(b->d_items);
+        delete b;
+        return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(e));
+    }
+    *out = b;
+    return EMPC_OK;
+}
+
+empc_status empc_solve_batched(empc_batch *b, void *stream) {
+    if (!b) return empc_fail_internal(EMPC_EINVAL, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const empc_ga &G = b->ga;
+    const int64_t pop = b->pop;
+    const uint32_t seed_lo = (uint32_t)G.seed;
+    const int64_t per = (pop + SEL_THREADS - 1) / SEL_THREADS;
+    for (int g = 0; g < G.generations; ++g) {
+        const int last = g == G.generations - 1;
+        hipLaunchKernelGGL(batch_population<float>,
+                           dim3((unsigned)((pop * b->ngmax + 255) / 256), (unsigned)b->nprob),
+                           dim3(256), 0, s, b->d_slots, pop, G.n_elite, G.elitism, (float)G.sigma,
+                           seed_lo, g, (const uint32_t *)b->d_tick);
+        for (const BatchClass &c : b->classes) {
+            const int *items = b->d_items + c.first;
+            if (c.model == EMPC_LINEAR) {
+                switch (c.a) {
+                    case 1: go_batch_linear_nu<1>(c.b, b->d_slots, items, c.count, pop, g, s); break;
+                    case 2: go_batch_linear_nu<2>(c.b, b->d_slots, items, c.count, pop, g, s); break;
+                    case 3: go_batch_linear_nu<3>(c.b, b->d_slots, items, c.count, pop, g, s); break;
+                    case 4: go_batch_linear_nu<4>(c.b, b->d_slots, items, c.count, pop, g, s); break;
+                    default: go_batch_linear_nu<5>(c.b, b->d_slots, items, c.count, pop, g, s); break;
+                }
+            } else {
+                switch (c.a) {
+                    case 4: go_batch_chain<4>(b->d_slots, items, c.count, pop, g, s); break;
+                    case 8: go_batch_chain<8>(b->d_slots, items, c.count, pop, g, s); break;
+                    case 16: go_batch_chain<16>(b->d_slots, items, c.count, pop, g, s); break;
+                    case 24: go_batch_chain<24>(b->d_slots, items, c.count, pop, g, s); break;
+                    default: go_batch_chain<40>(b->d_slots, items, c.count, pop, g, s); break;
+                }
+            }
+        }
+        if (per <= 4)
+            hipLaunchKernelGGL((batch_select<float, uint32_t, 4>), dim3(b->nprob), dim3(SEL_THREADS), 0,
+                               s, b->d_slots, pop, G.n_elite, g, last);
+        else if (per <= 16)
+            hipLaunchKernelGGL((batch_select<float, uint32_t, 16>), dim3(b->nprob), dim3(SEL_THREADS), 0,
+                               s, b->d_slots, pop, G.n_elite, g, last);
+        else
+            hipLaunchKernelGGL((batch_select<float, uint32_t, 0>), dim3(b->nprob), dim3(SEL_THREADS), 0,
+                               s, b->d_slots, pop, G.n_elite, g, last);
+    }
+    hipLaunchKernelGGL(batch_tick_advance, dim3(1), dim3(64), 0, s, b->d_tick);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(e));
+    return EMPC_OK;
+}
+
+empc_status empc_batch_destroy(empc_batch *b) {
+    if (!b) return EMPC_OK;
+    (void)hipFree(b->d_slots);
+    (void)hipFree(b->d_items);
+    delete b;
+    return EMPC_OK;
+}
+
+}  // extern "C"

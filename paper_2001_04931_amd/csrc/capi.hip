@@ -87,12 +87,15 @@ empc_status validate_ga(const empc_ga *G) {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Workspace of empc_solve, in order: header (has_elites, best_slot),
-// population knots [pm][pop], costs [pop], elite rows [k][pm], elite costs
-// [k], elite indices [k] (int64), best index (int64).
+// Workspace of empc_solve, in order: header (has_elites, best_slot), two
+// population buffers [pm][pop] (generation g writes buffer g % 2 and reads
+// its parents in place from the other one), costs [pop], elite rows [k][pm]
+// (the parents carried to the next tick), elite costs [k], elite indices
+// [k] (int64), best index (int64), and the parents as a structure of arrays
+// [pm][k] for gradient refinement.
 struct Workspace {
     int *has_elites, *best_slot;
-    void *knots, *cost, *elite_rows, *elite_cost;
+    void *knots[2], *cost, *elite_rows, *elite_cost, *elite_soa;
     int64_t *elite_idx, *best_idx;
     size_t bytes;
 };
@@ -105,12 +108,14 @@ Workspace layout(const empc_problem *P, const empc_ga *G, void *base) {
     w.has_elites = (int *)(b + off);
     w.best_slot = (int *)(b + off + sizeof(int));
     off += 256;
-    w.knots = b + off; off += align256(pm * pop * es);
+    w.knots[0] = b + off; off += align256(pm * pop * es);
+    w.knots[1] = b + off; off += align256(pm * pop * es);
     w.cost = b + off; off += align256(pop * es);
     w.elite_rows = b + off; off += align256(k * pm * es);
     w.elite_cost = b + off; off += align256(k * es);
     w.elite_idx = (int64_t *)(b + off); off += align256(k * sizeof(int64_t));
     w.best_idx = (int64_t *)(b + off); off += 256;
+    w.elite_soa = b + off; off += align256(k * pm * es);
     w.bytes = off;
     return w;
 }
@@ -126,42 +131,75 @@ Profile g_prof;
 template <typename T>
 hipError_t timed_rollout(const ProbView<T> &V, int model, const T *x0, const T *knots,
                          int64_t ncand, int64_t ld, T *cost, hipStream_t s) {
-    const bool rec = g_prof.on && g_prof.used < (int)g_prof.start.size();
-    if (rec) {
-        hipError_t e = hipEventRecord(g_prof.start[g_prof.used], s);
-        if (e != hipSuccess) return e;
-    }
-    hipError_t e = launch_rollout<T>(V, model, x0, knots, ncand, ld, cost, s);
-    if (e != hipSuccess) return e;
-    if (rec) {
-        e = hipEventRecord(g_prof.stop[g_prof.used], s);
+    Events ev;
+    if (g_prof.on && g_prof.used < (int)g_prof.start.size()) {
+        ev.start = g_prof.start[g_prof.used];
+        ev.stop = g_prof.stop[g_prof.used];
         ++g_prof.used;
     }
-    return e;
+    return launch_rollout<T>(V, model, x0, knots, ncand, ld, cost, s, ev);
+}
+
+// Gradient refinement of the parents after a selection: gather them, run
+// Adam, write the parent rows back, pick the best refined parent.
+template <typename T>
+hipError_t refine_parents(const empc_problem *P, const empc_ga *G, const Workspace &w,
+                          const void *x0, const T *cur, double lr, int steps, bool last,
+                          void *u_star, void *best_cost, hipStream_t s) {
+    const ProbView<T> V = view_of<T>(*P);
+    const int k = G->n_elite, pm = P->p * P->m;
+    hipError_t e = launch_gather_parents<T>(cur, G->pop, w.elite_idx, k, pm, (T *)w.elite_soa, s);
+    if (e != hipSuccess) return e;
+    e = launch_grad<T>(V, P->model, (const T *)x0, nullptr, k, k, nullptr, nullptr, steps, (T)lr,
+                       (T *)w.elite_soa, (T *)w.elite_cost, s);
+    if (e != hipSuccess) return e;
+    return launch_finish_refine<T>((const T *)w.elite_soa, k, pm, P->m, (const T *)w.elite_cost,
+                                   (T *)w.elite_rows, w.best_slot, last ? (T *)u_star : nullptr,
+                                   last ? (T *)best_cost : nullptr, s);
 }
 
 template <typename T>
 empc_status solve_t(const empc_problem *P, const empc_ga *G, const Workspace &w, const void *x0,
-                    uint32_t tick, void *u_star, void *best_cost, hipStream_t s) {
+                    uint32_t tick, void *u_star, void *best_cost, hipStream_t s,
+                    int adam_steps = 0, double lr = 0.0) {
     const ProbView<T> V = view_of<T>(*P);
     const int64_t pop = G->pop;
+    const bool refine = adam_steps > 0;
     for (int g = 0; g < G->generations; ++g) {
         const bool last = g == G->generations - 1;
-        hipError_t e = launch_population<T>(V, *G, nullptr, 0, nullptr, (const T *)w.elite_rows,
-                                            w.has_elites, 2, (T *)w.knots, pop, tick, (uint32_t)g, s);
+        T *cur = (T *)w.knots[g & 1];
+        const T *prev = (const T *)w.knots[(g + 1) & 1];
+        // generation 0 starts from the parents carried over from the last
+        // tick (or cold-starts); later ones read their parents in place
+        // (with refinement the parents are always the refined parent rows)
+        hipError_t e = (g == 0 || refine)
+                           ? launch_population<T>(V, *G, nullptr, 0, nullptr,
+                                                  (const T *)w.elite_rows, w.has_elites,
+                                                  g == 0 ? 2 : 0, cur, pop, tick, (uint32_t)g, s)
+                           : launch_population<T>(V, *G, prev, pop, w.elite_idx, nullptr,
+                                                  nullptr, 0, cur, pop, tick, (uint32_t)g, s);
         if (e != hipSuccess) return device_status(e, "population launch");
-        e = timed_rollout<T>(V, P->model, (const T *)x0, (const T *)w.knots, pop, pop, (T *)w.cost, s);
+        e = timed_rollout<T>(V, P->model, (const T *)x0, cur, pop, pop, (T *)w.cost, s);
         if (e != hipSuccess) return device_status(e, "rollout launch");
-        e = launch_select<T>(V, (const T *)w.cost, (const T *)w.knots, pop, pop, G->n_elite,
-                             w.elite_idx, w.best_idx, (T *)w.elite_rows, (T *)w.elite_cost,
-                             w.has_elites, w.best_slot, last ? (T *)u_star : nullptr,
-                             last ? (T *)best_cost : nullptr, s);
+        e = launch_select<T>(V, (const T *)w.cost, cur, pop, pop, G->n_elite, w.elite_idx,
+                             w.best_idx, (last && !refine) ? (T *)w.elite_rows : nullptr,
+                             (T *)w.elite_cost, w.has_elites, w.best_slot,
+                             (last && !refine) ? (T *)u_star : nullptr,
+                             (last && !refine) ? (T *)best_cost : nullptr, s);
         if (e != hipSuccess) return device_status(e, "select launch");
+        if (refine) {
+            e = refine_parents<T>(P, G, w, x0, cur, lr, adam_steps, last, u_star, best_cost, s);
+            if (e != hipSuccess) return device_status(e, "refine launch");
+        }
     }
     return EMPC_OK;
 }
 
 }  // namespace
+
+empc_status empc_validate_problem_internal(const empc_problem *P) { return validate_problem(P); }
+empc_status empc_validate_ga_internal(const empc_ga *G) { return validate_ga(G); }
+empc_status empc_fail_internal(empc_status s, const char *msg) { return fail(s, "%s", msg); }
 
 extern "C" {
 
@@ -263,6 +301,26 @@ empc_status empc_solve(const empc_problem *prob, const empc_ga *ga, void *worksp
     hipStream_t s = (hipStream_t)stream;
     return prob->dtype == EMPC_F32 ? solve_t<float>(prob, ga, w, x0, tick, u_star, best_cost, s)
                                    : solve_t<double>(prob, ga, w, x0, tick, u_star, best_cost, s);
+}
+
+empc_status empc_solve_refined(const empc_problem *prob, const empc_ga *ga, void *workspace,
+                               size_t ws_bytes, const void *x0, uint32_t tick, double lr,
+                               int32_t adam_steps, void *u_star, void *best_cost, void *stream) {
+    empc_status st = validate_problem(prob);
+    if (st) return st;
+    if ((st = validate_ga(ga))) return st;
+    if (adam_steps < 1 || !(lr >= 0.0) || !isfinite(lr))
+        return fail(EMPC_EINVAL, "need adam_steps >= 1 and a finite lr >= 0");
+    if ((st = validate_grad(prob))) return st;
+    if (!x0 || !u_star || !best_cost) return fail(EMPC_EINVAL, "x0, u_star and best_cost are required");
+    const Workspace w = layout(prob, ga, workspace);
+    if (!workspace || ws_bytes < w.bytes)
+        return fail(EMPC_EWORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, w.bytes);
+    if ((st = check_prior())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    return prob->dtype == EMPC_F32
+               ? solve_t<float>(prob, ga, w, x0, tick, u_star, best_cost, s, adam_steps, lr)
+               : solve_t<double>(prob, ga, w, x0, tick, u_star, best_cost, s, adam_steps, lr);
 }
 
 empc_status empc_grad(const empc_problem *prob, const void *x0, const void *knots, int64_t ncand,

@@ -121,6 +121,24 @@ __device__ inline uint64_t sort_key(double v) {
 }
 
 // ---------------------------------------------------------------------------
+// One problem of a batch: its view and its slice of the batch workspace.
+template <typename T>
+struct BatchSlot {
+    ProbView<T> P;
+    int model;
+    uint32_t key_hi;   // Philox key high word of this problem: seed_hi ^ index
+    const T *x0;       // n
+    T *knots[2];       // [pm][pop] each
+    T *cost;           // pop
+    T *elite_rows;     // [k][pm]
+    T *elite_cost;     // k
+    int64_t *elite_idx, *best_idx;
+    int *has_elites;
+    T *u_star;         // m (inside the caller's packed u* array)
+    T *best_cost;      // 1
+};
+
+// ---------------------------------------------------------------------------
 // Launchers (one per kernel family), defined in the .hip files.
 // All return a hipError_t from the launch.
 struct Limits {
@@ -130,9 +148,20 @@ struct Limits {
     static constexpr int MAX_ELITE = 256;
 };
 
+// Optional start / stop events stamped by a kernel's dispatch.
+struct Events {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 template <typename T>
 hipError_t launch_rollout(const ProbView<T> &P, int model, const T *x0, const T *knots,
-                          int64_t ncand, int64_t ld, T *cost, hipStream_t s);
+                          int64_t ncand, int64_t ld, T *cost, hipStream_t s,
+                          const Events &ev = Events());
+
+// Linear model only (defined per dtype in rollout_linear_f32.hip / _f64.hip).
+template <typename T>
+hipError_t launch_linear(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
+                         int64_t ld, T *cost, hipStream_t s, const Events &ev);
 
 template <typename T>
 hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *knots_in,
@@ -148,6 +177,13 @@ hipError_t launch_select(const ProbView<T> &P, const T *cost, const T *knots, in
                          int64_t pop, int k, int64_t *elite_idx, int64_t *best_idx, T *elite_rows,
                          T *elite_cost, int *has_elites, int *best_slot, T *u_star, T *best_cost,
                          hipStream_t s);
+
+template <typename T>
+hipError_t launch_gather_parents(const T *knots, int64_t ld, const int64_t *elite_idx, int k,
+                                 int pm, T *E, hipStream_t s);
+template <typename T>
+hipError_t launch_finish_refine(const T *E, int k, int pm, int m, const T *ecost, T *elite_rows,
+                                int *best_slot, T *u_star, T *best_cost, hipStream_t s);
 
 template <typename T>
 hipError_t launch_grad(const ProbView<T> &P, int model, const T *x0, const T *knots, int64_t ncand,

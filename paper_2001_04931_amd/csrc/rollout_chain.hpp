@@ -1,0 +1,327 @@
+// Pendulum-chain rollout + cost device code (gfx950), shared by the
+// single-problem kernel (rollout.hip) and the problem-batched one
+// (batched.hip).  One candidate per lane, joint state in registers, the
+// per-joint constants in LDS where every lane reads the same address.
+#pragma once
+#include <math.h>
+
+#include "internal.hpp"
+
+namespace empc {
+
+// ---------------------------------------------------------------------------
+// Pendulum chain.  Per-joint constants in LDS.
+template <typename T>
+struct JointConst {
+    T cg;    // g l_r M_r (gravity coefficient of absolute angle r)
+    T invI;  // 1 / I_j
+    T kst, dmp;
+    T wq, wv, wqf, wvf;  // stage and terminal weights of q_j and qd_j
+    T gq, gv;            // goals of q_j and qd_j
+    T wr, gu;            // input weight and goal
+};
+
+template <typename T>
+__device__ void chain_constants_lds(const ProbView<T> &P, JointConst<T> *jc) {
+    const int d = P.m;
+    for (int j = threadIdx.x; j < d; j += blockDim.x) {
+        T tail = 0;
+        for (int i = j; i < d; ++i) tail += P.mass[i];
+        T inert = 0, dist = 0;
+        for (int i = j; i < d; ++i) {
+            dist += P.len[i];
+            inert += P.mass[i] * dist * dist;
+        }
+        JointConst<T> c;
+        c.cg = P.gravity * P.len[j] * tail;
+        c.invI = (T)1 / inert;
+        c.kst = P.stiff[j];
+        c.dmp = P.damp[j];
+        c.wq = P.q[j];
+        c.wv = P.q[d + j];
+        c.wqf = P.qf ? P.qf[j] : (T)0;
+        c.wvf = P.qf ? P.qf[d + j] : (T)0;
+        c.gq = P.xg ? P.xg[j] : (T)0;
+        c.gv = P.xg ? P.xg[d + j] : (T)0;
+        c.wr = P.r[j];
+        c.gu = P.ug ? P.ug[j] : (T)0;
+        jc[j] = c;
+    }
+}
+
+template <typename T>
+__device__ inline T sin_of(T x);
+template <>
+__device__ inline float sin_of<float>(float x) { return sinf(x); }
+template <>
+__device__ inline double sin_of<double>(double x) { return sin(x); }
+
+// One thread: candidate `cand` of one problem; jc holds the problem's
+// per-joint constants.
+template <typename T, int DMAX>
+__device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const JointConst<T> *jc,
+                                                const T *__restrict__ x0,
+                                                const T *__restrict__ knots, int64_t ld,
+                                                T *__restrict__ cost, int64_t cand) {
+    const int d = P.m;
+    const T dt = P.dt;
+    T q[DMAX], v[DMAX], ua[DMAX], ub[DMAX];
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) {
+        q[j] = j < d ? x0[j] : (T)0;
+        v[j] = j < d ? x0[d + j] : (T)0;
+    }
+    const T inv_den = P.Tn > 1 ? (T)1 / (T)(P.Tn - 1) : (T)0;
+    T J = 0;
+    int cur_a = -1;
+    for (int k = 0; k < P.Tn; ++k) {
+        // re-read the per-joint constants from LDS every step instead of
+        // letting them be hoisted into (and overflow) registers
+        asm volatile("" ::: "memory");
+        const Knot kn = knot_at(P.Tn, P.p, k);
+        if (kn.a != cur_a) {
+            cur_a = kn.a;
+#pragma unroll
+            for (int j = 0; j < DMAX; ++j) {
+                ua[j] = j < d ? knots[(int64_t)(kn.a * d + j) * ld + cand] : (T)0;
+                ub[j] = j < d ? knots[(int64_t)(kn.b * d + j) * ld + cand] : (T)0;
+            }
+        }
+        const T c = (T)kn.rem * inv_den;
+        // gravity torque: G_j = sum_{r>=j} cg_r sin(phi_r), phi_r = q_0 + .. + q_r
+        T sg[DMAX];
+        T phi = 0;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            if (j < d) {
+                phi += q[j];
+                sg[j] = jc[j].cg * sin_of<T>(phi);
+            }
+        }
+        T G = 0, js = 0;
+#pragma unroll
+        for (int j = DMAX - 1; j >= 0; --j) {
+            if (j < d) {
+                const JointConst<T> cj = jc[j];
+                G += sg[j];
+                const T u = ((T)1 - c) * ua[j] + c * ub[j];
+                const T acc = (u - cj.kst * q[j] - cj.dmp * v[j] - G) * cj.invI;
+                v[j] = v[j] + dt * acc;
+                q[j] = q[j] + dt * v[j];
+                const T eq = cj.gq - q[j], ev = cj.gv - v[j], eu = cj.gu - u;
+                js += cj.wq * eq * eq + cj.wv * ev * ev + cj.wr * eu * eu;
+            }
+        }
+        J += js;
+    }
+    T jt = 0;
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) {
+        if (j < d) {
+            const T eq = jc[j].gq - q[j], ev = jc[j].gv - v[j];
+            jt += jc[j].wqf * eq * eq + jc[j].wvf * ev * ev;
+        }
+    }
+    cost[cand] = J + jt;
+}
+
+template <typename T, int DMAX>
+__global__ __launch_bounds__(256) void roll_chain(ProbView<T> P, const T *__restrict__ x0,
+                                                  const T *__restrict__ knots, int64_t ld,
+                                                  int64_t ncand, T *__restrict__ cost) {
+    __shared__ JointConst<T> jc[DMAX];
+    chain_constants_lds(P, jc);
+    __syncthreads();
+    const int64_t cand = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cand >= ncand) return;
+    chain_candidate<T, DMAX>(P, jc, x0, knots, ld, cost, cand);
+}
+
+// ---------------------------------------------------------------------------
+// Row layout: one candidate per 16-lane row, lane r owning joints
+// r*J .. r*J+J-1 (J = ceil(d/16)).  The cumulative angles are a prefix sum
+// over joints and the gravity torques a suffix sum, both done as a local sum
+// over the lane's J joints plus a scan over the 16 lanes of the row with DPP
+// row shifts (which never cross a row).
+template <typename T>
+__device__ inline T row_shift_up(T v, int n);  // lane r gets lane r-n of its row, 0 below
+template <>
+__device__ inline float row_shift_up<float>(float v, int n) {
+    int x = __float_as_int(v), y = 0;
+    switch (n) {
+        case 1: y = __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false); break;
+        case 2: y = __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false); break;
+        case 4: y = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false); break;
+        default: y = __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false); break;
+    }
+    return __int_as_float(y);
+}
+template <typename T>
+__device__ inline T row_shift_down(T v, int n);  // lane r gets lane r+n of its row, 0 above
+template <>
+__device__ inline float row_shift_down<float>(float v, int n) {
+    int x = __float_as_int(v), y = 0;
+    switch (n) {
+        case 1: y = __builtin_amdgcn_update_dpp(0, x, 0x101, 0xf, 0xf, false); break;
+        case 2: y = __builtin_amdgcn_update_dpp(0, x, 0x102, 0xf, 0xf, false); break;
+        case 4: y = __builtin_amdgcn_update_dpp(0, x, 0x104, 0xf, 0xf, false); break;
+        default: y = __builtin_amdgcn_update_dpp(0, x, 0x108, 0xf, 0xf, false); break;
+    }
+    return __int_as_float(y);
+}
+// 64-bit values: two 32-bit DPP moves
+template <>
+__device__ inline double row_shift_up<double>(double v, int n) {
+    const int lo = (int)(__double_as_longlong(v) & 0xffffffffll);
+    const int hi = (int)(__double_as_longlong(v) >> 32);
+    const float flo = row_shift_up<float>(__int_as_float(lo), n);
+    const float fhi = row_shift_up<float>(__int_as_float(hi), n);
+    return __longlong_as_double(((long long)(unsigned)__float_as_int(fhi) << 32) |
+                                (unsigned)__float_as_int(flo));
+}
+template <>
+__device__ inline double row_shift_down<double>(double v, int n) {
+    const int lo = (int)(__double_as_longlong(v) & 0xffffffffll);
+    const int hi = (int)(__double_as_longlong(v) >> 32);
+    const float flo = row_shift_down<float>(__int_as_float(lo), n);
+    const float fhi = row_shift_down<float>(__int_as_float(hi), n);
+    return __longlong_as_double(((long long)(unsigned)__float_as_int(fhi) << 32) |
+                                (unsigned)__float_as_int(flo));
+}
+// inclusive scans over the 16 lanes of a row
+template <typename T>
+__device__ inline T row_scan_up(T v) {
+    v += row_shift_up<T>(v, 1);
+    v += row_shift_up<T>(v, 2);
+    v += row_shift_up<T>(v, 4);
+    v += row_shift_up<T>(v, 8);
+    return v;
+}
+template <typename T>
+__device__ inline T row_scan_down(T v) {
+    v += row_shift_down<T>(v, 1);
+    v += row_shift_down<T>(v, 2);
+    v += row_shift_down<T>(v, 4);
+    v += row_shift_down<T>(v, 8);
+    return v;
+}
+
+// One candidate per 16-lane row.  `cand` is the row's candidate; r the lane
+// in the row.  Every lane of the wavefront must call this (DPP).
+template <typename T, int J>
+__device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const T *__restrict__ x0,
+                                                    const T *__restrict__ knots, int64_t ld,
+                                                    int64_t ncand, T *__restrict__ cost,
+                                                    int64_t cand, int r) {
+    const int d = P.m;
+    const bool valid = cand < ncand;
+    const int64_t cc = valid ? cand : ncand - 1;  // loads stay in bounds
+    // per-joint constants of this lane's joints (zero for joints past d)
+    T q[J], v[J], cg[J], invI[J], kst[J], dmp[J], wq[J], wv[J], gq[J], gv[J], wr[J], gu[J];
+    T ua[J], ub[J];
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+        const int j = r * J + i;
+        const bool in = j < d;
+        T tail = 0, inert = 0, dist = 0;
+        if (in) {
+            for (int t = j; t < d; ++t) {
+                tail += P.mass[t];
+                dist += P.len[t];
+                inert += P.mass[t] * dist * dist;
+            }
+        }
+        cg[i] = in ? P.gravity * P.len[j] * tail : (T)0;
+        invI[i] = in ? (T)1 / inert : (T)0;
+        kst[i] = in ? P.stiff[j] : (T)0;
+        dmp[i] = in ? P.damp[j] : (T)0;
+        wq[i] = in ? P.q[j] : (T)0;
+        wv[i] = in ? P.q[d + j] : (T)0;
+        gq[i] = (in && P.xg) ? P.xg[j] : (T)0;
+        gv[i] = (in && P.xg) ? P.xg[d + j] : (T)0;
+        wr[i] = in ? P.r[j] : (T)0;
+        gu[i] = (in && P.ug) ? P.ug[j] : (T)0;
+        q[i] = in ? x0[j] : (T)0;
+        v[i] = in ? x0[d + j] : (T)0;
+    }
+    const T dt = P.dt;
+    const T inv_den = P.Tn > 1 ? (T)1 / (T)(P.Tn - 1) : (T)0;
+    T J_ = 0;
+    int cur_a = -1;
+    for (int k = 0; k < P.Tn; ++k) {
+        const Knot kn = knot_at(P.Tn, P.p, k);
+        if (kn.a != cur_a) {  // uniform over the wavefront
+            cur_a = kn.a;
+#pragma unroll
+            for (int i = 0; i < J; ++i) {
+                const int j = r * J + i;
+                const int jc = j < d ? j : d - 1;
+                ua[i] = knots[(int64_t)(kn.a * d + jc) * ld + cc];
+                ub[i] = knots[(int64_t)(kn.b * d + jc) * ld + cc];
+            }
+        }
+        const T c = (T)kn.rem * inv_den;
+        // cumulative angles phi: local prefix over the lane's joints, then
+        // the row's exclusive prefix of lane totals
+        T loc[J];
+        T run = 0;
+#pragma unroll
+        for (int i = 0; i < J; ++i) {
+            run += q[i];
+            loc[i] = run;
+        }
+        const T before = row_scan_up<T>(run) - run;
+        T sg[J];
+#pragma unroll
+        for (int i = 0; i < J; ++i) sg[i] = cg[i] * sin_of<T>(before + loc[i]);
+        // gravity torque G_j = sum_{r >= j} cg_r sin(phi_r): local suffix plus
+        // the row's exclusive suffix of lane totals
+        T srun = 0, sloc[J];
+#pragma unroll
+        for (int i = J - 1; i >= 0; --i) {
+            srun += sg[i];
+            sloc[i] = srun;
+        }
+        const T after = row_scan_down<T>(srun) - srun;
+        T js = 0;
+#pragma unroll
+        for (int i = 0; i < J; ++i) {
+            const T G = after + sloc[i];
+            const T u = ((T)1 - c) * ua[i] + c * ub[i];
+            const T acc = (u - kst[i] * q[i] - dmp[i] * v[i] - G) * invI[i];
+            v[i] = v[i] + dt * acc;
+            q[i] = q[i] + dt * v[i];
+            const T eq = gq[i] - q[i], ev = gv[i] - v[i], eu = gu[i] - u;
+            js += wq[i] * eq * eq + wv[i] * ev * ev + wr[i] * eu * eu;
+        }
+        J_ += js;
+    }
+    T jt = 0;
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+        const int j = r * J + i;
+        if (j < d && P.qf) {
+            const T eq = gq[i] - q[i], ev = gv[i] - v[i];
+            jt += P.qf[j] * eq * eq + P.qf[d + j] * ev * ev;
+        }
+    }
+    T tot = J_ + jt;
+    // sum over the row's 16 lanes
+    tot += __shfl_xor(tot, 8, 16);
+    tot += __shfl_xor(tot, 4, 16);
+    tot += __shfl_xor(tot, 2, 16);
+    tot += __shfl_xor(tot, 1, 16);
+    if (r == 0 && valid) cost[cand] = tot;
+}
+
+template <typename T, int J>
+__global__ __launch_bounds__(256) void roll_chain_rows(ProbView<T> P, const T *__restrict__ x0,
+                                                       const T *__restrict__ knots, int64_t ld,
+                                                       int64_t ncand, T *__restrict__ cost) {
+    const int64_t cand0 = (int64_t)blockIdx.x * 16;  // 16 rows per block
+    if (cand0 + (threadIdx.x >> 6) * 4 >= ncand) return;  // whole wavefront past the end
+    chain_row_candidate<T, J>(P, x0, knots, ld, ncand, cost, cand0 + (threadIdx.x >> 4),
+                              threadIdx.x & 15);
+}
+
+}  // namespace empc

@@ -1,0 +1,310 @@
+// Linear-model rollout + cost kernel (gfx950 matrix cores), shared by the FP32
+// and FP64 translation units.
+//
+// Linear model (eq. 2): the population-batched step X <- A_d X + B_d U + w_d
+// is a dense contraction with M = n states, K = n + m, N = candidates, so it
+// runs on the matrix cores: v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64,
+// one wavefront per tile of 16 candidates.
+//
+// The accumulator of a 16x16x4 MFMA leaves lane l holding, in register v
+// (v = 0..3), row R(l/16, v) of column l%16, with R(g, v) = 4g + v for the
+// f32 instruction and R(g, v) = g + 4v for the f64 one.  The B operand of the
+// same instruction takes row l/16 of column l%16 from lane l.  So accumulator
+// register v of M-tile t, used as a B operand as it stands, supplies the K
+// slice made of state rows {16t + R(g, v) : g = 0..3}; permuting the columns
+// of A_d to match that K order (the contraction order is free) chains the
+// steps with no cross-lane data movement.  A_d, B_d live in registers as A
+// operands (one value per lane per MFMA), the state lives in accumulators,
+// and knot interpolation, the dynamics step and the cost are fused in one
+// loop over the horizon.
+#pragma once
+#include <hip/hip_ext.h>
+#include <math.h>
+
+#include "internal.hpp"
+
+namespace empc {
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __device__ static inline v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // accumulator row of lane group g, register v
+    __device__ static constexpr int row(int g, int v) { return 4 * g + v; }
+};
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __device__ static inline v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static constexpr int row(int g, int v) { return g + 4 * v; }
+};
+
+// NT = ceil(n / 16) M-tiles, NU = ceil(m / 4) input K-slices; HAS_XG: the
+// problem has a state goal (else (x - g) is x itself).
+//
+// Work per step.  The input enters a step as B_d u_k + w_d with
+// u_k = (1-c) U_a + c U_b (Sec. IV-D), so with V_j = B_d U_j + w_d computed
+// once per knot j the step is x_{k+1} = A_d x_k + V_a + c (V_b - V_a): the
+// accumulators start from that (NT fused multiply-adds of 4-vectors) and only
+// the 4 NT^2 MFMAs of A_d x_k remain in the step.  The stage cost is summed
+// per state row, S_i += (x_i - g_i)^2, and weighted by Q once at the end; the
+// input cost of a segment is summed in closed form (u is affine in c there):
+//   sum_k r (e0 + c_k du)^2 = r (n e0^2 + 2 e0 du sum c_k + du^2 sum c_k^2),
+// with the sums over c_k taken exactly in integers.
+// One wavefront: candidates 16*tile .. 16*tile+15 of one problem.
+template <typename T, int NT, int NU, bool HAS_XG>
+__device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__restrict__ x0,
+                                            const T *__restrict__ knots, int64_t ld,
+                                            int64_t ncand, T *__restrict__ cost, int64_t tile) {
+    typedef typename Mfma<T>::v4 v4;
+    const int lane = threadIdx.x & 63;
+    const int64_t cand0 = tile * 16;
+    if (cand0 >= ncand) return;  // wave-uniform
+    const int col = lane & 15, grp = lane >> 4;
+    const int64_t cand = cand0 + col;
+    const bool valid = cand < ncand;
+    const int n = P.n, m = P.m;
+
+    // A operands.  aX[mt][4t+v]: A_d[16mt + col][16t + R(grp, v)];
+    // aU[mt][s]: B_d[16mt + col][4s + grp].
+    T aX[NT][4 * NT];
+    T aU[NT][NU];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+        const int row = 16 * mt + col;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int kk = 16 * t + Mfma<T>::row(grp, v);
+                aX[mt][4 * t + v] = (row < n && kk < n) ? P.Ad[row * n + kk] : (T)0;
+            }
+#pragma unroll
+        for (int s = 0; s < NU; ++s) {
+            const int j = 4 * s + grp;
+            aU[mt][s] = (row < n && j < m) ? P.Bd[row * m + j] : (T)0;
+        }
+    }
+    // State, disturbance and goal in accumulator layout: row 16mt + R(grp, v).
+    v4 X[NT], Wd[NT], Xg[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * mt + Mfma<T>::row(grp, v);
+            const bool in = row < n;
+            X[mt][v] = in ? x0[row] : (T)0;
+            Wd[mt][v] = (in && P.wd) ? P.wd[row] : (T)0;
+            Xg[mt][v] = (in && HAS_XG && P.xg) ? P.xg[row] : (T)0;
+        }
+
+    const int p = P.p, Tn = P.Tn;
+    // Loads are unconditional and unmasked, so that each use waits only for
+    // its own load: a padded input row (j >= m) reads the candidate's own
+    // input m-1 (it meets zero B_d columns and zero R weights), a knot index
+    // past the last reads the last knot (it only ever meets c = 0), and a lane
+    // past the last candidate reads the last candidate (its cost is not
+    // stored).  A candidate's values thus only reach its own cost.
+    const int64_t cand_c = valid ? cand : ncand - 1;
+    auto load_knot = [&](int kn_idx, T *dst) {
+        const int kc = kn_idx < p ? kn_idx : p - 1;
+#pragma unroll
+        for (int s = 0; s < NU; ++s) {
+            const int j = 4 * s + grp;
+            dst[s] = knots[(int64_t)(kc * m + (j < m ? j : m - 1)) * ld + cand_c];
+        }
+    };
+    // V = B_d U + w_d for one knot (input slices as B operands)
+    auto knot_response = [&](const T *U, v4 *V) {
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) V[mt] = Mfma<T>::op(aU[mt][0], U[0], Wd[mt]);
+#pragma unroll
+        for (int s = 1; s < NU; ++s)
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt) V[mt] = Mfma<T>::op(aU[mt][s], U[s], V[mt]);
+    };
+    // Knot registers: four sets K0..K3 hold knots a..a+3 while segment a runs.
+    // The segment loop is unrolled four ways with the sets' roles rotating in
+    // the source, so that no register is copied: segment a refills the set it
+    // used for knot a with knot a+4, which is first read three segments later.
+    T K0[NU], K1[NU], K2[NU], K3[NU];
+    load_knot(0, K0);
+    load_knot(1, K1);
+    load_knot(2, K2);
+    load_knot(3, K3);
+    T Rw[NU], Ug[NU];
+#pragma unroll
+    for (int s = 0; s < NU; ++s) {
+        const int j = 4 * s + grp;
+        Rw[s] = j < m ? P.r[j] : (T)0;
+        Ug[s] = (j < m && P.ug) ? P.ug[j] : (T)0;
+    }
+    v4 Va[NT], Vb[NT], dV[NT];
+    knot_response(K0, Va);
+    knot_response(p > 1 ? K1 : K0, Vb);
+
+    const T inv_den = Tn > 1 ? (T)1 / (T)(Tn - 1) : (T)0;
+    // per-row stage-cost sums; starting from -(x_0 - g)^2 cancels exactly the
+    // term the first step adds for x_0, so that S sums x_1 .. x_T
+    v4 S[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const T e = X[mt][v] - Xg[mt][v];
+            S[mt][v] = -(e * e);
+        }
+    T Ju = 0;
+    int k = 0;
+    // segment a: steps with idx1 = a, knots ua = U_a, ub = U_min(a+1, p-1)
+    // (ub of the last segment is unused: c = 0 there); un = U_{a+2}
+    auto segment = [&](int a, T *ua, T *ub, T *un) {
+        // first step of segment a+1: ceil((a+1)(T-1)/(p-1))
+        const int kend = (p == 1 || a == p - 1) ? Tn
+                                                : ((a + 1) * (Tn - 1) + (p - 2)) / (p - 1);
+        const int nseg = kend - k;
+        // input cost of the segment in closed form; rem_k = r0 + i (p-1)
+        {
+            const int64_t q1 = p - 1;
+            const int64_t r0 = (p == 1 || Tn == 1) ? 0 : (int64_t)k * q1 - (int64_t)a * (Tn - 1);
+            const int64_t nn = nseg;
+            const int64_t s1 = nn * r0 + q1 * (nn * (nn - 1) / 2);
+            const int64_t s2 = nn * r0 * r0 + r0 * q1 * (nn * (nn - 1)) +
+                               q1 * q1 * ((nn - 1) * nn * (2 * nn - 1) / 6);
+            const T C1 = (T)s1 * inv_den, C2 = (T)s2 * inv_den * inv_den;
+#pragma unroll
+            for (int s = 0; s < NU; ++s) {
+                const T e0 = ua[s] - Ug[s];
+                const T du = (a == p - 1) ? (T)0 : ub[s] - ua[s];
+                Ju += Rw[s] * ((T)nseg * e0 * e0 + (T)2 * e0 * du * C1 + du * du * C2);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) dV[mt] = Vb[mt] - Va[mt];
+        for (; k < kend; ++k) {
+            const int rem = (p == 1 || Tn == 1) ? 0 : k * (p - 1) - a * (Tn - 1);
+            const T c = (T)rem * inv_den;
+            // two partial sums per M-tile (even / odd K slices): 2 NT
+            // independent accumulator chains, issued round-robin, so that no
+            // MFMA waits on the one just before it
+            v4 acc[NT][2];
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt) {
+                acc[mt][0] = Va[mt] + c * dV[mt];
+                acc[mt][1] = v4{0, 0, 0, 0};
+            }
+            // slot (t, v): the MFMA of every M-tile for that K slice, then one
+            // row of the stage-cost sums, so VALU and matrix work alternate
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+#pragma unroll
+                    for (int mt = 0; mt < NT; ++mt)
+                        acc[mt][v & 1] = Mfma<T>::op(aX[mt][4 * t + v], X[t][v], acc[mt][v & 1]);
+                    const T e = HAS_XG ? X[t][v] - Xg[t][v] : X[t][v];
+                    S[t][v] += e * e;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt) X[mt] = acc[mt][0] + acc[mt][1];
+        }
+        // next segment's second knot response, from knot a+2
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) Va[mt] = Vb[mt];
+        knot_response(un, Vb);
+        // the set of knot a is free: refill it with knot a+4
+        load_knot(a + 4, ua);
+    };
+    for (int a = 0; a < p; a += 4) {
+        segment(a, K0, K1, K2);
+        if (a + 1 < p) segment(a + 1, K1, K2, K3);
+        if (a + 2 < p) segment(a + 2, K2, K3, K0);
+        if (a + 3 < p) segment(a + 3, K3, K0, K1);
+    }
+    // x_T: stage and terminal weights; weights applied to the row sums
+    T J = Ju;
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * mt + Mfma<T>::row(grp, v);
+            const bool in = row < n;
+            const T e = X[mt][v] - Xg[mt][v];
+            const T q = in ? P.q[row] : (T)0;
+            const T qf = (in && P.qf) ? P.qf[row] : (T)0;
+            J += q * (S[mt][v] + e * e) + qf * e * e;
+        }
+    J += __shfl_xor(J, 16, 64);
+    J += __shfl_xor(J, 32, 64);
+    if (grp == 0 && valid) cost[cand] = J;
+}
+
+template <typename T, int NT, int NU, int WPB, bool HAS_XG>
+__global__ __launch_bounds__(64 * WPB) void roll_linear_mfma(ProbView<T> P,
+                                                             const T *__restrict__ x0,
+                                                             const T *__restrict__ knots,
+                                                             int64_t ld, int64_t ncand,
+                                                             T *__restrict__ cost) {
+    linear_tile<T, NT, NU, HAS_XG>(P, x0, knots, ld, ncand, cost,
+                                   (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6));
+}
+
+// Launch through hipExtLaunchKernelGGL when timing events are given: the
+// events are stamped by the kernel's own dispatch, with no extra stream
+// packets around it.
+template <typename K, typename... Args>
+static hipError_t launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                               const Events &ev, Args... args) {
+    if (ev.start)
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, ev.start, ev.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    return hipGetLastError();
+}
+
+template <typename T, int NT, int NU>
+static hipError_t go_linear(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
+                            int64_t ld, T *cost, hipStream_t s, const Events &ev) {
+    constexpr int WPB = 4;
+    const int64_t tiles = (ncand + 15) / 16;
+    const dim3 grid((unsigned)((tiles + WPB - 1) / WPB)), block(64 * WPB);
+    if (P.xg)
+        return launch_timed(roll_linear_mfma<T, NT, NU, WPB, true>, grid, block, 0, s, ev, P, x0,
+                            knots, ld, ncand, cost);
+    return launch_timed(roll_linear_mfma<T, NT, NU, WPB, false>, grid, block, 0, s, ev, P, x0,
+                        knots, ld, ncand, cost);
+}
+
+template <typename T, int NT>
+static hipError_t go_linear_nu(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
+                               int64_t ld, T *cost, hipStream_t s, const Events &ev) {
+    const int nu = (P.m + 3) / 4;
+    if (nu <= 1) return go_linear<T, NT, 1>(P, x0, knots, ncand, ld, cost, s, ev);
+    if (nu <= 2) return go_linear<T, NT, 2>(P, x0, knots, ncand, ld, cost, s, ev);
+    if (nu <= 4) return go_linear<T, NT, 4>(P, x0, knots, ncand, ld, cost, s, ev);
+    if (nu <= 6) return go_linear<T, NT, 6>(P, x0, knots, ncand, ld, cost, s, ev);
+    if (nu <= 8) return go_linear<T, NT, 8>(P, x0, knots, ncand, ld, cost, s, ev);
+    return go_linear<T, NT, 10>(P, x0, knots, ncand, ld, cost, s, ev);
+}
+
+template <typename T>
+hipError_t launch_linear(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
+                         int64_t ld, T *cost, hipStream_t s, const Events &ev) {
+    const int nt = (P.n + 15) / 16;
+    switch (nt) {
+        case 1: return go_linear_nu<T, 1>(P, x0, knots, ncand, ld, cost, s, ev);
+        case 2: return go_linear_nu<T, 2>(P, x0, knots, ncand, ld, cost, s, ev);
+        case 3: return go_linear_nu<T, 3>(P, x0, knots, ncand, ld, cost, s, ev);
+        case 4: return go_linear_nu<T, 4>(P, x0, knots, ncand, ld, cost, s, ev);
+        default: return go_linear_nu<T, 5>(P, x0, knots, ncand, ld, cost, s, ev);
+    }
+}
+
+}  // namespace empc

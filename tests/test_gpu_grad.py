@@ -145,3 +145,32 @@ def test_autograd_function(E):
     dJ, c = gpu_grad(E, prob, x0, knots, 8, F64)
     np.testing.assert_allclose(cost.detach().cpu().numpy(), c, rtol=1e-12)
     np.testing.assert_allclose(K.grad.cpu().numpy(), dJ * w.cpu().numpy()[None, :], rtol=1e-12)
+
+
+def test_refined_solve_fp64_matches_oracle(oracle_lib, E):
+    # gradient-refined ticks (Adam on the parents after every selection):
+    # FP64 keeps the parent sets identical, so whole ticks agree
+    prob = W.linear_chain(3, 20, 5, seed=2)
+    ga = W.GA(pop=256, n_elite=16, generations=3, sigma=0.1, seed=4)
+    dp = E.DeviceProblem(prob, F64)
+    s = E.Solver(dp, ga)
+    o = oracle_lib.Solver(prob, ga, refine=True, lr=0.01, adam_steps=5)
+    x = W.draw_x0(prob.n, 3)
+    for tick in range(3):
+        u, J = s.solve(dev(x, F64), tick, refine_steps=5, lr=0.01)
+        uo, Jo, _ = o.solve(x, tick)
+        np.testing.assert_allclose(u.cpu().numpy(), uo, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(float(J.item()), Jo, rtol=1e-9)
+        x = oracle_lib.step(prob, x, uo)
+
+
+def test_refined_solve_fp32_c2_not_worse(E):
+    prob, ga = W.config_c2(0)
+    ga = W.dataclasses.replace(ga, generations=5)
+    dp = E.DeviceProblem(prob, F32)
+    x0 = dev(W.draw_x0(prob.n, 0), F32)
+    plain = E.Solver(dp, ga)
+    refined = E.Solver(dp, ga)
+    _, Jp = plain.solve(x0, 0)
+    _, Jr = refined.solve(x0, 0, refine_steps=5, lr=0.01)
+    assert float(Jr.item()) <= float(Jp.item()) * (1 + 1e-4)
