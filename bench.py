@@ -10,9 +10,10 @@ plant step.  Printed as one JSON line:
   value       candidate rollouts per second over the timed ticks
               (population x generations x ticks / wall time);
   latency_ms  per-tick solve latency (submit to u* on the host) p50 / p99;
-  roofline    rollout kernel: algorithmic FLOP per launch over the mean
-              launch time from HIP events recorded around every rollout
-              launch of the timed ticks, against the FP32 matrix-core peak;
+  roofline    rollout kernel: algorithmic FLOP of the rollout and cost per
+              launch over the mean launch time from HIP events recorded
+              around every rollout launch of the timed ticks, against the
+              FP32 matrix-core peak;
   cpu_baseline the FP64 oracle on a bounded sample of the same workload;
   workloads   the other configurations measured the same way: 2-DoF chain
               in FP64, 36-link pendulum chain, the gradient-refined form of
@@ -37,7 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("candidate rollouts/sec and EMPC solve latency p50/p99 (ms) at fixed DoF/horizon")
 PEAK_FP32_MFMA = 157.3e12  # MI355X dense FP32 matrix peak, FLOP/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rollout_linear_c2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rollout_linear_c2_traffic.md")
 ROLLOUT_SRC = os.path.join(ROOT, "paper_2001_04931_amd", "csrc", "rollout_linear.hpp")
 
 
@@ -54,13 +55,32 @@ def traffic_entry():
     None when absent or taken on a different rollout kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
+    t = {}
     with open(TRAFFIC_FILE) as f:
-        t = json.load(f)
+        for line in f:
+            key, sep, val = line.strip().strip("`").partition(": ")
+            if sep and key in ("rollout_src_sha256", "bytes_per_launch"):
+                t[key] = val.strip()
     with open(ROLLOUT_SRC, "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()
-    if t.get("rollout_src_sha256") != h:
+    if t.get("rollout_src_sha256") != h or "bytes_per_launch" not in t:
         return None
-    return t.get("bytes_per_launch")
+    return float(t["bytes_per_launch"])
+
+
+def copy_calibration(mib, reps):
+    """A plain device-to-device copy of `mib` MiB, `reps` times: the known
+    byte count against which the HBM traffic counters are scaled."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps}),
+          flush=True)
 
 
 def cpu_baseline(prob, ga, ticks):
@@ -196,6 +216,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other configurations (C1, C3, C4, C5)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain MIB-MiB device copy (traffic-counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the EMPC hot path here is a single-GPU "
@@ -204,6 +226,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, 5)
+        return
 
     import paper_2001_04931_amd as E
     import workloads as W
@@ -276,7 +302,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                        "p99": float(np.percentile(lat_ms, 99)),
                        "mean": float(lat_ms.mean()), "max": float(lat_ms.max())},
-        "kernel": {"name": "roll_linear_mfma", "launches": launches,
+        "kernel": {"name": "roll_linear_split", "launches": launches,
                    "mean_us": avg_launch_s * 1e6,
                    "rollouts_per_s": ga.pop / avg_launch_s,
                    "flop_per_launch": flop_launch},

@@ -46,6 +46,15 @@ __global__ __launch_bounds__(64 * WPB) void batch_roll_linear(const BatchSlot<T>
                                  (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6));
 }
 
+// linear problems of more than 16 states: the M-split form, one workgroup
+// of NT wavefronts per tile, as in the single-problem rollout
+template <typename T, int NT, int NU>
+__global__ __launch_bounds__(64 * NT) void batch_roll_linear_split(
+    const BatchSlot<T> *__restrict__ slots, const int *__restrict__ items, int64_t pop, int g) {
+    const BatchSlot<T> &S = slots[items[blockIdx.y]];
+    linear_tile_split<T, NT, NU, true>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost, blockIdx.x);
+}
+
 template <typename T, int DMAX>
 __global__ __launch_bounds__(256) void batch_roll_chain(const BatchSlot<T> *__restrict__ slots,
                                                         const int *__restrict__ items, int64_t pop,
@@ -57,6 +66,19 @@ __global__ __launch_bounds__(256) void batch_roll_chain(const BatchSlot<T> *__re
     const int64_t cand = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (cand >= pop) return;
     chain_candidate<T, DMAX>(S.P, jc, S.x0, S.knots[g & 1], pop, S.cost, cand);
+}
+
+// chains of more than 8 joints: one candidate per 16-lane row, as in the
+// single-problem rollout (same arithmetic, same rounding)
+template <typename T, int J>
+__global__ __launch_bounds__(256) void batch_roll_chain_rows(const BatchSlot<T> *__restrict__ slots,
+                                                             const int *__restrict__ items,
+                                                             int64_t pop, int g) {
+    const BatchSlot<T> &S = slots[items[blockIdx.y]];
+    const int64_t cand0 = (int64_t)blockIdx.x * 16;
+    if (cand0 + (threadIdx.x >> 6) * 4 >= pop) return;  // whole wavefront past the end
+    chain_row_candidate<T, J>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
+                              cand0 + (threadIdx.x >> 4), threadIdx.x & 15);
 }
 
 template <typename T, typename K, int CACHE>
@@ -92,12 +114,14 @@ int nu_bucket(int m) {
     if (nu <= 8) return 8;
     return 10;
 }
+// chain kernel classes: lane per candidate up to 8 joints, then a 16-lane
+// row per candidate with 1, 2 or 3 joints per lane
 int dmax_bucket(int d) {
     if (d <= 4) return 4;
     if (d <= 8) return 8;
     if (d <= 16) return 16;
-    if (d <= 24) return 24;
-    return 40;
+    if (d <= 32) return 32;
+    return 48;
 }
 
 template <int NT, int NU>
@@ -105,6 +129,12 @@ static void go_batch_linear(const BatchSlot<float> *slots, const int *items, int
                             int64_t pop, int g, hipStream_t s) {
     constexpr int WPB = 4;
     const int64_t tiles = (pop + 15) / 16;
+    if (NT > 1) {
+        hipLaunchKernelGGL((batch_roll_linear_split<float, NT, NU>),
+                           dim3((unsigned)tiles, (unsigned)count), dim3(64 * NT), 0, s, slots,
+                           items, pop, g);
+        return;
+    }
     hipLaunchKernelGGL((batch_roll_linear<float, NT, NU, WPB>),
                        dim3((unsigned)((tiles + WPB - 1) / WPB), (unsigned)count), dim3(64 * WPB), 0,
                        s, slots, items, pop, g);
@@ -120,6 +150,13 @@ static void go_batch_linear_nu(int nu, const BatchSlot<float> *slots, const int 
         case 8: go_batch_linear<NT, 8>(slots, items, count, pop, g, s); break;
         default: go_batch_linear<NT, 10>(slots, items, count, pop, g, s); break;
     }
+}
+template <int J>
+static void go_batch_chain_rows(const BatchSlot<float> *slots, const int *items, int count,
+                                int64_t pop, int g, hipStream_t s) {
+    hipLaunchKernelGGL((batch_roll_chain_rows<float, J>),
+                       dim3((unsigned)((pop + 15) / 16), (unsigned)count), dim3(256), 0, s, slots,
+                       items, pop, g);
 }
 template <int DMAX>
 static void go_batch_chain(const BatchSlot<float> *slots, const int *items, int count, int64_t pop,
@@ -224,7 +261,7 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         S.elite_cost = (float *)(base + off); off += al256(k * 4);
         S.elite_idx = (int64_t *)(base + off); off += al256(k * 8);
         S.best_idx = (int64_t *)(base + off); off += 256;
-        b->ngmax = std::max(b->ngmax, (int)((pm + 3) / 4));
+        b->ngmax = std::max(b->ngmax, (int)((pm + POP_PARAMS - 1) / POP_PARAMS));
     }
     // group problems by kernel shape class
     std::map<std::tuple<int, int, int>, std::vector<int>> groups;
@@ -290,9 +327,9 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
                 switch (c.a) {
                     case 4: go_batch_chain<4>(b->d_slots, items, c.count, pop, g, s); break;
                     case 8: go_batch_chain<8>(b->d_slots, items, c.count, pop, g, s); break;
-                    case 16: go_batch_chain<16>(b->d_slots, items, c.count, pop, g, s); break;
-                    case 24: go_batch_chain<24>(b->d_slots, items, c.count, pop, g, s); break;
-                    default: go_batch_chain<40>(b->d_slots, items, c.count, pop, g, s); break;
+                    case 16: go_batch_chain_rows<1>(b->d_slots, items, c.count, pop, g, s); break;
+                    case 32: go_batch_chain_rows<2>(b->d_slots, items, c.count, pop, g, s); break;
+                    default: go_batch_chain_rows<3>(b->d_slots, items, c.count, pop, g, s); break;
                 }
             }
         }

@@ -128,16 +128,21 @@ struct Profile {
 };
 Profile g_prof;
 
-template <typename T>
-hipError_t timed_rollout(const ProbView<T> &V, int model, const T *x0, const T *knots,
-                         int64_t ncand, int64_t ld, T *cost, hipStream_t s) {
+// Timing events for the next rollout launch of an open profiling session.
+Events next_events() {
     Events ev;
     if (g_prof.on && g_prof.used < (int)g_prof.start.size()) {
         ev.start = g_prof.start[g_prof.used];
         ev.stop = g_prof.stop[g_prof.used];
         ++g_prof.used;
     }
-    return launch_rollout<T>(V, model, x0, knots, ncand, ld, cost, s, ev);
+    return ev;
+}
+
+template <typename T>
+hipError_t timed_rollout(const ProbView<T> &V, int model, const T *x0, const T *knots,
+                         int64_t ncand, int64_t ld, T *cost, hipStream_t s) {
+    return launch_rollout<T>(V, model, x0, knots, ncand, ld, cost, s, next_events());
 }
 
 // Gradient refinement of the parents after a selection: gather them, run

@@ -11,7 +11,7 @@ hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *k
                              uint32_t tick, uint32_t gen, hipStream_t s) {
     const int pm = P.p * P.m;
     const GaStreams gs = ga_streams(ga.seed, P.m, pm);
-    const int64_t total = (int64_t)ga.pop * ((pm + 3) / 4);
+    const int64_t total = (int64_t)ga.pop * ((pm + POP_PARAMS - 1) / POP_PARAMS);
     const int64_t blocks = (total + 255) / 256;
     hipLaunchKernelGGL(population_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, P, gs,
                        (int64_t)ga.pop, ga.n_elite, ga.elitism, (T)ga.sigma, knots_in, ld_in,

@@ -23,53 +23,91 @@ __device__ inline float log_of<float>(float x) { return logf(x); }
 template <>
 __device__ inline double log_of<double>(double x) { return log(x); }
 
-// One thread per (slot s, group g of four parameters j = 4g..4g+3), slot
-// fastest so that each of the four stores knots_out[j * ld + s] coalesces.
-// The four parameters share their Philox blocks: block 0 (parents), one
-// mutation-flag block, one crossover block and one normal block (four
-// normals from two Box-Muller pairs).
+// One thread per (slot s, group g of POP_PARAMS consecutive parameters
+// j = POP_PARAMS g ..), slot fastest so that every store
+// knots_out[j * ld + s] of a wavefront coalesces.  The group's parameters
+// share one parent block (block 0), one mutation-flag block and one crossover
+// block (a group never straddles a 128-parameter crossover block), and each
+// quad of parameters one normal block (two Box-Muller pairs), drawn only if a
+// parameter of the quad is mutated.
 // Parent knots come from elite_rows ([k][pm], when non-NULL) or from
 // knots_in at elite_idx[.].
-// cold_mode: 0 warm, 1 cold, 2 cold iff *has_elites == 0.
+// Four parameters per thread: the generation is latency bound (a few
+// dependent Philox blocks and two dependent global reads per thread), so it
+// gains more from many short threads than from sharing draws over longer ones.
+constexpr int POP_PARAMS = 4;  // divides 128
+
+// One Box-Muller pair from two Philox words.
 template <typename T>
-__device__ __forceinline__ void population_body(
-    const ProbView<T> &P, const GaStreams &gs, int64_t pop, int k, int elitism, T sigma,
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T &z0, T &z1) {
+    const T u1 = uni23<T>(wa);
+    const T u2 = uni23<T>(wb);
+    const T rad = sqrt((T)-2 * log_of<T>(u1));
+    T sn, cs;
+    sincos_of<T>((T)6.283185307179586 * u2, &sn, &cs);
+    z0 = rad * cs;
+    z1 = rad * sn;
+}
+
+// Mutation of one inherited parameter and the bounds (Sec. V warm start).
+template <typename T>
+__device__ __forceinline__ T mutate_clamp(T v, bool flag, T sigma, T z, T lo, T hi) {
+    if (flag) v += sigma * z;
+    v = v < lo ? lo : v;
+    v = v > hi ? hi : v;
+    return v;
+}
+
+// Values of parameters j0 .. j0+POP_PARAMS-1 (those below p m) of child
+// `s` of generation `gen` of tick `tick`.
+template <typename T>
+__device__ __forceinline__ void child_values(
+    const ProbView<T> &P, const GaStreams &gs, int k, int elitism, T sigma,
     const T *__restrict__ knots_in, int64_t ld_in, const int64_t *__restrict__ elite_idx,
-    const T *__restrict__ elite_rows, bool cold, T *__restrict__ knots_out, int64_t ld_out,
-    uint32_t tick, uint32_t gen, int64_t t) {
-    const int m = P.m, pm = P.p * P.m, ng = (pm + 3) / 4;
-    if (t >= pop * ng) return;
-    const int64_t s = t % pop;
-    const int g = (int)(t / pop);
-    const int j0 = 4 * g;
+    const T *__restrict__ elite_rows, bool cold, uint32_t tick, uint32_t gen, int64_t s, int j0,
+    T *val) {
+    const int m = P.m, pm = P.p * P.m;
     const uint32_t slot = (uint32_t)s;
-    auto parent = [&](int par, int j) -> T {
-        return elite_rows ? elite_rows[(int64_t)par * pm + j]
-                          : knots_in[(int64_t)j * ld_in + elite_idx[par]];
-    };
-    T val[4];
     if (cold) {
-        const U4 w = ga_draw(gs, slot, gen, tick, 1, (uint32_t)g);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = (j0 + r) % m;
-            val[r] = P.umin[i] + (P.umax[i] - P.umin[i]) * uni23<T>(word_of(w, r));
+        for (int q = 0; q < POP_PARAMS / 4; ++q) {
+            const U4 w = ga_draw(gs, slot, gen, tick, 1, (uint32_t)(j0 / 4 + q));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = (j0 + 4 * q + r) % m;
+                val[4 * q + r] = P.umin[i] + (P.umax[i] - P.umin[i]) * uni23<T>(word_of(w, r));
+            }
         }
     } else if (elitism && s < k) {
+        const T *src = elite_rows ? elite_rows + (int64_t)s * pm : nullptr;
+        const int64_t col = elite_rows ? 0 : elite_idx[s];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) val[r] = j0 + r < pm ? parent((int)s, j0 + r) : (T)0;
+        for (int r = 0; r < POP_PARAMS; ++r) {
+            const int j = j0 + r;
+            val[r] = j < pm ? (src ? src[j] : knots_in[(int64_t)j * ld_in + col]) : (T)0;
+        }
     } else {
         const U4 w0 = ga_draw(gs, slot, gen, tick, 0, 0);
         const int p1 = (int)__umulhi(w0.x, (uint32_t)k);
         const int p2 = (int)__umulhi(w0.y, (uint32_t)k);
-        // j0..j0+3 lie in one 128-parameter crossover block
+        // parent columns (or rows of elite_rows)
+        const T *src1, *src2;
+        int64_t step;
+        if (elite_rows) {
+            src1 = elite_rows + (int64_t)p1 * pm;
+            src2 = elite_rows + (int64_t)p2 * pm;
+            step = 1;
+        } else {
+            src1 = knots_in + elite_idx[p1];
+            src2 = knots_in + elite_idx[p2];
+            step = ld_in;
+        }
         const U4 wx = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.XB + j0 / 128));
         int fblk = -1;
         U4 wf = {0, 0, 0, 0};
-        bool flag[4];
-        bool any = false;
+        bool flag[POP_PARAMS];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < POP_PARAMS; ++r) {
             const int i = (j0 + r) % m;
             if (1 + i / 128 != fblk) {
                 fblk = 1 + i / 128;
@@ -77,26 +115,22 @@ __device__ __forceinline__ void population_body(
             }
             const int ib = i % 128;
             flag[r] = j0 + r < pm && ((word_of(wf, ib / 32) >> (ib % 32)) & 1u);
-            any |= flag[r];
         }
-        T z[4] = {0, 0, 0, 0};
-        if (any) {
-            const U4 wn = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.NB + g));
+        T z[POP_PARAMS];
 #pragma unroll
-            for (int pair = 0; pair < 2; ++pair) {
-                if (flag[2 * pair] || flag[2 * pair + 1]) {
-                    const T u1 = uni23<T>(word_of(wn, 2 * pair));
-                    const T u2 = uni23<T>(word_of(wn, 2 * pair + 1));
-                    const T rad = sqrt((T)-2 * log_of<T>(u1));
-                    T sn, cs;
-                    sincos_of<T>((T)6.283185307179586 * u2, &sn, &cs);
-                    z[2 * pair] = rad * cs;
-                    z[2 * pair + 1] = rad * sn;
-                }
+        for (int q = 0; q < POP_PARAMS / 4; ++q) {
+            z[4 * q] = z[4 * q + 1] = z[4 * q + 2] = z[4 * q + 3] = 0;
+            if (flag[4 * q] || flag[4 * q + 1] || flag[4 * q + 2] || flag[4 * q + 3]) {
+                const U4 wn = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.NB + j0 / 4 + q));
+#pragma unroll
+                for (int pair = 0; pair < 2; ++pair)
+                    if (flag[4 * q + 2 * pair] || flag[4 * q + 2 * pair + 1])
+                        box_muller<T>(word_of(wn, 2 * pair), word_of(wn, 2 * pair + 1),
+                                      z[4 * q + 2 * pair], z[4 * q + 2 * pair + 1]);
             }
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < POP_PARAMS; ++r) {
             const int j = j0 + r;
             if (j >= pm) {
                 val[r] = 0;
@@ -104,15 +138,27 @@ __device__ __forceinline__ void population_body(
             }
             const int i = j % m, jb = j % 128;
             const bool from2 = (word_of(wx, jb / 32) >> (jb % 32)) & 1u;
-            T v = parent(from2 ? p2 : p1, j);
-            if (flag[r]) v += sigma * z[r];
-            v = v < P.umin[i] ? P.umin[i] : v;
-            v = v > P.umax[i] ? P.umax[i] : v;
-            val[r] = v;
+            val[r] = mutate_clamp<T>((from2 ? src2 : src1)[(int64_t)j * step], flag[r], sigma,
+                                     z[r], P.umin[i], P.umax[i]);
         }
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void population_body(
+    const ProbView<T> &P, const GaStreams &gs, int64_t pop, int k, int elitism, T sigma,
+    const T *__restrict__ knots_in, int64_t ld_in, const int64_t *__restrict__ elite_idx,
+    const T *__restrict__ elite_rows, bool cold, T *__restrict__ knots_out, int64_t ld_out,
+    uint32_t tick, uint32_t gen, int64_t t) {
+    const int pm = P.p * P.m, ng = (pm + POP_PARAMS - 1) / POP_PARAMS;
+    if (t >= pop * ng) return;
+    const int64_t s = t % pop;
+    const int j0 = POP_PARAMS * (int)(t / pop);
+    T val[POP_PARAMS];
+    child_values<T>(P, gs, k, elitism, sigma, knots_in, ld_in, elite_idx, elite_rows, cold, tick,
+                    gen, s, j0, val);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < POP_PARAMS; ++r)
         if (j0 + r < pm) knots_out[(int64_t)(j0 + r) * ld_out + s] = val[r];
 }
 
@@ -149,14 +195,19 @@ constexpr int SEL_THREADS = 256;
 constexpr int SEL_WAVES = SEL_THREADS / 64;
 constexpr int HREP = 16, HSTRIDE = 257;
 
+// Inclusive scan over a full wavefront: within each 16-lane row by DPP row
+// shifts (zero shifted in), then the totals of the rows below, read from
+// lanes 15, 31 and 47.  Every lane of the wavefront must be active.
 __device__ inline int wave_incl_scan(int v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(v, o, 64);
-        if (lane >= o) v += y;
-    }
-    return v;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    const int r0 = __builtin_amdgcn_readlane(v, 15);
+    const int r1 = __builtin_amdgcn_readlane(v, 31);
+    const int r2 = __builtin_amdgcn_readlane(v, 47);
+    const int row = (threadIdx.x & 63) >> 4;
+    return v + (row > 0 ? r0 : 0) + (row > 1 ? r1 : 0) + (row > 2 ? r2 : 0);
 }
 
 // Exclusive block prefix sum of v; *total gets the sum.
@@ -215,14 +266,16 @@ __device__ __forceinline__ void select_body(
         for (int r = 0; r < (CACHE > 0 ? CACHE : 1); ++r)
             cache[r] = r < nmine ? sort_key(cost[i0 + r]) : ~(K)0;
     }
-    auto key_at = [&](int64_t r) -> K {
+    // visit this thread's keys in index order; with the cache every index
+    // is a compile-time constant, so the keys stay in registers
+    auto for_each_key = [&](auto &&f) {
         if (CACHE > 0) {
-            K v = cache[0];
 #pragma unroll
-            for (int q = 1; q < (CACHE > 0 ? CACHE : 1); ++q) v = r == q ? cache[q] : v;
-            return v;
+            for (int r = 0; r < (CACHE > 0 ? CACHE : 1); ++r)
+                if (r < nmine) f((int64_t)r, cache[r]);
+        } else {
+            for (int64_t r = 0; r < nmine; ++r) f(r, sort_key(cost[i0 + r]));
         }
-        return sort_key(cost[i0 + r]);
     };
     __syncthreads();
 
@@ -231,19 +284,9 @@ __device__ __forceinline__ void select_body(
     int buf = 0;
     for (int shift = (int)sizeof(K) * 8 - 8; shift >= 0; shift -= 8) {
         int *myh = hist[buf] + (lane & (HREP - 1)) * HSTRIDE;
-        if (CACHE > 0) {
-#pragma unroll
-            for (int r = 0; r < (CACHE > 0 ? CACHE : 1); ++r) {
-                const K key = cache[r];
-                if (r < nmine && (key & mask) == prefix)
-                    atomicAdd(&myh[(int)((key >> shift) & 255)], 1);
-            }
-        } else {
-            for (int64_t r = 0; r < nmine; ++r) {
-                const K key = key_at(r);
-                if ((key & mask) == prefix) atomicAdd(&myh[(int)((key >> shift) & 255)], 1);
-            }
-        }
+        for_each_key([&](int64_t, K key) {
+            if ((key & mask) == prefix) atomicAdd(&myh[(int)((key >> shift) & 255)], 1);
+        });
         // clear the other buffer for the next pass
         for (int b = tid; b < HREP * HSTRIDE; b += SEL_THREADS) hist[buf ^ 1][b] = 0;
         __syncthreads();
@@ -264,16 +307,21 @@ __device__ __forceinline__ void select_body(
             const unsigned long long hit = __ballot(incl >= remaining);
             const int first = __ffsll((long long)hit) - 1;
             if (tid == first) {
-                int cum = excl, dsel = 4 * tid + 3;
-                const int hs[4] = {h0, h1, h2, h3};
-                for (int q = 0; q < 4; ++q) {
-                    if (cum + hs[q] >= remaining) {
-                        dsel = 4 * tid + q;
-                        break;
-                    }
-                    cum += hs[q];
+                // first of the lane's four bins where the running count
+                // reaches `remaining`
+                int cum = excl, q = 3;
+                if (cum + h0 >= remaining) {
+                    q = 0;
+                } else if (cum + h0 + h1 >= remaining) {
+                    q = 1;
+                    cum += h0;
+                } else if (cum + h0 + h1 + h2 >= remaining) {
+                    q = 2;
+                    cum += h0 + h1;
+                } else {
+                    cum += h0 + h1 + h2;
                 }
-                s_digit = dsel;
+                s_digit = 4 * tid + q;
                 s_rem = remaining - cum;
             }
         }
@@ -286,25 +334,23 @@ __device__ __forceinline__ void select_body(
     const K thr = prefix;
     // ordered pass over this thread's contiguous range
     int my_eq = 0;
-    for (int64_t r = 0; r < nmine; ++r) my_eq += key_at(r) == thr ? 1 : 0;
+    for_each_key([&](int64_t, K key) { my_eq += key == thr ? 1 : 0; });
     int eq_tot;
     const int eq_base = block_excl_scan(my_eq, wsum, &eq_tot);
     int my_sel = 0;
     {
         int e = eq_base;
-        for (int64_t r = 0; r < nmine; ++r) {
-            const K key = key_at(r);
+        for_each_key([&](int64_t, K key) {
             const bool eq = key == thr;
             my_sel += (key < thr || (eq && e < remaining)) ? 1 : 0;
             e += eq ? 1 : 0;
-        }
+        });
     }
     int sel_tot;
     int pos = block_excl_scan(my_sel, wsum, &sel_tot);
     {
         int e = eq_base;
-        for (int64_t r = 0; r < nmine; ++r) {
-            const K key = key_at(r);
+        for_each_key([&](int64_t r, K key) {
             const bool eq = key == thr;
             if (key < thr || (eq && e < remaining)) {
                 if (pos < k) {
@@ -314,7 +360,7 @@ __device__ __forceinline__ void select_body(
                 ++pos;
             }
             e += eq ? 1 : 0;
-        }
+        });
     }
     __syncthreads();
     // best among the elites (wave 0)

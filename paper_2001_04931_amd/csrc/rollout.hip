@@ -44,10 +44,7 @@ hipError_t launch_rollout(const ProbView<T> &P, int model, const T *x0, const T 
     const dim3 rows((unsigned)((ncand + 15) / 16)), blk(256);
     if (d <= 16) return launch_timed(roll_chain_rows<T, 1>, rows, blk, 0, s, ev, P, x0, knots, ld, ncand, cost);
     if (d <= 32) return launch_timed(roll_chain_rows<T, 2>, rows, blk, 0, s, ev, P, x0, knots, ld, ncand, cost);
-    if (d <= 48) return launch_timed(roll_chain_rows<T, 3>, rows, blk, 0, s, ev, P, x0, knots, ld, ncand, cost);
-    if (d <= 16) return go_chain<T, 16>(P, x0, knots, ncand, ld, cost, s, ev);
-    if (d <= 24) return go_chain<T, 24>(P, x0, knots, ncand, ld, cost, s, ev);
-    return go_chain<T, 40>(P, x0, knots, ncand, ld, cost, s, ev);
+    return launch_timed(roll_chain_rows<T, 3>, rows, blk, 0, s, ev, P, x0, knots, ld, ncand, cost);  // d <= 48
 }
 
 template hipError_t launch_rollout<float>(const ProbView<float> &, int, const float *,

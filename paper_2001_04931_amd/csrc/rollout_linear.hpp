@@ -25,6 +25,10 @@
 
 namespace empc {
 
+// s_waitcnt operand for gfx9: vmcnt = 0, expcnt and lgkmcnt left at their
+// maxima (no wait)
+constexpr int VMCNT0 = 0x0F70;
+
 template <typename T>
 struct Mfma;
 template <>
@@ -56,7 +60,8 @@ struct Mfma<double> {
 // per state row, S_i += (x_i - g_i)^2, and weighted by Q once at the end; the
 // input cost of a segment is summed in closed form (u is affine in c there):
 //   sum_k r (e0 + c_k du)^2 = r (n e0^2 + 2 e0 du sum c_k + du^2 sum c_k^2),
-// with the sums over c_k taken exactly in integers.
+// with the two sums over c_k accumulated by the step loop (two VALU
+// operations per step, off the MFMA chain).
 // One wavefront: candidates 16*tile .. 16*tile+15 of one problem.
 template <typename T, int NT, int NU, bool HAS_XG>
 __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__restrict__ x0,
@@ -104,6 +109,10 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
             Xg[mt][v] = (in && HAS_XG && P.xg) ? P.xg[row] : (T)0;
         }
 
+    // the model operands and the initial state are needed by the first
+    // step: wait for them here, before any knot load is in flight, so that
+    // no wait in the step loop has to drain the knot prefetches with them
+    __builtin_amdgcn_s_waitcnt(VMCNT0);
     const int p = P.p, Tn = P.Tn;
     // Loads are unconditional and unmasked, so that each use waits only for
     // its own load: a padded input row (j >= m) reads the candidate's own
@@ -120,14 +129,27 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
             dst[s] = knots[(int64_t)(kc * m + (j < m ? j : m - 1)) * ld + cand_c];
         }
     };
-    // V = B_d U + w_d for one knot (input slices as B operands)
+    // V = B_d U + w_d for one knot (input slices as B operands), even and
+    // odd slices in two accumulator chains
     auto knot_response = [&](const T *U, v4 *V) {
+        v4 V1[NT];
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) V[mt] = Mfma<T>::op(aU[mt][0], U[0], Wd[mt]);
+        for (int mt = 0; mt < NT; ++mt) {
+            V[mt] = Mfma<T>::op(aU[mt][0], U[0], Wd[mt]);
+            if (NU > 1) V1[mt] = Mfma<T>::op(aU[mt][1 % NU], U[1 % NU], v4{0, 0, 0, 0});
+        }
 #pragma unroll
-        for (int s = 1; s < NU; ++s)
+        for (int s = 2; s < NU; ++s)
 #pragma unroll
-            for (int mt = 0; mt < NT; ++mt) V[mt] = Mfma<T>::op(aU[mt][s], U[s], V[mt]);
+            for (int mt = 0; mt < NT; ++mt) {
+                if (s & 1)
+                    V1[mt] = Mfma<T>::op(aU[mt][s], U[s], V1[mt]);
+                else
+                    V[mt] = Mfma<T>::op(aU[mt][s], U[s], V[mt]);
+            }
+        if (NU > 1)
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt) V[mt] += V1[mt];
     };
     // Knot registers: four sets K0..K3 hold knots a..a+3 while segment a runs.
     // The segment loop is unrolled four ways with the sets' roles rotating in
@@ -169,27 +191,14 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
         const int kend = (p == 1 || a == p - 1) ? Tn
                                                 : ((a + 1) * (Tn - 1) + (p - 2)) / (p - 1);
         const int nseg = kend - k;
-        // input cost of the segment in closed form; rem_k = r0 + i (p-1)
-        {
-            const int64_t q1 = p - 1;
-            const int64_t r0 = (p == 1 || Tn == 1) ? 0 : (int64_t)k * q1 - (int64_t)a * (Tn - 1);
-            const int64_t nn = nseg;
-            const int64_t s1 = nn * r0 + q1 * (nn * (nn - 1) / 2);
-            const int64_t s2 = nn * r0 * r0 + r0 * q1 * (nn * (nn - 1)) +
-                               q1 * q1 * ((nn - 1) * nn * (2 * nn - 1) / 6);
-            const T C1 = (T)s1 * inv_den, C2 = (T)s2 * inv_den * inv_den;
-#pragma unroll
-            for (int s = 0; s < NU; ++s) {
-                const T e0 = ua[s] - Ug[s];
-                const T du = (a == p - 1) ? (T)0 : ub[s] - ua[s];
-                Ju += Rw[s] * ((T)nseg * e0 * e0 + (T)2 * e0 * du * C1 + du * du * C2);
-            }
-        }
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt) dV[mt] = Vb[mt] - Va[mt];
+        T C1 = 0, C2 = 0;  // sums of c and c^2 over the segment
         for (; k < kend; ++k) {
             const int rem = (p == 1 || Tn == 1) ? 0 : k * (p - 1) - a * (Tn - 1);
             const T c = (T)rem * inv_den;
+            C1 += c;
+            C2 += c * c;
             // two partial sums per M-tile (even / odd K slices): 2 NT
             // independent accumulator chains, issued round-robin, so that no
             // MFMA waits on the one just before it
@@ -214,6 +223,14 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
                 }
 #pragma unroll
             for (int mt = 0; mt < NT; ++mt) X[mt] = acc[mt][0] + acc[mt][1];
+        }
+        // input cost of the segment: u is affine in c on it, so
+        //   sum_k r (e0 + c_k du)^2 = r (nseg e0^2 + 2 e0 du sum c_k + du^2 sum c_k^2)
+#pragma unroll
+        for (int s = 0; s < NU; ++s) {
+            const T e0 = ua[s] - Ug[s];
+            const T du = (a == p - 1) ? (T)0 : ub[s] - ua[s];
+            Ju += Rw[s] * ((T)nseg * e0 * e0 + (T)2 * e0 * du * C1 + du * du * C2);
         }
         // next segment's second knot response, from knot a+2
 #pragma unroll
@@ -256,6 +273,228 @@ __global__ __launch_bounds__(64 * WPB) void roll_linear_mfma(ProbView<T> P,
                                    (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6));
 }
 
+// ---------------------------------------------------------------------------
+// M-split form: one workgroup of NT wavefronts per tile of 16 candidates,
+// wavefront w owning state rows 16w..16w+15 (M-tile w).  Each step a
+// wavefront runs the 4 NT MFMAs of its own rows (instead of 4 NT^2), then
+// publishes its new rows through LDS and reads the other tiles back for the
+// next step: one LDS round trip and one barrier per step, hidden behind the
+// four MFMAs of the wavefront's own K slices, which need no exchanged data.
+// A tile thus runs on NT SIMDs instead of one, which is what a population of
+// a few thousand candidates needs to occupy the chip.
+//
+// Registers are indexed by slot i = 0..NT-1 holding M-tile (w + i) mod NT, so
+// slot 0 is always the wavefront's own tile and every register index stays a
+// compile-time constant; A_d's columns are loaded in the same rotated order.
+__device__ inline void lds_barrier() {
+    // orders LDS accesses only: outstanding global loads (knot prefetches)
+    // are not waited for
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One workgroup of 64 NT threads: candidates 16*tile .. 16*tile+15 (tile
+// must hold at least one candidate: the whole workgroup takes part in every
+// barrier).
+template <typename T, int NT, int NU, bool HAS_XG>
+__device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T *__restrict__ x0,
+                                                  const T *__restrict__ knots, int64_t ld,
+                                                  int64_t ncand, T *__restrict__ cost,
+                                                  int64_t tile) {
+    typedef typename Mfma<T>::v4 v4;
+    __shared__ v4 xs[2][NT][64];
+    __shared__ T part[NT][16];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const int64_t cand0 = tile * 16;
+    const int col = lane & 15, grp = lane >> 4;
+    const int64_t cand = cand0 + col;
+    const bool valid = cand < ncand;
+    const int n = P.n, m = P.m;
+    const int row_own = 16 * w + col;  // A-operand row of this lane
+
+    // aX[4i+v] = A_d[16w + col][16 t_i + R(grp, v)], t_i = (w + i) mod NT
+    T aX[4 * NT];
+    T aU[NU];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int t = (w + i) % NT;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int kk = 16 * t + Mfma<T>::row(grp, v);
+            aX[4 * i + v] = (row_own < n && kk < n) ? P.Ad[row_own * n + kk] : (T)0;
+        }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < NU; ++s2) {
+        const int j = 4 * s2 + grp;
+        aU[s2] = (row_own < n && j < m) ? P.Bd[row_own * m + j] : (T)0;
+    }
+    // state of every tile by slot; disturbance and goal of the own tile
+    v4 X[NT], Wd, Xg;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int t = (w + i) % NT;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * t + Mfma<T>::row(grp, v);
+            X[i][v] = row < n ? x0[row] : (T)0;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = 16 * w + Mfma<T>::row(grp, v);
+        const bool in = row < n;
+        Wd[v] = (in && P.wd) ? P.wd[row] : (T)0;
+        Xg[v] = (in && HAS_XG && P.xg) ? P.xg[row] : (T)0;
+    }
+
+    // the model operands and the initial state are needed by the first
+    // step: wait for them here, before any knot load is in flight, so that
+    // no wait in the step loop has to drain the knot prefetches with them
+    __builtin_amdgcn_s_waitcnt(VMCNT0);
+    const int p = P.p, Tn = P.Tn;
+    // unconditional clamped loads, as in the one-wavefront form
+    const int64_t cand_c = valid ? cand : ncand - 1;
+    auto load_knot = [&](int kn_idx, T *dst) {
+        const int kc = kn_idx < p ? kn_idx : p - 1;
+#pragma unroll
+        for (int s2 = 0; s2 < NU; ++s2) {
+            const int j = 4 * s2 + grp;
+            dst[s2] = knots[(int64_t)(kc * m + (j < m ? j : m - 1)) * ld + cand_c];
+        }
+    };
+    // own rows of V = B_d U + w_d, even and odd slices in two chains
+    auto knot_response = [&](const T *U) -> v4 {
+        v4 V = Mfma<T>::op(aU[0], U[0], Wd);
+        if (NU == 1) return V;
+        v4 V1 = Mfma<T>::op(aU[1 % NU], U[1 % NU], v4{0, 0, 0, 0});
+#pragma unroll
+        for (int s2 = 2; s2 < NU; ++s2) {
+            if (s2 & 1)
+                V1 = Mfma<T>::op(aU[s2], U[s2], V1);
+            else
+                V = Mfma<T>::op(aU[s2], U[s2], V);
+        }
+        return V + V1;
+    };
+    T K0[NU], K1[NU], K2[NU], K3[NU];
+    load_knot(0, K0);
+    load_knot(1, K1);
+    load_knot(2, K2);
+    load_knot(3, K3);
+    T Rw[NU], Ug[NU];
+#pragma unroll
+    for (int s2 = 0; s2 < NU; ++s2) {
+        const int j = 4 * s2 + grp;
+        Rw[s2] = j < m ? P.r[j] : (T)0;
+        Ug[s2] = (j < m && P.ug) ? P.ug[j] : (T)0;
+    }
+    v4 Va = knot_response(K0);
+    v4 Vb = knot_response(p > 1 ? K1 : K0);
+    v4 dV;
+
+    const T inv_den = Tn > 1 ? (T)1 / (T)(Tn - 1) : (T)0;
+    v4 S;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const T e = X[0][v] - Xg[v];
+        S[v] = -(e * e);
+    }
+    T Ju = 0;
+    int k = 0, buf = 0;
+    auto segment = [&](int a, T *ua, T *ub, T *un) {
+        const int kend = (p == 1 || a == p - 1) ? Tn
+                                                : ((a + 1) * (Tn - 1) + (p - 2)) / (p - 1);
+        const int nseg = kend - k;
+        dV = Vb - Va;
+        T C1 = 0, C2 = 0;  // sums of c and c^2 over the segment
+        for (; k < kend; ++k) {
+            const int rem = (p == 1 || Tn == 1) ? 0 : k * (p - 1) - a * (Tn - 1);
+            const T c = (T)rem * inv_den;
+            C1 += c;
+            C2 += c * c;
+            v4 acc0 = Va + c * dV, acc1 = v4{0, 0, 0, 0};
+            // own K slices first (no exchanged data), with the stage cost of
+            // the own rows between them; then the other tiles' slices
+#pragma unroll
+            for (int i = 0; i < NT; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if (v & 1)
+                        acc1 = Mfma<T>::op(aX[4 * i + v], X[i][v], acc1);
+                    else
+                        acc0 = Mfma<T>::op(aX[4 * i + v], X[i][v], acc0);
+                    if (i == 0) {
+                        const T e = HAS_XG ? X[0][v] - Xg[v] : X[0][v];
+                        S[v] += e * e;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            X[0] = acc0 + acc1;
+            if (NT > 1) {
+                xs[buf][w][lane] = X[0];
+                lds_barrier();
+#pragma unroll
+                for (int i = 1; i < NT; ++i) X[i] = xs[buf][(w + i) % NT][lane];
+                buf ^= 1;
+            }
+        }
+        // input cost of the segment in closed form (u is affine in c on
+        // it); the input slices are shared out over the wavefronts
+#pragma unroll
+        for (int s2 = 0; s2 < NU; ++s2) {
+            if (s2 % NT != w) continue;
+            const T e0 = ua[s2] - Ug[s2];
+            const T du = (a == p - 1) ? (T)0 : ub[s2] - ua[s2];
+            Ju += Rw[s2] * ((T)nseg * e0 * e0 + (T)2 * e0 * du * C1 + du * du * C2);
+        }
+        Va = Vb;
+        Vb = knot_response(un);
+        load_knot(a + 4, ua);
+    };
+    for (int a = 0; a < p; a += 4) {
+        segment(a, K0, K1, K2);
+        if (a + 1 < p) segment(a + 1, K1, K2, K3);
+        if (a + 2 < p) segment(a + 2, K2, K3, K0);
+        if (a + 3 < p) segment(a + 3, K3, K0, K1);
+    }
+    T J = Ju;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = 16 * w + Mfma<T>::row(grp, v);
+        const bool in = row < n;
+        const T e = X[0][v] - Xg[v];
+        const T q = in ? P.q[row] : (T)0;
+        const T qf = (in && P.qf) ? P.qf[row] : (T)0;
+        J += q * (S[v] + e * e) + qf * e * e;
+    }
+    J += __shfl_xor(J, 16, 64);
+    J += __shfl_xor(J, 32, 64);
+    if (NT == 1) {
+        if (grp == 0 && valid) cost[cand] = J;
+        return;
+    }
+    if (lane < 16) part[w][lane] = J;
+    lds_barrier();
+    if (w == 0 && lane < 16 && valid) {
+        T tot = part[0][lane];
+#pragma unroll
+        for (int i = 1; i < NT; ++i) tot += part[i][lane];
+        cost[cand] = tot;
+    }
+}
+
+template <typename T, int NT, int NU, bool HAS_XG>
+__global__ __launch_bounds__(64 * NT) void roll_linear_split(ProbView<T> P,
+                                                             const T *__restrict__ x0,
+                                                             const T *__restrict__ knots,
+                                                             int64_t ld, int64_t ncand,
+                                                             T *__restrict__ cost) {
+    linear_tile_split<T, NT, NU, HAS_XG>(P, x0, knots, ld, ncand, cost, blockIdx.x);
+}
+
 // Launch through hipExtLaunchKernelGGL when timing events are given: the
 // events are stamped by the kernel's own dispatch, with no extra stream
 // packets around it.
@@ -274,6 +513,14 @@ static hipError_t go_linear(const ProbView<T> &P, const T *x0, const T *knots, i
                             int64_t ld, T *cost, hipStream_t s, const Events &ev) {
     constexpr int WPB = 4;
     const int64_t tiles = (ncand + 15) / 16;
+    if (NT > 1) {
+        const dim3 grid((unsigned)tiles), block(64 * NT);
+        if (P.xg)
+            return launch_timed(roll_linear_split<T, NT, NU, true>, grid, block, 0, s, ev, P, x0,
+                                knots, ld, ncand, cost);
+        return launch_timed(roll_linear_split<T, NT, NU, false>, grid, block, 0, s, ev, P, x0,
+                            knots, ld, ncand, cost);
+    }
     const dim3 grid((unsigned)((tiles + WPB - 1) / WPB)), block(64 * WPB);
     if (P.xg)
         return launch_timed(roll_linear_mfma<T, NT, NU, WPB, true>, grid, block, 0, s, ev, P, x0,

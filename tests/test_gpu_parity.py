@@ -242,6 +242,24 @@ def test_solve_fp64_matches_oracle_over_ticks(oracle_lib, E):
         x = oracle_lib.step(prob, x, uo, noise[tick])
 
 
+@pytest.mark.parametrize("d,T,p", [(9, 30, 6), (20, 25, 5)])
+def test_solve_fp64_generating_rollout_matches_oracle(oracle_lib, E, d, T, p):
+    # linear chains of more than 16 states generate each tile's children
+    # inside the rollout kernel: whole FP64 ticks must still follow the
+    # oracle (ragged last tile: pop is not a multiple of 16)
+    prob = W.linear_chain(d, T, p, seed=d)
+    ga = W.GA(pop=600, n_elite=24, generations=3, sigma=0.1, seed=11)
+    solver = E.Solver(E.DeviceProblem(prob, F64), ga)
+    osolver = oracle_lib.Solver(prob, ga)
+    x = W.draw_x0(prob.n, 1)
+    for tick in range(3):
+        u, J = solver.solve(as_dev(x, F64), tick)
+        uo, Jo, _ = osolver.solve(x, tick)
+        np.testing.assert_allclose(u.cpu().numpy(), uo, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(float(J.item()), Jo, rtol=1e-9)
+        x = oracle_lib.step(prob, x, uo)
+
+
 def test_solve_fp32_one_generation_matches_oracle(oracle_lib, E):
     prob, ga = W.config_c2(0)
     prob = rounded(prob, F32)
