@@ -41,9 +41,10 @@ template <typename T, int NT, int NU, int WPB>
 __global__ __launch_bounds__(64 * WPB) void batch_roll_linear(const BatchSlot<T> *__restrict__ slots,
                                                               const int *__restrict__ items,
                                                               int64_t pop, int g) {
-    const BatchSlot<T> &S = slots[items[blockIdx.y]];
+    const int64_t w = xcd_swizzle_2d();
+    const BatchSlot<T> &S = slots[items[w / gridDim.x]];
     linear_tile<T, NT, NU, true>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
-                                 (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6));
+                                 (w % gridDim.x) * WPB + (threadIdx.x >> 6));
 }
 
 // linear problems of more than 16 states: the M-split form, one workgroup
@@ -51,8 +52,10 @@ __global__ __launch_bounds__(64 * WPB) void batch_roll_linear(const BatchSlot<T>
 template <typename T, int NT, int NU>
 __global__ __launch_bounds__(64 * NT) void batch_roll_linear_split(
     const BatchSlot<T> *__restrict__ slots, const int *__restrict__ items, int64_t pop, int g) {
-    const BatchSlot<T> &S = slots[items[blockIdx.y]];
-    linear_tile_split<T, NT, NU, true>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost, blockIdx.x);
+    const int64_t w = xcd_swizzle_2d();
+    const BatchSlot<T> &S = slots[items[w / gridDim.x]];
+    linear_tile_split<T, NT, NU, true>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
+                                       w % gridDim.x);
 }
 
 template <typename T, int DMAX>
@@ -74,8 +77,9 @@ template <typename T, int J>
 __global__ __launch_bounds__(256) void batch_roll_chain_rows(const BatchSlot<T> *__restrict__ slots,
                                                              const int *__restrict__ items,
                                                              int64_t pop, int g) {
-    const BatchSlot<T> &S = slots[items[blockIdx.y]];
-    const int64_t cand0 = (int64_t)blockIdx.x * 16;
+    const int64_t w = xcd_swizzle_2d();
+    const BatchSlot<T> &S = slots[items[w / gridDim.x]];
+    const int64_t cand0 = (w % gridDim.x) * 16;
     if (cand0 + (threadIdx.x >> 6) * 4 >= pop) return;  // whole wavefront past the end
     chain_row_candidate<T, J>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
                               cand0 + (threadIdx.x >> 4), threadIdx.x & 15);
@@ -129,7 +133,7 @@ static void go_batch_linear(const BatchSlot<float> *slots, const int *items, int
                             int64_t pop, int g, hipStream_t s) {
     constexpr int WPB = 4;
     const int64_t tiles = (pop + 15) / 16;
-    if (NT > 1) {
+    if (NT > 1 && tiles * count < SPLIT_MAX_TILES) {
         hipLaunchKernelGGL((batch_roll_linear_split<float, NT, NU>),
                            dim3((unsigned)tiles, (unsigned)count), dim3(64 * NT), 0, s, slots,
                            items, pop, g);

@@ -152,6 +152,23 @@ struct Limits {
 };
 
 // Optional start / stop events stamped by a kernel's dispatch.
+// Workgroups are dispatched to the chip's 8 XCDs round-robin (linear
+// workgroup b on XCD b mod 8), and each XCD has its own L2.  The rollout
+// kernels map workgroup b to work item xcd_swizzle(b, nb) instead of b, so
+// that each XCD gets one contiguous range of tiles: neighbouring tiles share
+// cache lines of the candidate-innermost knot layout, which are then fetched
+// by one L2 instead of two.  A bijection of [0, nb).
+__device__ inline int64_t xcd_swizzle(int64_t b, int64_t nb) {
+    constexpr int64_t NX = 8;
+    const int64_t q = nb / NX, r = nb % NX, x = b % NX;
+    return x * q + (x < r ? x : r) + b / NX;
+}
+// The same for a 2-D grid (x fastest): returns the swizzled linear index.
+__device__ inline int64_t xcd_swizzle_2d() {
+    const int64_t nb = (int64_t)gridDim.x * gridDim.y;
+    return xcd_swizzle((int64_t)blockIdx.y * gridDim.x + blockIdx.x, nb);
+}
+
 struct Events {
     hipEvent_t start = nullptr, stop = nullptr;
 };

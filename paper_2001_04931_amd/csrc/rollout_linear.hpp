@@ -182,7 +182,11 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
             const T e = X[mt][v] - Xg[mt][v];
             S[mt][v] = -(e * e);
         }
-    T Ju = 0;
+    // input cost, input slice s summed into Ju[s mod NT] (the share of
+    // M-tile s mod NT in the M-split form)
+    T Ju[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) Ju[mt] = 0;
     int k = 0;
     // segment a: steps with idx1 = a, knots ua = U_a, ub = U_min(a+1, p-1)
     // (ub of the last segment is unused: c = 0 there); un = U_{a+2}
@@ -208,17 +212,21 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
                 acc[mt][0] = Va[mt] + c * dV[mt];
                 acc[mt][1] = v4{0, 0, 0, 0};
             }
-            // slot (t, v): the MFMA of every M-tile for that K slice, then one
-            // row of the stage-cost sums, so VALU and matrix work alternate
+            // slot (i, v): for every M-tile mt the MFMA of K slice (t, v),
+            // t = (mt + i) mod NT (the K order of the M-split form, so that
+            // both forms round identically), then one row of the stage-cost
+            // sums, so VALU and matrix work alternate
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int i = 0; i < NT; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
 #pragma unroll
-                    for (int mt = 0; mt < NT; ++mt)
+                    for (int mt = 0; mt < NT; ++mt) {
+                        const int t = (mt + i) % NT;
                         acc[mt][v & 1] = Mfma<T>::op(aX[mt][4 * t + v], X[t][v], acc[mt][v & 1]);
-                    const T e = HAS_XG ? X[t][v] - Xg[t][v] : X[t][v];
-                    S[t][v] += e * e;
+                    }
+                    const T e = HAS_XG ? X[i][v] - Xg[i][v] : X[i][v];
+                    S[i][v] += e * e;
                     __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
@@ -230,7 +238,7 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
         for (int s = 0; s < NU; ++s) {
             const T e0 = ua[s] - Ug[s];
             const T du = (a == p - 1) ? (T)0 : ub[s] - ua[s];
-            Ju += Rw[s] * ((T)nseg * e0 * e0 + (T)2 * e0 * du * C1 + du * du * C2);
+            Ju[s % NT] += Rw[s] * ((T)nseg * e0 * e0 + (T)2 * e0 * du * C1 + du * du * C2);
         }
         // next segment's second knot response, from knot a+2
 #pragma unroll
@@ -245,10 +253,13 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
         if (a + 2 < p) segment(a + 2, K2, K3, K0);
         if (a + 3 < p) segment(a + 3, K3, K0, K1);
     }
-    // x_T: stage and terminal weights; weights applied to the row sums
-    T J = Ju;
+    // x_T: stage and terminal weights; weights applied to the row sums.
+    // Per M-tile partial costs, reduced over the tile's rows and then summed
+    // in tile order, as the M-split form does.
+    T J = 0;
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt)
+    for (int mt = 0; mt < NT; ++mt) {
+        T Jm = Ju[mt];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * mt + Mfma<T>::row(grp, v);
@@ -256,10 +267,12 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
             const T e = X[mt][v] - Xg[mt][v];
             const T q = in ? P.q[row] : (T)0;
             const T qf = (in && P.qf) ? P.qf[row] : (T)0;
-            J += q * (S[mt][v] + e * e) + qf * e * e;
+            Jm += q * (S[mt][v] + e * e) + qf * e * e;
         }
-    J += __shfl_xor(J, 16, 64);
-    J += __shfl_xor(J, 32, 64);
+        Jm += __shfl_xor(Jm, 16, 64);
+        Jm += __shfl_xor(Jm, 32, 64);
+        J = mt == 0 ? Jm : J + Jm;
+    }
     if (grp == 0 && valid) cost[cand] = J;
 }
 
@@ -270,7 +283,7 @@ __global__ __launch_bounds__(64 * WPB) void roll_linear_mfma(ProbView<T> P,
                                                              int64_t ld, int64_t ncand,
                                                              T *__restrict__ cost) {
     linear_tile<T, NT, NU, HAS_XG>(P, x0, knots, ld, ncand, cost,
-                                   (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6));
+                                   xcd_swizzle(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6));
 }
 
 // ---------------------------------------------------------------------------
@@ -492,7 +505,8 @@ __global__ __launch_bounds__(64 * NT) void roll_linear_split(ProbView<T> P,
                                                              const T *__restrict__ knots,
                                                              int64_t ld, int64_t ncand,
                                                              T *__restrict__ cost) {
-    linear_tile_split<T, NT, NU, HAS_XG>(P, x0, knots, ld, ncand, cost, blockIdx.x);
+    linear_tile_split<T, NT, NU, HAS_XG>(P, x0, knots, ld, ncand, cost,
+                                         xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
 // Launch through hipExtLaunchKernelGGL when timing events are given: the
@@ -508,12 +522,17 @@ static hipError_t launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipS
     return hipGetLastError();
 }
 
+// The M-split form (NT wavefronts per tile) when the one-wavefront form
+// would leave SIMDs idle: fewer tiles than the chip's 1024 SIMDs.  The two
+// forms round identically, so the choice never changes a result.
+constexpr int64_t SPLIT_MAX_TILES = 1024;
+
 template <typename T, int NT, int NU>
 static hipError_t go_linear(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
                             int64_t ld, T *cost, hipStream_t s, const Events &ev) {
     constexpr int WPB = 4;
     const int64_t tiles = (ncand + 15) / 16;
-    if (NT > 1) {
+    if (NT > 1 && tiles < SPLIT_MAX_TILES) {
         const dim3 grid((unsigned)tiles), block(64 * NT);
         if (P.xg)
             return launch_timed(roll_linear_split<T, NT, NU, true>, grid, block, 0, s, ev, P, x0,

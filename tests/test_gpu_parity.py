@@ -71,6 +71,32 @@ def test_rollout_linear_chain_shapes(oracle_lib, E, dtype, d):
     check_costs(oracle_lib, E, prob, ncand=16 * 5 + 7, ld=100, dtype=dtype, seed=d)
 
 
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("d", [14, 21, 36])
+def test_rollout_linear_forms_round_identically(oracle_lib, E, dtype, d):
+    # a launch of fewer than 1024 tiles runs the M-split form, a larger one
+    # the one-wavefront form: the same candidates must get the same bits
+    prob = W.linear_chain(d, 23, 4, seed=d).cast(npdt(dtype))
+    big = 16 * 1024 + 5
+    x0 = W.draw_x0(prob.n, d)
+    knots = W.draw_knots(prob, big, d + 1)
+    dp = E.DeviceProblem(prob, dtype)
+    K = torch.as_tensor(knots, dtype=dtype).cuda()
+    X0 = torch.as_tensor(x0, dtype=dtype).cuda()
+    small = torch.zeros(300, dtype=dtype, device="cuda")
+    full = torch.zeros(big, dtype=dtype, device="cuda")
+    E.empc_rollout_cost(dp, X0, K, 300, big, small)
+    E.empc_rollout_cost(dp, X0, K, big, big, full)
+    torch.cuda.synchronize()
+    assert torch.equal(small, full[:300])
+    # and both against the oracle on a sample
+    idx = np.arange(0, big, 997)
+    want = oracle_lib.rollout_cost(prob, x0.astype(npdt(dtype)).astype(np.float64),
+                                   np.ascontiguousarray(knots[:, idx].astype(npdt(dtype))
+                                                        .astype(np.float64)), len(idx))
+    np.testing.assert_allclose(full.cpu().numpy()[idx], want, rtol=RTOL[dtype])
+
+
 def test_rollout_linear_c2_shape(oracle_lib, E):
     prob, _ = W.config_c2(0)
     check_costs(oracle_lib, E, prob, ncand=131, ld=131, dtype=F32)
