@@ -174,20 +174,24 @@ __global__ __launch_bounds__(256) void population_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Selection: one workgroup of 256 threads (4 wavefronts; a small group keeps
-// its barriers cheap, and 4096..16384 keys need no more).  Thread t owns the
-// contiguous index range [t*per, (t+1)*per), per = ceil(pop / 256), with the
-// sortable keys cached in registers when per <= CACHE.
-//  1. radix select of the k-th smallest key, 8 bits per pass.  Costs of a
-//     population cluster, so most keys of a pass hit the same few bins: the
-//     histogram is replicated 16 times (lane % 16 picks the replica, replicas
-//     257 words apart so that one bin of different replicas falls in
-//     different LDS banks), which bounds same-address atomics to 4 lanes;
-//     two histogram buffers alternate so that clearing the next pass's
-//     buffer needs no barrier of its own;
+// Selection (parent selection: the numParents lowest costs).  One workgroup
+// of 256 threads (4 wavefronts; a small group keeps its barriers cheap, and
+// 4096..16384 keys need no more).  Thread t owns the contiguous index range
+// [t per, (t+1) per), per = ceil(pop / 256), with the sortable keys cached
+// in registers when per <= CACHE (loaded 16 bytes at a time).
+//  1. radix select of the k-th smallest key, 8 bits per pass, starting below
+//     the bytes that every key shares (from the block's min and max key).
+//     Costs of a population cluster, so most keys of a pass hit the same few
+//     bins: the histogram is replicated 16 times (lane % 16 picks the
+//     replica, replicas 257 words apart so that one bin of different
+//     replicas falls in different LDS banks), which bounds same-address
+//     atomics to 4 lanes; two histogram buffers alternate so that clearing
+//     the next pass's buffer needs no barrier of its own, and every
+//     wavefront scans the bin totals itself, so a pass has two barriers;
 //  2. keys below the threshold are taken, keys equal to it by ascending index
-//     until k are taken; two block prefix sums place every taken index, so
-//     the elite list comes out in ascending index order;
+//     until k are taken; one block prefix sum of the packed (below, equal)
+//     counts places every taken index, so the elite list comes out in
+//     ascending index order;
 //  3. best = lowest (key, index) among the elites; elite indices, costs,
 //     optionally the elite knot rows, u* = knot 0 of the best, the best cost
 //     and the warm-start flag.
@@ -223,9 +227,27 @@ __device__ inline int block_excl_scan(int v, int *wsum, int *total) {
         base += w < wave ? x : 0;
         tot += x;
     }
-    __syncthreads();
     *total = tot;
     return base + incl - v;
+}
+
+template <typename K>
+__device__ inline K wave_min(K v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const K u = __shfl_xor(v, o, 64);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+template <typename K>
+__device__ inline K wave_max(K v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const K u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
 }
 
 // Inverse of sort_key (NaN keys decode to a NaN, -0 to +0).
@@ -246,25 +268,35 @@ __device__ __forceinline__ void select_body(
     __shared__ int hist[2][HREP * HSTRIDE];
     __shared__ int tot[256];
     __shared__ int wsum[SEL_WAVES];
-    __shared__ int s_digit, s_rem;
+    __shared__ K s_lo[SEL_WAVES], s_hi[SEL_WAVES];
     __shared__ int64_t s_elite[Limits::MAX_ELITE];
     __shared__ K s_ekey[Limits::MAX_ELITE];
     __shared__ int s_best_slot;
     const int tid = threadIdx.x, lane = tid & 63;
-    for (int s = tid; s < k; s += SEL_THREADS) {
-        s_elite[s] = 0;
-        s_ekey[s] = ~(K)0;
-    }
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int b = tid; b < HREP * HSTRIDE; b += SEL_THREADS) hist[0][b] = 0;
 
     const int64_t per = (pop + SEL_THREADS - 1) / SEL_THREADS;
     const int64_t i0 = (int64_t)tid * per;
     const int64_t nmine = per < pop - i0 ? per : (pop - i0 > 0 ? pop - i0 : 0);
     K cache[CACHE > 0 ? CACHE : 1];
-    if (CACHE > 0) {
+    if constexpr (CACHE > 0) {
+        typedef T v4 __attribute__((ext_vector_type(4)));
+        const bool vec = CACHE % 4 == 0 && nmine == CACHE &&
+                         (reinterpret_cast<uintptr_t>(cost + i0) & (sizeof(v4) - 1)) == 0;
+        if (vec) {
 #pragma unroll
-        for (int r = 0; r < (CACHE > 0 ? CACHE : 1); ++r)
-            cache[r] = r < nmine ? sort_key(cost[i0 + r]) : ~(K)0;
+            for (int q = 0; q < CACHE / 4; ++q) {
+                const v4 c = reinterpret_cast<const v4 *>(cost + i0)[q];
+                cache[4 * q + 0] = sort_key(c.x);
+                cache[4 * q + 1] = sort_key(c.y);
+                cache[4 * q + 2] = sort_key(c.z);
+                cache[4 * q + 3] = sort_key(c.w);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < CACHE; ++r) cache[r] = r < nmine ? sort_key(cost[i0 + r]) : ~(K)0;
+        }
     }
     // visit this thread's keys in index order; with the cache every index
     // is a compile-time constant, so the keys stay in registers
@@ -277,12 +309,36 @@ __device__ __forceinline__ void select_body(
             for (int64_t r = 0; r < nmine; ++r) f(r, sort_key(cost[i0 + r]));
         }
     };
+    {  // the block's smallest and largest key
+        K lo = ~(K)0, hi = 0;
+        for_each_key([&](int64_t, K key) {
+            lo = key < lo ? key : lo;
+            hi = key > hi ? key : hi;
+        });
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        if (lane == 0) {
+            s_lo[wave] = lo;
+            s_hi[wave] = hi;
+        }
+    }
     __syncthreads();
-
-    K prefix = 0, mask = 0;
+    K lo = s_lo[0], hi = s_hi[0];
+#pragma unroll
+    for (int w = 1; w < SEL_WAVES; ++w) {
+        lo = s_lo[w] < lo ? s_lo[w] : lo;
+        hi = s_hi[w] > hi ? s_hi[w] : hi;
+    }
+    // bytes every key shares need no pass: start at the highest byte where
+    // the smallest and the largest key differ (byte 0 if they are equal)
+    constexpr int BITS = (int)sizeof(K) * 8;
+    int top = BITS - 8;
+    while (top > 0 && (((lo ^ hi) >> top) & 255) == 0) top -= 8;
+    K mask = (~(K)0 << top) << 8;  // the bytes above `top` (two shifts: no shift by BITS)
+    K prefix = lo & mask;
     int remaining = k;
     int buf = 0;
-    for (int shift = (int)sizeof(K) * 8 - 8; shift >= 0; shift -= 8) {
+    for (int shift = top; shift >= 0; shift -= 8) {
         int *myh = hist[buf] + (lane & (HREP - 1)) * HSTRIDE;
         for_each_key([&](int64_t, K key) {
             if ((key & mask) == prefix) atomicAdd(&myh[(int)((key >> shift) & 255)], 1);
@@ -297,59 +353,53 @@ __device__ __forceinline__ void select_body(
             tot[tid] = sum;
         }
         __syncthreads();
-        if (tid < 64) {
-            // lane owns bins 4*lane .. 4*lane+3
-            const int h0 = tot[4 * tid], h1 = tot[4 * tid + 1], h2 = tot[4 * tid + 2],
-                      h3 = tot[4 * tid + 3];
-            const int own = h0 + h1 + h2 + h3;
-            const int incl = wave_incl_scan(own);
-            const int excl = incl - own;
-            const unsigned long long hit = __ballot(incl >= remaining);
-            const int first = __ffsll((long long)hit) - 1;
-            if (tid == first) {
-                // first of the lane's four bins where the running count
-                // reaches `remaining`
-                int cum = excl, q = 3;
-                if (cum + h0 >= remaining) {
-                    q = 0;
-                } else if (cum + h0 + h1 >= remaining) {
-                    q = 1;
-                    cum += h0;
-                } else if (cum + h0 + h1 + h2 >= remaining) {
-                    q = 2;
-                    cum += h0 + h1;
-                } else {
-                    cum += h0 + h1 + h2;
-                }
-                s_digit = 4 * tid + q;
-                s_rem = remaining - cum;
-            }
+        // every wavefront finds the digit itself: lane owns bins 4 lane .. +3
+        const int h0 = tot[4 * lane], h1 = tot[4 * lane + 1], h2 = tot[4 * lane + 2],
+                  h3 = tot[4 * lane + 3];
+        const int own = h0 + h1 + h2 + h3;
+        const int incl = wave_incl_scan(own);
+        const unsigned long long hit = __ballot(incl >= remaining);
+        const int first = __ffsll((long long)hit) - 1;
+        int cum = incl - own, q = 3;
+        if (cum + h0 >= remaining) {
+            q = 0;
+        } else if (cum + h0 + h1 >= remaining) {
+            q = 1;
+            cum += h0;
+        } else if (cum + h0 + h1 + h2 >= remaining) {
+            q = 2;
+            cum += h0 + h1;
+        } else {
+            cum += h0 + h1 + h2;
         }
-        __syncthreads();
-        prefix |= (K)s_digit << shift;
+        const int digit = __builtin_amdgcn_readlane(4 * lane + q, first);
+        remaining -= __builtin_amdgcn_readlane(cum, first);
+        prefix |= (K)digit << shift;
         mask |= (K)255 << shift;
-        remaining = s_rem;
         buf ^= 1;
     }
     const K thr = prefix;
-    // ordered pass over this thread's contiguous range
-    int my_eq = 0;
-    for_each_key([&](int64_t, K key) { my_eq += key == thr ? 1 : 0; });
-    int eq_tot;
-    const int eq_base = block_excl_scan(my_eq, wsum, &eq_tot);
-    int my_sel = 0;
-    {
-        int e = eq_base;
-        for_each_key([&](int64_t, K key) {
-            const bool eq = key == thr;
-            my_sel += (key < thr || (eq && e < remaining)) ? 1 : 0;
-            e += eq ? 1 : 0;
-        });
+    // ordered pass over this thread's contiguous range: one scan of the
+    // packed counts (below the threshold in the low half, equal in the high)
+    int my_lt = 0, my_eq = 0;
+    for_each_key([&](int64_t, K key) {
+        my_lt += key < thr ? 1 : 0;
+        my_eq += key == thr ? 1 : 0;
+    });
+    int packed_tot, lt_base, eq_base;
+    if (CACHE > 0) {  // per-thread counts <= 64, block totals < 2^16
+        const int base = block_excl_scan(my_lt | (my_eq << 16), wsum, &packed_tot);
+        lt_base = base & 0xFFFF;
+        eq_base = base >> 16;
+    } else {
+        int t1;
+        lt_base = block_excl_scan(my_lt, wsum, &t1);
+        __syncthreads();
+        eq_base = block_excl_scan(my_eq, wsum, &t1);
     }
-    int sel_tot;
-    int pos = block_excl_scan(my_sel, wsum, &sel_tot);
     {
         int e = eq_base;
+        int pos = lt_base + min(eq_base, remaining);
         for_each_key([&](int64_t r, K key) {
             const bool eq = key == thr;
             if (key < thr || (eq && e < remaining)) {

@@ -245,6 +245,51 @@ def test_selection_ties_nan_inf(oracle_lib, E, dtype):
         assert best == want_best
 
 
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_selection_degenerate_and_large(oracle_lib, E, dtype):
+    # all keys equal; ties at the threshold spread over every quarter of the
+    # index range; all NaN; a population above the register-cached sizes
+    prob = W.linear_chain(2, 10, 3, seed=0)
+    rng = np.random.default_rng(3)
+    cases = [
+        (np.full(4096, 2.5), 64),
+        (np.r_[np.zeros(10), np.ones(4086)], 64),
+        (np.where(np.arange(4096) % 97 == 0, 0.5, 1.0), 200),
+        (np.full(300, np.nan), 17),
+        (np.round(rng.normal(0, 1, 20000), 2), 100),
+        (rng.permutation(np.arange(70001, dtype=np.float64)), 256),
+    ]
+    for cost, k in cases:
+        pop = len(cost)
+        cost = cost.astype(npdt(dtype)).astype(np.float64)
+        ga = W.GA(pop=pop, n_elite=k, generations=1, sigma=0.1, seed=1)
+        knots = W.draw_knots(prob, pop, 1)
+        _, eidx, best = gpu_generation(E, prob, ga, knots, cost, 0, 0, dtype)
+        want_idx, want_best = oracle_lib.select(cost, k)
+        np.testing.assert_array_equal(eidx, want_idx)
+        assert best == want_best
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_selection_random_bands(oracle_lib, E, dtype):
+    # costs of a real population sit in a narrow band, so the radix passes
+    # start below the bytes every key shares: random pops, k and bands
+    prob = W.linear_chain(2, 10, 3, seed=0)
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        pop = int(rng.integers(1, 5000)) if trial % 5 else 4096
+        k = int(rng.integers(1, min(pop, 256) + 1))
+        lo = float(rng.choice([0.5, 40.0, 403.0, 1e4]))
+        width = lo * float(rng.choice([1e-6, 1e-3, 0.1, 0.25, 3.0]))
+        cost = (lo + width * rng.random(pop)).astype(npdt(dtype)).astype(np.float64)
+        ga = W.GA(pop=pop, n_elite=k, generations=1, sigma=0.1, seed=1)
+        knots = W.draw_knots(prob, pop, 1)
+        _, eidx, best = gpu_generation(E, prob, ga, knots, cost, 0, 0, dtype)
+        want_idx, want_best = oracle_lib.select(cost, k)
+        np.testing.assert_array_equal(eidx, want_idx, err_msg="trial %d" % trial)
+        assert best == want_best, trial
+
+
 # ---------------------------------------------------------------------------
 # solve
 
