@@ -1,11 +1,15 @@
 // Adjoint gradient of the rollout cost with respect to the knots, and Adam
 // refinement built on it (gfx950).
 //
-// One wavefront (one workgroup of 64 lanes) per candidate.  Linear model:
-// lane i owns state i (n <= 64) and, for i < m, input i; the state vector is
-// exchanged through LDS each step and A_d, B_d sit in LDS.  Pendulum chain:
-// lane j owns joint j (d <= 64); the cumulative angles, gravity torques and
-// the adjoint's prefix / suffix sums are wavefront scans.
+// One wavefront (one workgroup of 64 lanes) per candidate: a few dozen
+// elites each run a sequential chain of 3T dependent steps per Adam step, so
+// the latency of one step is what counts.  Linear model: lane i owns state i
+// (n <= 64) and, for i < m, input i, and holds row i and column i of A_d and
+// of B_d in registers; the other lanes' states (or adjoints) are read with
+// v_readlane, so a step touches no LDS and needs no barrier.  Pendulum
+// chain: lane j owns joint j (d <= 64); the cumulative angles, gravity
+// torques and the adjoint's prefix / suffix sums are wavefront scans on DPP
+// row shifts.
 //
 // With lambda_k = dJ/dx_k:
 //   lambda_T = 2 (Q + Q_f)(x_T - g),
@@ -19,35 +23,6 @@
 #include "internal.hpp"
 
 namespace empc {
-
-template <typename T>
-__device__ inline T wsum(T v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-// inclusive prefix sum over lanes 0..63
-template <typename T>
-__device__ inline T scan_up(T v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const T y = __shfl_up(v, o, 64);
-        if (lane >= o) v += y;
-    }
-    return v;
-}
-// inclusive suffix sum over lanes 63..0
-template <typename T>
-__device__ inline T scan_down(T v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const T y = __shfl_down(v, o, 64);
-        if (lane + o < 64) v += y;
-    }
-    return v;
-}
 
 template <typename T>
 __device__ inline T sin_f(T x);
@@ -65,7 +40,7 @@ __device__ inline double cos_f<double>(double x) { return cos(x); }
 // LDS plan (element counts), shared with the host-side size check.
 struct GradPlan {
     int S, nchk;
-    size_t oA, oB, oU, oG, oM1, oM2, oX, oUin, oChk, oSeg, total;
+    size_t oU, oG, oM1, oM2, oXb, oUb, oChk, oSeg, total;
 };
 inline GradPlan grad_plan(int model, int n, int m, int T, int p) {
     GradPlan g;
@@ -74,14 +49,12 @@ inline GradPlan grad_plan(int model, int n, int m, int T, int p) {
     g.nchk = (T + g.S - 1) / g.S;
     const size_t pm = (size_t)p * m;
     size_t o = 0;
-    g.oA = o; o += model == EMPC_LINEAR ? (size_t)n * n : 0;
-    g.oB = o; o += model == EMPC_LINEAR ? (size_t)n * m : 0;
     g.oU = o; o += pm;
     g.oG = o; o += pm;
     g.oM1 = o; o += pm;
     g.oM2 = o; o += pm;
-    g.oX = o; o += 64;
-    g.oUin = o; o += 64;
+    g.oXb = o; o += 64;  // broadcast slots: states (or adjoints)
+    g.oUb = o; o += 64;  // and inputs of the current step
     g.oChk = o; o += (size_t)g.nchk * n;
     g.oSeg = o; o += (size_t)g.S * n;
     g.total = o;
@@ -95,8 +68,10 @@ struct Lane {
     T cg, invI, kst, dmp, wq, wv, wqf, wvf, gq, gv, wr, gu;  // chain joint j
 };
 
-template <typename T>
-__global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, int model, GradPlan G,
+// LIN: linear model with NMAX >= n, m (register operand length); else the
+// pendulum chain (NMAX unused).
+template <typename T, bool LIN, int NMAX>
+__global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
                                                      const T *__restrict__ x0,
                                                      const T *__restrict__ knots, int64_t ld,
                                                      T *__restrict__ dJ, T *__restrict__ cost,
@@ -104,19 +79,25 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, int model, G
                                                      T *__restrict__ cost_io) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
-    T *sA = sm + G.oA, *sB = sm + G.oB, *sU = sm + G.oU, *sG = sm + G.oG;
-    T *sM1 = sm + G.oM1, *sM2 = sm + G.oM2, *sX = sm + G.oX, *sUin = sm + G.oUin;
+    T *sU = sm + G.oU, *sG = sm + G.oG;
+    T *sM1 = sm + G.oM1, *sM2 = sm + G.oM2;
     T *sChk = sm + G.oChk, *sSeg = sm + G.oSeg;
+    T *sXb = sm + G.oXb, *sUb = sm + G.oUb;
     const int lane = threadIdx.x;
     const int64_t cand = blockIdx.x;
     const int n = P.n, m = P.m, pm = P.p * P.m, Tn = P.Tn, S = G.S;
-    const bool lin = model == EMPC_LINEAR;
+    constexpr bool lin = LIN;
     const bool refine = steps > 0;
 
-    // ---- load
-    if (lin) {
-        for (int t = lane; t < n * n; t += 64) sA[t] = P.Ad[t];
-        for (int t = lane; t < n * m; t += 64) sB[t] = P.Bd[t];
+    // ---- load: row and column `lane` of A_d and B_d (zero padded)
+    constexpr int NR = LIN ? NMAX : 1;
+    T aRow[NR], aCol[NR], bRow[NR], bCol[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        aRow[j] = (LIN && lane < n && j < n) ? P.Ad[lane * n + j] : (T)0;
+        aCol[j] = (LIN && lane < n && j < n) ? P.Ad[j * n + lane] : (T)0;
+        bRow[j] = (LIN && lane < n && j < m) ? P.Bd[lane * m + j] : (T)0;
+        bCol[j] = (LIN && lane < m && j < n) ? P.Bd[j * m + lane] : (T)0;
     }
     const T *src = refine ? knots_io : knots;
     for (int j = lane; j < pm; j += 64) {
@@ -161,28 +142,40 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, int model, G
 
     const int d = m;  // chain joints
     // lane-owned state: linear xi (state lane); chain (q, v) of joint lane
-    auto input_at = [&](int k) -> T {  // lane's own input at step k (lane < m)
-        const Knot kn = knot_at(Tn, P.p, k);
+    auto input_kn = [&](const Knot &kn) -> T {  // lane's own input (lane < m)
         const T c = (T)kn.rem / (T)kn.den;
         if (lane >= m) return (T)0;
         return ((T)1 - c) * sU[kn.a * m + lane] + c * sU[kn.b * m + lane];
     };
-    // one linear step: xi <- A x + B u + w (u of this step in sUin)
-    auto lin_step = [&](T xi) -> T {
-        if (lane < n) sX[lane] = xi;
-        __syncthreads();
-        T s = L.w;
-        if (lane < n) {
-            for (int j = 0; j < n; ++j) s += sA[lane * n + j] * sX[j];
-            for (int j = 0; j < m; ++j) s += sB[lane * m + j] * sUin[j];
+    auto input_at = [&](int k) -> T { return input_kn(knot_at(Tn, P.p, k)); };
+    // sum_j c[j] v_j with v_j published by lane j: one LDS store per lane,
+    // then every lane reads the vector back 16 bytes at a time (broadcast
+    // reads).  The LDS operations of a wavefront complete in order, so the
+    // reads see the stores; the next store comes after these values are used.
+    typedef T vec __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int VW = 16 / sizeof(T);
+    auto bcast_dot = [&](T *slot, T v, const T *c, T acc) -> T {
+        slot[lane] = v;
+#pragma unroll
+        for (int j = 0; j < NR; j += VW) {
+            const vec w = *reinterpret_cast<const vec *>(slot + j);
+#pragma unroll
+            for (int q = 0; q < VW; ++q) acc += c[j + q] * w[q];
         }
-        __syncthreads();
-        return lane < n ? s : (T)0;
+        return acc;
+    };
+    // one linear step: xi <- A x + (B u + w) (lane j < m holds u_j); the
+    // input part does not depend on the state, so its LDS round trip and
+    // products overlap the state's
+    auto lin_step = [&](T xi, T u) -> T {
+        const T bu = bcast_dot(sUb, lane < m ? u : (T)0, bRow, L.w);
+        const T ax = bcast_dot(sXb, lane < n ? xi : (T)0, aRow, (T)0);
+        return lane < n ? ax + bu : (T)0;
     };
     auto chain_step = [&](T &q, T &v, T u) {
-        const T phi = scan_up(q);
+        const T phi = wave_scan_up<T>(q);
         const T sg = L.cg * sin_f<T>(phi);
-        const T Gj = scan_down(sg);
+        const T Gj = wave_scan_down<T>(sg);
         const T acc = (u - L.kst * q - L.dmp * v - Gj) * L.invI;
         v = v + P.dt * acc;
         q = q + P.dt * v;
@@ -205,8 +198,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, int model, G
             }
             const T u = input_at(k);
             if (lin) {
-                if (lane < m) sUin[lane] = u;
-                xi = lin_step(xi);
+                xi = lin_step(xi, u);
                 const T e = L.xg - xi, eu = L.ug - u;
                 J += L.q * e * e + L.r * eu * eu;
             } else {
@@ -222,7 +214,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, int model, G
             const T eq = L.gq - qj, ev = L.gv - vj;
             J += L.wqf * eq * eq + L.wvf * ev * ev;
         }
-        return wsum(J);
+        return wave_total<T>(J);
     };
 
     // backward pass from the final state: fills sG with dJ/dknots
@@ -236,6 +228,16 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, int model, G
             lv = (T)2 * (L.wv + L.wvf) * (vT - L.gv);
         }
         __syncthreads();
+        // dJ/du_k goes to knots a and b of step k with weights 1-c and c;
+        // summed in registers while the knot pair stays, then added to sG
+        int cur_a = -1, cur_b = -1;
+        T gA = 0, gB = 0;
+        auto flush = [&]() {
+            if (cur_a >= 0 && lane < m) {
+                sG[cur_a * m + lane] += gA;
+                sG[cur_b * m + lane] += gB;
+            }
+        };
         for (int sg = G.nchk - 1; sg >= 0; --sg) {
             const int k0 = sg * S, k1 = min(k0 + S, Tn);
             // recompute x_k0 .. x_{k1-1} into sSeg
@@ -256,8 +258,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, int model, G
                 if (k + 1 < k1) {
                     const T u = input_at(k);
                     if (lin) {
-                        if (lane < m) sUin[lane] = u;
-                        xi = lin_step(xi);
+                        xi = lin_step(xi, u);
                     } else {
                         chain_step(qj, vj, u);
                     }
@@ -267,17 +268,21 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, int model, G
             for (int k = k1 - 1; k >= k0; --k) {
                 const Knot kn = knot_at(Tn, P.p, k);
                 const T c = (T)kn.rem / (T)kn.den;
-                const T u = input_at(k);
+                const T u = input_kn(kn);
                 T gu;
                 if (lin) {
-                    if (lane < n) sX[lane] = lam;
-                    __syncthreads();
+                    // B^T lambda and A^T lambda, lambda_i published by lane i
                     T bu = 0, ax = 0;
-                    if (lane < m)
-                        for (int i = 0; i < n; ++i) bu += sB[i * m + lane] * sX[i];
-                    if (lane < n)
-                        for (int i = 0; i < n; ++i) ax += sA[i * n + lane] * sX[i];
-                    __syncthreads();
+                    sXb[lane] = lane < n ? lam : (T)0;
+#pragma unroll
+                    for (int i = 0; i < NR; i += VW) {
+                        const vec w = *reinterpret_cast<const vec *>(sXb + i);
+#pragma unroll
+                        for (int q = 0; q < VW; ++q) {
+                            bu += bCol[i + q] * w[q];
+                            ax += aCol[i + q] * w[q];
+                        }
+                    }
                     gu = (T)2 * L.r * (u - L.ug) + bu;
                     if (k >= 1 && lane < n) {
                         const T xk = sSeg[(k - k0) * n + lane];
@@ -286,13 +291,13 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, int model, G
                 } else {
                     const T qk = lane < d ? sSeg[(k - k0) * n + lane] : (T)0;
                     const T vk = lane < d ? sSeg[(k - k0) * n + d + lane] : (T)0;
-                    const T phi = scan_up(qk);
-                    const T Sv = scan_down(L.cg * cos_f<T>(phi));
+                    const T phi = wave_scan_up<T>(qk);
+                    const T Sv = wave_scan_down<T>(L.cg * cos_f<T>(phi));
                     const T mu = lv + P.dt * lq;
                     const T nu = mu * L.invI;
-                    const T pf = scan_up(nu);
+                    const T pf = wave_scan_up<T>(nu);
                     const T sn = Sv * nu;
-                    const T R = scan_down(sn) - sn;
+                    const T R = wave_scan_down<T>(sn) - sn;
                     const T dadq = -L.kst * nu - (Sv * pf + R);
                     const T lq_n = lq + P.dt * dadq;
                     const T lv_n = mu - P.dt * L.dmp * nu;
@@ -302,13 +307,19 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, int model, G
                         lv = lv_n + (T)2 * L.wv * (vk - L.gv);
                     }
                 }
-                if (lane < m) {
-                    sG[kn.a * m + lane] += ((T)1 - c) * gu;
-                    sG[kn.b * m + lane] += c * gu;
+                if (kn.a != cur_a) {  // uniform
+                    flush();
+                    cur_a = kn.a;
+                    cur_b = kn.b;
+                    gA = 0;
+                    gB = 0;
                 }
+                gA += ((T)1 - c) * gu;
+                gB += c * gu;
             }
             __syncthreads();
         }
+        flush();
         __syncthreads();
     };
 
@@ -360,14 +371,22 @@ hipError_t launch_grad(const ProbView<T> &P, int model, const T *x0, const T *kn
                        T *cost_io, hipStream_t s) {
     const GradPlan G = grad_plan(model, P.n, P.m, P.Tn, P.p);
     const size_t bytes = G.total * sizeof(T);
-    if (bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)adjoint_kernel<T>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(adjoint_kernel<T>, dim3((unsigned)ncand), dim3(64), bytes, s, P, model, G,
-                       x0, knots, ld, dJ, cost, refine_steps, lr, knots_io, cost_io);
-    return hipGetLastError();
+    auto go = [&](auto kernel) {
+        if (bytes > 65536) {
+            hipError_t e = hipFuncSetAttribute((const void *)kernel,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)bytes);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kernel, dim3((unsigned)ncand), dim3(64), bytes, s, P, G, x0, knots, ld,
+                           dJ, cost, refine_steps, lr, knots_io, cost_io);
+        return hipGetLastError();
+    };
+    if (model != EMPC_LINEAR) return go(adjoint_kernel<T, false, 1>);
+    const int nm = P.n > P.m ? P.n : P.m;
+    if (nm <= 16) return go(adjoint_kernel<T, true, 16>);
+    if (nm <= 32) return go(adjoint_kernel<T, true, 32>);
+    return go(adjoint_kernel<T, true, 64>);
 }
 template hipError_t launch_grad<float>(const ProbView<float> &, int, const float *, const float *,
                                        int64_t, int64_t, float *, float *, int, float, float *,

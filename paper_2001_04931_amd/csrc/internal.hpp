@@ -169,6 +169,108 @@ __device__ inline int64_t xcd_swizzle_2d() {
     return xcd_swizzle((int64_t)blockIdx.y * gridDim.x + blockIdx.x, nb);
 }
 
+// ---------------------------------------------------------------------------
+// Cross-lane helpers on DPP row shifts (a row = 16 lanes; shifted-in lanes
+// read 0) and lane reads.  Every lane of the wavefront must be active.
+template <typename T>
+__device__ inline T row_shift_up(T v, int n);  // lane r gets lane r-n of its row, 0 below
+template <>
+__device__ inline float row_shift_up<float>(float v, int n) {
+    int x = __float_as_int(v), y = 0;
+    switch (n) {
+        case 1: y = __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false); break;
+        case 2: y = __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false); break;
+        case 4: y = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false); break;
+        default: y = __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false); break;
+    }
+    return __int_as_float(y);
+}
+template <typename T>
+__device__ inline T row_shift_down(T v, int n);  // lane r gets lane r+n of its row, 0 above
+template <>
+__device__ inline float row_shift_down<float>(float v, int n) {
+    int x = __float_as_int(v), y = 0;
+    switch (n) {
+        case 1: y = __builtin_amdgcn_update_dpp(0, x, 0x101, 0xf, 0xf, false); break;
+        case 2: y = __builtin_amdgcn_update_dpp(0, x, 0x102, 0xf, 0xf, false); break;
+        case 4: y = __builtin_amdgcn_update_dpp(0, x, 0x104, 0xf, 0xf, false); break;
+        default: y = __builtin_amdgcn_update_dpp(0, x, 0x108, 0xf, 0xf, false); break;
+    }
+    return __int_as_float(y);
+}
+// 64-bit values: two 32-bit DPP moves
+template <>
+__device__ inline double row_shift_up<double>(double v, int n) {
+    const int lo = (int)(__double_as_longlong(v) & 0xffffffffll);
+    const int hi = (int)(__double_as_longlong(v) >> 32);
+    const float flo = row_shift_up<float>(__int_as_float(lo), n);
+    const float fhi = row_shift_up<float>(__int_as_float(hi), n);
+    return __longlong_as_double(((long long)(unsigned)__float_as_int(fhi) << 32) |
+                                (unsigned)__float_as_int(flo));
+}
+template <>
+__device__ inline double row_shift_down<double>(double v, int n) {
+    const int lo = (int)(__double_as_longlong(v) & 0xffffffffll);
+    const int hi = (int)(__double_as_longlong(v) >> 32);
+    const float flo = row_shift_down<float>(__int_as_float(lo), n);
+    const float fhi = row_shift_down<float>(__int_as_float(hi), n);
+    return __longlong_as_double(((long long)(unsigned)__float_as_int(fhi) << 32) |
+                                (unsigned)__float_as_int(flo));
+}
+// inclusive scans over the 16 lanes of a row
+template <typename T>
+__device__ inline T row_scan_up(T v) {
+    v += row_shift_up<T>(v, 1);
+    v += row_shift_up<T>(v, 2);
+    v += row_shift_up<T>(v, 4);
+    v += row_shift_up<T>(v, 8);
+    return v;
+}
+template <typename T>
+__device__ inline T row_scan_down(T v) {
+    v += row_shift_down<T>(v, 1);
+    v += row_shift_down<T>(v, 2);
+    v += row_shift_down<T>(v, 4);
+    v += row_shift_down<T>(v, 8);
+    return v;
+}
+
+// lane j's value in every lane
+template <typename T>
+__device__ inline T lane_bcast(T v, int j);
+template <>
+__device__ inline float lane_bcast<float>(float v, int j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+template <>
+__device__ inline double lane_bcast<double>(double v, int j) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), j);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// inclusive prefix sum over the 64 lanes of a wavefront
+template <typename T>
+__device__ inline T wave_scan_up(T v) {
+    v = row_scan_up<T>(v);
+    const T r0 = lane_bcast<T>(v, 15), r1 = lane_bcast<T>(v, 31), r2 = lane_bcast<T>(v, 47);
+    const int row = (threadIdx.x & 63) >> 4;
+    return v + (row > 0 ? r0 : (T)0) + (row > 1 ? r1 : (T)0) + (row > 2 ? r2 : (T)0);
+}
+// inclusive suffix sum over the 64 lanes of a wavefront
+template <typename T>
+__device__ inline T wave_scan_down(T v) {
+    v = row_scan_down<T>(v);
+    const T r1 = lane_bcast<T>(v, 16), r2 = lane_bcast<T>(v, 32), r3 = lane_bcast<T>(v, 48);
+    const int row = (threadIdx.x & 63) >> 4;
+    return v + (row < 1 ? r1 : (T)0) + (row < 2 ? r2 : (T)0) + (row < 3 ? r3 : (T)0);
+}
+// sum over the 64 lanes, in every lane
+template <typename T>
+__device__ inline T wave_total(T v) {
+    return lane_bcast<T>(wave_scan_up<T>(v), 63);
+}
+
 struct Events {
     hipEvent_t start = nullptr, stop = nullptr;
 };

@@ -143,69 +143,6 @@ __global__ __launch_bounds__(256) void roll_chain(ProbView<T> P, const T *__rest
 // over joints and the gravity torques a suffix sum, both done as a local sum
 // over the lane's J joints plus a scan over the 16 lanes of the row with DPP
 // row shifts (which never cross a row).
-template <typename T>
-__device__ inline T row_shift_up(T v, int n);  // lane r gets lane r-n of its row, 0 below
-template <>
-__device__ inline float row_shift_up<float>(float v, int n) {
-    int x = __float_as_int(v), y = 0;
-    switch (n) {
-        case 1: y = __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false); break;
-        case 2: y = __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false); break;
-        case 4: y = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false); break;
-        default: y = __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false); break;
-    }
-    return __int_as_float(y);
-}
-template <typename T>
-__device__ inline T row_shift_down(T v, int n);  // lane r gets lane r+n of its row, 0 above
-template <>
-__device__ inline float row_shift_down<float>(float v, int n) {
-    int x = __float_as_int(v), y = 0;
-    switch (n) {
-        case 1: y = __builtin_amdgcn_update_dpp(0, x, 0x101, 0xf, 0xf, false); break;
-        case 2: y = __builtin_amdgcn_update_dpp(0, x, 0x102, 0xf, 0xf, false); break;
-        case 4: y = __builtin_amdgcn_update_dpp(0, x, 0x104, 0xf, 0xf, false); break;
-        default: y = __builtin_amdgcn_update_dpp(0, x, 0x108, 0xf, 0xf, false); break;
-    }
-    return __int_as_float(y);
-}
-// 64-bit values: two 32-bit DPP moves
-template <>
-__device__ inline double row_shift_up<double>(double v, int n) {
-    const int lo = (int)(__double_as_longlong(v) & 0xffffffffll);
-    const int hi = (int)(__double_as_longlong(v) >> 32);
-    const float flo = row_shift_up<float>(__int_as_float(lo), n);
-    const float fhi = row_shift_up<float>(__int_as_float(hi), n);
-    return __longlong_as_double(((long long)(unsigned)__float_as_int(fhi) << 32) |
-                                (unsigned)__float_as_int(flo));
-}
-template <>
-__device__ inline double row_shift_down<double>(double v, int n) {
-    const int lo = (int)(__double_as_longlong(v) & 0xffffffffll);
-    const int hi = (int)(__double_as_longlong(v) >> 32);
-    const float flo = row_shift_down<float>(__int_as_float(lo), n);
-    const float fhi = row_shift_down<float>(__int_as_float(hi), n);
-    return __longlong_as_double(((long long)(unsigned)__float_as_int(fhi) << 32) |
-                                (unsigned)__float_as_int(flo));
-}
-// inclusive scans over the 16 lanes of a row
-template <typename T>
-__device__ inline T row_scan_up(T v) {
-    v += row_shift_up<T>(v, 1);
-    v += row_shift_up<T>(v, 2);
-    v += row_shift_up<T>(v, 4);
-    v += row_shift_up<T>(v, 8);
-    return v;
-}
-template <typename T>
-__device__ inline T row_scan_down(T v) {
-    v += row_shift_down<T>(v, 1);
-    v += row_shift_down<T>(v, 2);
-    v += row_shift_down<T>(v, 4);
-    v += row_shift_down<T>(v, 8);
-    return v;
-}
-
 // One candidate per 16-lane row.  `cand` is the row's candidate; r the lane
 // in the row.  Every lane of the wavefront must call this (DPP).
 template <typename T, int J>
