@@ -18,7 +18,7 @@
 namespace empc {
 
 template <typename T>
-__global__ __launch_bounds__(256) void batch_population(const BatchSlot<T> *__restrict__ slots,
+__global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<T> *__restrict__ slots,
                                                         int64_t pop, int k, int elitism, T sigma,
                                                         uint32_t seed_lo, int g,
                                                         const uint32_t *__restrict__ tick) {
@@ -31,10 +31,11 @@ __global__ __launch_bounds__(256) void batch_population(const BatchSlot<T> *__re
     gs.NB = gs.XB + (P.p * P.m + 127) / 128;
     const bool first = g == 0;
     const bool cold = first && *S.has_elites == 0;
-    population_body<T>(P, gs, pop, k, elitism, sigma, first ? nullptr : S.knots[(g + 1) & 1], pop,
+    const int64_t nts = pop_tiles_s(pop);
+    population_tile<T>(P, gs, pop, k, elitism, sigma, first ? nullptr : S.knots[(g + 1) & 1], pop,
                        first ? nullptr : S.elite_idx, first ? S.elite_rows : nullptr, cold,
-                       S.knots[g & 1], pop, *tick, (uint32_t)g,
-                       (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                       S.knots[g & 1], pop, *tick, (uint32_t)g, blockIdx.x % nts,
+                       (int)(blockIdx.x / nts));
 }
 
 template <typename T, int NT, int NU, int WPB>
@@ -265,7 +266,7 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         S.elite_cost = (float *)(base + off); off += al256(k * 4);
         S.elite_idx = (int64_t *)(base + off); off += al256(k * 8);
         S.best_idx = (int64_t *)(base + off); off += 256;
-        b->ngmax = std::max(b->ngmax, (int)((pm + POP_PARAMS - 1) / POP_PARAMS));
+        b->ngmax = std::max(b->ngmax, pop_tiles_g((int)pm));
     }
     // group problems by kernel shape class
     std::map<std::tuple<int, int, int>, std::vector<int>> groups;
@@ -314,8 +315,8 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
     for (int g = 0; g < G.generations; ++g) {
         const int last = g == G.generations - 1;
         hipLaunchKernelGGL(batch_population<float>,
-                           dim3((unsigned)((pop * b->ngmax + 255) / 256), (unsigned)b->nprob),
-                           dim3(256), 0, s, b->d_slots, pop, G.n_elite, G.elitism, (float)G.sigma,
+                           dim3((unsigned)(pop_tiles_s(pop) * b->ngmax), (unsigned)b->nprob),
+                           dim3(POP_THREADS), 0, s, b->d_slots, pop, G.n_elite, G.elitism, (float)G.sigma,
                            seed_lo, g, (const uint32_t *)b->d_tick);
         for (const BatchClass &c : b->classes) {
             const int *items = b->d_items + c.first;

@@ -11,9 +11,8 @@ hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *k
                              uint32_t tick, uint32_t gen, hipStream_t s) {
     const int pm = P.p * P.m;
     const GaStreams gs = ga_streams(ga.seed, P.m, pm);
-    const int64_t total = (int64_t)ga.pop * ((pm + POP_PARAMS - 1) / POP_PARAMS);
-    const int64_t blocks = (total + 255) / 256;
-    hipLaunchKernelGGL(population_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, P, gs,
+    const int64_t blocks = pop_tiles_s(ga.pop) * pop_tiles_g(pm);
+    hipLaunchKernelGGL(population_kernel<T>, dim3((unsigned)blocks), dim3(POP_THREADS), 0, s, P, gs,
                        (int64_t)ga.pop, ga.n_elite, ga.elitism, (T)ga.sigma, knots_in, ld_in,
                        elite_idx, elite_rows, has_elites, cold_mode, knots_out, ld_out, tick, gen);
     return hipGetLastError();

@@ -23,20 +23,6 @@ __device__ inline float log_of<float>(float x) { return logf(x); }
 template <>
 __device__ inline double log_of<double>(double x) { return log(x); }
 
-// One thread per (slot s, group g of POP_PARAMS consecutive parameters
-// j = POP_PARAMS g ..), slot fastest so that every store
-// knots_out[j * ld + s] of a wavefront coalesces.  The group's parameters
-// share one parent block (block 0), one mutation-flag block and one crossover
-// block (a group never straddles a 128-parameter crossover block), and each
-// quad of parameters one normal block (two Box-Muller pairs), drawn only if a
-// parameter of the quad is mutated.
-// Parent knots come from elite_rows ([k][pm], when non-NULL) or from
-// knots_in at elite_idx[.].
-// Four parameters per thread: the generation is latency bound (a few
-// dependent Philox blocks and two dependent global reads per thread), so it
-// gains more from many short threads than from sharing draws over longer ones.
-constexpr int POP_PARAMS = 4;  // divides 128
-
 // One Box-Muller pair from two Philox words.
 template <typename T>
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T &z0, T &z1) {
@@ -58,119 +44,125 @@ __device__ __forceinline__ T mutate_clamp(T v, bool flag, T sigma, T z, T lo, T 
     return v;
 }
 
-// Values of parameters j0 .. j0+POP_PARAMS-1 (those below p m) of child
-// `s` of generation `gen` of tick `tick`.
-template <typename T>
-__device__ __forceinline__ void child_values(
-    const ProbView<T> &P, const GaStreams &gs, int k, int elitism, T sigma,
-    const T *__restrict__ knots_in, int64_t ld_in, const int64_t *__restrict__ elite_idx,
-    const T *__restrict__ elite_rows, bool cold, uint32_t tick, uint32_t gen, int64_t s, int j0,
-    T *val) {
-    const int m = P.m, pm = P.p * P.m;
-    const uint32_t slot = (uint32_t)s;
-    if (cold) {
-#pragma unroll
-        for (int q = 0; q < POP_PARAMS / 4; ++q) {
-            const U4 w = ga_draw(gs, slot, gen, tick, 1, (uint32_t)(j0 / 4 + q));
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = (j0 + 4 * q + r) % m;
-                val[4 * q + r] = P.umin[i] + (P.umax[i] - P.umin[i]) * uni23<T>(word_of(w, r));
-            }
-        }
-    } else if (elitism && s < k) {
-        const T *src = elite_rows ? elite_rows + (int64_t)s * pm : nullptr;
-        const int64_t col = elite_rows ? 0 : elite_idx[s];
-#pragma unroll
-        for (int r = 0; r < POP_PARAMS; ++r) {
-            const int j = j0 + r;
-            val[r] = j < pm ? (src ? src[j] : knots_in[(int64_t)j * ld_in + col]) : (T)0;
-        }
-    } else {
-        const U4 w0 = ga_draw(gs, slot, gen, tick, 0, 0);
-        const int p1 = (int)__umulhi(w0.x, (uint32_t)k);
-        const int p2 = (int)__umulhi(w0.y, (uint32_t)k);
-        // parent columns (or rows of elite_rows)
-        const T *src1, *src2;
-        int64_t step;
-        if (elite_rows) {
-            src1 = elite_rows + (int64_t)p1 * pm;
-            src2 = elite_rows + (int64_t)p2 * pm;
-            step = 1;
-        } else {
-            src1 = knots_in + elite_idx[p1];
-            src2 = knots_in + elite_idx[p2];
-            step = ld_in;
-        }
-        const U4 wx = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.XB + j0 / 128));
-        int fblk = -1;
-        U4 wf = {0, 0, 0, 0};
-        bool flag[POP_PARAMS];
-#pragma unroll
-        for (int r = 0; r < POP_PARAMS; ++r) {
-            const int i = (j0 + r) % m;
-            if (1 + i / 128 != fblk) {
-                fblk = 1 + i / 128;
-                wf = ga_draw(gs, slot, gen, tick, 0, (uint32_t)fblk);
-            }
-            const int ib = i % 128;
-            flag[r] = j0 + r < pm && ((word_of(wf, ib / 32) >> (ib % 32)) & 1u);
-        }
-        T z[POP_PARAMS];
-#pragma unroll
-        for (int q = 0; q < POP_PARAMS / 4; ++q) {
-            z[4 * q] = z[4 * q + 1] = z[4 * q + 2] = z[4 * q + 3] = 0;
-            if (flag[4 * q] || flag[4 * q + 1] || flag[4 * q + 2] || flag[4 * q + 3]) {
-                const U4 wn = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.NB + j0 / 4 + q));
-#pragma unroll
-                for (int pair = 0; pair < 2; ++pair)
-                    if (flag[4 * q + 2 * pair] || flag[4 * q + 2 * pair + 1])
-                        box_muller<T>(word_of(wn, 2 * pair), word_of(wn, 2 * pair + 1),
-                                      z[4 * q + 2 * pair], z[4 * q + 2 * pair + 1]);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < POP_PARAMS; ++r) {
-            const int j = j0 + r;
-            if (j >= pm) {
-                val[r] = 0;
-                continue;
-            }
-            const int i = j % m, jb = j % 128;
-            const bool from2 = (word_of(wx, jb / 32) >> (jb % 32)) & 1u;
-            val[r] = mutate_clamp<T>((from2 ? src2 : src1)[(int64_t)j * step], flag[r], sigma,
-                                     z[r], P.umin[i], P.umax[i]);
-        }
-    }
-}
+// Next population (Sec. V, Alg. 1 warm / cold start).  One workgroup of 256
+// threads per tile of 64 slots x 4 groups of 4 consecutive parameters: lane l
+// of wavefront w builds parameters 4 g .. 4 g + 3 (g = 4 tile_g + w) of slot
+// 64 tile_s + l, so that each store of a wavefront covers 64 consecutive
+// slots.  The draws that belong to a slot rather than to a parameter (block
+// 0: the two parents; the mutation-flag block; the crossover block of the
+// tile's 16 parameters, which never straddle a 128-parameter block) are
+// taken once per slot by wavefronts 0, 1 and 2 and shared through LDS; each
+// thread then draws only its own normal block (two Box-Muller pairs), and
+// only if one of its four inputs is flagged.  Parent knots come from
+// elite_rows ([k][p m], when non-NULL) or from knots_in at elite_idx[.].
+// Inputs per problem: at most 128 (one mutation-flag block).
+constexpr int POP_SLOTS = 64;   // slots per workgroup, one per lane
+constexpr int POP_GROUPS = 4;   // groups of four parameters, one per wavefront
+constexpr int POP_THREADS = 64 * POP_GROUPS;
 
 template <typename T>
-__device__ __forceinline__ void population_body(
+__device__ __forceinline__ void population_tile(
     const ProbView<T> &P, const GaStreams &gs, int64_t pop, int k, int elitism, T sigma,
     const T *__restrict__ knots_in, int64_t ld_in, const int64_t *__restrict__ elite_idx,
     const T *__restrict__ elite_rows, bool cold, T *__restrict__ knots_out, int64_t ld_out,
-    uint32_t tick, uint32_t gen, int64_t t) {
-    const int pm = P.p * P.m, ng = (pm + POP_PARAMS - 1) / POP_PARAMS;
-    if (t >= pop * ng) return;
-    const int64_t s = t % pop;
-    const int j0 = POP_PARAMS * (int)(t / pop);
-    T val[POP_PARAMS];
-    child_values<T>(P, gs, k, elitism, sigma, knots_in, ld_in, elite_idx, elite_rows, cold, tick,
-                    gen, s, j0, val);
+    uint32_t tick, uint32_t gen, int64_t tile_s, int tile_g) {
+    __shared__ int64_t s_src[POP_SLOTS][2];
+    __shared__ uint32_t s_flag[POP_SLOTS][4];
+    __shared__ uint32_t s_xw[POP_SLOTS][4];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int m = P.m, pm = P.p * P.m;
+    if (tile_g * POP_GROUPS * 4 >= pm) return;  // whole workgroup: no parameter here
+    const int64_t s = tile_s * POP_SLOTS + lane;
+    const int j0 = 4 * (tile_g * POP_GROUPS + w);
+    const uint32_t slot = (uint32_t)s;
+    if (!cold && s < pop) {
+        if (w == 0) {
+            const U4 w0 = ga_draw(gs, slot, gen, tick, 0, 0);
+            const int p1 = (int)__umulhi(w0.x, (uint32_t)k);
+            const int p2 = (int)__umulhi(w0.y, (uint32_t)k);
+            s_src[lane][0] = elite_rows ? (int64_t)p1 * pm : elite_idx[p1];
+            s_src[lane][1] = elite_rows ? (int64_t)p2 * pm : elite_idx[p2];
+        } else if (w == 1) {
+            const U4 wf = ga_draw(gs, slot, gen, tick, 0, 1);
+            s_flag[lane][0] = wf.x;
+            s_flag[lane][1] = wf.y;
+            s_flag[lane][2] = wf.z;
+            s_flag[lane][3] = wf.w;
+        } else if (w == 2) {
+            const int xb = (tile_g * POP_GROUPS * 4) / 128;
+            const U4 wx = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.XB + xb));
+            s_xw[lane][0] = wx.x;
+            s_xw[lane][1] = wx.y;
+            s_xw[lane][2] = wx.z;
+            s_xw[lane][3] = wx.w;
+        }
+    }
+    __syncthreads();
+    if (s >= pop || j0 >= pm) return;
+    T val[4];
+    if (cold) {
+        const U4 wc = ga_draw(gs, slot, gen, tick, 1, (uint32_t)(j0 / 4));
 #pragma unroll
-    for (int r = 0; r < POP_PARAMS; ++r)
+        for (int r = 0; r < 4; ++r) {
+            const int i = (j0 + r) % m;
+            val[r] = P.umin[i] + (P.umax[i] - P.umin[i]) * uni23<T>(word_of(wc, r));
+        }
+    } else {
+        const T *base = elite_rows ? elite_rows : knots_in;
+        const int64_t step = elite_rows ? 1 : ld_in;
+        if (elitism && s < k) {
+            const int64_t src = elite_rows ? s * pm : elite_idx[s];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                val[r] = j0 + r < pm ? base[src + (int64_t)(j0 + r) * step] : (T)0;
+        } else {
+            const int64_t src1 = s_src[lane][0], src2 = s_src[lane][1];
+            bool flag[4];
+            int ii[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ii[r] = (j0 + r) % m;
+                flag[r] = j0 + r < pm && ((s_flag[lane][ii[r] / 32] >> (ii[r] % 32)) & 1u);
+            }
+            T z[4] = {0, 0, 0, 0};
+            if (flag[0] || flag[1] || flag[2] || flag[3]) {
+                const U4 wn = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.NB + j0 / 4));
+                if (flag[0] || flag[1]) box_muller<T>(wn.x, wn.y, z[0], z[1]);
+                if (flag[2] || flag[3]) box_muller<T>(wn.z, wn.w, z[2], z[3]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 + r, jb = j % 128;
+                if (j >= pm) {
+                    val[r] = 0;
+                    continue;
+                }
+                const bool from2 = (s_xw[lane][jb / 32] >> (jb % 32)) & 1u;
+                val[r] = mutate_clamp<T>(base[(from2 ? src2 : src1) + (int64_t)j * step], flag[r],
+                                         sigma, z[r], P.umin[ii[r]], P.umax[ii[r]]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
         if (j0 + r < pm) knots_out[(int64_t)(j0 + r) * ld_out + s] = val[r];
 }
 
+// tiles of a population of `pop` slots and p m parameters
+__host__ __device__ inline int64_t pop_tiles_s(int64_t pop) { return (pop + POP_SLOTS - 1) / POP_SLOTS; }
+__host__ __device__ inline int pop_tiles_g(int pm) { return ((pm + 3) / 4 + POP_GROUPS - 1) / POP_GROUPS; }
+
 template <typename T>
-__global__ __launch_bounds__(256) void population_kernel(
+__global__ __launch_bounds__(POP_THREADS) void population_kernel(
     ProbView<T> P, GaStreams gs, int64_t pop, int k, int elitism, T sigma,
     const T *__restrict__ knots_in, int64_t ld_in, const int64_t *__restrict__ elite_idx,
     const T *__restrict__ elite_rows, const int *__restrict__ has_elites, int cold_mode,
     T *__restrict__ knots_out, int64_t ld_out, uint32_t tick, uint32_t gen) {
     const bool cold = cold_mode == 1 || (cold_mode == 2 && *has_elites == 0);
-    population_body<T>(P, gs, pop, k, elitism, sigma, knots_in, ld_in, elite_idx, elite_rows, cold,
-                       knots_out, ld_out, tick, gen, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    const int64_t nts = pop_tiles_s(pop);
+    population_tile<T>(P, gs, pop, k, elitism, sigma, knots_in, ld_in, elite_idx, elite_rows, cold,
+                       knots_out, ld_out, tick, gen, blockIdx.x % nts, (int)(blockIdx.x / nts));
 }
 
 // ---------------------------------------------------------------------------
