@@ -75,14 +75,25 @@ __global__ void plant_kernel(ProbView<T> P, int model, const T *__restrict__ x,
         return;
     }
     const int d = m;
-    for (int j = threadIdx.x; j < d; j += blockDim.x) {
-        T G = 0;
-        for (int r = j; r < d; ++r) {
-            T phi = 0, tail = 0;
-            for (int s = 0; s <= r; ++s) phi += xs[s];
-            for (int i = r; i < d; ++i) tail += P.mass[i];
-            G += P.gravity * P.len[r] * tail * sin_of<T>(phi);
+    // gravity term of each absolute angle, g l_r (sum_{i>=r} m_i) sin(phi_r),
+    // phi_r = q_0 + .. + q_r; one thread walks the chain once
+    __shared__ T sg[Limits::MAX_D_CHAIN];
+    if (threadIdx.x == 0) {
+        T phi = 0;
+        for (int r = 0; r < d; ++r) {
+            phi += xs[r];
+            sg[r] = phi;
         }
+        T tail = 0;
+        for (int r = d - 1; r >= 0; --r) {
+            tail += P.mass[r];
+            sg[r] = P.gravity * P.len[r] * tail * sin_of<T>(sg[r]);
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < d; j += blockDim.x) {
+        T G = 0;  // gravity torque on joint j: sum over r >= j
+        for (int r = d - 1; r >= j; --r) G += sg[r];
         T inert = 0, dist = 0;
         for (int i = j; i < d; ++i) {
             dist += P.len[i];

@@ -56,6 +56,20 @@ __device__ inline float sin_of<float>(float x) { return sinf(x); }
 template <>
 __device__ inline double sin_of<double>(double x) { return sin(x); }
 
+// sin for the rollout's gravity torques.  FP32: the hardware transcendental
+// (v_sin_f32 takes its argument in revolutions), two instructions instead of
+// the library's range reduction and polynomial; its absolute error (a few
+// 1e-7) is of the order of FP32 rounding of the cumulative angle itself.
+// FP64: the library sin.
+template <typename T>
+__device__ inline T sin_rollout(T x);
+template <>
+__device__ inline float sin_rollout<float>(float x) {
+    return __builtin_amdgcn_sinf(x * 0.15915494309189535f);
+}
+template <>
+__device__ inline double sin_rollout<double>(double x) { return sin(x); }
+
 // One thread: candidate `cand` of one problem; jc holds the problem's
 // per-joint constants.
 template <typename T, int DMAX>
@@ -95,7 +109,7 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
         for (int j = 0; j < DMAX; ++j) {
             if (j < d) {
                 phi += q[j];
-                sg[j] = jc[j].cg * sin_of<T>(phi);
+                sg[j] = jc[j].cg * sin_rollout<T>(phi);
             }
         }
         T G = 0, js = 0;
@@ -210,7 +224,7 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
         const T before = row_scan_up<T>(run) - run;
         T sg[J];
 #pragma unroll
-        for (int i = 0; i < J; ++i) sg[i] = cg[i] * sin_of<T>(before + loc[i]);
+        for (int i = 0; i < J; ++i) sg[i] = cg[i] * sin_rollout<T>(before + loc[i]);
         // gravity torque G_j = sum_{r >= j} cg_r sin(phi_r): local suffix plus
         // the row's exclusive suffix of lane totals
         T srun = 0, sloc[J];
