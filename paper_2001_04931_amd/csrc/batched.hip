@@ -108,7 +108,16 @@ struct BatchClass {
     int a, b;    // linear: (NT, NU bucket); chain: (DMAX, 0)
     int first;   // offset in the device item list
     int count;
+    double work;  // rough cost estimate, to spread classes over streams
+    int stream;   // side stream its rollout runs on
 };
+
+// The rollouts of the kernel-shape classes are independent, so they run on
+// side streams forked from and joined back into the caller's stream (in a
+// captured graph: parallel branches); the GPU fills the tail of one class's
+// launch with another's.  At most this many side streams (the box's hardware
+// queues bound the useful number).
+constexpr int BATCH_STREAMS = 4;
 
 int nu_bucket(int m) {
     const int nu = (m + 3) / 4;
@@ -184,6 +193,10 @@ struct empc_batch {
     BatchSlot<float> *d_slots = nullptr;
     int *d_items = nullptr;
     uint32_t *d_tick = nullptr;
+    int nstreams = 0;
+    hipStream_t side[BATCH_STREAMS] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[BATCH_STREAMS] = {};
 };
 
 namespace {
@@ -285,8 +298,28 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         c.b = std::get<2>(kv.first);
         c.first = (int)items.size();
         c.count = (int)kv.second.size();
+        c.work = 0;
+        for (int i : kv.second) {  // per candidate-step: MFMAs (linear), joints (chain)
+            const empc_problem &P = probs[i];
+            c.work += (double)P.T * (P.model == EMPC_LINEAR ? 4.0 * c.a * c.a * 8.0 : 3.0 * P.m);
+        }
         items.insert(items.end(), kv.second.begin(), kv.second.end());
         b->classes.push_back(c);
+    }
+    // spread the classes over the side streams, largest first onto the least
+    // loaded stream
+    b->nstreams = std::min<int>(BATCH_STREAMS, (int)b->classes.size());
+    {
+        std::vector<int> order(b->classes.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::sort(order.begin(), order.end(),
+                  [&](int x, int y) { return b->classes[x].work > b->classes[y].work; });
+        std::vector<double> load(b->nstreams, 0.0);
+        for (int ci : order) {
+            const int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            b->classes[ci].stream = st;
+            load[st] += b->classes[ci].work;
+        }
     }
     b->d_tick = (uint32_t *)base;
     hipError_t e = hipMalloc(&b->d_slots, sizeof(BatchSlot<float>) * nprob);
@@ -295,9 +328,19 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         e = hipMemcpy(b->d_slots, slots.data(), sizeof(BatchSlot<float>) * nprob, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_items, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int i = 0; i < b->nstreams && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
         (void)hipFree(b->d_slots);
         (void)hipFree(b->d_items);
+        for (int i = 0; i < BATCH_STREAMS; ++i) {
+            if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+            if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+        }
+        if (b->fork) (void)hipEventDestroy(b->fork);
         delete b;
         return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(e));
     }
@@ -318,8 +361,13 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
                            dim3((unsigned)(pop_tiles_s(pop) * b->ngmax), (unsigned)b->nprob),
                            dim3(POP_THREADS), 0, s, b->d_slots, pop, G.n_elite, G.elitism, (float)G.sigma,
                            seed_lo, g, (const uint32_t *)b->d_tick);
+        hipError_t fe = hipEventRecord(b->fork, s);
+        for (int i = 0; i < b->nstreams && fe == hipSuccess; ++i)
+            fe = hipStreamWaitEvent(b->side[i], b->fork, 0);
+        if (fe != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(fe));
         for (const BatchClass &c : b->classes) {
             const int *items = b->d_items + c.first;
+            hipStream_t s = b->side[c.stream];
             if (c.model == EMPC_LINEAR) {
                 switch (c.a) {
                     case 1: go_batch_linear_nu<1>(c.b, b->d_slots, items, c.count, pop, g, s); break;
@@ -338,6 +386,11 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
                 }
             }
         }
+        for (int i = 0; i < b->nstreams && fe == hipSuccess; ++i) {
+            fe = hipEventRecord(b->join[i], b->side[i]);
+            if (fe == hipSuccess) fe = hipStreamWaitEvent(s, b->join[i], 0);
+        }
+        if (fe != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(fe));
         if (per <= 4)
             hipLaunchKernelGGL((batch_select<float, uint32_t, 4>), dim3(b->nprob), dim3(SEL_THREADS), 0,
                                s, b->d_slots, pop, G.n_elite, g, last);
@@ -356,6 +409,12 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
 
 empc_status empc_batch_destroy(empc_batch *b) {
     if (!b) return EMPC_OK;
+    for (int i = 0; i < BATCH_STREAMS; ++i) {
+        if (b->side[i]) (void)hipStreamSynchronize(b->side[i]);
+        if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     (void)hipFree(b->d_slots);
     (void)hipFree(b->d_items);
     delete b;
