@@ -90,7 +90,7 @@ template <typename T, typename K, int CACHE>
 __global__ __launch_bounds__(SEL_THREADS) void batch_select(const BatchSlot<T> *__restrict__ slots,
                                                             int64_t pop, int k, int g, int last) {
     const BatchSlot<T> &S = slots[blockIdx.x];
-    select_body<T, K, CACHE>(S.cost, pop, k, S.knots[g & 1], pop, S.P.p * S.P.m, S.P.m,
+    select_body<T, K, CACHE, SEL_THREADS>(S.cost, pop, k, S.knots[g & 1], pop, S.P.p * S.P.m, S.P.m,
                              S.elite_idx, S.best_idx, last ? S.elite_rows : nullptr, S.elite_cost,
                              S.has_elites, nullptr, last ? S.u_star : nullptr,
                              last ? S.best_cost : nullptr);

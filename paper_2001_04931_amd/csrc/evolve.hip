@@ -32,23 +32,26 @@ hipError_t launch_select(const ProbView<T> &P, const T *cost, const T *knots, in
                          T *elite_cost, int *has_elites, int *best_slot, T *u_star, T *best_cost,
                          hipStream_t s) {
     typedef typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type K;
-    const int64_t per = (pop + SEL_THREADS - 1) / SEL_THREADS;
-    if (per <= 4)
-        hipLaunchKernelGGL((select_kernel<T, K, 4>), dim3(1), dim3(SEL_THREADS), 0, s, cost, pop,
-                           k, knots, ld, P.p * P.m, P.m, elite_idx, best_idx, elite_rows,
-                           elite_cost, has_elites, best_slot, u_star, best_cost);
-    else if (per <= 16)
-        hipLaunchKernelGGL((select_kernel<T, K, 16>), dim3(1), dim3(SEL_THREADS), 0, s, cost, pop,
-                           k, knots, ld, P.p * P.m, P.m, elite_idx, best_idx, elite_rows,
-                           elite_cost, has_elites, best_slot, u_star, best_cost);
-    else if (per <= 64)
-        hipLaunchKernelGGL((select_kernel<T, K, 64>), dim3(1), dim3(SEL_THREADS), 0, s, cost, pop,
-                           k, knots, ld, P.p * P.m, P.m, elite_idx, best_idx, elite_rows,
-                           elite_cost, has_elites, best_slot, u_star, best_cost);
-    else
-        hipLaunchKernelGGL((select_kernel<T, K, 0>), dim3(1), dim3(SEL_THREADS), 0, s, cost, pop,
-                           k, knots, ld, P.p * P.m, P.m, elite_idx, best_idx, elite_rows,
-                           elite_cost, has_elites, best_slot, u_star, best_cost);
+    auto go = [&](auto kernel, int nthr) {
+        hipLaunchKernelGGL(kernel, dim3(1), dim3(nthr), 0, s, cost, pop, k, knots, ld, P.p * P.m,
+                           P.m, elite_idx, best_idx, elite_rows, elite_cost, has_elites, best_slot,
+                           u_star, best_cost);
+    };
+    // 256 threads up to 1024 candidates, else 1024 threads (measured at
+    // 4096: 7.1 against 9.2 us; at 16384: 11.6 against 21.4 us)
+    if (pop <= 1024) {
+        go(select_kernel<T, K, 4, 256>, 256);
+    } else {
+        const int64_t per = (pop + 1023) / 1024;
+        if (per <= 4)
+            go(select_kernel<T, K, 4, 1024>, 1024);
+        else if (per <= 16)
+            go(select_kernel<T, K, 16, 1024>, 1024);
+        else if (per <= 64)
+            go(select_kernel<T, K, 64, 1024>, 1024);
+        else
+            go(select_kernel<T, K, 0, 1024>, 1024);
+    }
     return hipGetLastError();
 }
 template hipError_t launch_select<float>(const ProbView<float> &, const float *, const float *,

@@ -171,6 +171,7 @@ __global__ __launch_bounds__(POP_THREADS) void population_kernel(
 // 4096..16384 keys need no more).  Thread t owns the contiguous index range
 // [t per, (t+1) per), per = ceil(pop / 256), with the sortable keys cached
 // in registers when per <= CACHE (loaded 16 bytes at a time).
+//     Populations above 1024 use a workgroup of 1024 threads instead.
 //  1. radix select of the k-th smallest key, 8 bits per pass, starting below
 //     the bytes that every key shares (from the block's min and max key).
 //     Costs of a population cluster, so most keys of a pass hit the same few
@@ -206,7 +207,8 @@ __device__ inline int wave_incl_scan(int v) {
     return v + (row > 0 ? r0 : 0) + (row > 1 ? r1 : 0) + (row > 2 ? r2 : 0);
 }
 
-// Exclusive block prefix sum of v; *total gets the sum.
+// Exclusive block prefix sum of v over NW wavefronts; *total gets the sum.
+template <int NW>
 __device__ inline int block_excl_scan(int v, int *wsum, int *total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int incl = wave_incl_scan(v);
@@ -214,7 +216,7 @@ __device__ inline int block_excl_scan(int v, int *wsum, int *total) {
     __syncthreads();
     int base = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < SEL_WAVES; ++w) {
+    for (int w = 0; w < NW; ++w) {
         const int x = wsum[w];
         base += w < wave ? x : 0;
         tot += x;
@@ -251,7 +253,7 @@ __device__ inline double key_value(uint64_t k) {
         (long long)((k & 0x8000000000000000ull) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k));
 }
 
-template <typename T, typename K, int CACHE>
+template <typename T, typename K, int CACHE, int NTHR = SEL_THREADS>
 __device__ __forceinline__ void select_body(
     const T *__restrict__ cost, int64_t pop, int k, const T *__restrict__ knots, int64_t ld,
     int pm, int m, int64_t *__restrict__ elite_idx_out, int64_t *__restrict__ best_idx_out,
@@ -259,16 +261,16 @@ __device__ __forceinline__ void select_body(
     int *__restrict__ best_slot_out, T *__restrict__ u_star, T *__restrict__ best_cost) {
     __shared__ int hist[2][HREP * HSTRIDE];
     __shared__ int tot[256];
-    __shared__ int wsum[SEL_WAVES];
-    __shared__ K s_lo[SEL_WAVES], s_hi[SEL_WAVES];
+    __shared__ int wsum[(NTHR / 64)];
+    __shared__ K s_lo[(NTHR / 64)], s_hi[(NTHR / 64)];
     __shared__ int64_t s_elite[Limits::MAX_ELITE];
     __shared__ K s_ekey[Limits::MAX_ELITE];
     __shared__ int s_best_slot;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int b = tid; b < HREP * HSTRIDE; b += SEL_THREADS) hist[0][b] = 0;
+    for (int b = tid; b < HREP * HSTRIDE; b += NTHR) hist[0][b] = 0;
 
-    const int64_t per = (pop + SEL_THREADS - 1) / SEL_THREADS;
+    const int64_t per = (pop + NTHR - 1) / NTHR;
     const int64_t i0 = (int64_t)tid * per;
     const int64_t nmine = per < pop - i0 ? per : (pop - i0 > 0 ? pop - i0 : 0);
     K cache[CACHE > 0 ? CACHE : 1];
@@ -317,7 +319,7 @@ __device__ __forceinline__ void select_body(
     __syncthreads();
     K lo = s_lo[0], hi = s_hi[0];
 #pragma unroll
-    for (int w = 1; w < SEL_WAVES; ++w) {
+    for (int w = 1; w < (NTHR / 64); ++w) {
         lo = s_lo[w] < lo ? s_lo[w] : lo;
         hi = s_hi[w] > hi ? s_hi[w] : hi;
     }
@@ -336,9 +338,9 @@ __device__ __forceinline__ void select_body(
             if ((key & mask) == prefix) atomicAdd(&myh[(int)((key >> shift) & 255)], 1);
         });
         // clear the other buffer for the next pass
-        for (int b = tid; b < HREP * HSTRIDE; b += SEL_THREADS) hist[buf ^ 1][b] = 0;
+        for (int b = tid; b < HREP * HSTRIDE; b += NTHR) hist[buf ^ 1][b] = 0;
         __syncthreads();
-        {
+        if (tid < 256) {  // one bin per thread
             int sum = 0;
 #pragma unroll
             for (int rep = 0; rep < HREP; ++rep) sum += hist[buf][rep * HSTRIDE + tid];
@@ -379,15 +381,15 @@ __device__ __forceinline__ void select_body(
         my_eq += key == thr ? 1 : 0;
     });
     int packed_tot, lt_base, eq_base;
-    if (CACHE > 0) {  // per-thread counts <= 64, block totals < 2^16
-        const int base = block_excl_scan(my_lt | (my_eq << 16), wsum, &packed_tot);
+    if (CACHE > 0 && pop < (1 << 15)) {  // below < k <= 256, equal < 2^15: packed in 31 bits
+        const int base = block_excl_scan<NTHR / 64>(my_lt | (my_eq << 16), wsum, &packed_tot);
         lt_base = base & 0xFFFF;
         eq_base = base >> 16;
     } else {
         int t1;
-        lt_base = block_excl_scan(my_lt, wsum, &t1);
+        lt_base = block_excl_scan<NTHR / 64>(my_lt, wsum, &t1);
         __syncthreads();
-        eq_base = block_excl_scan(my_eq, wsum, &t1);
+        eq_base = block_excl_scan<NTHR / 64>(my_eq, wsum, &t1);
     }
     {
         int e = eq_base;
@@ -429,12 +431,12 @@ __device__ __forceinline__ void select_body(
     }
     __syncthreads();
     const int bslot = s_best_slot;
-    for (int s = tid; s < k; s += SEL_THREADS) {
+    for (int s = tid; s < k; s += NTHR) {
         if (elite_idx_out) elite_idx_out[s] = s_elite[s];
         if (elite_cost) elite_cost[s] = key_value(s_ekey[s]);
     }
     if (elite_rows)
-        for (int t = tid; t < k * pm; t += SEL_THREADS) {
+        for (int t = tid; t < k * pm; t += NTHR) {
             const int s = t / pm, j = t - s * pm;
             elite_rows[t] = knots[(int64_t)j * ld + s_elite[s]];
         }
@@ -446,17 +448,18 @@ __device__ __forceinline__ void select_body(
     }
     // u*(i) = get_u_from_U(U_best(i), t = 0): knot 0 (idx1 = 0, c = 0)
     if (u_star)
-        for (int i = tid; i < m; i += SEL_THREADS) u_star[i] = knots[(int64_t)i * ld + s_elite[bslot]];
+        for (int i = tid; i < m; i += NTHR) u_star[i] = knots[(int64_t)i * ld + s_elite[bslot]];
 }
 
-template <typename T, typename K, int CACHE>
-__global__ __launch_bounds__(SEL_THREADS) void select_kernel(
+template <typename T, typename K, int CACHE, int NTHR>
+__global__ __launch_bounds__(NTHR) void select_kernel(
     const T *__restrict__ cost, int64_t pop, int k, const T *__restrict__ knots, int64_t ld,
     int pm, int m, int64_t *__restrict__ elite_idx_out, int64_t *__restrict__ best_idx_out,
     T *__restrict__ elite_rows, T *__restrict__ elite_cost, int *__restrict__ has_elites,
     int *__restrict__ best_slot_out, T *__restrict__ u_star, T *__restrict__ best_cost) {
-    select_body<T, K, CACHE>(cost, pop, k, knots, ld, pm, m, elite_idx_out, best_idx_out,
-                             elite_rows, elite_cost, has_elites, best_slot_out, u_star, best_cost);
+    select_body<T, K, CACHE, NTHR>(cost, pop, k, knots, ld, pm, m, elite_idx_out, best_idx_out,
+                                   elite_rows, elite_cost, has_elites, best_slot_out, u_star,
+                                   best_cost);
 }
 
 
