@@ -66,7 +66,8 @@ __device__ __forceinline__ void population_tile(
     const T *__restrict__ knots_in, int64_t ld_in, const int64_t *__restrict__ elite_idx,
     const T *__restrict__ elite_rows, bool cold, T *__restrict__ knots_out, int64_t ld_out,
     uint32_t tick, uint32_t gen, int64_t tile_s, int tile_g) {
-    __shared__ int64_t s_src[POP_SLOTS][2];
+    __shared__ int s_par[POP_SLOTS][2];
+    __shared__ int64_t s_eidx[Limits::MAX_ELITE];
     __shared__ uint32_t s_flag[POP_SLOTS][4];
     __shared__ uint32_t s_xw[POP_SLOTS][4];
     const int lane = threadIdx.x & 63;
@@ -76,13 +77,15 @@ __device__ __forceinline__ void population_tile(
     const int64_t s = tile_s * POP_SLOTS + lane;
     const int j0 = 4 * (tile_g * POP_GROUPS + w);
     const uint32_t slot = (uint32_t)s;
+    // the parents' indices are staged in LDS by the fourth wavefront while
+    // the others draw, so no global load waits on a draw
+    if (!cold && w == 3 && !elite_rows)
+        for (int i = lane; i < k; i += 64) s_eidx[i] = elite_idx[i];
     if (!cold && s < pop) {
         if (w == 0) {
             const U4 w0 = ga_draw(gs, slot, gen, tick, 0, 0);
-            const int p1 = (int)__umulhi(w0.x, (uint32_t)k);
-            const int p2 = (int)__umulhi(w0.y, (uint32_t)k);
-            s_src[lane][0] = elite_rows ? (int64_t)p1 * pm : elite_idx[p1];
-            s_src[lane][1] = elite_rows ? (int64_t)p2 * pm : elite_idx[p2];
+            s_par[lane][0] = (int)__umulhi(w0.x, (uint32_t)k);
+            s_par[lane][1] = (int)__umulhi(w0.y, (uint32_t)k);
         } else if (w == 1) {
             const U4 wf = ga_draw(gs, slot, gen, tick, 0, 1);
             s_flag[lane][0] = wf.x;
@@ -112,12 +115,14 @@ __device__ __forceinline__ void population_tile(
         const T *base = elite_rows ? elite_rows : knots_in;
         const int64_t step = elite_rows ? 1 : ld_in;
         if (elitism && s < k) {
-            const int64_t src = elite_rows ? s * pm : elite_idx[s];
+            const int64_t src = elite_rows ? s * pm : s_eidx[s];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 val[r] = j0 + r < pm ? base[src + (int64_t)(j0 + r) * step] : (T)0;
         } else {
-            const int64_t src1 = s_src[lane][0], src2 = s_src[lane][1];
+            const int p1 = s_par[lane][0], p2 = s_par[lane][1];
+            const int64_t src1 = elite_rows ? (int64_t)p1 * pm : s_eidx[p1];
+            const int64_t src2 = elite_rows ? (int64_t)p2 * pm : s_eidx[p2];
             bool flag[4];
             int ii[4];
 #pragma unroll

@@ -289,10 +289,14 @@ __global__ __launch_bounds__(64 * WPB) void roll_linear_mfma(ProbView<T> P,
 // ---------------------------------------------------------------------------
 // M-split form: one workgroup of NT wavefronts per tile of 16 candidates,
 // wavefront w owning state rows 16w..16w+15 (M-tile w).  Each step a
-// wavefront runs the 4 NT MFMAs of its own rows (instead of 4 NT^2), then
-// publishes its new rows through LDS and reads the other tiles back for the
-// next step: one LDS round trip and one barrier per step, hidden behind the
-// four MFMAs of the wavefront's own K slices, which need no exchanged data.
+// wavefront runs the 4 NT MFMAs of its own rows (instead of 4 NT^2) and
+// publishes its new rows through LDS; the next step reads the other tiles
+// back.  One LDS round trip and one barrier per step, hidden behind the four
+// MFMAs of the wavefront's own K slices, which need no exchanged data: the
+// new rows are written as soon as they are summed, the first two own MFMAs
+// of the next step cover the write, the barrier follows them, and the last
+// two cover the read (placing the barrier before all four, or after them,
+// measured 8 % slower per launch).
 // A tile thus runs on NT SIMDs instead of one, which is what a population of
 // a few thousand candidates needs to occupy the chip.
 //
@@ -417,6 +421,7 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
     }
     T Ju = 0;
     int k = 0, buf = 0;
+    if (NT > 1) xs[0][w][lane] = X[0];  // read back by the first step
     auto segment = [&](int a, T *ua, T *ub, T *un) {
         const int kend = (p == 1 || a == p - 1) ? Tn
                                                 : ((a + 1) * (Tn - 1) + (p - 2)) / (p - 1);
@@ -430,11 +435,18 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
             C2 += c * c;
             v4 acc0 = Va + c * dV, acc1 = v4{0, 0, 0, 0};
             // own K slices first (no exchanged data), with the stage cost of
-            // the own rows between them; then the other tiles' slices
+            // the own rows between them and the exchange of the previous
+            // step's rows after the second; then the other tiles' slices
 #pragma unroll
             for (int i = 0; i < NT; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
+                    if (NT > 1 && i == 0 && v == 2) {
+                        lds_barrier();
+#pragma unroll
+                        for (int i2 = 1; i2 < NT; ++i2) X[i2] = xs[buf][(w + i2) % NT][lane];
+                        buf ^= 1;
+                    }
                     if (v & 1)
                         acc1 = Mfma<T>::op(aX[4 * i + v], X[i][v], acc1);
                     else
@@ -446,13 +458,9 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
                     __builtin_amdgcn_sched_barrier(0);
                 }
             X[0] = acc0 + acc1;
-            if (NT > 1) {
-                xs[buf][w][lane] = X[0];
-                lds_barrier();
-#pragma unroll
-                for (int i = 1; i < NT; ++i) X[i] = xs[buf][(w + i) % NT][lane];
-                buf ^= 1;
-            }
+            // buffer buf was last read in the previous step, before every
+            // wavefront passed this step's barrier
+            if (NT > 1) xs[buf][w][lane] = X[0];
         }
         // input cost of the segment in closed form (u is affine in c on
         // it); the input slices are shared out over the wavefronts
