@@ -152,20 +152,35 @@ def summary(rate, lats, **extra):
     return d
 
 
-def other_workloads(E, W):
+WORKLOADS = ("c1", "c3", "c4", "c5")
+
+
+def other_workloads(E, W, names=WORKLOADS):
     """The remaining benchmark configurations, measured the same way."""
     import torch
 
     out = {}
-    prob, ga = W.config_c1(0)
-    rate, lats, _ = closed_loop(E, W, prob, ga, torch.float64, 100, 5)
-    out["c1_fp64_2dof"] = summary(rate, lats, ticks=100, dtype="f64")
+    if "c1" in names:
+        prob, ga = W.config_c1(0)
+        rate, lats, _ = closed_loop(E, W, prob, ga, torch.float64, 100, 5)
+        out["c1_fp64_2dof"] = summary(rate, lats, ticks=100, dtype="f64")
 
-    prob, ga = W.config_c3(0)
-    rate, lats, _ = closed_loop(E, W, prob, ga, torch.float32, 10, 2)
-    out["c3_fp32_36link_chain"] = summary(rate, lats, ticks=10, dtype="f32")
+    if "c3" in names:
+        prob, ga = W.config_c3(0)
+        rate, lats, _ = closed_loop(E, W, prob, ga, torch.float32, 10, 2)
+        out["c3_fp32_36link_chain"] = summary(rate, lats, ticks=10, dtype="f32")
+    if "c4" in names:
+        out.update(refined_workload(E, W))
+    if "c5" in names:
+        out.update(batched_workload(E, W))
+    return out
 
-    # gradient-refined form beside plain EMPC on the same ticks
+
+def refined_workload(E, W):
+    """C4: the gradient-refined form beside plain EMPC on the same ticks."""
+    import torch
+
+    out = {}
     prob, ga = W.config_c2(0)
     rate_p, lats_p, costs_p = closed_loop(E, W, prob, ga, torch.float32, 10, 1, noise_std=1e-3)
     rate_r, lats_r, costs_r = closed_loop(E, W, prob, ga, torch.float32, 10, 1, noise_std=1e-3,
@@ -174,11 +189,19 @@ def other_workloads(E, W):
         rate_r, lats_r, ticks=10, dtype="f32", adam_steps_per_generation=5, elites_refined=64,
         plain_rollouts_per_s=rate_p,
         first_tick_best_cost={"plain": costs_p[0], "refined": costs_r[0]})
+    return out
 
-    # 512 uneven problems, one tick per HIP-graph replay
+
+def batched_workload(E, W):
+    """C5: 512 uneven problems, one tick per HIP-graph replay."""
+    import torch
+
+    out = {}
     probs, ga = W.config_c5(512, 0)
     dps = [E.DeviceProblem(p.cast(np.float32), torch.float32) for p in probs]
-    bs = E.BatchSolver(dps, ga)
+    t_tune = time.perf_counter()
+    bs = E.BatchSolver(dps, ga)  # autotunes the launch shapes
+    t_tune = time.perf_counter() - t_tune
     for i, p in enumerate(probs):
         bs.set_x0(i, W.draw_x0(p.n, i))
     torch.cuda.synchronize()
@@ -204,7 +227,11 @@ def other_workloads(E, W):
     lats = np.array(lats)
     out["c5_fp32_512_problems"] = summary(
         len(probs) * ga.pop * ga.generations * ticks / wall, lats, ticks=ticks, dtype="f32",
-        problems=len(probs), within_2ms=float(np.mean(lats <= 2.0)))
+        problems=len(probs), within_2ms=float(np.mean(lats <= 2.0)),
+        plan_and_autotune_s=round(t_tune, 3),
+        shapes=["%s%s x%d: shape %d of us %s, stream %d" % (
+            "lin" if c["model"] == "linear" else "chain", list(c["shape"]), c["problems"],
+            c["variant"], c["tuned_us"], c["stream"]) for c in bs.classes()])
     bs.close()
     return out
 
@@ -218,6 +245,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other configurations (C1, C3, C4, C5)")
+    ap.add_argument("--only", choices=WORKLOADS, default=None,
+                    help="run only this other configuration (for profiling) and print "
+                         "its summary instead of the benchmark line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain MIB-MiB device copy (traffic-counter scale)")
     args = ap.parse_args()
@@ -237,6 +267,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.only:
+        print(json.dumps(other_workloads(E, W, (args.only,))), flush=True)
+        return
     prob, ga = W.config_c2(0)
     dtype = torch.float32
     dp = E.DeviceProblem(prob, dtype)

@@ -193,6 +193,38 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
 empc_status empc_solve_batched(empc_batch *plan, void *stream);
 empc_status empc_batch_destroy(empc_batch *plan);
 
+/* Launch-shape autotuner of a batch plan.  The plan groups its problems into
+ * classes that share a rollout kernel (linear: state tiles of 16 and input
+ * slices of 4; chain: joints per lane); each class has a few launch shapes
+ * (linear: one wavefront per 16-candidate tile with 4, 2 or 1 wavefronts per
+ * workgroup, or the M-split form with one wavefront per state tile; chain:
+ * workgroup sizes), and every shape of a class runs the same per-candidate
+ * arithmetic, so the shape changes the time, never a result.
+ * empc_batch_create picks shapes by a fixed rule.  empc_batch_autotune(plan,
+ * reps, stream) times every shape of every class on the plan's own problems
+ * (one untimed and `reps` timed launches each, on `stream`, after one
+ * generation-0 population), keeps the fastest per class, then times the
+ * generation's rollouts with 1..4 side streams, the classes spread over them
+ * by their measured times, and keeps the fastest count.  Host call that
+ * blocks until the timing is done; it overwrites only the generation-0
+ * population and the costs in the workspace (the next solve rewrites both),
+ * so the warm-start state and the tick counter are unchanged.  Call it
+ * before capturing a graph of empc_solve_batched.  EMPC_EINVAL for a NULL
+ * plan or reps < 1.
+ * empc_batch_classes(plan) -> number of classes (0 for NULL).
+ * empc_batch_class_info(plan, cls, info[7]) fills model, the two shape
+ *   parameters (linear: state tiles, input-slice bucket; chain: joint
+ *   bucket, 0), problem count, chosen shape, number of shapes, side stream.
+ * empc_batch_class_times(plan, cls, us[4]) gives the mean launch time in
+ *   microseconds the autotuner measured for each shape (-1: not measured).
+ * empc_batch_set_variant(plan, cls, variant) sets a class's shape by hand
+ *   (EMPC_EINVAL if out of range). */
+empc_status empc_batch_autotune(empc_batch *plan, int32_t reps, void *stream);
+int32_t empc_batch_classes(const empc_batch *plan);
+empc_status empc_batch_class_info(const empc_batch *plan, int32_t cls, int32_t *info);
+empc_status empc_batch_class_times(const empc_batch *plan, int32_t cls, float *us);
+empc_status empc_batch_set_variant(empc_batch *plan, int32_t cls, int32_t variant);
+
 /* Kernel timing.  empc_profile_begin(max_launches) creates a pool of HIP
  * event pairs (host call, may allocate); until empc_profile_end, every
  * rollout launch made by empc_rollout_cost and empc_solve (at most

@@ -78,6 +78,13 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(_vp)], ctypes.c_int),
             "empc_solve_batched": ([_vp, _vp], ctypes.c_int),
             "empc_batch_destroy": ([_vp], ctypes.c_int),
+            "empc_batch_autotune": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
+            "empc_batch_classes": ([_vp], ctypes.c_int32),
+            "empc_batch_class_info": ([_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+                                      ctypes.c_int),
+            "empc_batch_class_times": ([_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)],
+                                       ctypes.c_int),
+            "empc_batch_set_variant": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
             "empc_profile_begin": ([ctypes.c_int32], ctypes.c_int),
             "empc_profile_end": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
                                  ctypes.c_int),
@@ -94,7 +101,10 @@ def exported_symbols():
     return ["empc_status_str", "empc_last_error", "empc_rollout_cost", "empc_generation",
             "empc_workspace_bytes", "empc_solve", "empc_solve_refined", "empc_grad", "empc_refine", "empc_plant_step",
             "empc_batch_workspace_bytes", "empc_batch_create", "empc_solve_batched",
-            "empc_batch_destroy", "empc_profile_begin", "empc_profile_end"]
+            "empc_batch_destroy", "empc_batch_autotune", "empc_batch_classes",
+            "empc_batch_class_info", "empc_batch_class_times", "empc_batch_set_variant",
+            "empc_profile_begin",
+            "empc_profile_end"]
 
 
 def _check(status: int):
@@ -189,6 +199,29 @@ def empc_solve_batched(plan, stream=None):
 
 def empc_batch_destroy(plan):
     _check(lib().empc_batch_destroy(plan))
+
+
+def empc_batch_autotune(plan, reps=5, stream=None):
+    _check(lib().empc_batch_autotune(plan, int(reps), _stream(stream)))
+
+
+def empc_batch_classes(plan) -> int:
+    return int(lib().empc_batch_classes(plan))
+
+
+def empc_batch_class_info(plan, cls) -> dict:
+    info = (ctypes.c_int32 * 7)()
+    _check(lib().empc_batch_class_info(plan, int(cls), info))
+    us = (ctypes.c_float * 4)()
+    _check(lib().empc_batch_class_times(plan, int(cls), us))
+    return {"model": "linear" if info[0] == EMPC_LINEAR else "pendulum_chain",
+            "shape": (int(info[1]), int(info[2])), "problems": int(info[3]),
+            "variant": int(info[4]), "variants": int(info[5]), "stream": int(info[6]),
+            "tuned_us": [round(float(us[v]), 1) for v in range(int(info[5]))]}
+
+
+def empc_batch_set_variant(plan, cls, variant):
+    _check(lib().empc_batch_set_variant(plan, int(cls), int(variant)))
 
 
 def empc_profile_begin(max_launches):
@@ -319,7 +352,7 @@ class BatchSolver:
     packed outputs.  The device tick counter starts at 0 and advances by one
     per solve()."""
 
-    def __init__(self, dprobs, ga):
+    def __init__(self, dprobs, ga, autotune=True, tune_reps=5):
         self.dprobs = list(dprobs)
         self.ga = make_ga(ga)
         n = len(self.dprobs)
@@ -337,6 +370,19 @@ class BatchSolver:
         self.best_cost = torch.zeros(n, dtype=torch.float32, device=dev)
         self.plan = empc_batch_create(arr, n, self.ga, self.workspace, self.x0, self.u_star,
                                       self.best_cost)
+        if autotune:
+            self.autotune(tune_reps)
+
+    def autotune(self, reps=5, stream=None):
+        """Time every launch shape of every kernel class on these problems
+        and keep the fastest (results do not depend on the choice)."""
+        empc_batch_autotune(self.plan, reps, stream)
+
+    def classes(self):
+        return [empc_batch_class_info(self.plan, i) for i in range(empc_batch_classes(self.plan))]
+
+    def set_variant(self, cls, variant):
+        empc_batch_set_variant(self.plan, cls, variant)
 
     def set_x0(self, i, x):
         self.x0[int(self.x_off[i]):int(self.x_off[i + 1])] = torch.as_tensor(

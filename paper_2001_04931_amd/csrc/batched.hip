@@ -73,14 +73,15 @@ __global__ __launch_bounds__(256) void batch_roll_chain(const BatchSlot<T> *__re
 }
 
 // chains of more than 8 joints: one candidate per 16-lane row, as in the
-// single-problem rollout (same arithmetic, same rounding)
-template <typename T, int J>
-__global__ __launch_bounds__(256) void batch_roll_chain_rows(const BatchSlot<T> *__restrict__ slots,
-                                                             const int *__restrict__ items,
-                                                             int64_t pop, int g) {
+// single-problem rollout (same arithmetic, same rounding); WPB wavefronts
+// (4 WPB candidates) per workgroup
+template <typename T, int J, int WPB>
+__global__ __launch_bounds__(64 * WPB) void batch_roll_chain_rows(const BatchSlot<T> *__restrict__ slots,
+                                                                  const int *__restrict__ items,
+                                                                  int64_t pop, int g) {
     const int64_t w = xcd_swizzle_2d();
     const BatchSlot<T> &S = slots[items[w / gridDim.x]];
-    const int64_t cand0 = (w % gridDim.x) * 16;
+    const int64_t cand0 = (w % gridDim.x) * (4 * WPB);
     if (cand0 + (threadIdx.x >> 6) * 4 >= pop) return;  // whole wavefront past the end
     chain_row_candidate<T, J>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
                               cand0 + (threadIdx.x >> 4), threadIdx.x & 15);
@@ -108,9 +109,23 @@ struct BatchClass {
     int a, b;    // linear: (NT, NU bucket); chain: (DMAX, 0)
     int first;   // offset in the device item list
     int count;
-    double work;  // rough cost estimate, to spread classes over streams
+    double work;  // cost estimate (rule-based, or measured by the autotuner)
     int stream;   // side stream its rollout runs on
+    int variant;  // launch shape, one of class_variants(); all round identically
+    float tuned_us[4] = {-1, -1, -1, -1};  // autotuner: mean launch time per shape
 };
+
+// Launch shapes a class can use.  Every shape of a class runs the same
+// per-candidate device code in the same order, so the choice changes the
+// time, never a result.
+//   linear:   0..2  one wavefront per tile, 4 / 2 / 1 wavefronts per
+//                   workgroup; 3  the M-split form (NT > 1 only)
+//   chain, lane per candidate (DMAX <= 8): 0..2  256 / 128 / 64 threads
+//   chain, row per candidate:              0..2  4 / 2 / 1 wavefronts
+int class_variants(const BatchClass &c) {
+    if (c.model == EMPC_LINEAR) return c.a > 1 ? 4 : 3;
+    return 3;
+}
 
 // The rollouts of the kernel-shape classes are independent, so they run on
 // side streams forked from and joined back into the caller's stream (in a
@@ -138,46 +153,82 @@ int dmax_bucket(int d) {
     return 48;
 }
 
-template <int NT, int NU>
-static void go_batch_linear(const BatchSlot<float> *slots, const int *items, int count,
-                            int64_t pop, int g, hipStream_t s) {
-    constexpr int WPB = 4;
+template <int NT, int NU, int WPB>
+static void go_batch_linear_wpb(const BatchSlot<float> *slots, const int *items, int count,
+                                int64_t pop, int g, hipStream_t s) {
     const int64_t tiles = (pop + 15) / 16;
-    if (NT > 1 && tiles * count < SPLIT_MAX_TILES) {
-        hipLaunchKernelGGL((batch_roll_linear_split<float, NT, NU>),
-                           dim3((unsigned)tiles, (unsigned)count), dim3(64 * NT), 0, s, slots,
-                           items, pop, g);
-        return;
-    }
     hipLaunchKernelGGL((batch_roll_linear<float, NT, NU, WPB>),
                        dim3((unsigned)((tiles + WPB - 1) / WPB), (unsigned)count), dim3(64 * WPB), 0,
                        s, slots, items, pop, g);
 }
+template <int NT, int NU>
+static void go_batch_linear(int variant, const BatchSlot<float> *slots, const int *items,
+                            int count, int64_t pop, int g, hipStream_t s) {
+    if (NT > 1 && variant == 3) {
+        hipLaunchKernelGGL((batch_roll_linear_split<float, NT, NU>),
+                           dim3((unsigned)((pop + 15) / 16), (unsigned)count), dim3(64 * NT), 0, s,
+                           slots, items, pop, g);
+        return;
+    }
+    if (variant == 1) return go_batch_linear_wpb<NT, NU, 2>(slots, items, count, pop, g, s);
+    if (variant == 2) return go_batch_linear_wpb<NT, NU, 1>(slots, items, count, pop, g, s);
+    go_batch_linear_wpb<NT, NU, 4>(slots, items, count, pop, g, s);
+}
 template <int NT>
-static void go_batch_linear_nu(int nu, const BatchSlot<float> *slots, const int *items, int count,
-                               int64_t pop, int g, hipStream_t s) {
+static void go_batch_linear_nu(int nu, int variant, const BatchSlot<float> *slots,
+                               const int *items, int count, int64_t pop, int g, hipStream_t s) {
     switch (nu) {
-        case 1: go_batch_linear<NT, 1>(slots, items, count, pop, g, s); break;
-        case 2: go_batch_linear<NT, 2>(slots, items, count, pop, g, s); break;
-        case 4: go_batch_linear<NT, 4>(slots, items, count, pop, g, s); break;
-        case 6: go_batch_linear<NT, 6>(slots, items, count, pop, g, s); break;
-        case 8: go_batch_linear<NT, 8>(slots, items, count, pop, g, s); break;
-        default: go_batch_linear<NT, 10>(slots, items, count, pop, g, s); break;
+        case 1: go_batch_linear<NT, 1>(variant, slots, items, count, pop, g, s); break;
+        case 2: go_batch_linear<NT, 2>(variant, slots, items, count, pop, g, s); break;
+        case 4: go_batch_linear<NT, 4>(variant, slots, items, count, pop, g, s); break;
+        case 6: go_batch_linear<NT, 6>(variant, slots, items, count, pop, g, s); break;
+        case 8: go_batch_linear<NT, 8>(variant, slots, items, count, pop, g, s); break;
+        default: go_batch_linear<NT, 10>(variant, slots, items, count, pop, g, s); break;
     }
 }
+template <int J, int WPB>
+static void go_batch_chain_rows_wpb(const BatchSlot<float> *slots, const int *items, int count,
+                                    int64_t pop, int g, hipStream_t s) {
+    hipLaunchKernelGGL((batch_roll_chain_rows<float, J, WPB>),
+                       dim3((unsigned)((pop + 4 * WPB - 1) / (4 * WPB)), (unsigned)count),
+                       dim3(64 * WPB), 0, s, slots, items, pop, g);
+}
 template <int J>
-static void go_batch_chain_rows(const BatchSlot<float> *slots, const int *items, int count,
-                                int64_t pop, int g, hipStream_t s) {
-    hipLaunchKernelGGL((batch_roll_chain_rows<float, J>),
-                       dim3((unsigned)((pop + 15) / 16), (unsigned)count), dim3(256), 0, s, slots,
-                       items, pop, g);
+static void go_batch_chain_rows(int variant, const BatchSlot<float> *slots, const int *items,
+                                int count, int64_t pop, int g, hipStream_t s) {
+    if (variant == 1) return go_batch_chain_rows_wpb<J, 2>(slots, items, count, pop, g, s);
+    if (variant == 2) return go_batch_chain_rows_wpb<J, 1>(slots, items, count, pop, g, s);
+    go_batch_chain_rows_wpb<J, 4>(slots, items, count, pop, g, s);
 }
 template <int DMAX>
-static void go_batch_chain(const BatchSlot<float> *slots, const int *items, int count, int64_t pop,
-                           int g, hipStream_t s) {
+static void go_batch_chain(int variant, const BatchSlot<float> *slots, const int *items,
+                           int count, int64_t pop, int g, hipStream_t s) {
+    const int threads = variant == 1 ? 128 : variant == 2 ? 64 : 256;
     hipLaunchKernelGGL((batch_roll_chain<float, DMAX>),
-                       dim3((unsigned)((pop + 255) / 256), (unsigned)count), dim3(256), 0, s, slots,
-                       items, pop, g);
+                       dim3((unsigned)((pop + threads - 1) / threads), (unsigned)count),
+                       dim3(threads), 0, s, slots, items, pop, g);
+}
+// one class's rollout launch, in its chosen shape
+static void launch_class(const BatchClass &c, int variant, const BatchSlot<float> *slots,
+                         const int *d_items, int64_t pop, int g, hipStream_t s) {
+    const int *items = d_items + c.first;
+    if (c.model == EMPC_LINEAR) {
+        switch (c.a) {
+            case 1: go_batch_linear_nu<1>(c.b, variant, slots, items, c.count, pop, g, s); break;
+            case 2: go_batch_linear_nu<2>(c.b, variant, slots, items, c.count, pop, g, s); break;
+            case 3: go_batch_linear_nu<3>(c.b, variant, slots, items, c.count, pop, g, s); break;
+            case 4: go_batch_linear_nu<4>(c.b, variant, slots, items, c.count, pop, g, s); break;
+            default: go_batch_linear_nu<5>(c.b, variant, slots, items, c.count, pop, g, s); break;
+        }
+        return;
+    }
+    switch (c.a) {
+        case 4: go_batch_chain<4>(variant, slots, items, c.count, pop, g, s); break;
+        case 8: go_batch_chain<8>(variant, slots, items, c.count, pop, g, s); break;
+        case 16: go_batch_chain_rows<1>(variant, slots, items, c.count, pop, g, s); break;
+        case 32: go_batch_chain_rows<2>(variant, slots, items, c.count, pop, g, s); break;
+        default: go_batch_chain_rows<3>(variant, slots, items, c.count, pop, g, s); break;
+    }
 }
 
 }  // namespace empc
@@ -193,7 +244,7 @@ struct empc_batch {
     BatchSlot<float> *d_slots = nullptr;
     int *d_items = nullptr;
     uint32_t *d_tick = nullptr;
-    int nstreams = 0;
+    int nstreams = 0;  // side streams in use (all BATCH_STREAMS are created)
     hipStream_t side[BATCH_STREAMS] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[BATCH_STREAMS] = {};
@@ -202,6 +253,39 @@ struct empc_batch {
 namespace {
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Spread the classes over ns side streams: largest work first, each onto
+// the least loaded stream.
+void assign_streams(empc_batch *b, int ns) {
+    b->nstreams = std::max(1, std::min<int>(ns, (int)b->classes.size()));
+    std::vector<int> order(b->classes.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::sort(order.begin(), order.end(),
+              [&](int x, int y) { return b->classes[x].work > b->classes[y].work; });
+    std::vector<double> load(b->nstreams, 0.0);
+    for (int ci : order) {
+        const int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        b->classes[ci].stream = st;
+        load[st] += b->classes[ci].work;
+    }
+}
+
+// The rollouts of one generation: fork the side streams from s, each class
+// on its stream, join them back into s.
+hipError_t rollout_phase(empc_batch *b, int g, hipStream_t s) {
+    hipError_t e = hipEventRecord(b->fork, s);
+    for (int i = 0; i < b->nstreams && e == hipSuccess; ++i)
+        e = hipStreamWaitEvent(b->side[i], b->fork, 0);
+    if (e != hipSuccess) return e;
+    for (const BatchClass &c : b->classes)
+        launch_class(c, c.variant, b->d_slots, b->d_items, b->pop, g, b->side[c.stream]);
+    for (int i = 0; i < b->nstreams && e == hipSuccess; ++i) {
+        e = hipEventRecord(b->join[i], b->side[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[i], 0);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    return e;
+}
 
 // Per-problem workspace, after a 256-byte header holding the tick counter:
 // flag (256 B), two populations [pm][pop], costs [pop], parent rows [k][pm],
@@ -303,24 +387,14 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
             const empc_problem &P = probs[i];
             c.work += (double)P.T * (P.model == EMPC_LINEAR ? 4.0 * c.a * c.a * 8.0 : 3.0 * P.m);
         }
+        // rule-based shape until the autotuner measures: the M-split form
+        // while the class has fewer tiles than the chip has SIMDs
+        c.variant = (c.model == EMPC_LINEAR && c.a > 1 &&
+                     ((ga->pop + 15) / 16) * c.count < SPLIT_MAX_TILES) ? 3 : 0;
         items.insert(items.end(), kv.second.begin(), kv.second.end());
         b->classes.push_back(c);
     }
-    // spread the classes over the side streams, largest first onto the least
-    // loaded stream
-    b->nstreams = std::min<int>(BATCH_STREAMS, (int)b->classes.size());
-    {
-        std::vector<int> order(b->classes.size());
-        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-        std::sort(order.begin(), order.end(),
-                  [&](int x, int y) { return b->classes[x].work > b->classes[y].work; });
-        std::vector<double> load(b->nstreams, 0.0);
-        for (int ci : order) {
-            const int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            b->classes[ci].stream = st;
-            load[st] += b->classes[ci].work;
-        }
-    }
+    assign_streams(b, BATCH_STREAMS);
     b->d_tick = (uint32_t *)base;
     hipError_t e = hipMalloc(&b->d_slots, sizeof(BatchSlot<float>) * nprob);
     if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(int) * items.size());
@@ -329,7 +403,7 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
     if (e == hipSuccess)
         e = hipMemcpy(b->d_items, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
-    for (int i = 0; i < b->nstreams && e == hipSuccess; ++i) {
+    for (int i = 0; i < BATCH_STREAMS && e == hipSuccess; ++i) {
         e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming);
     }
@@ -361,35 +435,7 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
                            dim3((unsigned)(pop_tiles_s(pop) * b->ngmax), (unsigned)b->nprob),
                            dim3(POP_THREADS), 0, s, b->d_slots, pop, G.n_elite, G.elitism, (float)G.sigma,
                            seed_lo, g, (const uint32_t *)b->d_tick);
-        hipError_t fe = hipEventRecord(b->fork, s);
-        for (int i = 0; i < b->nstreams && fe == hipSuccess; ++i)
-            fe = hipStreamWaitEvent(b->side[i], b->fork, 0);
-        if (fe != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(fe));
-        for (const BatchClass &c : b->classes) {
-            const int *items = b->d_items + c.first;
-            hipStream_t s = b->side[c.stream];
-            if (c.model == EMPC_LINEAR) {
-                switch (c.a) {
-                    case 1: go_batch_linear_nu<1>(c.b, b->d_slots, items, c.count, pop, g, s); break;
-                    case 2: go_batch_linear_nu<2>(c.b, b->d_slots, items, c.count, pop, g, s); break;
-                    case 3: go_batch_linear_nu<3>(c.b, b->d_slots, items, c.count, pop, g, s); break;
-                    case 4: go_batch_linear_nu<4>(c.b, b->d_slots, items, c.count, pop, g, s); break;
-                    default: go_batch_linear_nu<5>(c.b, b->d_slots, items, c.count, pop, g, s); break;
-                }
-            } else {
-                switch (c.a) {
-                    case 4: go_batch_chain<4>(b->d_slots, items, c.count, pop, g, s); break;
-                    case 8: go_batch_chain<8>(b->d_slots, items, c.count, pop, g, s); break;
-                    case 16: go_batch_chain_rows<1>(b->d_slots, items, c.count, pop, g, s); break;
-                    case 32: go_batch_chain_rows<2>(b->d_slots, items, c.count, pop, g, s); break;
-                    default: go_batch_chain_rows<3>(b->d_slots, items, c.count, pop, g, s); break;
-                }
-            }
-        }
-        for (int i = 0; i < b->nstreams && fe == hipSuccess; ++i) {
-            fe = hipEventRecord(b->join[i], b->side[i]);
-            if (fe == hipSuccess) fe = hipStreamWaitEvent(s, b->join[i], 0);
-        }
+        const hipError_t fe = rollout_phase(b, g, s);
         if (fe != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(fe));
         if (per <= 4)
             hipLaunchKernelGGL((batch_select<float, uint32_t, 4>), dim3(b->nprob), dim3(SEL_THREADS), 0,
@@ -404,6 +450,105 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
     hipLaunchKernelGGL(batch_tick_advance, dim3(1), dim3(64), 0, s, b->d_tick);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(e));
+    return EMPC_OK;
+}
+
+empc_status empc_batch_autotune(empc_batch *b, int32_t reps, void *stream) {
+    if (!b) return empc_fail_internal(EMPC_EINVAL, "batch is NULL");
+    if (reps < 1) return empc_fail_internal(EMPC_EINVAL, "reps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const empc_ga &G = b->ga;
+    // a generation-0 population, so that the timed rollouts read defined
+    // knots; the parents, costs kept across ticks and the tick counter are
+    // left as they are
+    hipLaunchKernelGGL(batch_population<float>,
+                       dim3((unsigned)(pop_tiles_s(b->pop) * b->ngmax), (unsigned)b->nprob),
+                       dim3(POP_THREADS), 0, s, b->d_slots, b->pop, G.n_elite, G.elitism,
+                       (float)G.sigma, (uint32_t)G.seed, 0, (const uint32_t *)b->d_tick);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    // mean time of one launch sequence over `reps` back-to-back runs, after
+    // one untimed run
+    auto time_it = [&](auto &&enqueue) -> float {
+        float ms = 0;
+        if (e == hipSuccess) e = enqueue();
+        if (e == hipSuccess) e = hipEventRecord(t0, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = enqueue();
+        if (e == hipSuccess) e = hipEventRecord(t1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        return ms / reps;
+    };
+    // each class alone: its fastest launch shape
+    for (BatchClass &c : b->classes) {
+        float best = 0;
+        int best_v = c.variant;
+        for (int v = 0; v < class_variants(c) && e == hipSuccess; ++v) {
+            const float ms = time_it([&]() {
+                launch_class(c, v, b->d_slots, b->d_items, b->pop, 0, s);
+                return hipGetLastError();
+            });
+            c.tuned_us[v] = ms * 1e3f;
+            if (v == 0 || ms < best) {
+                best = ms;
+                best_v = v;
+            }
+        }
+        c.variant = best_v;
+        c.work = best;
+    }
+    // then the number of side streams, with the classes spread by their
+    // measured times
+    int best_ns = 1;
+    float best = 0;
+    for (int ns = 1; ns <= std::min<int>(BATCH_STREAMS, (int)b->classes.size()) && e == hipSuccess;
+         ++ns) {
+        assign_streams(b, ns);
+        const float ms = time_it([&]() { return rollout_phase(b, 0, s); });
+        if (ns == 1 || ms < best) {
+            best = ms;
+            best_ns = ns;
+        }
+    }
+    assign_streams(b, best_ns);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(e));
+    return EMPC_OK;
+}
+
+int32_t empc_batch_classes(const empc_batch *b) { return b ? (int32_t)b->classes.size() : 0; }
+
+empc_status empc_batch_class_info(const empc_batch *b, int32_t cls, int32_t *info) {
+    if (!b || !info || cls < 0 || cls >= (int32_t)b->classes.size())
+        return empc_fail_internal(EMPC_EINVAL, "bad batch, class index or info pointer");
+    const BatchClass &c = b->classes[cls];
+    info[0] = c.model;
+    info[1] = c.a;
+    info[2] = c.b;
+    info[3] = c.count;
+    info[4] = c.variant;
+    info[5] = class_variants(c);
+    info[6] = c.stream;
+    return EMPC_OK;
+}
+
+empc_status empc_batch_class_times(const empc_batch *b, int32_t cls, float *us) {
+    if (!b || !us || cls < 0 || cls >= (int32_t)b->classes.size())
+        return empc_fail_internal(EMPC_EINVAL, "bad batch, class index or output pointer");
+    for (int v = 0; v < 4; ++v) us[v] = b->classes[cls].tuned_us[v];
+    return EMPC_OK;
+}
+
+empc_status empc_batch_set_variant(empc_batch *b, int32_t cls, int32_t variant) {
+    if (!b || cls < 0 || cls >= (int32_t)b->classes.size())
+        return empc_fail_internal(EMPC_EINVAL, "bad batch or class index");
+    BatchClass &c = b->classes[cls];
+    if (variant < 0 || variant >= class_variants(c))
+        return empc_fail_internal(EMPC_EINVAL, "no such launch shape for this class");
+    c.variant = variant;
     return EMPC_OK;
 }
 

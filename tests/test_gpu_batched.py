@@ -105,3 +105,63 @@ def test_batched_graph_replay_matches_eager(E):
         _ = eager.u_star.cpu()
     eager.close()
     graphed.close()
+
+
+def _run_ticks(bs, x0s, ticks):
+    for i, x in enumerate(x0s):
+        bs.set_x0(i, x)
+    out = []
+    for _ in range(ticks):
+        bs.solve()
+        torch.cuda.synchronize()
+        out.append((bs.u_star.clone(), bs.best_cost.clone()))
+    return out
+
+
+def test_batch_launch_shapes_round_identically(E):
+    """Every launch shape of every kernel class gives the same bits: the
+    shape only changes how candidates are packed into workgroups."""
+    probs = mixed_problems(2)
+    ga = W.GA(pop=200, n_elite=8, generations=2, sigma=0.1, seed=77)
+    dps = [E.DeviceProblem(p, F32) for p in probs]
+    x0s = [W.draw_x0(p.n, 30 + i).astype(np.float32) for i, p in enumerate(probs)]
+    base = E.BatchSolver(dps, ga, autotune=False)
+    classes = base.classes()
+    assert {c["model"] for c in classes} == {"linear", "pendulum_chain"}
+    assert any(c["variants"] == 4 for c in classes)  # a linear class with the M-split form
+    ref = _run_ticks(base, x0s, 2)
+    base.close()
+    for v in range(4):
+        bs = E.BatchSolver(dps, ga, autotune=False)
+        for ci, c in enumerate(bs.classes()):
+            bs.set_variant(ci, min(v, c["variants"] - 1))
+        assert all(c["variant"] == min(v, c["variants"] - 1) for c in bs.classes())
+        got = _run_ticks(bs, x0s, 2)
+        for t, ((u0, j0), (u1, j1)) in enumerate(zip(ref, got)):
+            assert torch.equal(u0, u1), (v, t)
+            assert torch.equal(j0, j1), (v, t)
+        with pytest.raises(E.EmpcError):
+            bs.set_variant(0, classes[0]["variants"])
+        bs.close()
+
+
+def test_batch_autotune_keeps_state_and_results(E):
+    """Autotuning between two ticks leaves the warm-start state alone: the
+    second tick equals that of an untuned plan."""
+    probs = mixed_problems(3)
+    ga = W.GA(pop=256, n_elite=16, generations=2, sigma=0.1, seed=91)
+    dps = [E.DeviceProblem(p, F32) for p in probs]
+    x0s = [W.draw_x0(p.n, 50 + i).astype(np.float32) for i, p in enumerate(probs)]
+    plain = E.BatchSolver(dps, ga, autotune=False)
+    ref = _run_ticks(plain, x0s, 2)
+    plain.close()
+    tuned = E.BatchSolver(dps, ga, autotune=True, tune_reps=2)
+    got = _run_ticks(tuned, x0s, 1)
+    tuned.autotune(2)
+    for c in tuned.classes():
+        assert 0 <= c["variant"] < c["variants"] and 0 <= c["stream"] < 4
+    got += _run_ticks(tuned, x0s, 1)
+    for t, ((u0, j0), (u1, j1)) in enumerate(zip(ref, got)):
+        assert torch.equal(u0, u1), t
+        assert torch.equal(j0, j1), t
+    tuned.close()
