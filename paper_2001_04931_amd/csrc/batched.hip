@@ -288,7 +288,7 @@ hipError_t rollout_phase(empc_batch *b, int g, hipStream_t s) {
 }
 
 // Per-problem workspace, after a 256-byte header holding the tick counter:
-// flag (256 B), two populations [pm][pop], costs [pop], parent rows [k][pm],
+// flag (256 B), two populations [pm][pop], costs [pop], parent knots [pm][k],
 // parent costs [k], parent indices [k], best index.
 size_t slot_bytes(const empc_problem &P, const empc_ga &G) {
     const size_t pm = (size_t)P.p * P.m, pop = G.pop, k = G.n_elite;

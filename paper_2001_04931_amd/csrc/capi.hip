@@ -89,7 +89,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Workspace of empc_solve, in order: header (has_elites, best_slot), two
 // population buffers [pm][pop] (generation g writes buffer g % 2 and reads
-// its parents in place from the other one), costs [pop], elite rows [k][pm]
+// its parents in place from the other one), costs [pop], elite knots [pm][k]
 // (the parents carried to the next tick), elite costs [k], elite indices
 // [k] (int64), best index (int64), and the parents as a structure of arrays
 // [pm][k] for gradient refinement.

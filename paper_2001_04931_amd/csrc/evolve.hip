@@ -65,8 +65,8 @@ template hipError_t launch_select<double>(const ProbView<double> &, const double
 // ---------------------------------------------------------------------------
 // Gradient-refined solves: the parents of a generation, gathered into a
 // structure-of-arrays block [pm][k], are refined by Adam (adjoint.hip), then
-// copied back to parent rows [k][pm] for the next population, and the best
-// refined parent gives u* and the best cost.
+// copied to the parent buffer (the same [pm][k] layout) for the next
+// population, and the best refined parent gives u* and the best cost.
 template <typename T>
 __global__ __launch_bounds__(256) void gather_parents_kernel(const T *__restrict__ knots,
                                                              int64_t ld,
@@ -88,10 +88,7 @@ __global__ __launch_bounds__(256) void finish_refine_kernel(const T *__restrict_
     typedef typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type K;
     __shared__ int s_best;
     const int tid = threadIdx.x;
-    for (int t = tid; t < k * pm; t += blockDim.x) {
-        const int s = t / pm, j = t - s * pm;
-        elite_rows[t] = E[(int64_t)j * k + s];
-    }
+    for (int t = tid; t < k * pm; t += blockDim.x) elite_rows[t] = E[t];  // same layout
     if (tid < 64) {
         K bk = ~(K)0;
         int bs = k;

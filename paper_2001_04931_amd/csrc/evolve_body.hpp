@@ -34,6 +34,21 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T &z0, T &z
     z0 = rad * cs;
     z1 = rad * sn;
 }
+// FP32: the hardware's log2, square root, sine and cosine (the last two take
+// the angle in revolutions, so 2 pi u2 needs no multiply and no range
+// reduction: u2 is in (0, 1]).  Absolute error of z below 3e-6 for |z| < 6,
+// i.e. below 3e-7 after the sigma = 0.1 scaling, against about 1e-7 for the
+// library functions; their range-reduced polynomials cost several times the
+// instructions.
+template <>
+__device__ __forceinline__ void box_muller<float>(uint32_t wa, uint32_t wb, float &z0, float &z1) {
+    const float u1 = uni23<float>(wa);
+    const float u2 = uni23<float>(wb);
+    const float rad =
+        __builtin_amdgcn_sqrtf(-2.0f * 0.6931471805599453f * __builtin_amdgcn_logf(u1));
+    z0 = rad * __builtin_amdgcn_cosf(u2);
+    z1 = rad * __builtin_amdgcn_sinf(u2);
+}
 
 // Mutation of one inherited parameter and the bounds (Sec. V warm start).
 template <typename T>
@@ -54,7 +69,8 @@ __device__ __forceinline__ T mutate_clamp(T v, bool flag, T sigma, T z, T lo, T 
 // taken once per slot by wavefronts 0, 1 and 2 and shared through LDS; each
 // thread then draws only its own normal block (two Box-Muller pairs), and
 // only if one of its four inputs is flagged.  Parent knots come from
-// elite_rows ([k][p m], when non-NULL) or from knots_in at elite_idx[.].
+// elite_rows ([p m][k], parameter-major, when non-NULL: the k parents of one
+// parameter share two cache lines) or from knots_in at elite_idx[.].
 // Inputs per problem: at most 128 (one mutation-flag block).
 constexpr int POP_SLOTS = 64;   // slots per workgroup, one per lane
 constexpr int POP_GROUPS = 4;   // groups of four parameters, one per wavefront
@@ -113,16 +129,16 @@ __device__ __forceinline__ void population_tile(
         }
     } else {
         const T *base = elite_rows ? elite_rows : knots_in;
-        const int64_t step = elite_rows ? 1 : ld_in;
+        const int64_t step = elite_rows ? k : ld_in;
         if (elitism && s < k) {
-            const int64_t src = elite_rows ? s * pm : s_eidx[s];
+            const int64_t src = elite_rows ? s : s_eidx[s];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 val[r] = j0 + r < pm ? base[src + (int64_t)(j0 + r) * step] : (T)0;
         } else {
             const int p1 = s_par[lane][0], p2 = s_par[lane][1];
-            const int64_t src1 = elite_rows ? (int64_t)p1 * pm : s_eidx[p1];
-            const int64_t src2 = elite_rows ? (int64_t)p2 * pm : s_eidx[p2];
+            const int64_t src1 = elite_rows ? (int64_t)p1 : s_eidx[p1];
+            const int64_t src2 = elite_rows ? (int64_t)p2 : s_eidx[p2];
             bool flag[4];
             int ii[4];
 #pragma unroll
@@ -440,9 +456,9 @@ __device__ __forceinline__ void select_body(
         if (elite_idx_out) elite_idx_out[s] = s_elite[s];
         if (elite_cost) elite_cost[s] = key_value(s_ekey[s]);
     }
-    if (elite_rows)
+    if (elite_rows)  // parameter-major: elite_rows[j k + s]
         for (int t = tid; t < k * pm; t += NTHR) {
-            const int s = t / pm, j = t - s * pm;
+            const int j = t / k, s = t - j * k;
             elite_rows[t] = knots[(int64_t)j * ld + s_elite[s]];
         }
     if (tid == 0) {

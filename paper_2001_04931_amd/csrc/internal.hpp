@@ -133,7 +133,7 @@ struct BatchSlot {
     const T *x0;       // n
     T *knots[2];       // [pm][pop] each
     T *cost;           // pop
-    T *elite_rows;     // [k][pm]
+    T *elite_rows;     // [pm][k], parameter-major
     T *elite_cost;     // k
     int64_t *elite_idx, *best_idx;
     int *has_elites;
@@ -292,7 +292,7 @@ hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *k
                              uint32_t tick, uint32_t gen, hipStream_t s);
 
 // Selection writes elite indices (ascending), best index, and optionally the
-// elite knot rows [k][pm], elite costs [k], the warm-start flag, u* and the
+// elite knots [pm][k] (parameter-major), elite costs [k], the warm-start flag, u* and the
 // best cost.
 template <typename T>
 hipError_t launch_select(const ProbView<T> &P, const T *cost, const T *knots, int64_t ld,

@@ -165,3 +165,23 @@ def test_batch_autotune_keeps_state_and_results(E):
         assert torch.equal(u0, u1), t
         assert torch.equal(j0, j1), t
     tuned.close()
+
+
+def test_large_population_single_matches_batched(E):
+    """A C3-sized chain (360 parameters) with a large population: the
+    single-problem solve (1024-thread selection, parents read in place after
+    the first generation) equals the batched one bit for bit."""
+    prob = W.pendulum_chain(36, 100, 10, seed=4).cast(np.float32)
+    ga = W.GA(pop=6000, n_elite=64, generations=3, sigma=0.1, seed=0x5EED)
+    dp = E.DeviceProblem(prob, F32)
+    bs = E.BatchSolver([dp], ga, autotune=False)
+    single = E.Solver(dp, ga)  # problem 0 of a batch uses the seed unchanged
+    x0 = W.draw_x0(prob.n, 11).astype(np.float32)
+    bs.set_x0(0, x0)
+    for tick in range(2):
+        bs.solve()
+        u, J = single.solve(torch.tensor(x0, device="cuda"), tick)
+        torch.cuda.synchronize()
+        assert torch.equal(bs.u_of(0), u), tick
+        assert torch.equal(bs.best_cost[0:1], J), tick
+    bs.close()
