@@ -5,11 +5,13 @@
 // elites each run a sequential chain of 3T dependent steps per Adam step, so
 // the latency of one step is what counts.  Linear model: lane i owns state i
 // (n <= 64) and, for i < m, input i, and holds row i and column i of A_d and
-// of B_d in registers; the other lanes' states (or adjoints) are read with
-// v_readlane, so a step touches no LDS and needs no barrier.  Pendulum
-// chain: lane j owns joint j (d <= 64); the cumulative angles, gravity
-// torques and the adjoint's prefix / suffix sums are wavefront scans on DPP
-// row shifts.
+// of B_d in registers; each lane publishes its state (or adjoint) to LDS and
+// reads the whole vector back with broadcast 16-byte loads (the LDS
+// operations of one wavefront complete in order, so no barrier is needed),
+// and every dot product runs on four partial sums, so its dependent chain
+// is a quarter of its length.  Pendulum chain: lane j owns joint j
+// (d <= 64); the cumulative angles, gravity torques and the adjoint's
+// prefix / suffix sums are wavefront scans on DPP row shifts.
 //
 // With lambda_k = dJ/dx_k:
 //   lambda_T = 2 (Q + Q_f)(x_T - g),
@@ -19,6 +21,8 @@
 // are stored every S = ceil(sqrt(T)) steps on the forward pass; the backward
 // pass recomputes each segment of S states from its checkpoint.
 #include <math.h>
+
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -39,8 +43,8 @@ __device__ inline double cos_f<double>(double x) { return cos(x); }
 
 // LDS plan (element counts), shared with the host-side size check.
 struct GradPlan {
-    int S, nchk;
-    size_t oU, oG, oM1, oM2, oXb, oUb, oChk, oSeg, total;
+    int S, nchk, us;  // us: row stride of the input table (m rounded up to 4)
+    size_t oU, oG, oM1, oM2, oXb, oChk, oSeg, oUk, oBu, oC, total;
 };
 inline GradPlan grad_plan(int model, int n, int m, int T, int p) {
     GradPlan g;
@@ -54,9 +58,16 @@ inline GradPlan grad_plan(int model, int n, int m, int T, int p) {
     g.oM1 = o; o += pm;
     g.oM2 = o; o += pm;
     g.oXb = o; o += 64;  // broadcast slots: states (or adjoints)
-    g.oUb = o; o += 64;  // and inputs of the current step
     g.oChk = o; o += (size_t)g.nchk * n;
     g.oSeg = o; o += (size_t)g.S * n;
+    // per-step tables of the current knots: inputs u_k (rows of us, plus
+    // 64 of padding for whole-vector reads of the last row), the linear
+    // model's B_d u_k + w_d, and the blend weights c_k
+    g.us = (m + 3) / 4 * 4;
+    o = (o + 3) / 4 * 4;  // 16-byte aligned rows (whole-vector reads)
+    g.oUk = o; o += (size_t)T * g.us + 64;
+    g.oBu = o; o += model == EMPC_LINEAR ? (size_t)T * n : 0;
+    g.oC = o; o += (size_t)T;
     g.total = o;
     return g;
 }
@@ -68,9 +79,9 @@ struct Lane {
     T cg, invI, kst, dmp, wq, wv, wqf, wvf, gq, gv, wr, gu;  // chain joint j
 };
 
-// LIN: linear model with NMAX >= n, m (register operand length); else the
-// pendulum chain (NMAX unused).
-template <typename T, bool LIN, int NMAX>
+// LIN: linear model with NMAX >= n and MMAX >= m (register operand
+// lengths); else the pendulum chain (NMAX, MMAX unused).
+template <typename T, bool LIN, int NMAX, int MMAX>
 __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
                                                      const T *__restrict__ x0,
                                                      const T *__restrict__ knots, int64_t ld,
@@ -82,7 +93,8 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
     T *sU = sm + G.oU, *sG = sm + G.oG;
     T *sM1 = sm + G.oM1, *sM2 = sm + G.oM2;
     T *sChk = sm + G.oChk, *sSeg = sm + G.oSeg;
-    T *sXb = sm + G.oXb, *sUb = sm + G.oUb;
+    T *sXb = sm + G.oXb;
+    T *sUk = sm + G.oUk, *sBu = sm + G.oBu, *sC = sm + G.oC;
     const int lane = threadIdx.x;
     const int64_t cand = blockIdx.x;
     const int n = P.n, m = P.m, pm = P.p * P.m, Tn = P.Tn, S = G.S;
@@ -90,15 +102,17 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
     const bool refine = steps > 0;
 
     // ---- load: row and column `lane` of A_d and B_d (zero padded)
-    constexpr int NR = LIN ? NMAX : 1;
-    T aRow[NR], aCol[NR], bRow[NR], bCol[NR];
+    constexpr int NR = LIN ? NMAX : 4;
+    constexpr int MR = LIN ? MMAX : 4;
+    T aRow[NR], aCol[NR], bRow[MR], bCol[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         aRow[j] = (LIN && lane < n && j < n) ? P.Ad[lane * n + j] : (T)0;
         aCol[j] = (LIN && lane < n && j < n) ? P.Ad[j * n + lane] : (T)0;
-        bRow[j] = (LIN && lane < n && j < m) ? P.Bd[lane * m + j] : (T)0;
         bCol[j] = (LIN && lane < m && j < n) ? P.Bd[j * m + lane] : (T)0;
     }
+#pragma unroll
+    for (int j = 0; j < MR; ++j) bRow[j] = (LIN && lane < n && j < m) ? P.Bd[lane * m + j] : (T)0;
     const T *src = refine ? knots_io : knots;
     for (int j = lane; j < pm; j += 64) {
         sU[j] = src[(int64_t)j * ld + cand];
@@ -142,35 +156,57 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
 
     const int d = m;  // chain joints
     // lane-owned state: linear xi (state lane); chain (q, v) of joint lane
-    auto input_kn = [&](const Knot &kn) -> T {  // lane's own input (lane < m)
-        const T c = (T)kn.rem / (T)kn.den;
-        if (lane >= m) return (T)0;
-        return ((T)1 - c) * sU[kn.a * m + lane] + c * sU[kn.b * m + lane];
-    };
-    auto input_at = [&](int k) -> T { return input_kn(knot_at(Tn, P.p, k)); };
     // sum_j c[j] v_j with v_j published by lane j: one LDS store per lane,
     // then every lane reads the vector back 16 bytes at a time (broadcast
     // reads).  The LDS operations of a wavefront complete in order, so the
     // reads see the stores; the next store comes after these values are used.
     typedef T vec __attribute__((ext_vector_type(16 / sizeof(T))));
     constexpr int VW = 16 / sizeof(T);
-    auto bcast_dot = [&](T *slot, T v, const T *c, T acc) -> T {
-        slot[lane] = v;
+    // acc + sum_{j < N} c[j] w_j over the vector published at `slot`, in
+    // four partial sums (term j goes to sum j mod 4), added pairwise
+    auto slot_dot = [&](const T *slot, const T *c, auto NC, T acc) -> T {
+        constexpr int N = decltype(NC)::value;
+        T a[4] = {acc, (T)0, (T)0, (T)0};
 #pragma unroll
-        for (int j = 0; j < NR; j += VW) {
+        for (int j = 0; j < N; j += VW) {
             const vec w = *reinterpret_cast<const vec *>(slot + j);
 #pragma unroll
-            for (int q = 0; q < VW; ++q) acc += c[j + q] * w[q];
+            for (int q = 0; q < VW; ++q) a[(j + q) & 3] += c[j + q] * w[q];
         }
-        return acc;
+        return (a[0] + a[1]) + (a[2] + a[3]);
     };
-    // one linear step: xi <- A x + (B u + w) (lane j < m holds u_j); the
-    // input part does not depend on the state, so its LDS round trip and
-    // products overlap the state's
-    auto lin_step = [&](T xi, T u) -> T {
-        const T bu = bcast_dot(sUb, lane < m ? u : (T)0, bRow, L.w);
-        const T ax = bcast_dot(sXb, lane < n ? xi : (T)0, aRow, (T)0);
-        return lane < n ? ax + bu : (T)0;
+    // Tables of the current knots, built before each forward pass (the
+    // iterations are independent, so they pipeline): c_k, the lane's input
+    // u_k, and for the linear model B_d u_k + w_d.  The step chains then
+    // read them instead of interpolating and multiplying.  (Each lane reads
+    // the u_k rows it needs only after its own writes and those of the other
+    // lanes: the LDS operations of a wavefront complete in order.)
+    auto tabulate = [&]() {
+        for (int k = lane; k < Tn; k += 64) {
+            const Knot kn = knot_at(Tn, P.p, k);
+            sC[k] = (T)kn.rem / (T)kn.den;
+        }
+        for (int k = 0; k < Tn; ++k) {
+            const Knot kn = knot_at(Tn, P.p, k);
+            const T c = sC[k];
+            if (lane < G.us)
+                sUk[k * G.us + lane] =
+                    lane < m ? ((T)1 - c) * sU[kn.a * m + lane] + c * sU[kn.b * m + lane] : (T)0;
+        }
+        sUk[Tn * G.us + lane] = 0;  // padding read by the last row's vector loads
+        if (lin)
+            for (int k = 0; k < Tn; ++k) {
+                const T bu = slot_dot(sUk + k * G.us, bRow, std::integral_constant<int, MR>(), L.w);
+                if (lane < n) sBu[k * n + lane] = bu;
+            }
+    };
+    // the lane's input at step k (0 for lanes >= m)
+    auto input_at = [&](int k) -> T { return sUk[k * G.us + lane]; };
+    // one linear step: xi <- A x + (B u_k + w)
+    auto lin_step = [&](T xi, int k) -> T {
+        sXb[lane] = lane < n ? xi : (T)0;
+        const T ax = slot_dot(sXb, aRow, std::integral_constant<int, NR>(), (T)0);
+        return lane < n ? ax + sBu[k * n + lane] : (T)0;
     };
     auto chain_step = [&](T &q, T &v, T u) {
         const T phi = wave_scan_up<T>(q);
@@ -183,6 +219,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
 
     // forward pass: returns J; stores checkpoints when chk != 0
     auto forward = [&](bool chk, T &xi, T &qj, T &vj) -> T {
+        tabulate();
         T J = 0;
         xi = (lin && lane < n) ? x0[lane] : (T)0;
         qj = (!lin && lane < d) ? x0[lane] : (T)0;
@@ -198,7 +235,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
             }
             const T u = input_at(k);
             if (lin) {
-                xi = lin_step(xi, u);
+                xi = lin_step(xi, k);
                 const T e = L.xg - xi, eu = L.ug - u;
                 J += L.q * e * e + L.r * eu * eu;
             } else {
@@ -256,33 +293,24 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
                     sSeg[(k - k0) * n + d + lane] = vj;
                 }
                 if (k + 1 < k1) {
-                    const T u = input_at(k);
                     if (lin) {
-                        xi = lin_step(xi, u);
+                        xi = lin_step(xi, k);
                     } else {
-                        chain_step(qj, vj, u);
+                        chain_step(qj, vj, input_at(k));
                     }
                 }
             }
             __syncthreads();
             for (int k = k1 - 1; k >= k0; --k) {
                 const Knot kn = knot_at(Tn, P.p, k);
-                const T c = (T)kn.rem / (T)kn.den;
-                const T u = input_kn(kn);
+                const T c = sC[k];
+                const T u = input_at(k);
                 T gu;
                 if (lin) {
                     // B^T lambda and A^T lambda, lambda_i published by lane i
-                    T bu = 0, ax = 0;
                     sXb[lane] = lane < n ? lam : (T)0;
-#pragma unroll
-                    for (int i = 0; i < NR; i += VW) {
-                        const vec w = *reinterpret_cast<const vec *>(sXb + i);
-#pragma unroll
-                        for (int q = 0; q < VW; ++q) {
-                            bu += bCol[i + q] * w[q];
-                            ax += aCol[i + q] * w[q];
-                        }
-                    }
+                    const T bu = slot_dot(sXb, bCol, std::integral_constant<int, NR>(), (T)0);
+                    const T ax = slot_dot(sXb, aCol, std::integral_constant<int, NR>(), (T)0);
                     gu = (T)2 * L.r * (u - L.ug) + bu;
                     if (k >= 1 && lane < n) {
                         const T xk = sSeg[(k - k0) * n + lane];
@@ -382,11 +410,18 @@ hipError_t launch_grad(const ProbView<T> &P, int model, const T *x0, const T *kn
                            dJ, cost, refine_steps, lr, knots_io, cost_io);
         return hipGetLastError();
     };
-    if (model != EMPC_LINEAR) return go(adjoint_kernel<T, false, 1>);
-    const int nm = P.n > P.m ? P.n : P.m;
-    if (nm <= 16) return go(adjoint_kernel<T, true, 16>);
-    if (nm <= 32) return go(adjoint_kernel<T, true, 32>);
-    return go(adjoint_kernel<T, true, 64>);
+    if (model != EMPC_LINEAR) return go(adjoint_kernel<T, false, 4, 4>);
+    // register operand lengths: n and m each rounded up to 16, 32 or 64
+    const int nb = P.n <= 16 ? 16 : P.n <= 32 ? 32 : 64;
+    const int mb = P.m <= 16 ? 16 : P.m <= 32 ? 32 : 64;
+    switch (nb * 100 + mb) {
+        case 1616: return go(adjoint_kernel<T, true, 16, 16>);
+        case 3216: return go(adjoint_kernel<T, true, 32, 16>);
+        case 3232: return go(adjoint_kernel<T, true, 32, 32>);
+        case 6416: return go(adjoint_kernel<T, true, 64, 16>);
+        case 6432: return go(adjoint_kernel<T, true, 64, 32>);
+        default: return go(adjoint_kernel<T, true, 64, 64>);
+    }
 }
 template hipError_t launch_grad<float>(const ProbView<float> &, int, const float *, const float *,
                                        int64_t, int64_t, float *, float *, int, float, float *,
