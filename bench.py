@@ -19,8 +19,10 @@ plant step.  Printed as one JSON line:
   cpu_baseline the FP64 oracle on a bounded sample of the same workload;
   workloads   the other configurations measured the same way: 2-DoF chain
               in FP64, 36-link pendulum chain, the gradient-refined form of
-              the 14-DoF run beside plain EMPC, and 512 uneven problems
-              solved together, one HIP-graph replay per tick.
+              the 14-DoF run beside plain EMPC, 512 uneven problems solved
+              together, one HIP-graph replay per tick, and the 14-DoF loop
+              with 1 / 3 / 20 generations per tick and the warm-start
+              variants.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -152,7 +154,7 @@ def summary(rate, lats, **extra):
     return d
 
 
-WORKLOADS = ("c1", "c3", "c4", "c5")
+WORKLOADS = ("c1", "c3", "c4", "c5", "c2v")
 
 
 def other_workloads(E, W, names=WORKLOADS):
@@ -173,7 +175,30 @@ def other_workloads(E, W, names=WORKLOADS):
         out.update(refined_workload(E, W))
     if "c5" in names:
         out.update(batched_workload(E, W))
+    if "c2v" in names:
+        out.update(variants_workload(E, W))
     return out
+
+
+def variants_workload(E, W):
+    """The 14-DoF closed loop with fewer generations per tick (the paper's one
+    and three iterations per control step) and with the warm-start variants
+    (carried parents moved one step later per tick, noise growing with the
+    distance to the goal): throughput, latency and the mean best cost of
+    the ticks (lower: the loop holds the chain nearer the goal)."""
+    import torch
+
+    prob, ga = W.config_c2(0)
+    runs = {"G1": dict(generations=1), "G3": dict(generations=3), "G20": {},
+            "G20_shift_noise_schedule": dict(shift=True, sigma_min=0.01, sigma_dist=1.0)}
+    out = {}
+    for name, kw in runs.items():
+        g = W.dataclasses.replace(ga, **kw)
+        rate, lats, costs = closed_loop(E, W, prob, g, torch.float32, 30, 2, noise_std=1e-3)
+        out[name] = summary(rate, lats, ticks=30, dtype="f32", generations=g.generations,
+                            mean_best_cost=float(np.mean(costs)),
+                            last_best_cost=float(costs[-1]))
+    return {"c2_variants": out}
 
 
 def refined_workload(E, W):
@@ -244,7 +269,7 @@ def main():
     ap.add_argument("--cpu-ticks", type=int, default=8, help="oracle ticks for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-workloads", action="store_true",
-                    help="skip the other configurations (C1, C3, C4, C5)")
+                    help="skip the other configurations (C1, C3, C4, C5, C2 variants)")
     ap.add_argument("--only", choices=WORKLOADS, default=None,
                     help="run only this other configuration (for profiling) and print "
                          "its summary instead of the benchmark line")

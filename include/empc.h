@@ -94,6 +94,19 @@ typedef struct {
                          /*    0..n_elite-1; 0: every slot is a child            */
     double sigma;        /* standard deviation of the mutation noise             */
     uint64_t seed;       /* key of the counter-based random streams              */
+    /* Warm-start and exploration variants (all 0: the plain method).
+     * shift = 1: at the first generation of a warm-started solve the carried
+     *   parents are moved one control step later in time, knot j taking the
+     *   carried input at its time plus one step, (1-d) U_j + d U_{j+1} with
+     *   d = (p-1)/(T-1), and the last knot held; the parents kept by elitism
+     *   are the moved ones (the receding horizon advances by one step per
+     *   tick).
+     * sigma_dist > 0: the mutation noise of a solve is
+     *   sigma_min + (sigma - sigma_min) min(1, |x0 - x_goal|_2 / sigma_dist),
+     *   smaller near the goal (Sec. VII); otherwise sigma is used as is. */
+    int32_t shift;
+    double sigma_min;    /* noise at the goal, 0 <= sigma_min                    */
+    double sigma_dist;   /* distance at which the noise reaches sigma, >= 0      */
 } empc_ga;
 
 /* Human-readable name of a status code (static string). */

@@ -49,7 +49,9 @@ class _OrProblem(ctypes.Structure):
 class _OrGA(ctypes.Structure):
     _fields_ = [("pop", ctypes.c_int), ("n_elite", ctypes.c_int),
                 ("generations", ctypes.c_int), ("elitism", ctypes.c_int),
-                ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("shift", ctypes.c_int), ("sigma_min", ctypes.c_double),
+                ("sigma_dist", ctypes.c_double)]
 
 
 _lib = None
@@ -80,6 +82,9 @@ def lib():
                                ctypes.POINTER(ctypes.c_int), _dp, ctypes.c_uint32, _dp, _dp, _dp,
                                _dp, _dp, _i64p, ctypes.c_int, ctypes.c_double, ctypes.c_int]
         L.or_solve.restype = ctypes.c_int
+        L.or_shift_knots.argtypes = [ctypes.POINTER(_OrProblem), _dp, ctypes.c_int]
+        L.or_sigma_at.argtypes = [ctypes.POINTER(_OrProblem), ctypes.POINTER(_OrGA), _dp]
+        L.or_sigma_at.restype = ctypes.c_double
         L.or_grad.argtypes = [ctypes.POINTER(_OrProblem), _dp, _dp, ctypes.c_int64,
                               ctypes.c_int64, _dp, _dp]
         L.or_refine.argtypes = [ctypes.POINTER(_OrProblem), _dp, _dp, ctypes.c_int64,
@@ -129,7 +134,26 @@ def _ga_struct(ga, pop=None):
     g.elitism = 1 if ga.elitism else 0
     g.sigma = float(ga.sigma)
     g.seed = int(ga.seed)
+    g.shift = 1 if getattr(ga, "shift", False) else 0
+    g.sigma_min = float(getattr(ga, "sigma_min", 0.0))
+    g.sigma_dist = float(getattr(ga, "sigma_dist", 0.0))
     return g
+
+
+def shift_knots(prob, rows):
+    """Parent rows [k][p*m] moved one control step later (a copy)."""
+    P = OracleProblem(prob)
+    out = np.array(rows, dtype=np.float64, order="C", copy=True)
+    lib().or_shift_knots(P.ref, _ptr(out), out.shape[0])
+    return out
+
+
+def sigma_at(prob, ga, x0):
+    """Mutation noise of a solve from state x0."""
+    P = OracleProblem(prob)
+    G = _ga_struct(ga)
+    x0 = _f64(x0)
+    return float(lib().or_sigma_at(P.ref, ctypes.byref(G), _ptr(x0)))
 
 
 def philox4x32_10(ctr, key):

@@ -515,6 +515,40 @@ void or_refine(const or_problem *P, const double *x0, double *knots, int64_t nca
  * each generation.  refine != 0 applies or_refine to the elites after each
  * selection.  Returns the index of the best candidate in the last
  * generation. */
+/* ---------------------------------------------------------------------------
+ * Warm start moved one control step later (a variant; the paper keeps the
+ * parents as they are).  Knot a sits at step a (T-1)/(p-1); the moved knot a
+ * is the carried input one step after that time, which lies between knots a
+ * and a+1 at the fraction d = (p-1)/(T-1) of their spacing, so
+ * U'_a = (1-d) U_a + d U_{a+1}; the last knot has no successor and is held.
+ * rows: k rows of p*m parameters, moved in place. */
+void or_shift_knots(const or_problem *P, double *rows, int k) {
+    int m = P->m, p = P->p, pm = p * m;
+    if (p < 2) return;
+    double d = (double)(p - 1) / (double)(P->T - 1);
+    for (int s = 0; s < k; ++s) {
+        double *U = rows + (size_t)s * pm;
+        for (int a = 0; a < p - 1; ++a)
+            for (int i = 0; i < m; ++i) U[a * m + i] = (1.0 - d) * U[a * m + i] + d * U[(a + 1) * m + i];
+    }
+}
+
+/* Mutation noise of a solve from state x0 (Sec. VII: exploration noise as a
+ * function of the distance to the goal; the function is not given, so: linear
+ * in the Euclidean distance, sigma_min at the goal, sigma from sigma_dist
+ * on).  sigma_dist = 0 keeps sigma. */
+double or_sigma_at(const or_problem *P, const or_ga *G, const double *x0) {
+    if (!(G->sigma_dist > 0.0)) return G->sigma;
+    double d2 = 0.0;
+    for (int i = 0; i < P->n; ++i) {
+        double e = x0[i] - x_goal_at(P, i);
+        d2 += e * e;
+    }
+    double r = sqrt(d2) / G->sigma_dist;
+    if (r > 1.0) r = 1.0;
+    return G->sigma_min + (G->sigma - G->sigma_min) * r;
+}
+
 int or_solve(const or_problem *P, const or_ga *G, double *elite_knots, int *has_elites,
              const double *x0, uint32_t tick, double *u_star, double *best_cost,
              double *gen_best, double *knots_ws, double *cost_ws, int64_t *idx_ws, int refine,
@@ -525,8 +559,11 @@ int or_solve(const or_problem *P, const or_ga *G, double *elite_knots, int *has_
     int best_slot = 0;
     double *ek = (double *)malloc(sizeof(double) * (size_t)k * pm);
     double *ec = (double *)malloc(sizeof(double) * (size_t)k);
+    or_ga Gt = *G; /* this solve's noise */
+    Gt.sigma = or_sigma_at(P, G, x0);
+    if (G->shift && *has_elites) or_shift_knots(P, elite_knots, k);
     for (int g = 0; g < G->generations; ++g) {
-        or_next_population(P, G, elite_knots, !*has_elites, tick, (uint32_t)g, knots_ws, pop);
+        or_next_population(P, &Gt, elite_knots, !*has_elites, tick, (uint32_t)g, knots_ws, pop);
         or_rollout_cost(P, x0, knots_ws, pop, pop, cost_ws);
         or_select(cost_ws, pop, k, idx_ws, &best);
         for (int s = 0; s < k; ++s) {

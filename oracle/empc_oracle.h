@@ -63,6 +63,9 @@ typedef struct {
     int pop, n_elite, generations, elitism;
     double sigma;
     uint64_t seed;
+    int shift;          /* 1: move the carried parents one step later per solve */
+    double sigma_min;   /* noise at the goal (sigma_dist > 0)                    */
+    double sigma_dist;  /* > 0: distance-dependent noise, see or_sigma_at        */
 } or_ga;
 
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -77,6 +80,8 @@ void or_rollout_cost(const or_problem *P, const double *x0, const double *knots,
 void or_select(const double *cost, int64_t pop, int k, int64_t *elite_idx, int64_t *best);
 void or_next_population(const or_problem *P, const or_ga *G, const double *elite_knots, int cold,
                         uint32_t tick, uint32_t gen, double *knots, int64_t ld);
+void or_shift_knots(const or_problem *P, double *rows, int k);
+double or_sigma_at(const or_problem *P, const or_ga *G, const double *x0);
 int or_solve(const or_problem *P, const or_ga *G, double *elite_knots, int *has_elites,
              const double *x0, uint32_t tick, double *u_star, double *best_cost,
              double *gen_best, double *knots_ws, double *cost_ws, int64_t *idx_ws, int refine,

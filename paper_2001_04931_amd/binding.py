@@ -44,7 +44,9 @@ class EmpcProblem(ctypes.Structure):
 class EmpcGA(ctypes.Structure):
     _fields_ = [("pop", ctypes.c_int32), ("n_elite", ctypes.c_int32),
                 ("generations", ctypes.c_int32), ("elitism", ctypes.c_int32),
-                ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("shift", ctypes.c_int32), ("sigma_min", ctypes.c_double),
+                ("sigma_dist", ctypes.c_double)]
 
 
 _lib = None
@@ -290,6 +292,9 @@ def make_ga(ga) -> EmpcGA:
     g.pop, g.n_elite, g.generations = int(ga.pop), int(ga.n_elite), int(ga.generations)
     g.elitism = 1 if getattr(ga, "elitism", True) else 0
     g.sigma, g.seed = float(ga.sigma), int(ga.seed)
+    g.shift = 1 if getattr(ga, "shift", False) else 0
+    g.sigma_min = float(getattr(ga, "sigma_min", 0.0))
+    g.sigma_dist = float(getattr(ga, "sigma_dist", 0.0))
     return g
 
 

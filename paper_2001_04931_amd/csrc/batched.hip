@@ -21,7 +21,8 @@ template <typename T>
 __global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<T> *__restrict__ slots,
                                                         int64_t pop, int k, int elitism, T sigma,
                                                         uint32_t seed_lo, int g,
-                                                        const uint32_t *__restrict__ tick) {
+                                                        const uint32_t *__restrict__ tick,
+                                                        int shift, T sigma_min, T sigma_dist) {
     const BatchSlot<T> &S = slots[blockIdx.y];
     const ProbView<T> P = S.P;
     GaStreams gs;
@@ -32,10 +33,15 @@ __global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<
     const bool first = g == 0;
     const bool cold = first && *S.has_elites == 0;
     const int64_t nts = pop_tiles_s(pop);
+    PopVariant<T> var;
+    var.x0 = S.x0;
+    var.sigma_min = sigma_min;
+    var.sigma_dist = sigma_dist;
+    var.shift = first ? shift : 0;
     population_tile<T>(P, gs, pop, k, elitism, sigma, first ? nullptr : S.knots[(g + 1) & 1], pop,
                        first ? nullptr : S.elite_idx, first ? S.elite_rows : nullptr, cold,
                        S.knots[g & 1], pop, *tick, (uint32_t)g, blockIdx.x % nts,
-                       (int)(blockIdx.x / nts));
+                       (int)(blockIdx.x / nts), var);
 }
 
 template <typename T, int NT, int NU, int WPB>
@@ -434,7 +440,8 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
         hipLaunchKernelGGL(batch_population<float>,
                            dim3((unsigned)(pop_tiles_s(pop) * b->ngmax), (unsigned)b->nprob),
                            dim3(POP_THREADS), 0, s, b->d_slots, pop, G.n_elite, G.elitism, (float)G.sigma,
-                           seed_lo, g, (const uint32_t *)b->d_tick);
+                           seed_lo, g, (const uint32_t *)b->d_tick, G.shift, (float)G.sigma_min,
+                           (float)G.sigma_dist);
         const hipError_t fe = rollout_phase(b, g, s);
         if (fe != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(fe));
         if (per <= 4)
@@ -464,7 +471,8 @@ empc_status empc_batch_autotune(empc_batch *b, int32_t reps, void *stream) {
     hipLaunchKernelGGL(batch_population<float>,
                        dim3((unsigned)(pop_tiles_s(b->pop) * b->ngmax), (unsigned)b->nprob),
                        dim3(POP_THREADS), 0, s, b->d_slots, b->pop, G.n_elite, G.elitism,
-                       (float)G.sigma, (uint32_t)G.seed, 0, (const uint32_t *)b->d_tick);
+                       (float)G.sigma, (uint32_t)G.seed, 0, (const uint32_t *)b->d_tick, G.shift,
+                       (float)G.sigma_min, (float)G.sigma_dist);
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventCreate(&t0);

@@ -82,6 +82,11 @@ empc_status validate_ga(const empc_ga *G) {
         return fail(EMPC_EUNSUPPORTED, "n_elite=%d above %d", G->n_elite, Limits::MAX_ELITE);
     if (G->generations < 1) return fail(EMPC_EINVAL, "generations=%d must be >= 1", G->generations);
     if (!(G->sigma >= 0.0) || !isfinite(G->sigma)) return fail(EMPC_EINVAL, "sigma must be finite, >= 0");
+    if (G->shift != 0 && G->shift != 1) return fail(EMPC_EINVAL, "shift=%d must be 0 or 1", G->shift);
+    if (!(G->sigma_min >= 0.0) || !isfinite(G->sigma_min))
+        return fail(EMPC_EINVAL, "sigma_min must be finite, >= 0");
+    if (!(G->sigma_dist >= 0.0) || !isfinite(G->sigma_dist))
+        return fail(EMPC_EINVAL, "sigma_dist must be finite, >= 0");
     return EMPC_OK;
 }
 
@@ -177,12 +182,15 @@ empc_status solve_t(const empc_problem *P, const empc_ga *G, const Workspace &w,
         // generation 0 starts from the parents carried over from the last
         // tick (or cold-starts); later ones read their parents in place
         // (with refinement the parents are always the refined parent rows)
+        // (the optional shift moves the carried parents once, at generation 0)
+        const PopVariant<T> var = pop_variant<T>(*G, x0, g == 0);
         hipError_t e = (g == 0 || refine)
                            ? launch_population<T>(V, *G, nullptr, 0, nullptr,
                                                   (const T *)w.elite_rows, w.has_elites,
-                                                  g == 0 ? 2 : 0, cur, pop, tick, (uint32_t)g, s)
+                                                  g == 0 ? 2 : 0, cur, pop, tick, (uint32_t)g, s,
+                                                  var)
                            : launch_population<T>(V, *G, prev, pop, w.elite_idx, nullptr,
-                                                  nullptr, 0, cur, pop, tick, (uint32_t)g, s);
+                                                  nullptr, 0, cur, pop, tick, (uint32_t)g, s, var);
         if (e != hipSuccess) return device_status(e, "population launch");
         e = timed_rollout<T>(V, P->model, (const T *)x0, cur, pop, pop, (T *)w.cost, s);
         if (e != hipSuccess) return device_status(e, "rollout launch");

@@ -8,23 +8,27 @@ template <typename T>
 hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *knots_in,
                              int64_t ld_in, const int64_t *elite_idx, const T *elite_rows,
                              const int *has_elites, int cold_mode, T *knots_out, int64_t ld_out,
-                             uint32_t tick, uint32_t gen, hipStream_t s) {
+                             uint32_t tick, uint32_t gen, hipStream_t s,
+                             const PopVariant<T> &var) {
     const int pm = P.p * P.m;
     const GaStreams gs = ga_streams(ga.seed, P.m, pm);
     const int64_t blocks = pop_tiles_s(ga.pop) * pop_tiles_g(pm);
     hipLaunchKernelGGL(population_kernel<T>, dim3((unsigned)blocks), dim3(POP_THREADS), 0, s, P, gs,
                        (int64_t)ga.pop, ga.n_elite, ga.elitism, (T)ga.sigma, knots_in, ld_in,
-                       elite_idx, elite_rows, has_elites, cold_mode, knots_out, ld_out, tick, gen);
+                       elite_idx, elite_rows, has_elites, cold_mode, knots_out, ld_out, tick, gen,
+                       var);
     return hipGetLastError();
 }
 template hipError_t launch_population<float>(const ProbView<float> &, const empc_ga &,
                                              const float *, int64_t, const int64_t *,
                                              const float *, const int *, int, float *, int64_t,
-                                             uint32_t, uint32_t, hipStream_t);
+                                             uint32_t, uint32_t, hipStream_t,
+                                             const PopVariant<float> &);
 template hipError_t launch_population<double>(const ProbView<double> &, const empc_ga &,
                                               const double *, int64_t, const int64_t *,
                                               const double *, const int *, int, double *,
-                                              int64_t, uint32_t, uint32_t, hipStream_t);
+                                              int64_t, uint32_t, uint32_t, hipStream_t,
+                                              const PopVariant<double> &);
 
 template <typename T>
 hipError_t launch_select(const ProbView<T> &P, const T *cost, const T *knots, int64_t ld,

@@ -81,7 +81,7 @@ __device__ __forceinline__ void population_tile(
     const ProbView<T> &P, const GaStreams &gs, int64_t pop, int k, int elitism, T sigma,
     const T *__restrict__ knots_in, int64_t ld_in, const int64_t *__restrict__ elite_idx,
     const T *__restrict__ elite_rows, bool cold, T *__restrict__ knots_out, int64_t ld_out,
-    uint32_t tick, uint32_t gen, int64_t tile_s, int tile_g) {
+    uint32_t tick, uint32_t gen, int64_t tile_s, int tile_g, const PopVariant<T> &var) {
     __shared__ int s_par[POP_SLOTS][2];
     __shared__ int64_t s_eidx[Limits::MAX_ELITE];
     __shared__ uint32_t s_flag[POP_SLOTS][4];
@@ -119,6 +119,17 @@ __device__ __forceinline__ void population_tile(
     }
     __syncthreads();
     if (s >= pop || j0 >= pm) return;
+    // distance-dependent mutation noise (Sec. VII): sigma_min at the goal,
+    // growing linearly to sigma at distance sigma_dist (uniform per wavefront)
+    if (var.sigma_dist > (T)0) {
+        T d2 = 0;
+        for (int i = 0; i < P.n; ++i) {
+            const T e = var.x0[i] - (P.xg ? P.xg[i] : (T)0);
+            d2 += e * e;
+        }
+        const T r = sqrt(d2) / var.sigma_dist;
+        sigma = var.sigma_min + (sigma - var.sigma_min) * (r < (T)1 ? r : (T)1);
+    }
     T val[4];
     if (cold) {
         const U4 wc = ga_draw(gs, slot, gen, tick, 1, (uint32_t)(j0 / 4));
@@ -130,11 +141,19 @@ __device__ __forceinline__ void population_tile(
     } else {
         const T *base = elite_rows ? elite_rows : knots_in;
         const int64_t step = elite_rows ? k : ld_in;
+        // parameter j of the parent stored at src; with the shift, the
+        // carried input one control step later, (1-d) U_a + d U_{a+1} for
+        // knot a < p-1 (d = (p-1)/(T-1), the knot spacing in steps inverted)
+        const T d = P.p > 1 ? (T)(P.p - 1) / (T)(P.Tn - 1) : (T)0;
+        auto parent = [&](int64_t src, int j) -> T {
+            const T v = base[src + (int64_t)j * step];
+            if (!var.shift || j / m >= P.p - 1) return v;
+            return ((T)1 - d) * v + d * base[src + (int64_t)(j + m) * step];
+        };
         if (elitism && s < k) {
             const int64_t src = elite_rows ? s : s_eidx[s];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                val[r] = j0 + r < pm ? base[src + (int64_t)(j0 + r) * step] : (T)0;
+            for (int r = 0; r < 4; ++r) val[r] = j0 + r < pm ? parent(src, j0 + r) : (T)0;
         } else {
             const int p1 = s_par[lane][0], p2 = s_par[lane][1];
             const int64_t src1 = elite_rows ? (int64_t)p1 : s_eidx[p1];
@@ -160,8 +179,8 @@ __device__ __forceinline__ void population_tile(
                     continue;
                 }
                 const bool from2 = (s_xw[lane][jb / 32] >> (jb % 32)) & 1u;
-                val[r] = mutate_clamp<T>(base[(from2 ? src2 : src1) + (int64_t)j * step], flag[r],
-                                         sigma, z[r], P.umin[ii[r]], P.umax[ii[r]]);
+                val[r] = mutate_clamp<T>(parent(from2 ? src2 : src1, j), flag[r], sigma, z[r],
+                                         P.umin[ii[r]], P.umax[ii[r]]);
             }
         }
     }
@@ -179,11 +198,12 @@ __global__ __launch_bounds__(POP_THREADS) void population_kernel(
     ProbView<T> P, GaStreams gs, int64_t pop, int k, int elitism, T sigma,
     const T *__restrict__ knots_in, int64_t ld_in, const int64_t *__restrict__ elite_idx,
     const T *__restrict__ elite_rows, const int *__restrict__ has_elites, int cold_mode,
-    T *__restrict__ knots_out, int64_t ld_out, uint32_t tick, uint32_t gen) {
+    T *__restrict__ knots_out, int64_t ld_out, uint32_t tick, uint32_t gen, PopVariant<T> var) {
     const bool cold = cold_mode == 1 || (cold_mode == 2 && *has_elites == 0);
     const int64_t nts = pop_tiles_s(pop);
     population_tile<T>(P, gs, pop, k, elitism, sigma, knots_in, ld_in, elite_idx, elite_rows, cold,
-                       knots_out, ld_out, tick, gen, blockIdx.x % nts, (int)(blockIdx.x / nts));
+                       knots_out, ld_out, tick, gen, blockIdx.x % nts, (int)(blockIdx.x / nts),
+                       var);
 }
 
 // ---------------------------------------------------------------------------

@@ -285,11 +285,31 @@ template <typename T>
 hipError_t launch_linear(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
                          int64_t ld, T *cost, hipStream_t s, const Events &ev);
 
+// Warm-start and exploration variants of a population launch (empc_ga):
+// shift the carried parents one control step later (parents read from
+// elite_rows only), and the distance-dependent mutation noise (needs x0).
+template <typename T>
+struct PopVariant {
+    const T *x0 = nullptr;  // state of the solve (for sigma_dist > 0)
+    T sigma_min = 0, sigma_dist = 0;
+    int shift = 0;
+};
+template <typename T>
+inline PopVariant<T> pop_variant(const empc_ga &ga, const void *x0, bool shift_now) {
+    PopVariant<T> v;
+    v.x0 = (const T *)x0;
+    v.sigma_min = (T)ga.sigma_min;
+    v.sigma_dist = x0 ? (T)ga.sigma_dist : (T)0;
+    v.shift = (ga.shift && shift_now) ? 1 : 0;
+    return v;
+}
+
 template <typename T>
 hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *knots_in,
                              int64_t ld_in, const int64_t *elite_idx, const T *elite_rows,
                              const int *has_elites, int cold_mode, T *knots_out, int64_t ld_out,
-                             uint32_t tick, uint32_t gen, hipStream_t s);
+                             uint32_t tick, uint32_t gen, hipStream_t s,
+                             const PopVariant<T> &var = PopVariant<T>());
 
 // Selection writes elite indices (ascending), best index, and optionally the
 // elite knots [pm][k] (parameter-major), elite costs [k], the warm-start flag, u* and the

@@ -39,9 +39,10 @@ def mixed_problems(seed=0):
     return probs
 
 
-def test_batched_equals_single_solves(E):
+@pytest.mark.parametrize("variant", [{}, dict(shift=True, sigma_min=0.01, sigma_dist=0.8)])
+def test_batched_equals_single_solves(E, variant):
     probs = mixed_problems()
-    ga = W.GA(pop=256, n_elite=16, generations=2, sigma=0.1, seed=0xABCDEF0123)
+    ga = W.GA(pop=256, n_elite=16, generations=2, sigma=0.1, seed=0xABCDEF0123, **variant)
     dps = [E.DeviceProblem(p, F32) for p in probs]
     bs = E.BatchSolver(dps, ga)
     singles = [E.Solver(dp, W.dataclasses.replace(ga, seed=ga.seed ^ (i << 32)))

@@ -147,11 +147,13 @@ def test_autograd_function(E):
     np.testing.assert_allclose(K.grad.cpu().numpy(), dJ * w.cpu().numpy()[None, :], rtol=1e-12)
 
 
-def test_refined_solve_fp64_matches_oracle(oracle_lib, E):
+@pytest.mark.parametrize("shift", [False, True])
+def test_refined_solve_fp64_matches_oracle(oracle_lib, E, shift):
     # gradient-refined ticks (Adam on the parents after every selection):
-    # FP64 keeps the parent sets identical, so whole ticks agree
+    # FP64 keeps the parent sets identical, so whole ticks agree (also with
+    # the carried parents moved one step later per tick)
     prob = W.linear_chain(3, 20, 5, seed=2)
-    ga = W.GA(pop=256, n_elite=16, generations=3, sigma=0.1, seed=4)
+    ga = W.GA(pop=256, n_elite=16, generations=3, sigma=0.1, seed=4, shift=shift)
     dp = E.DeviceProblem(prob, F64)
     s = E.Solver(dp, ga)
     o = oracle_lib.Solver(prob, ga, refine=True, lr=0.01, adam_steps=5)

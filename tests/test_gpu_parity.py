@@ -294,10 +294,18 @@ def test_selection_random_bands(oracle_lib, E, dtype):
 # solve
 
 
-def test_solve_fp64_matches_oracle_over_ticks(oracle_lib, E):
+# warm-start variants: carried parents moved one step later per tick, and the
+# mutation noise growing with the distance to the goal (0.02 at the goal, the
+# configured sigma from distance 1 on)
+VARIANTS = {"plain": {}, "shift+noise_schedule": dict(shift=True, sigma_min=0.02, sigma_dist=1.0)}
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_solve_fp64_matches_oracle_over_ticks(oracle_lib, E, variant):
     # FP64 keeps every elite set identical to the oracle's, so whole
     # multi-generation, multi-tick trajectories agree
     prob, ga = W.config_c1(0)
+    ga = W.dataclasses.replace(ga, **VARIANTS[variant])
     dp = E.DeviceProblem(prob, F64)
     solver = E.Solver(dp, ga)
     osolver = oracle_lib.Solver(prob, ga)

@@ -512,6 +512,95 @@ def test_solve_warm_start_and_elitism_over_ticks(oracle_lib):
 
 
 # ---------------------------------------------------------------------------
+# warm-start variants: parents moved one step later, distance-dependent noise
+
+
+@pytest.mark.parametrize("T,p", [(9, 5), (13, 4), (21, 11)])
+def test_shift_samples_the_carried_input_one_step_later(oracle_lib, T, p):
+    # knot a sits at step a (T-1)/(p-1), an integer for these (T, p); the moved
+    # knot must be the carried piecewise-linear input at that step plus one,
+    # evaluated with the interpolation weights of Sec. IV-D (pinned above by
+    # the worked example), and the last knot is held
+    m = 3
+    prob = W.linear_chain(m, T, p, seed=1)
+    rng = np.random.default_rng(5)
+    rows = rng.uniform(-1, 1, (4, p * m))
+    moved = oracle_lib.shift_knots(prob, rows)
+    step = (T - 1) // (p - 1)
+    for s in range(rows.shape[0]):
+        U = rows[s].reshape(p, m)
+        for a in range(p - 1):
+            ka, kb, c = oracle_lib.knot_weights(T, p, a * step + 1)
+            want = (1 - c) * U[ka] + c * U[kb]
+            np.testing.assert_allclose(moved[s].reshape(p, m)[a], want, rtol=0, atol=1e-15)
+        np.testing.assert_array_equal(moved[s].reshape(p, m)[p - 1], U[p - 1])
+
+
+def test_shift_special_cases(oracle_lib):
+    rng = np.random.default_rng(6)
+    # p = T: every step has its own knot, so the move is exactly "next knot"
+    prob = W.linear_chain(2, 7, 7, seed=2)
+    rows = rng.uniform(-1, 1, (3, 14))
+    moved = oracle_lib.shift_knots(prob, rows)
+    np.testing.assert_array_equal(moved[:, :12], rows[:, 2:])
+    np.testing.assert_array_equal(moved[:, 12:], rows[:, 12:])
+    # p = 1: a constant input has nothing to move
+    prob1 = W.linear_chain(2, 7, 1, seed=2)
+    rows1 = rng.uniform(-1, 1, (3, 2))
+    np.testing.assert_array_equal(oracle_lib.shift_knots(prob1, rows1), rows1)
+    # a constant trajectory stays constant
+    prob5 = W.linear_chain(2, 10, 4, seed=2)
+    const = np.tile(np.array([0.3, -0.7]), (2, 4))
+    np.testing.assert_allclose(oracle_lib.shift_knots(prob5, const), const, rtol=0, atol=1e-15)
+
+
+def test_sigma_schedule(oracle_lib):
+    prob = W.linear_chain(2, 10, 4, seed=3)
+    ga = W.GA(pop=8, n_elite=2, generations=1, sigma=0.4, seed=1, sigma_min=0.05, sigma_dist=2.0)
+    goal = np.zeros(prob.n)
+    assert oracle_lib.sigma_at(prob, ga, goal) == 0.05
+    e = np.array([0.6, 0.0, 0.8, 0.0])  # distance 1 = half of sigma_dist
+    np.testing.assert_allclose(oracle_lib.sigma_at(prob, ga, e), 0.05 + 0.35 * 0.5, rtol=1e-15)
+    assert oracle_lib.sigma_at(prob, ga, 3 * e) == 0.4  # beyond sigma_dist
+    plain = W.dataclasses.replace(ga, sigma_dist=0.0)
+    assert oracle_lib.sigma_at(prob, plain, goal) == 0.4
+
+
+def test_solve_noise_schedule_limits(oracle_lib):
+    # at the goal with sigma_min = 0 the schedule gives no noise, so the solve
+    # equals one with sigma = 0; at or beyond sigma_dist it equals the plain
+    # solve with sigma
+    prob = W.linear_chain(2, 12, 4, seed=4)
+    ga = W.GA(pop=64, n_elite=8, generations=3, sigma=0.3, seed=9, sigma_min=0.0, sigma_dist=1.0)
+    far = np.full(prob.n, 2.0)
+    for x0, twin in ((np.zeros(prob.n), W.dataclasses.replace(ga, sigma=0.0, sigma_dist=0.0)),
+                     (far, W.dataclasses.replace(ga, sigma_dist=0.0))):
+        a, b = oracle_lib.Solver(prob, ga), oracle_lib.Solver(prob, twin)
+        for tick in range(2):
+            ua, Ja, _ = a.solve(x0, tick)
+            ub, Jb, _ = b.solve(x0, tick)
+            assert Ja == Jb and np.array_equal(ua, ub)
+            assert np.array_equal(a.elite_knots, b.elite_knots)
+
+
+def test_solve_shift_moves_carried_parents_once_per_tick(oracle_lib):
+    # with the shift, a tick equals the plain tick started from the carried
+    # parents moved one step later; the first (cold) tick has nothing to move
+    prob = W.linear_chain(2, 17, 5, seed=8)
+    ga = W.GA(pop=48, n_elite=6, generations=2, sigma=0.1, seed=4, shift=True)
+    a = oracle_lib.Solver(prob, ga)
+    b = oracle_lib.Solver(prob, W.dataclasses.replace(ga, shift=False))
+    x = W.draw_x0(prob.n, 3)
+    for tick in range(3):
+        if tick > 0:
+            b.elite_knots[:] = oracle_lib.shift_knots(prob, b.elite_knots)
+        ua, Ja, _ = a.solve(x, tick)
+        ub, Jb, _ = b.solve(x, tick)
+        assert Ja == Jb and np.array_equal(ua, ub), tick
+        x = oracle_lib.step(prob, x, ua)
+
+
+# ---------------------------------------------------------------------------
 # adjoint gradient
 
 

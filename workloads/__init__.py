@@ -94,6 +94,10 @@ class GA:
     sigma: float
     seed: int
     elitism: bool = True
+    # warm-start and exploration variants (defaults: the plain method)
+    shift: bool = False       # move the carried parents one step later per tick
+    sigma_min: float = 0.0    # noise at the goal
+    sigma_dist: float = 0.0   # > 0: noise grows linearly up to sigma at this distance
 
 
 def zoh(A: np.ndarray, B: np.ndarray, dt: float):
