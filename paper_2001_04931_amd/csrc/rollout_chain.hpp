@@ -196,22 +196,46 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
         v[i] = in ? x0[d + j] : (T)0;
     }
     const T dt = P.dt;
-    const T inv_den = P.Tn > 1 ? (T)1 / (T)(P.Tn - 1) : (T)0;
-    T J_ = 0;
-    int cur_a = -1;
-    for (int k = 0; k < P.Tn; ++k) {
-        const Knot kn = knot_at(P.Tn, P.p, k);
-        if (kn.a != cur_a) {  // uniform over the wavefront
-            cur_a = kn.a;
+    const int Tn = P.Tn, p = P.p, den = Tn - 1;
+    const T inv_den = Tn > 1 ? (T)1 / (T)den : (T)0;
+    // knot position of step k tracked incrementally: k (p-1) = a (T-1) + rem
+    int a = 0, rem = 0;
+    // knots a, a+1 (b) and a+2 (prefetched) of the lane's joints
+    T un[J], du[J];
+    auto load_knot = [&](int kn, T *dst) {
+        const int kc = kn < p ? kn : p - 1;
 #pragma unroll
-            for (int i = 0; i < J; ++i) {
-                const int j = r * J + i;
-                const int jc = j < d ? j : d - 1;
-                ua[i] = knots[(int64_t)(kn.a * d + jc) * ld + cc];
-                ub[i] = knots[(int64_t)(kn.b * d + jc) * ld + cc];
-            }
+        for (int i = 0; i < J; ++i) {
+            const int j = r * J + i;
+            dst[i] = knots[(int64_t)(kc * d + (j < d ? j : d - 1)) * ld + cc];
         }
-        const T c = (T)kn.rem * inv_den;
+    };
+    load_knot(0, ua);
+    load_knot(1, ub);
+    load_knot(2, un);
+#pragma unroll
+    for (int i = 0; i < J; ++i) du[i] = ub[i] - ua[i];
+    // stage cost: per joint sums of squared errors, weighted at the end; the
+    // input cost of a knot segment in closed form (u = U_a + c dU is affine
+    // in c there): sum (g - U_a - c dU)^2 = n e0^2 - 2 e0 dU C1 + dU^2 C2,
+    // e0 = g - U_a, with C1, C2 the sums of c and c^2 over the segment
+    T Sq[J], Sv[J];
+#pragma unroll
+    for (int i = 0; i < J; ++i) Sq[i] = Sv[i] = 0;
+    T Ju = 0, C1 = 0, C2 = 0;
+    int nseg = 0;
+    auto flush_input = [&]() {
+#pragma unroll
+        for (int i = 0; i < J; ++i) {
+            const T e0 = gu[i] - ua[i];
+            Ju += wr[i] * ((T)nseg * e0 * e0 - (T)2 * e0 * du[i] * C1 + du[i] * du[i] * C2);
+        }
+    };
+    for (int k = 0; k < Tn; ++k) {
+        const T c = (T)rem * inv_den;
+        C1 += c;
+        C2 += c * c;
+        ++nseg;
         // cumulative angles phi: local prefix over the lane's joints, then
         // the row's exclusive prefix of lane totals
         T loc[J];
@@ -234,19 +258,40 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
             sloc[i] = srun;
         }
         const T after = row_scan_down<T>(srun) - srun;
-        T js = 0;
 #pragma unroll
         for (int i = 0; i < J; ++i) {
             const T G = after + sloc[i];
-            const T u = ((T)1 - c) * ua[i] + c * ub[i];
+            const T u = ua[i] + c * du[i];
             const T acc = (u - kst[i] * q[i] - dmp[i] * v[i] - G) * invI[i];
             v[i] = v[i] + dt * acc;
             q[i] = q[i] + dt * v[i];
-            const T eq = gq[i] - q[i], ev = gv[i] - v[i], eu = gu[i] - u;
-            js += wq[i] * eq * eq + wv[i] * ev * ev + wr[i] * eu * eu;
+            const T eq = gq[i] - q[i], ev = gv[i] - v[i];
+            Sq[i] += eq * eq;
+            Sv[i] += ev * ev;
         }
-        J_ += js;
+        // advance the knot position to step k + 1 (uniform)
+        if (p > 1 && Tn > 1) {
+            rem += p - 1;
+            if (rem >= den && k + 1 < Tn) {
+                flush_input();
+                C1 = C2 = 0;
+                nseg = 0;
+                rem -= den;
+                ++a;
+#pragma unroll
+                for (int i = 0; i < J; ++i) {
+                    ua[i] = ub[i];
+                    ub[i] = un[i];
+                    du[i] = ub[i] - ua[i];
+                }
+                load_knot(a + 2, un);
+            }
+        }
     }
+    flush_input();
+    T J_ = Ju;
+#pragma unroll
+    for (int i = 0; i < J; ++i) J_ += wq[i] * Sq[i] + wv[i] * Sv[i];
     T jt = 0;
 #pragma unroll
     for (int i = 0; i < J; ++i) {
