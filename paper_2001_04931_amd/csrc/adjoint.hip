@@ -1,9 +1,12 @@
 // Adjoint gradient of the rollout cost with respect to the knots, and Adam
 // refinement built on it (gfx950).
 //
-// One wavefront (one workgroup of 64 lanes) per candidate: a few dozen
-// elites each run a sequential chain of 3T dependent steps per Adam step, so
-// the latency of one step is what counts.  Linear model: lane i owns state i
+// One workgroup of two wavefronts per candidate: a few dozen elites each run
+// a sequential chain of dependent steps per Adam step, so the latency of one
+// step is what counts.  Wavefront 0 runs the forward pass and the backward
+// steps; wavefront 1 recomputes the states of the next checkpoint segment
+// (into the other of two LDS buffers) while wavefront 0 walks the current one
+// backward, so an Adam step is T + S + T dependent steps instead of 3T.  Linear model: lane i owns state i
 // (n <= 64) and, for i < m, input i, and holds row i and column i of A_d and
 // of B_d in registers; each lane publishes its state (or adjoint) to LDS and
 // reads the whole vector back with broadcast 16-byte loads (the LDS
@@ -57,9 +60,9 @@ inline GradPlan grad_plan(int model, int n, int m, int T, int p) {
     g.oG = o; o += pm;
     g.oM1 = o; o += pm;
     g.oM2 = o; o += pm;
-    g.oXb = o; o += 64;  // broadcast slots: states (or adjoints)
+    g.oXb = o; o += 128;  // broadcast slots of the two wavefronts: states (or adjoints)
     g.oChk = o; o += (size_t)g.nchk * n;
-    g.oSeg = o; o += (size_t)g.S * n;
+    g.oSeg = o; o += (size_t)2 * g.S * n;  // two recomputed segments
     // per-step tables of the current knots: inputs u_k (rows of us, plus
     // 64 of padding for whole-vector reads of the last row), the linear
     // model's B_d u_k + w_d, and the blend weights c_k
@@ -82,7 +85,7 @@ struct Lane {
 // LIN: linear model with NMAX >= n and MMAX >= m (register operand
 // lengths); else the pendulum chain (NMAX, MMAX unused).
 template <typename T, bool LIN, int NMAX, int MMAX>
-__global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
+__global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
                                                      const T *__restrict__ x0,
                                                      const T *__restrict__ knots, int64_t ld,
                                                      T *__restrict__ dJ, T *__restrict__ cost,
@@ -92,10 +95,11 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
     T *sm = (T *)smem_raw;
     T *sU = sm + G.oU, *sG = sm + G.oG;
     T *sM1 = sm + G.oM1, *sM2 = sm + G.oM2;
-    T *sChk = sm + G.oChk, *sSeg = sm + G.oSeg;
-    T *sXb = sm + G.oXb;
+    T *sChk = sm + G.oChk;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    T *sXb = sm + G.oXb + 64 * wave;  // this wavefront's broadcast slots
     T *sUk = sm + G.oUk, *sBu = sm + G.oBu, *sC = sm + G.oC;
-    const int lane = threadIdx.x;
     const int64_t cand = blockIdx.x;
     const int n = P.n, m = P.m, pm = P.p * P.m, Tn = P.Tn, S = G.S;
     constexpr bool lin = LIN;
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
 #pragma unroll
     for (int j = 0; j < MR; ++j) bRow[j] = (LIN && lane < n && j < m) ? P.Bd[lane * m + j] : (T)0;
     const T *src = refine ? knots_io : knots;
-    for (int j = lane; j < pm; j += 64) {
+    for (int j = threadIdx.x; j < pm; j += 128) {
         sU[j] = src[(int64_t)j * ld + cand];
         sM1[j] = 0;
         sM2[j] = 0;
@@ -254,9 +258,38 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
         return wave_total<T>(J);
     };
 
-    // backward pass from the final state: fills sG with dJ/dknots
+    // states x_k0 .. x_{k1-1} of checkpoint segment sg, recomputed into seg
+    auto recompute = [&](int sg, T *seg) {
+        const int k0 = sg * S, k1 = min(k0 + S, Tn);
+        T xi = 0, qj = 0, vj = 0;
+        if (lin) {
+            if (lane < n) xi = sChk[sg * n + lane];
+        } else if (lane < d) {
+            qj = sChk[sg * n + lane];
+            vj = sChk[sg * n + d + lane];
+        }
+        for (int k = k0; k < k1; ++k) {
+            if (lin) {
+                if (lane < n) seg[(k - k0) * n + lane] = xi;
+            } else if (lane < d) {
+                seg[(k - k0) * n + lane] = qj;
+                seg[(k - k0) * n + d + lane] = vj;
+            }
+            if (k + 1 < k1) {
+                if (lin) {
+                    xi = lin_step(xi, k);
+                } else {
+                    chain_step(qj, vj, input_at(k));
+                }
+            }
+        }
+    };
+
+    // backward pass from the final state (wavefront 0's xT / qT, vT): fills
+    // sG with dJ/dknots.  Both wavefronts call it: wavefront 0 walks the
+    // segments backward, wavefront 1 recomputes one segment ahead of it.
     auto backward = [&](T xT, T qT, T vT) {
-        for (int j = lane; j < pm; j += 64) sG[j] = 0;
+        for (int j = threadIdx.x; j < pm; j += 128) sG[j] = 0;
         T lam = 0, lq = 0, lv = 0;
         if (lin) {
             lam = (T)2 * (L.q + L.qf) * (xT - L.xg);
@@ -264,6 +297,8 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
             lq = (T)2 * (L.wq + L.wqf) * (qT - L.gq);
             lv = (T)2 * (L.wv + L.wvf) * (vT - L.gv);
         }
+        T *segbuf[2] = {sm + G.oSeg, sm + G.oSeg + (size_t)S * n};
+        if (wave == 1) recompute(G.nchk - 1, segbuf[(G.nchk - 1) & 1]);
         __syncthreads();
         // dJ/du_k goes to knots a and b of step k with weights 1-c and c;
         // summed in registers while the knot pair stays, then added to sG
@@ -276,98 +311,85 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
             }
         };
         for (int sg = G.nchk - 1; sg >= 0; --sg) {
-            const int k0 = sg * S, k1 = min(k0 + S, Tn);
-            // recompute x_k0 .. x_{k1-1} into sSeg
-            T xi = 0, qj = 0, vj = 0;
-            if (lin) {
-                if (lane < n) xi = sChk[sg * n + lane];
-            } else if (lane < d) {
-                qj = sChk[sg * n + lane];
-                vj = sChk[sg * n + d + lane];
-            }
-            for (int k = k0; k < k1; ++k) {
-                if (lin) {
-                    if (lane < n) sSeg[(k - k0) * n + lane] = xi;
-                } else if (lane < d) {
-                    sSeg[(k - k0) * n + lane] = qj;
-                    sSeg[(k - k0) * n + d + lane] = vj;
-                }
-                if (k + 1 < k1) {
+            if (wave == 1) {
+                if (sg > 0) recompute(sg - 1, segbuf[(sg - 1) & 1]);
+            } else {
+                const int k0 = sg * S, k1 = min(k0 + S, Tn);
+                const T *sSeg = segbuf[sg & 1];
+                for (int k = k1 - 1; k >= k0; --k) {
+                    const Knot kn = knot_at(Tn, P.p, k);
+                    const T c = sC[k];
+                    const T u = input_at(k);
+                    T gu;
                     if (lin) {
-                        xi = lin_step(xi, k);
+                        // B^T lambda and A^T lambda, lambda_i published by lane i
+                        sXb[lane] = lane < n ? lam : (T)0;
+                        const T bu = slot_dot(sXb, bCol, std::integral_constant<int, NR>(), (T)0);
+                        const T ax = slot_dot(sXb, aCol, std::integral_constant<int, NR>(), (T)0);
+                        gu = (T)2 * L.r * (u - L.ug) + bu;
+                        if (k >= 1 && lane < n) {
+                            const T xk = sSeg[(k - k0) * n + lane];
+                            lam = (T)2 * L.q * (xk - L.xg) + ax;
+                        }
                     } else {
-                        chain_step(qj, vj, input_at(k));
+                        const T qk = lane < d ? sSeg[(k - k0) * n + lane] : (T)0;
+                        const T vk = lane < d ? sSeg[(k - k0) * n + d + lane] : (T)0;
+                        const T phi = wave_scan_up<T>(qk);
+                        const T Sv = wave_scan_down<T>(L.cg * cos_f<T>(phi));
+                        const T mu = lv + P.dt * lq;
+                        const T nu = mu * L.invI;
+                        const T pf = wave_scan_up<T>(nu);
+                        const T sn = Sv * nu;
+                        const T R = wave_scan_down<T>(sn) - sn;
+                        const T dadq = -L.kst * nu - (Sv * pf + R);
+                        const T lq_n = lq + P.dt * dadq;
+                        const T lv_n = mu - P.dt * L.dmp * nu;
+                        gu = (T)2 * L.wr * (u - L.gu) + P.dt * nu;
+                        if (k >= 1) {
+                            lq = lq_n + (T)2 * L.wq * (qk - L.gq);
+                            lv = lv_n + (T)2 * L.wv * (vk - L.gv);
+                        }
                     }
+                    if (kn.a != cur_a) {  // uniform
+                        flush();
+                        cur_a = kn.a;
+                        cur_b = kn.b;
+                        gA = 0;
+                        gB = 0;
+                    }
+                    gA += ((T)1 - c) * gu;
+                    gB += c * gu;
                 }
             }
-            __syncthreads();
-            for (int k = k1 - 1; k >= k0; --k) {
-                const Knot kn = knot_at(Tn, P.p, k);
-                const T c = sC[k];
-                const T u = input_at(k);
-                T gu;
-                if (lin) {
-                    // B^T lambda and A^T lambda, lambda_i published by lane i
-                    sXb[lane] = lane < n ? lam : (T)0;
-                    const T bu = slot_dot(sXb, bCol, std::integral_constant<int, NR>(), (T)0);
-                    const T ax = slot_dot(sXb, aCol, std::integral_constant<int, NR>(), (T)0);
-                    gu = (T)2 * L.r * (u - L.ug) + bu;
-                    if (k >= 1 && lane < n) {
-                        const T xk = sSeg[(k - k0) * n + lane];
-                        lam = (T)2 * L.q * (xk - L.xg) + ax;
-                    }
-                } else {
-                    const T qk = lane < d ? sSeg[(k - k0) * n + lane] : (T)0;
-                    const T vk = lane < d ? sSeg[(k - k0) * n + d + lane] : (T)0;
-                    const T phi = wave_scan_up<T>(qk);
-                    const T Sv = wave_scan_down<T>(L.cg * cos_f<T>(phi));
-                    const T mu = lv + P.dt * lq;
-                    const T nu = mu * L.invI;
-                    const T pf = wave_scan_up<T>(nu);
-                    const T sn = Sv * nu;
-                    const T R = wave_scan_down<T>(sn) - sn;
-                    const T dadq = -L.kst * nu - (Sv * pf + R);
-                    const T lq_n = lq + P.dt * dadq;
-                    const T lv_n = mu - P.dt * L.dmp * nu;
-                    gu = (T)2 * L.wr * (u - L.gu) + P.dt * nu;
-                    if (k >= 1) {
-                        lq = lq_n + (T)2 * L.wq * (qk - L.gq);
-                        lv = lv_n + (T)2 * L.wv * (vk - L.gv);
-                    }
-                }
-                if (kn.a != cur_a) {  // uniform
-                    flush();
-                    cur_a = kn.a;
-                    cur_b = kn.b;
-                    gA = 0;
-                    gB = 0;
-                }
-                gA += ((T)1 - c) * gu;
-                gB += c * gu;
-            }
+            // segment sg - 1 recomputed, segment sg walked: the buffers swap
             __syncthreads();
         }
-        flush();
+        if (wave == 0) flush();
         __syncthreads();
     };
 
-    T xi, qj, vj;
+    // wavefront 0 owns the forward passes; both take part in the backward
+    // passes and the Adam updates (barriers between the phases)
+    T xi = 0, qj = 0, vj = 0;
     if (!refine) {
-        const T J = forward(true, xi, qj, vj);
+        T J = 0;
+        if (wave == 0) J = forward(true, xi, qj, vj);
+        __syncthreads();  // checkpoints and input tables
         backward(xi, qj, vj);
-        for (int j = lane; j < pm; j += 64) dJ[(int64_t)j * ld + cand] = sG[j];
-        if (cost && lane == 0) cost[cand] = J;
+        for (int j = threadIdx.x; j < pm; j += 128) dJ[(int64_t)j * ld + cand] = sG[j];
+        if (cost && threadIdx.x == 0) cost[cand] = J;
         return;
     }
     // Adam (Kingma & Ba 2015), bias-corrected, clamp after each update
     const T b1 = (T)0.9, b2 = (T)0.999, eps = (T)1e-8;
     T b1t = 1, b2t = 1;
     for (int t = 1; t <= steps; ++t) {
-        forward(true, xi, qj, vj);
+        if (wave == 0) forward(true, xi, qj, vj);
+        __syncthreads();  // checkpoints and input tables
         backward(xi, qj, vj);
         b1t *= b1;
         b2t *= b2;
-        for (int j = lane; j < pm; j += 64) {
+        for (int j = threadIdx.x; j < pm; j += 128) {
             const T g = sG[j];
             const T m1 = b1 * sM1[j] + ((T)1 - b1) * g;
             const T m2 = b2 * sM2[j] + ((T)1 - b2) * g * g;
@@ -382,10 +404,12 @@ __global__ __launch_bounds__(64) void adjoint_kernel(ProbView<T> P, GradPlan G,
         }
         __syncthreads();
     }
-    const T Jn = forward(false, xi, qj, vj);
-    if (Jn < cost_io[cand]) {  // uniform: Jn is a wave sum
-        for (int j = lane; j < pm; j += 64) knots_io[(int64_t)j * ld + cand] = sU[j];
-        if (lane == 0) cost_io[cand] = Jn;
+    if (wave == 0) {
+        const T Jn = forward(false, xi, qj, vj);
+        if (Jn < cost_io[cand]) {  // uniform: Jn is a wave sum
+            for (int j = lane; j < pm; j += 64) knots_io[(int64_t)j * ld + cand] = sU[j];
+            if (lane == 0) cost_io[cand] = Jn;
+        }
     }
 }
 
@@ -406,7 +430,7 @@ hipError_t launch_grad(const ProbView<T> &P, int model, const T *x0, const T *kn
                                                (int)bytes);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(kernel, dim3((unsigned)ncand), dim3(64), bytes, s, P, G, x0, knots, ld,
+        hipLaunchKernelGGL(kernel, dim3((unsigned)ncand), dim3(128), bytes, s, P, G, x0, knots, ld,
                            dJ, cost, refine_steps, lr, knots_io, cost_io);
         return hipGetLastError();
     };
