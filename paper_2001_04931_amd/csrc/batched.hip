@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <map>
 #include <vector>
 
@@ -17,13 +18,18 @@
 
 namespace empc {
 
+// One workgroup per (problem, population tile) that holds parameters: the
+// map lists them problem after problem, so problems with fewer parameters
+// take fewer workgroups (no workgroups that would only exit).
 template <typename T>
 __global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<T> *__restrict__ slots,
+                                                        const int2 *__restrict__ popmap,
                                                         int64_t pop, int k, int elitism, T sigma,
                                                         uint32_t seed_lo, int g,
                                                         const uint32_t *__restrict__ tick,
                                                         int shift, T sigma_min, T sigma_dist) {
-    const BatchSlot<T> &S = slots[blockIdx.y];
+    const int2 e = popmap[blockIdx.x];  // (problem, tile within the problem)
+    const BatchSlot<T> &S = slots[e.x];
     const ProbView<T> P = S.P;
     GaStreams gs;
     gs.k0 = seed_lo;
@@ -40,8 +46,7 @@ __global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<
     var.shift = first ? shift : 0;
     population_tile<T>(P, gs, pop, k, elitism, sigma, first ? nullptr : S.knots[(g + 1) & 1], pop,
                        first ? nullptr : S.elite_idx, first ? S.elite_rows : nullptr, cold,
-                       S.knots[g & 1], pop, *tick, (uint32_t)g, blockIdx.x % nts,
-                       (int)(blockIdx.x / nts), var);
+                       S.knots[g & 1], pop, *tick, (uint32_t)g, e.y % nts, (int)(e.y / nts), var);
 }
 
 template <typename T, int NT, int NU, int WPB>
@@ -245,9 +250,10 @@ struct empc_batch {
     int nprob = 0;
     empc_ga ga{};
     int64_t pop = 0;
-    int ngmax = 0;
     std::vector<BatchClass> classes;
     BatchSlot<float> *d_slots = nullptr;
+    int2 *d_popmap = nullptr;  // population workgroups: (problem, tile)
+    int64_t pop_wgs = 0;
     int *d_items = nullptr;
     uint32_t *d_tick = nullptr;
     int nstreams = 0;  // side streams in use (all BATCH_STREAMS are created)
@@ -369,8 +375,21 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         S.elite_cost = (float *)(base + off); off += al256(k * 4);
         S.elite_idx = (int64_t *)(base + off); off += al256(k * 8);
         S.best_idx = (int64_t *)(base + off); off += 256;
-        b->ngmax = std::max(b->ngmax, pop_tiles_g((int)pm));
     }
+    int64_t total_wgs = 0;
+    for (int i = 0; i < nprob; ++i)
+        total_wgs += pop_tiles_s(ga->pop) * pop_tiles_g(probs[i].p * probs[i].m);
+    if (total_wgs > INT32_MAX) {
+        delete b;
+        return empc_fail_internal(EMPC_EUNSUPPORTED, "batch population grid above 2^31 workgroups");
+    }
+    std::vector<int2> popmap;
+    popmap.reserve((size_t)total_wgs);
+    for (int i = 0; i < nprob; ++i) {
+        const int64_t wgs = pop_tiles_s(ga->pop) * pop_tiles_g(probs[i].p * probs[i].m);
+        for (int64_t t = 0; t < wgs; ++t) popmap.push_back(make_int2(i, (int)t));
+    }
+    b->pop_wgs = total_wgs;
     // group problems by kernel shape class
     std::map<std::tuple<int, int, int>, std::vector<int>> groups;
     for (int i = 0; i < nprob; ++i) {
@@ -404,6 +423,9 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
     b->d_tick = (uint32_t *)base;
     hipError_t e = hipMalloc(&b->d_slots, sizeof(BatchSlot<float>) * nprob);
     if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(int) * items.size());
+    if (e == hipSuccess) e = hipMalloc(&b->d_popmap, sizeof(int2) * popmap.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_popmap, popmap.data(), sizeof(int2) * popmap.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_slots, slots.data(), sizeof(BatchSlot<float>) * nprob, hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -416,6 +438,7 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
     if (e != hipSuccess) {
         (void)hipFree(b->d_slots);
         (void)hipFree(b->d_items);
+        (void)hipFree(b->d_popmap);
         for (int i = 0; i < BATCH_STREAMS; ++i) {
             if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
             if (b->join[i]) (void)hipEventDestroy(b->join[i]);
@@ -437,9 +460,8 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
     const int64_t per = (pop + SEL_THREADS - 1) / SEL_THREADS;
     for (int g = 0; g < G.generations; ++g) {
         const int last = g == G.generations - 1;
-        hipLaunchKernelGGL(batch_population<float>,
-                           dim3((unsigned)(pop_tiles_s(pop) * b->ngmax), (unsigned)b->nprob),
-                           dim3(POP_THREADS), 0, s, b->d_slots, pop, G.n_elite, G.elitism, (float)G.sigma,
+        hipLaunchKernelGGL(batch_population<float>, dim3((unsigned)b->pop_wgs), dim3(POP_THREADS), 0,
+                           s, b->d_slots, b->d_popmap, pop, G.n_elite, G.elitism, (float)G.sigma,
                            seed_lo, g, (const uint32_t *)b->d_tick, G.shift, (float)G.sigma_min,
                            (float)G.sigma_dist);
         const hipError_t fe = rollout_phase(b, g, s);
@@ -468,9 +490,8 @@ empc_status empc_batch_autotune(empc_batch *b, int32_t reps, void *stream) {
     // a generation-0 population, so that the timed rollouts read defined
     // knots; the parents, costs kept across ticks and the tick counter are
     // left as they are
-    hipLaunchKernelGGL(batch_population<float>,
-                       dim3((unsigned)(pop_tiles_s(b->pop) * b->ngmax), (unsigned)b->nprob),
-                       dim3(POP_THREADS), 0, s, b->d_slots, b->pop, G.n_elite, G.elitism,
+    hipLaunchKernelGGL(batch_population<float>, dim3((unsigned)b->pop_wgs), dim3(POP_THREADS), 0, s,
+                       b->d_slots, b->d_popmap, b->pop, G.n_elite, G.elitism,
                        (float)G.sigma, (uint32_t)G.seed, 0, (const uint32_t *)b->d_tick, G.shift,
                        (float)G.sigma_min, (float)G.sigma_dist);
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -570,6 +591,7 @@ empc_status empc_batch_destroy(empc_batch *b) {
     if (b->fork) (void)hipEventDestroy(b->fork);
     (void)hipFree(b->d_slots);
     (void)hipFree(b->d_items);
+    (void)hipFree(b->d_popmap);
     delete b;
     return EMPC_OK;
 }

@@ -321,6 +321,38 @@ def test_solve_fp64_matches_oracle_over_ticks(oracle_lib, E, variant):
         x = oracle_lib.step(prob, x, uo, noise[tick])
 
 
+EDGE_SOLVES = {
+    # name: (model maker, d, T, p, GA fields)
+    "all_parents": (W.linear_chain, 2, 10, 3, dict(pop=8, n_elite=8, generations=2)),
+    "one_parent": (W.linear_chain, 3, 12, 4, dict(pop=50, n_elite=1, generations=3)),
+    "ragged_population_chain": (W.pendulum_chain, 5, 15, 5, dict(pop=70, n_elite=5, generations=2)),
+    "knot_per_step": (W.linear_chain, 2, 6, 6, dict(pop=40, n_elite=4, generations=2)),
+    "single_knot_chain": (W.pendulum_chain, 3, 9, 1, dict(pop=33, n_elite=3, generations=2)),
+    "no_elitism": (W.linear_chain, 4, 15, 4, dict(pop=100, n_elite=10, generations=3, elitism=False)),
+    "one_step_horizon": (W.linear_chain, 2, 1, 1, dict(pop=20, n_elite=2, generations=2)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(EDGE_SOLVES))
+def test_solve_fp64_edge_shapes(oracle_lib, E, case):
+    # degenerate and ragged shapes of the method: every slot a parent, a
+    # single parent, a population that is not a multiple of any tile, one
+    # knot per step, a single knot, no elitism, a one-step horizon; FP64
+    # keeps every selection identical, so whole ticks follow the oracle
+    mk, d, T, p, g = EDGE_SOLVES[case]
+    prob = mk(d, T, p, seed=d + T)
+    ga = W.GA(sigma=0.1, seed=31, **g)
+    solver = E.Solver(E.DeviceProblem(prob, F64), ga)
+    osolver = oracle_lib.Solver(prob, ga)
+    x = W.draw_x0(prob.n, 2)
+    for tick in range(2):
+        u, J = solver.solve(as_dev(x, F64), tick)
+        uo, Jo, _ = osolver.solve(x, tick)
+        np.testing.assert_allclose(u.cpu().numpy(), uo, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(float(J.item()), Jo, rtol=1e-9, atol=1e-300)
+        x = oracle_lib.step(prob, x, uo)
+
+
 @pytest.mark.parametrize("d,T,p", [(9, 30, 6), (20, 25, 5)])
 def test_solve_fp64_generating_rollout_matches_oracle(oracle_lib, E, d, T, p):
     # linear chains of more than 16 states generate each tile's children
