@@ -7,13 +7,18 @@
 // one wavefront per tile of 16 candidates.
 //
 // The accumulator of a 16x16x4 MFMA leaves lane l holding, in register v
-// (v = 0..3), row R(l/16, v) of column l%16, with R(g, v) = 4g + v for the
-// f32 instruction and R(g, v) = g + 4v for the f64 one.  The B operand of the
-// same instruction takes row l/16 of column l%16 from lane l.  So accumulator
-// register v of M-tile t, used as a B operand as it stands, supplies the K
-// slice made of state rows {16t + R(g, v) : g = 0..3}; permuting the columns
-// of A_d to match that K order (the contraction order is free) chains the
-// steps with no cross-lane data movement.  A_d, B_d live in registers as A
+// (v = 0..3), output row 4g + v (f32 instruction) or g + 4v (f64) of column
+// l%16, g = l/16; the A operand takes row l%16 from lane l, the B operand row
+// l/16 of column l%16.  State i of an M-tile is placed on output row i (f64)
+// or on row 4 (i mod 4) + i div 4 (f32), i.e. the A operand of lane c holds
+// the row of state c (f64) or of state (c div 4) + 4 (c mod 4) (f32), so that
+// in both cases accumulator register v of lane group g holds state g + 4v.
+// Accumulator register v of M-tile t, used as a B operand as it stands, then
+// supplies the K slice of states {16t + g + 4v : g = 0..3}; the columns of
+// A_d are taken in that K order (the contraction order is free), which
+// chains the steps with no cross-lane data movement.  The last slice of the
+// last M-tile holds states 16 NT - 4 .. 16 NT - 1: when those are all padding
+// (n <= 16 NT - 4) its MFMAs, which would only add zeros, are skipped.  A_d, B_d live in registers as A
 // operands (one value per lane per MFMA), the state lives in accumulators,
 // and knot interpolation, the dynamics step and the cost are fused in one
 // loop over the horizon.
@@ -37,8 +42,10 @@ struct Mfma<float> {
     __device__ static inline v4 op(float a, float b, v4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
-    // accumulator row of lane group g, register v
-    __device__ static constexpr int row(int g, int v) { return 4 * g + v; }
+    // state held by register v of lane group g, and the state whose row the
+    // A operand of lane c (output row c) carries
+    __device__ static constexpr int row(int g, int v) { return g + 4 * v; }
+    __device__ static constexpr int mstate(int c) { return (c >> 2) + 4 * (c & 3); }
 };
 template <>
 struct Mfma<double> {
@@ -47,6 +54,7 @@ struct Mfma<double> {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     __device__ static constexpr int row(int g, int v) { return g + 4 * v; }
+    __device__ static constexpr int mstate(int c) { return c; }
 };
 
 // NT = ceil(n / 16) M-tiles, NU = ceil(m / 4) input K-slices; HAS_XG: the
@@ -75,14 +83,15 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
     const int64_t cand = cand0 + col;
     const bool valid = cand < ncand;
     const int n = P.n, m = P.m;
+    const bool skip_last = n <= 16 * NT - 4;  // the last K slice is all padding
 
-    // A operands.  aX[mt][4t+v]: A_d[16mt + col][16t + R(grp, v)];
-    // aU[mt][s]: B_d[16mt + col][4s + grp].
+    // A operands.  aX[mt][4t+v]: A_d[16mt + M(col)][16t + R(grp, v)];
+    // aU[mt][s]: B_d[16mt + M(col)][4s + grp]  (M = Mfma<T>::mstate, R = row).
     T aX[NT][4 * NT];
     T aU[NT][NU];
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt) {
-        const int row = 16 * mt + col;
+        const int row = 16 * mt + Mfma<T>::mstate(col);
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -223,6 +232,7 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
 #pragma unroll
                     for (int mt = 0; mt < NT; ++mt) {
                         const int t = (mt + i) % NT;
+                        if (v == 3 && t == NT - 1 && skip_last) continue;  // padding slice
                         acc[mt][v & 1] = Mfma<T>::op(aX[mt][4 * t + v], X[t][v], acc[mt][v & 1]);
                     }
                     const T e = HAS_XG ? X[i][v] - Xg[i][v] : X[i][v];
@@ -329,7 +339,8 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
     const int64_t cand = cand0 + col;
     const bool valid = cand < ncand;
     const int n = P.n, m = P.m;
-    const int row_own = 16 * w + col;  // A-operand row of this lane
+    const int row_own = 16 * w + Mfma<T>::mstate(col);  // state of this lane's A-operand row
+    const bool skip_last = n <= 16 * NT - 4;            // the last K slice is all padding
 
     // aX[4i+v] = A_d[16w + col][16 t_i + R(grp, v)], t_i = (w + i) mod NT
     T aX[4 * NT];
@@ -447,10 +458,14 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
                         for (int i2 = 1; i2 < NT; ++i2) X[i2] = xs[buf][(w + i2) % NT][lane];
                         buf ^= 1;
                     }
-                    if (v & 1)
+                    const bool pad = v == 3 && (w + i) % NT == NT - 1 && skip_last;
+                    if (pad) {
+                        // padding slice: its products are zero
+                    } else if (v & 1) {
                         acc1 = Mfma<T>::op(aX[4 * i + v], X[i][v], acc1);
-                    else
+                    } else {
                         acc0 = Mfma<T>::op(aX[4 * i + v], X[i][v], acc0);
+                    }
                     if (i == 0) {
                         const T e = HAS_XG ? X[0][v] - Xg[v] : X[0][v];
                         S[v] += e * e;
