@@ -16,9 +16,10 @@
 // Accumulator register v of M-tile t, used as a B operand as it stands, then
 // supplies the K slice of states {16t + g + 4v : g = 0..3}; the columns of
 // A_d are taken in that K order (the contraction order is free), which
-// chains the steps with no cross-lane data movement.  The last slice of the
-// last M-tile holds states 16 NT - 4 .. 16 NT - 1: when those are all padding
-// (n <= 16 NT - 4) its MFMAs, which would only add zeros, are skipped.  A_d, B_d live in registers as A
+// chains the steps with no cross-lane data movement.  Slice v of the last
+// M-tile holds states 16 (NT-1) + 4v .. + 3, so the slices past the last
+// state are all padding and their MFMAs, which would only add zeros, are
+// skipped (C2, n = 28: one of eight slices).  A_d, B_d live in registers as A
 // operands (one value per lane per MFMA), the state lives in accumulators,
 // and knot interpolation, the dynamics step and the cost are fused in one
 // loop over the horizon.
@@ -83,7 +84,8 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
     const int64_t cand = cand0 + col;
     const bool valid = cand < ncand;
     const int n = P.n, m = P.m;
-    const bool skip_last = n <= 16 * NT - 4;  // the last K slice is all padding
+    // K slices v >= live of the last M-tile hold only padding states
+    const int live = (n - 16 * (NT - 1) + 3) / 4;
 
     // A operands.  aX[mt][4t+v]: A_d[16mt + M(col)][16t + R(grp, v)];
     // aU[mt][s]: B_d[16mt + M(col)][4s + grp]  (M = Mfma<T>::mstate, R = row).
@@ -232,7 +234,7 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
 #pragma unroll
                     for (int mt = 0; mt < NT; ++mt) {
                         const int t = (mt + i) % NT;
-                        if (v == 3 && t == NT - 1 && skip_last) continue;  // padding slice
+                        if (t == NT - 1 && v >= live) continue;  // padding slice
                         acc[mt][v & 1] = Mfma<T>::op(aX[mt][4 * t + v], X[t][v], acc[mt][v & 1]);
                     }
                     const T e = HAS_XG ? X[i][v] - Xg[i][v] : X[i][v];
@@ -340,7 +342,7 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
     const bool valid = cand < ncand;
     const int n = P.n, m = P.m;
     const int row_own = 16 * w + Mfma<T>::mstate(col);  // state of this lane's A-operand row
-    const bool skip_last = n <= 16 * NT - 4;            // the last K slice is all padding
+    const int live = (n - 16 * (NT - 1) + 3) / 4;      // live K slices of the last M-tile
 
     // aX[4i+v] = A_d[16w + col][16 t_i + R(grp, v)], t_i = (w + i) mod NT
     T aX[4 * NT];
@@ -458,7 +460,7 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
                         for (int i2 = 1; i2 < NT; ++i2) X[i2] = xs[buf][(w + i2) % NT][lane];
                         buf ^= 1;
                     }
-                    const bool pad = v == 3 && (w + i) % NT == NT - 1 && skip_last;
+                    const bool pad = (w + i) % NT == NT - 1 && v >= live;
                     if (pad) {
                         // padding slice: its products are zero
                     } else if (v & 1) {
