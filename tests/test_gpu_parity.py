@@ -246,6 +246,27 @@ def test_selection_ties_nan_inf(oracle_lib, E, dtype):
 
 
 @pytest.mark.parametrize("dtype", [F32, F64])
+def test_selection_small_populations(oracle_lib, E, dtype):
+    # populations of at most 256 take the rank-based path (every key counts
+    # the keys ordered before it): heavy ties, NaN / inf / signed zeros, every
+    # k from 1 to pop on a few sizes, exact equality with the oracle
+    prob = W.linear_chain(2, 10, 3, seed=0)
+    rng = np.random.default_rng(11)
+    cases = [(pop, k) for pop in (2, 16, 63, 64, 65, 200, 256) for k in sorted({1, 2, pop // 3 or 1, pop})]
+    for pop, k in cases:
+        ga = W.GA(pop=pop, n_elite=k, generations=1, sigma=0.1, seed=1)
+        cost = np.round(rng.normal(0, 1, pop), 0)  # many exact ties
+        cost[rng.random(pop) < 0.05] = np.nan
+        cost[rng.random(pop) < 0.05] = np.inf
+        cost[rng.random(pop) < 0.05] = -0.0
+        knots = W.draw_knots(prob, pop, 1)
+        _, eidx, best = gpu_generation(E, prob, ga, knots, cost, 0, 0, dtype)
+        want_idx, want_best = oracle_lib.select(cost, k)
+        np.testing.assert_array_equal(eidx, want_idx, err_msg="pop %d k %d" % (pop, k))
+        assert best == want_best, (pop, k)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
 def test_selection_degenerate_and_large(oracle_lib, E, dtype):
     # all keys equal; ties at the threshold spread over every quarter of the
     # index range; all NaN; a population above the register-cached sizes
