@@ -43,7 +43,7 @@ class _OrProblem(ctypes.Structure):
                 ("stiff", _dp), ("damp", _dp), ("mass", _dp), ("len", _dp),
                 ("gravity", ctypes.c_double), ("dt", ctypes.c_double),
                 ("q", _dp), ("r", _dp), ("qf", _dp), ("x_goal", _dp), ("u_goal", _dp),
-                ("u_min", _dp), ("u_max", _dp)]
+                ("u_min", _dp), ("u_max", _dp), ("x_min", _dp), ("x_max", _dp), ("qb", _dp)]
 
 
 class _OrGA(ctypes.Structure):
@@ -112,8 +112,9 @@ class OracleProblem:
         for name, cname in (("Ad", "Ad"), ("Bd", "Bd"), ("wd", "wd"), ("stiffness", "stiff"),
                             ("damping", "damp"), ("mass", "mass"), ("length", "len"),
                             ("q", "q"), ("r", "r"), ("qf", "qf"), ("x_goal", "x_goal"),
-                            ("u_goal", "u_goal"), ("u_min", "u_min"), ("u_max", "u_max")):
-            v = getattr(prob, name)
+                            ("u_goal", "u_goal"), ("u_min", "u_min"), ("u_max", "u_max"),
+                            ("x_min", "x_min"), ("x_max", "x_max"), ("qb", "qb")):
+            v = getattr(prob, name, None)
             if v is not None:
                 v = _f64(v)
                 self._keep[name] = v

@@ -204,8 +204,31 @@ void or_plant_step(const or_problem *P, const double *x, const double *u, const 
 static double x_goal_at(const or_problem *P, int i) { return P->x_goal ? P->x_goal[i] : 0.0; }
 static double u_goal_at(const or_problem *P, int i) { return P->u_goal ? P->u_goal[i] : 0.0; }
 
-static double stage_cost(const or_problem *P, const double *x, const double *u) {
+/* State box as a soft constraint (a variant: the paper names non-smooth
+ * costs and constraints as what a sampling method admits, Sec. VII): the
+ * squared distance of each state to [x_min, x_max], weighted by qb. */
+static double box_penalty(const or_problem *P, const double *x) {
     double J = 0.0;
+    if (!P->qb) return 0.0;
+    for (int i = 0; i < P->n; ++i) {
+        double over = x[i] - P->x_max[i], under = P->x_min[i] - x[i];
+        if (over > 0.0) J += P->qb[i] * over * over;
+        if (under > 0.0) J += P->qb[i] * under * under;
+    }
+    return J;
+}
+
+/* d box_penalty / d x_i */
+static double box_penalty_grad(const or_problem *P, const double *x, int i) {
+    if (!P->qb) return 0.0;
+    double over = x[i] - P->x_max[i], under = P->x_min[i] - x[i];
+    if (over > 0.0) return 2.0 * P->qb[i] * over;
+    if (under > 0.0) return -2.0 * P->qb[i] * under;
+    return 0.0;
+}
+
+static double stage_cost(const or_problem *P, const double *x, const double *u) {
+    double J = box_penalty(P, x);
     for (int i = 0; i < P->n; ++i) {
         double e = x_goal_at(P, i) - x[i];
         J += P->q[i] * e * e;
@@ -435,7 +458,7 @@ static void grad_one(const or_problem *P, const double *x0, const double *knots,
     const double *xT = traj + (size_t)T * n;
     for (int i = 0; i < n; ++i) {
         double e = xT[i] - x_goal_at(P, i);
-        lam[i] = 2.0 * (P->q[i] + (P->qf ? P->qf[i] : 0.0)) * e;
+        lam[i] = 2.0 * (P->q[i] + (P->qf ? P->qf[i] : 0.0)) * e + box_penalty_grad(P, xT, i);
     }
     for (int k = T - 1; k >= 0; --k) {
         const double *xk = traj + (size_t)k * n;
@@ -453,7 +476,8 @@ static void grad_one(const or_problem *P, const double *x0, const double *knots,
             dJ[(int64_t)(b * m + i) * ldg + cand] += c * g;
         }
         if (k > 0)
-            for (int i = 0; i < n; ++i) lam[i] = 2.0 * P->q[i] * (xk[i] - x_goal_at(P, i)) + lamx[i];
+            for (int i = 0; i < n; ++i)
+                lam[i] = 2.0 * P->q[i] * (xk[i] - x_goal_at(P, i)) + box_penalty_grad(P, xk, i) + lamx[i];
     }
     free(traj); free(lam); free(lamx); free(lamu); free(u); free(tm); free(in);
 }

@@ -56,6 +56,9 @@ typedef struct {
     const double *x_goal;   /* n, may be NULL (= 0)                            */
     const double *u_goal;   /* m, may be NULL (= 0)                            */
     const double *u_min, *u_max; /* m                                          */
+    /* state box as a soft constraint (NULL qb: none): each of x_1..x_T adds
+     * sum_i qb_i (max(0, x_i - x_max_i)^2 + max(0, x_min_i - x_i)^2)      */
+    const double *x_min, *x_max, *qb; /* n                                     */
 } or_problem;
 
 /* Tunables of Alg. 1: numSims (pop), numParents (n_elite), sigma_noise. */

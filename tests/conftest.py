@@ -16,7 +16,10 @@ def pytest_configure(config):
 def oracle_lib():
     import oracle
 
-    oracle.build(force=not os.path.exists(oracle._LIB))
+    src = [oracle._SRC, os.path.join(os.path.dirname(oracle._SRC), "empc_oracle.h")]
+    stale = not os.path.exists(oracle._LIB) or any(
+        os.path.getmtime(f) > os.path.getmtime(oracle._LIB) for f in src)
+    oracle.build(force=stale)
     return oracle
 
 

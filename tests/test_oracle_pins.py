@@ -601,6 +601,69 @@ def test_solve_shift_moves_carried_parents_once_per_tick(oracle_lib):
 
 
 # ---------------------------------------------------------------------------
+# state box as a soft constraint
+
+
+def with_box(prob, lo, hi, qb):
+    out = W.dataclasses.replace(prob)
+    out.x_min = np.full(prob.n, float(lo)) if np.isscalar(lo) else np.asarray(lo, float)
+    out.x_max = np.full(prob.n, float(hi)) if np.isscalar(hi) else np.asarray(hi, float)
+    out.qb = np.full(prob.n, float(qb)) if np.isscalar(qb) else np.asarray(qb, float)
+    return out
+
+
+def test_box_penalty_inside_is_free(oracle_lib):
+    prob = W.linear_chain(3, 20, 4, seed=1)
+    x0 = W.draw_x0(prob.n, 1)
+    knots = W.draw_knots(prob, 8, seed=1)
+    plain = oracle_lib.rollout_cost(prob, x0, knots)
+    boxed = oracle_lib.rollout_cost(with_box(prob, -1e6, 1e6, 5.0), x0, knots)
+    np.testing.assert_array_equal(plain, boxed)
+
+
+def test_box_penalty_closed_form(oracle_lib):
+    # x_{k+1} = x_k (A = 1, B = 0), q = r = 0: the state sits at x0 outside
+    # the box for all T steps, so J = T qb (x0 - x_max)^2, and mirrored below
+    for x0, lo, hi in ((2.5, -1.0, 1.0), (-3.0, -1.0, 0.5)):
+        T = 17
+        prob = W.Problem(model=W.LINEAR, n=1, m=1, T=T, p=3, Ad=np.ones((1, 1)),
+                         Bd=np.zeros((1, 1)), q=np.zeros(1), r=np.zeros(1), qf=np.zeros(1),
+                         x_goal=np.zeros(1), u_goal=np.zeros(1), u_min=-np.ones(1),
+                         u_max=np.ones(1))
+        knots = W.draw_knots(prob, 3, seed=2)
+        d = x0 - hi if x0 > hi else lo - x0
+        J = oracle_lib.rollout_cost(with_box(prob, lo, hi, 0.7), np.array([x0]), knots)
+        np.testing.assert_allclose(J, T * 0.7 * d * d, rtol=1e-14)
+
+
+@pytest.mark.parametrize("model", ["linear", "chain"])
+def test_box_penalty_gradient_central_differences(oracle_lib, model):
+    # the penalty is piecewise quadratic: away from the box faces central
+    # differences with h = 1e-4 are exact up to rounding for the linear
+    # model and O(h^2) for the chain
+    if model == "linear":
+        prob = with_box(W.linear_chain(3, 25, 5, seed=4), -0.05, 0.05, 4.0)
+    else:
+        prob = with_box(W.pendulum_chain(4, 25, 5, seed=4), -0.1, 0.1, 3.0)
+    x0 = W.draw_x0(prob.n, 4)
+    knots = W.draw_knots(prob, 2, seed=4)
+    dJ, cost = oracle_lib.grad(prob, x0, knots)
+    plain = W.dataclasses.replace(prob, qb=None, x_min=None, x_max=None)
+    assert np.all(cost > oracle_lib.rollout_cost(plain, x0, knots))  # the box is active
+    h = 1e-4
+    for cand in range(2):
+        fd = np.zeros(prob.p * prob.m)
+        for j in range(prob.p * prob.m):
+            kp = knots[:, cand:cand + 1].copy()
+            km = kp.copy()
+            kp[j] += h
+            km[j] -= h
+            fd[j] = (oracle_lib.rollout_cost(prob, x0, kp)[0] -
+                     oracle_lib.rollout_cost(prob, x0, km)[0]) / (2 * h)
+        np.testing.assert_allclose(dJ[:, cand], fd, rtol=1e-4, atol=1e-5 * np.abs(fd).max())
+
+
+# ---------------------------------------------------------------------------
 # adjoint gradient
 
 

@@ -64,6 +64,11 @@ class Problem:
     damping: Optional[np.ndarray] = None
     mass: Optional[np.ndarray] = None
     length: Optional[np.ndarray] = None
+    # state box as a soft constraint (None: none): qb_i times the squared
+    # distance of x_i to [x_min_i, x_max_i], on every state x_1..x_T
+    x_min: Optional[np.ndarray] = None
+    x_max: Optional[np.ndarray] = None
+    qb: Optional[np.ndarray] = None
     gravity: float = GRAVITY
     dt: float = 0.0
 
