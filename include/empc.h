@@ -83,6 +83,15 @@ typedef struct {
     const void *u_goal;    /* m; NULL = 0                                        */
     const void *u_min;     /* m  input lower bounds                              */
     const void *u_max;     /* m  input upper bounds                              */
+    /* State box as a soft constraint (a variant, not in the paper's cost;
+     * Sec. VII names constraints and non-smooth costs among what a sampling
+     * method admits).  qb NULL: none.  Else x_min, x_max (n each) are
+     * required and every state x_1..x_T adds
+     *   sum_i qb_i (max(0, x_i - x_max_i)^2 + max(0, x_min_i - x_i)^2)
+     * to the cost (and its derivative to the adjoint). */
+    const void *x_min;     /* n  state lower bounds (with qb)                    */
+    const void *x_max;     /* n  state upper bounds (with qb)                    */
+    const void *qb;        /* n  weights of the box penalty; NULL = none         */
 } empc_problem;
 
 /* Tunables of Alg. 1: numSims = pop, numParents = n_elite, sigma_noise. */

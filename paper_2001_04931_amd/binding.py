@@ -38,7 +38,7 @@ class EmpcProblem(ctypes.Structure):
                 ("stiffness", _vp), ("damping", _vp), ("mass", _vp), ("length", _vp),
                 ("gravity", ctypes.c_double), ("dt", ctypes.c_double),
                 ("q", _vp), ("r", _vp), ("qf", _vp), ("x_goal", _vp), ("u_goal", _vp),
-                ("u_min", _vp), ("u_max", _vp)]
+                ("u_min", _vp), ("u_max", _vp), ("x_min", _vp), ("x_max", _vp), ("qb", _vp)]
 
 
 class EmpcGA(ctypes.Structure):
@@ -246,12 +246,15 @@ class DeviceProblem:
 
     `prob` is any object with the fields of the C struct: model, n, m, T, p,
     Ad, Bd, wd (linear) or stiffness, damping, mass, length, gravity, dt
-    (chain), and q, r, qf, x_goal, u_goal, u_min, u_max (host arrays).
+    (chain), and q, r, qf, x_goal, u_goal, u_min, u_max, and optionally the
+    state box x_min, x_max, qb (host arrays).
     """
 
     _ARRAYS = ("Ad", "Bd", "wd", "stiffness", "damping", "mass", "length", "q", "r", "qf",
-               "x_goal", "u_goal", "u_min", "u_max")
-    _OPTIONAL = ("wd", "qf", "x_goal", "u_goal")
+               "x_goal", "u_goal", "u_min", "u_max", "x_min", "x_max", "qb")
+    # may be None (NULL); the zero-droppable ones are also passed as NULL
+    # when all zero (x_min / x_max are bounds: a zero bound is kept)
+    _OPTIONAL = ("wd", "qf", "x_goal", "u_goal", "qb")
 
     def __init__(self, prob, dtype=torch.float32, device="cuda"):
         self.prob, self.dtype, self.device = prob, dtype, torch.device(device)

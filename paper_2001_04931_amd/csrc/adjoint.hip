@@ -80,6 +80,8 @@ struct Lane {
     // per-lane constants (linear: state/input role; chain: joint role)
     T q, qf, xg, r, ug, w;                // linear state i / input i
     T cg, invI, kst, dmp, wq, wv, wqf, wvf, gq, gv, wr, gu;  // chain joint j
+    T lo, hi, bq;                         // state box penalty: linear state i, chain q_j
+    T lov, hiv, bv;                       // chain qd_j
 };
 
 // LIN: linear model with NMAX >= n and MMAX >= m (register operand
@@ -132,6 +134,10 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
         L.w = (si && P.wd) ? P.wd[lane] : (T)0;
         L.r = ui ? P.r[lane] : (T)0;
         L.ug = (ui && P.ug) ? P.ug[lane] : (T)0;
+        const bool bx = si && P.qb;
+        L.bq = bx ? P.qb[lane] : (T)0;
+        L.lo = bx ? P.xlo[lane] : (T)0;
+        L.hi = bx ? P.xhi[lane] : (T)0;
     } else {
         const int d = m;
         const bool in = lane < d;
@@ -155,10 +161,18 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
         L.gv = (in && P.xg) ? P.xg[d + lane] : (T)0;
         L.wr = in ? P.r[lane] : (T)0;
         L.gu = (in && P.ug) ? P.ug[lane] : (T)0;
+        const bool bx = in && P.qb;
+        L.bq = bx ? P.qb[lane] : (T)0;
+        L.lo = bx ? P.xlo[lane] : (T)0;
+        L.hi = bx ? P.xhi[lane] : (T)0;
+        L.bv = bx ? P.qb[d + lane] : (T)0;
+        L.lov = bx ? P.xlo[d + lane] : (T)0;
+        L.hiv = bx ? P.xhi[d + lane] : (T)0;
     }
     __syncthreads();
 
     const int d = m;  // chain joints
+    const bool box = P.qb != nullptr;  // state box penalty (uniform)
     // lane-owned state: linear xi (state lane); chain (q, v) of joint lane
     // sum_j c[j] v_j with v_j published by lane j: one LDS store per lane,
     // then every lane reads the vector back 16 bytes at a time (broadcast
@@ -242,10 +256,12 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
                 xi = lin_step(xi, k);
                 const T e = L.xg - xi, eu = L.ug - u;
                 J += L.q * e * e + L.r * eu * eu;
+                if (box) J += L.bq * box_pen(xi, L.lo, L.hi);
             } else {
                 chain_step(qj, vj, u);
                 const T eq = L.gq - qj, ev = L.gv - vj, eu = L.gu - u;
                 J += L.wq * eq * eq + L.wv * ev * ev + L.wr * eu * eu;
+                if (box) J += L.bq * box_pen(qj, L.lo, L.hi) + L.bv * box_pen(vj, L.lov, L.hiv);
             }
         }
         if (lin) {
@@ -293,9 +309,14 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
         T lam = 0, lq = 0, lv = 0;
         if (lin) {
             lam = (T)2 * (L.q + L.qf) * (xT - L.xg);
+            if (box) lam += box_pen_grad(xT, L.lo, L.hi, L.bq);
         } else {
             lq = (T)2 * (L.wq + L.wqf) * (qT - L.gq);
             lv = (T)2 * (L.wv + L.wvf) * (vT - L.gv);
+            if (box) {
+                lq += box_pen_grad(qT, L.lo, L.hi, L.bq);
+                lv += box_pen_grad(vT, L.lov, L.hiv, L.bv);
+            }
         }
         T *segbuf[2] = {sm + G.oSeg, sm + G.oSeg + (size_t)S * n};
         if (wave == 1) recompute(G.nchk - 1, segbuf[(G.nchk - 1) & 1]);
@@ -330,6 +351,7 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
                         if (k >= 1 && lane < n) {
                             const T xk = sSeg[(k - k0) * n + lane];
                             lam = (T)2 * L.q * (xk - L.xg) + ax;
+                            if (box) lam += box_pen_grad(xk, L.lo, L.hi, L.bq);
                         }
                     } else {
                         const T qk = lane < d ? sSeg[(k - k0) * n + lane] : (T)0;
@@ -348,6 +370,10 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
                         if (k >= 1) {
                             lq = lq_n + (T)2 * L.wq * (qk - L.gq);
                             lv = lv_n + (T)2 * L.wv * (vk - L.gv);
+                            if (box) {
+                                lq += box_pen_grad(qk, L.lo, L.hi, L.bq);
+                                lv += box_pen_grad(vk, L.lov, L.hiv, L.bv);
+                            }
                         }
                     }
                     if (kn.a != cur_a) {  // uniform

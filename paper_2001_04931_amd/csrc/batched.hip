@@ -49,28 +49,28 @@ __global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<
                        S.knots[g & 1], pop, *tick, (uint32_t)g, e.y % nts, (int)(e.y / nts), var);
 }
 
-template <typename T, int NT, int NU, int WPB>
+template <typename T, int NT, int NU, int WPB, bool BOX>
 __global__ __launch_bounds__(64 * WPB) void batch_roll_linear(const BatchSlot<T> *__restrict__ slots,
                                                               const int *__restrict__ items,
                                                               int64_t pop, int g) {
     const int64_t w = xcd_swizzle_2d();
     const BatchSlot<T> &S = slots[items[w / gridDim.x]];
-    linear_tile<T, NT, NU, true>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
+    linear_tile<T, NT, NU, true, BOX>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
                                  (w % gridDim.x) * WPB + (threadIdx.x >> 6));
 }
 
 // linear problems of more than 16 states: the M-split form, one workgroup
 // of NT wavefronts per tile, as in the single-problem rollout
-template <typename T, int NT, int NU>
+template <typename T, int NT, int NU, bool BOX>
 __global__ __launch_bounds__(64 * NT) void batch_roll_linear_split(
     const BatchSlot<T> *__restrict__ slots, const int *__restrict__ items, int64_t pop, int g) {
     const int64_t w = xcd_swizzle_2d();
     const BatchSlot<T> &S = slots[items[w / gridDim.x]];
-    linear_tile_split<T, NT, NU, true>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
+    linear_tile_split<T, NT, NU, true, BOX>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
                                        w % gridDim.x);
 }
 
-template <typename T, int DMAX>
+template <typename T, int DMAX, bool BOX>
 __global__ __launch_bounds__(256) void batch_roll_chain(const BatchSlot<T> *__restrict__ slots,
                                                         const int *__restrict__ items, int64_t pop,
                                                         int g) {
@@ -80,13 +80,13 @@ __global__ __launch_bounds__(256) void batch_roll_chain(const BatchSlot<T> *__re
     __syncthreads();
     const int64_t cand = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (cand >= pop) return;
-    chain_candidate<T, DMAX>(S.P, jc, S.x0, S.knots[g & 1], pop, S.cost, cand);
+    chain_candidate<T, DMAX, BOX>(S.P, jc, S.x0, S.knots[g & 1], pop, S.cost, cand);
 }
 
 // chains of more than 8 joints: one candidate per 16-lane row, as in the
 // single-problem rollout (same arithmetic, same rounding); WPB wavefronts
 // (4 WPB candidates) per workgroup
-template <typename T, int J, int WPB>
+template <typename T, int J, int WPB, bool BOX>
 __global__ __launch_bounds__(64 * WPB) void batch_roll_chain_rows(const BatchSlot<T> *__restrict__ slots,
                                                                   const int *__restrict__ items,
                                                                   int64_t pop, int g) {
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(64 * WPB) void batch_roll_chain_rows(const BatchSlo
     const BatchSlot<T> &S = slots[items[w / gridDim.x]];
     const int64_t cand0 = (w % gridDim.x) * (4 * WPB);
     if (cand0 + (threadIdx.x >> 6) * 4 >= pop) return;  // whole wavefront past the end
-    chain_row_candidate<T, J>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
+    chain_row_candidate<T, J, BOX>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
                               cand0 + (threadIdx.x >> 4), threadIdx.x & 15);
 }
 
@@ -118,6 +118,7 @@ __global__ void batch_tick_advance(uint32_t *tick) {
 struct BatchClass {
     int model;   // EMPC_LINEAR / EMPC_PENDULUM_CHAIN
     int a, b;    // linear: (NT, NU bucket); chain: (DMAX, 0)
+    int box;     // the problems have a state box penalty
     int first;   // offset in the device item list
     int count;
     double work;  // cost estimate (rule-based, or measured by the autotuner)
@@ -164,60 +165,78 @@ int dmax_bucket(int d) {
     return 48;
 }
 
-template <int NT, int NU, int WPB>
+template <int NT, int NU, int WPB, bool BOX>
 static void go_batch_linear_wpb(const BatchSlot<float> *slots, const int *items, int count,
                                 int64_t pop, int g, hipStream_t s) {
     const int64_t tiles = (pop + 15) / 16;
-    hipLaunchKernelGGL((batch_roll_linear<float, NT, NU, WPB>),
+    hipLaunchKernelGGL((batch_roll_linear<float, NT, NU, WPB, BOX>),
                        dim3((unsigned)((tiles + WPB - 1) / WPB), (unsigned)count), dim3(64 * WPB), 0,
                        s, slots, items, pop, g);
 }
-template <int NT, int NU>
-static void go_batch_linear(int variant, const BatchSlot<float> *slots, const int *items,
-                            int count, int64_t pop, int g, hipStream_t s) {
+template <int NT, int NU, bool BOX>
+static void go_batch_linear_box(int variant, const BatchSlot<float> *slots, const int *items,
+                                int count, int64_t pop, int g, hipStream_t s) {
     if (NT > 1 && variant == 3) {
-        hipLaunchKernelGGL((batch_roll_linear_split<float, NT, NU>),
+        hipLaunchKernelGGL((batch_roll_linear_split<float, NT, NU, BOX>),
                            dim3((unsigned)((pop + 15) / 16), (unsigned)count), dim3(64 * NT), 0, s,
                            slots, items, pop, g);
         return;
     }
-    if (variant == 1) return go_batch_linear_wpb<NT, NU, 2>(slots, items, count, pop, g, s);
-    if (variant == 2) return go_batch_linear_wpb<NT, NU, 1>(slots, items, count, pop, g, s);
-    go_batch_linear_wpb<NT, NU, 4>(slots, items, count, pop, g, s);
+    if (variant == 1) return go_batch_linear_wpb<NT, NU, 2, BOX>(slots, items, count, pop, g, s);
+    if (variant == 2) return go_batch_linear_wpb<NT, NU, 1, BOX>(slots, items, count, pop, g, s);
+    go_batch_linear_wpb<NT, NU, 4, BOX>(slots, items, count, pop, g, s);
+}
+template <int NT, int NU>
+static void go_batch_linear(int box, int variant, const BatchSlot<float> *slots, const int *items,
+                            int count, int64_t pop, int g, hipStream_t s) {
+    if (box) return go_batch_linear_box<NT, NU, true>(variant, slots, items, count, pop, g, s);
+    go_batch_linear_box<NT, NU, false>(variant, slots, items, count, pop, g, s);
 }
 template <int NT>
-static void go_batch_linear_nu(int nu, int variant, const BatchSlot<float> *slots,
+static void go_batch_linear_nu(int nu, int box, int variant, const BatchSlot<float> *slots,
                                const int *items, int count, int64_t pop, int g, hipStream_t s) {
     switch (nu) {
-        case 1: go_batch_linear<NT, 1>(variant, slots, items, count, pop, g, s); break;
-        case 2: go_batch_linear<NT, 2>(variant, slots, items, count, pop, g, s); break;
-        case 4: go_batch_linear<NT, 4>(variant, slots, items, count, pop, g, s); break;
-        case 6: go_batch_linear<NT, 6>(variant, slots, items, count, pop, g, s); break;
-        case 8: go_batch_linear<NT, 8>(variant, slots, items, count, pop, g, s); break;
-        default: go_batch_linear<NT, 10>(variant, slots, items, count, pop, g, s); break;
+        case 1: go_batch_linear<NT, 1>(box, variant, slots, items, count, pop, g, s); break;
+        case 2: go_batch_linear<NT, 2>(box, variant, slots, items, count, pop, g, s); break;
+        case 4: go_batch_linear<NT, 4>(box, variant, slots, items, count, pop, g, s); break;
+        case 6: go_batch_linear<NT, 6>(box, variant, slots, items, count, pop, g, s); break;
+        case 8: go_batch_linear<NT, 8>(box, variant, slots, items, count, pop, g, s); break;
+        default: go_batch_linear<NT, 10>(box, variant, slots, items, count, pop, g, s); break;
     }
 }
-template <int J, int WPB>
+template <int J, int WPB, bool BOX>
 static void go_batch_chain_rows_wpb(const BatchSlot<float> *slots, const int *items, int count,
                                     int64_t pop, int g, hipStream_t s) {
-    hipLaunchKernelGGL((batch_roll_chain_rows<float, J, WPB>),
+    hipLaunchKernelGGL((batch_roll_chain_rows<float, J, WPB, BOX>),
                        dim3((unsigned)((pop + 4 * WPB - 1) / (4 * WPB)), (unsigned)count),
                        dim3(64 * WPB), 0, s, slots, items, pop, g);
 }
-template <int J>
-static void go_batch_chain_rows(int variant, const BatchSlot<float> *slots, const int *items,
-                                int count, int64_t pop, int g, hipStream_t s) {
-    if (variant == 1) return go_batch_chain_rows_wpb<J, 2>(slots, items, count, pop, g, s);
-    if (variant == 2) return go_batch_chain_rows_wpb<J, 1>(slots, items, count, pop, g, s);
-    go_batch_chain_rows_wpb<J, 4>(slots, items, count, pop, g, s);
+template <int J, bool BOX>
+static void go_batch_chain_rows_box(int variant, const BatchSlot<float> *slots, const int *items,
+                                    int count, int64_t pop, int g, hipStream_t s) {
+    if (variant == 1) return go_batch_chain_rows_wpb<J, 2, BOX>(slots, items, count, pop, g, s);
+    if (variant == 2) return go_batch_chain_rows_wpb<J, 1, BOX>(slots, items, count, pop, g, s);
+    go_batch_chain_rows_wpb<J, 4, BOX>(slots, items, count, pop, g, s);
 }
-template <int DMAX>
-static void go_batch_chain(int variant, const BatchSlot<float> *slots, const int *items,
-                           int count, int64_t pop, int g, hipStream_t s) {
+template <int J>
+static void go_batch_chain_rows(int box, int variant, const BatchSlot<float> *slots,
+                                const int *items, int count, int64_t pop, int g, hipStream_t s) {
+    if (box) return go_batch_chain_rows_box<J, true>(variant, slots, items, count, pop, g, s);
+    go_batch_chain_rows_box<J, false>(variant, slots, items, count, pop, g, s);
+}
+template <int DMAX, bool BOX>
+static void go_batch_chain_box(int variant, const BatchSlot<float> *slots, const int *items,
+                               int count, int64_t pop, int g, hipStream_t s) {
     const int threads = variant == 1 ? 128 : variant == 2 ? 64 : 256;
-    hipLaunchKernelGGL((batch_roll_chain<float, DMAX>),
+    hipLaunchKernelGGL((batch_roll_chain<float, DMAX, BOX>),
                        dim3((unsigned)((pop + threads - 1) / threads), (unsigned)count),
                        dim3(threads), 0, s, slots, items, pop, g);
+}
+template <int DMAX>
+static void go_batch_chain(int box, int variant, const BatchSlot<float> *slots, const int *items,
+                           int count, int64_t pop, int g, hipStream_t s) {
+    if (box) return go_batch_chain_box<DMAX, true>(variant, slots, items, count, pop, g, s);
+    go_batch_chain_box<DMAX, false>(variant, slots, items, count, pop, g, s);
 }
 // one class's rollout launch, in its chosen shape
 static void launch_class(const BatchClass &c, int variant, const BatchSlot<float> *slots,
@@ -225,20 +244,20 @@ static void launch_class(const BatchClass &c, int variant, const BatchSlot<float
     const int *items = d_items + c.first;
     if (c.model == EMPC_LINEAR) {
         switch (c.a) {
-            case 1: go_batch_linear_nu<1>(c.b, variant, slots, items, c.count, pop, g, s); break;
-            case 2: go_batch_linear_nu<2>(c.b, variant, slots, items, c.count, pop, g, s); break;
-            case 3: go_batch_linear_nu<3>(c.b, variant, slots, items, c.count, pop, g, s); break;
-            case 4: go_batch_linear_nu<4>(c.b, variant, slots, items, c.count, pop, g, s); break;
-            default: go_batch_linear_nu<5>(c.b, variant, slots, items, c.count, pop, g, s); break;
+            case 1: go_batch_linear_nu<1>(c.b, c.box, variant, slots, items, c.count, pop, g, s); break;
+            case 2: go_batch_linear_nu<2>(c.b, c.box, variant, slots, items, c.count, pop, g, s); break;
+            case 3: go_batch_linear_nu<3>(c.b, c.box, variant, slots, items, c.count, pop, g, s); break;
+            case 4: go_batch_linear_nu<4>(c.b, c.box, variant, slots, items, c.count, pop, g, s); break;
+            default: go_batch_linear_nu<5>(c.b, c.box, variant, slots, items, c.count, pop, g, s); break;
         }
         return;
     }
     switch (c.a) {
-        case 4: go_batch_chain<4>(variant, slots, items, c.count, pop, g, s); break;
-        case 8: go_batch_chain<8>(variant, slots, items, c.count, pop, g, s); break;
-        case 16: go_batch_chain_rows<1>(variant, slots, items, c.count, pop, g, s); break;
-        case 32: go_batch_chain_rows<2>(variant, slots, items, c.count, pop, g, s); break;
-        default: go_batch_chain_rows<3>(variant, slots, items, c.count, pop, g, s); break;
+        case 4: go_batch_chain<4>(c.box, variant, slots, items, c.count, pop, g, s); break;
+        case 8: go_batch_chain<8>(c.box, variant, slots, items, c.count, pop, g, s); break;
+        case 16: go_batch_chain_rows<1>(c.box, variant, slots, items, c.count, pop, g, s); break;
+        case 32: go_batch_chain_rows<2>(c.box, variant, slots, items, c.count, pop, g, s); break;
+        default: go_batch_chain_rows<3>(c.box, variant, slots, items, c.count, pop, g, s); break;
     }
 }
 
@@ -391,13 +410,13 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
     }
     b->pop_wgs = total_wgs;
     // group problems by kernel shape class
-    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
     for (int i = 0; i < nprob; ++i) {
         const empc_problem &P = probs[i];
         if (P.model == EMPC_LINEAR)
-            groups[std::make_tuple(0, (P.n + 15) / 16, nu_bucket(P.m))].push_back(i);
+            groups[std::make_tuple(0, (P.n + 15) / 16, nu_bucket(P.m), P.qb ? 1 : 0)].push_back(i);
         else
-            groups[std::make_tuple(1, dmax_bucket(P.m), 0)].push_back(i);
+            groups[std::make_tuple(1, dmax_bucket(P.m), 0, P.qb ? 1 : 0)].push_back(i);
     }
     std::vector<int> items;
     for (auto &kv : groups) {
@@ -405,6 +424,7 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         c.model = std::get<0>(kv.first) == 0 ? EMPC_LINEAR : EMPC_PENDULUM_CHAIN;
         c.a = std::get<1>(kv.first);
         c.b = std::get<2>(kv.first);
+        c.box = std::get<3>(kv.first);
         c.first = (int)items.size();
         c.count = (int)kv.second.size();
         c.work = 0;

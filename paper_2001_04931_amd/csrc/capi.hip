@@ -47,6 +47,8 @@ empc_status validate_problem(const empc_problem *P) {
     if (P->p < 1 || P->p > P->T) return fail(EMPC_EINVAL, "p=%d outside [1, T=%d]", P->p, P->T);
     if (!P->q || !P->r || !P->u_min || !P->u_max)
         return fail(EMPC_EINVAL, "q, r, u_min and u_max are required");
+    if (P->qb && (!P->x_min || !P->x_max))
+        return fail(EMPC_EINVAL, "the state box penalty (qb) needs x_min and x_max");
     if (P->model == EMPC_LINEAR) {
         if (!P->Ad || !P->Bd) return fail(EMPC_EINVAL, "linear model needs Ad and Bd");
         if (P->n > Limits::MAX_N_LINEAR || P->m > Limits::MAX_M_LINEAR)

@@ -21,6 +21,7 @@ struct ProbView {
     const T *stiff, *damp, *mass, *len;
     T gravity, dt;
     const T *q, *r, *qf, *xg, *ug, *umin, *umax;
+    const T *xlo, *xhi, *qb;  // state box penalty (qb NULL: none)
 };
 
 template <typename T>
@@ -34,7 +35,21 @@ inline ProbView<T> view_of(const empc_problem &P) {
     v.q = (const T *)P.q; v.r = (const T *)P.r; v.qf = (const T *)P.qf;
     v.xg = (const T *)P.x_goal; v.ug = (const T *)P.u_goal;
     v.umin = (const T *)P.u_min; v.umax = (const T *)P.u_max;
+    v.xlo = (const T *)P.x_min; v.xhi = (const T *)P.x_max; v.qb = (const T *)P.qb;
     return v;
+}
+
+// State box penalty of one state: squared distance to [lo, hi] (unweighted),
+// and the derivative of w times it.
+template <typename T>
+__host__ __device__ inline T box_pen(T x, T lo, T hi) {
+    const T o = x - hi, u = lo - x;
+    return (o > (T)0 ? o * o : (T)0) + (u > (T)0 ? u * u : (T)0);
+}
+template <typename T>
+__host__ __device__ inline T box_pen_grad(T x, T lo, T hi, T w) {
+    const T o = x - hi, u = lo - x;
+    return o > (T)0 ? (T)2 * w * o : (u > (T)0 ? (T)-2 * w * u : (T)0);
 }
 
 // Knot interpolation of Sec. IV-D in exact integers: with num = k (p-1) and

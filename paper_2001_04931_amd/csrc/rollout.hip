@@ -24,12 +24,31 @@ static hipError_t launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipS
     return hipGetLastError();
 }
 
-template <typename T, int DMAX>
+template <typename T, int DMAX, bool BOX>
 static hipError_t go_chain(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
                            int64_t ld, T *cost, hipStream_t s, const Events &ev) {
     const int64_t blocks = (ncand + 255) / 256;
-    return launch_timed(roll_chain<T, DMAX>, dim3((unsigned)blocks), dim3(256), 0, s, ev, P, x0,
-                        knots, ld, ncand, cost);
+    return launch_timed(roll_chain<T, DMAX, BOX>, dim3((unsigned)blocks), dim3(256), 0, s, ev, P,
+                        x0, knots, ld, ncand, cost);
+}
+
+template <typename T, bool BOX>
+static hipError_t go_chain_forms(const ProbView<T> &P, const T *x0, const T *knots,
+                                 int64_t ncand, int64_t ld, T *cost, hipStream_t s,
+                                 const Events &ev) {
+    const int d = P.m;
+    if (d <= 4) return go_chain<T, 4, BOX>(P, x0, knots, ncand, ld, cost, s, ev);
+    if (d <= 8) return go_chain<T, 8, BOX>(P, x0, knots, ncand, ld, cost, s, ev);
+    // one candidate per 16-lane row for larger chains
+    const dim3 rows((unsigned)((ncand + 15) / 16)), blk(256);
+    if (d <= 16)
+        return launch_timed(roll_chain_rows<T, 1, BOX>, rows, blk, 0, s, ev, P, x0, knots, ld,
+                            ncand, cost);
+    if (d <= 32)
+        return launch_timed(roll_chain_rows<T, 2, BOX>, rows, blk, 0, s, ev, P, x0, knots, ld,
+                            ncand, cost);
+    return launch_timed(roll_chain_rows<T, 3, BOX>, rows, blk, 0, s, ev, P, x0, knots, ld, ncand,
+                        cost);  // d <= 48
 }
 
 template <typename T>
@@ -37,14 +56,8 @@ hipError_t launch_rollout(const ProbView<T> &P, int model, const T *x0, const T 
                           int64_t ncand, int64_t ld, T *cost, hipStream_t s, const Events &ev) {
     if (ncand <= 0) return hipSuccess;
     if (model == EMPC_LINEAR) return launch_linear<T>(P, x0, knots, ncand, ld, cost, s, ev);
-    const int d = P.m;
-    if (d <= 4) return go_chain<T, 4>(P, x0, knots, ncand, ld, cost, s, ev);
-    if (d <= 8) return go_chain<T, 8>(P, x0, knots, ncand, ld, cost, s, ev);
-    // one candidate per 16-lane row for larger chains
-    const dim3 rows((unsigned)((ncand + 15) / 16)), blk(256);
-    if (d <= 16) return launch_timed(roll_chain_rows<T, 1>, rows, blk, 0, s, ev, P, x0, knots, ld, ncand, cost);
-    if (d <= 32) return launch_timed(roll_chain_rows<T, 2>, rows, blk, 0, s, ev, P, x0, knots, ld, ncand, cost);
-    return launch_timed(roll_chain_rows<T, 3>, rows, blk, 0, s, ev, P, x0, knots, ld, ncand, cost);  // d <= 48
+    if (P.qb) return go_chain_forms<T, true>(P, x0, knots, ncand, ld, cost, s, ev);
+    return go_chain_forms<T, false>(P, x0, knots, ncand, ld, cost, s, ev);
 }
 
 template hipError_t launch_rollout<float>(const ProbView<float> &, int, const float *,

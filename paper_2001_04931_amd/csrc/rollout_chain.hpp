@@ -19,6 +19,8 @@ struct JointConst {
     T wq, wv, wqf, wvf;  // stage and terminal weights of q_j and qd_j
     T gq, gv;            // goals of q_j and qd_j
     T wr, gu;            // input weight and goal
+    T bq, bv;            // state box penalty weights of q_j and qd_j (0: none)
+    T loq, hiq, lov, hiv;  // and its bounds
 };
 
 template <typename T>
@@ -45,6 +47,13 @@ __device__ void chain_constants_lds(const ProbView<T> &P, JointConst<T> *jc) {
         c.gv = P.xg ? P.xg[d + j] : (T)0;
         c.wr = P.r[j];
         c.gu = P.ug ? P.ug[j] : (T)0;
+        const bool box = P.qb != nullptr;
+        c.bq = box ? P.qb[j] : (T)0;
+        c.bv = box ? P.qb[d + j] : (T)0;
+        c.loq = box ? P.xlo[j] : (T)0;
+        c.hiq = box ? P.xhi[j] : (T)0;
+        c.lov = box ? P.xlo[d + j] : (T)0;
+        c.hiv = box ? P.xhi[d + j] : (T)0;
         jc[j] = c;
     }
 }
@@ -71,14 +80,15 @@ template <>
 __device__ inline double sin_rollout<double>(double x) { return sin(x); }
 
 // One thread: candidate `cand` of one problem; jc holds the problem's
-// per-joint constants.
-template <typename T, int DMAX>
+// per-joint constants.  BOX: the problem has a state box penalty.
+template <typename T, int DMAX, bool BOX>
 __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const JointConst<T> *jc,
                                                 const T *__restrict__ x0,
                                                 const T *__restrict__ knots, int64_t ld,
                                                 T *__restrict__ cost, int64_t cand) {
     const int d = P.m;
     const T dt = P.dt;
+    constexpr bool box = BOX;
     T q[DMAX], v[DMAX], ua[DMAX], ub[DMAX];
 #pragma unroll
     for (int j = 0; j < DMAX; ++j) {
@@ -124,6 +134,8 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
                 q[j] = q[j] + dt * v[j];
                 const T eq = cj.gq - q[j], ev = cj.gv - v[j], eu = cj.gu - u;
                 js += cj.wq * eq * eq + cj.wv * ev * ev + cj.wr * eu * eu;
+                if (box)
+                    js += cj.bq * box_pen(q[j], cj.loq, cj.hiq) + cj.bv * box_pen(v[j], cj.lov, cj.hiv);
             }
         }
         J += js;
@@ -139,7 +151,7 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
     cost[cand] = J + jt;
 }
 
-template <typename T, int DMAX>
+template <typename T, int DMAX, bool BOX>
 __global__ __launch_bounds__(256) void roll_chain(ProbView<T> P, const T *__restrict__ x0,
                                                   const T *__restrict__ knots, int64_t ld,
                                                   int64_t ncand, T *__restrict__ cost) {
@@ -148,7 +160,7 @@ __global__ __launch_bounds__(256) void roll_chain(ProbView<T> P, const T *__rest
     __syncthreads();
     const int64_t cand = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (cand >= ncand) return;
-    chain_candidate<T, DMAX>(P, jc, x0, knots, ld, cost, cand);
+    chain_candidate<T, DMAX, BOX>(P, jc, x0, knots, ld, cost, cand);
 }
 
 // ---------------------------------------------------------------------------
@@ -158,8 +170,9 @@ __global__ __launch_bounds__(256) void roll_chain(ProbView<T> P, const T *__rest
 // over the lane's J joints plus a scan over the 16 lanes of the row with DPP
 // row shifts (which never cross a row).
 // One candidate per 16-lane row.  `cand` is the row's candidate; r the lane
-// in the row.  Every lane of the wavefront must call this (DPP).
-template <typename T, int J>
+// in the row.  Every lane of the wavefront must call this (DPP).  BOX: the
+// problem has a state box penalty.
+template <typename T, int J, bool BOX>
 __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const T *__restrict__ x0,
                                                     const T *__restrict__ knots, int64_t ld,
                                                     int64_t ncand, T *__restrict__ cost,
@@ -170,6 +183,9 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
     // per-joint constants of this lane's joints (zero for joints past d)
     T q[J], v[J], cg[J], invI[J], kst[J], dmp[J], wq[J], wv[J], gq[J], gv[J], wr[J], gu[J];
     T ua[J], ub[J];
+    // state box penalty: weights, bounds and running sums
+    constexpr bool box = BOX;
+    T bq[J], bv[J], loq[J], hiq[J], lov[J], hiv[J], Pq[J], Pv[J];
 #pragma unroll
     for (int i = 0; i < J; ++i) {
         const int j = r * J + i;
@@ -194,6 +210,14 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
         gu[i] = (in && P.ug) ? P.ug[j] : (T)0;
         q[i] = in ? x0[j] : (T)0;
         v[i] = in ? x0[d + j] : (T)0;
+        const bool bx = in && box;
+        bq[i] = bx ? P.qb[j] : (T)0;
+        bv[i] = bx ? P.qb[d + j] : (T)0;
+        loq[i] = bx ? P.xlo[j] : (T)0;
+        hiq[i] = bx ? P.xhi[j] : (T)0;
+        lov[i] = bx ? P.xlo[d + j] : (T)0;
+        hiv[i] = bx ? P.xhi[d + j] : (T)0;
+        Pq[i] = Pv[i] = 0;
     }
     const T dt = P.dt;
     const int Tn = P.Tn, p = P.p, den = Tn - 1;
@@ -212,7 +236,6 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
     };
     load_knot(0, ua);
     load_knot(1, ub);
-    load_knot(2, un);
 #pragma unroll
     for (int i = 0; i < J; ++i) du[i] = ub[i] - ua[i];
     // stage cost: per joint sums of squared errors, weighted at the end; the
@@ -231,7 +254,15 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
             Ju += wr[i] * ((T)nseg * e0 * e0 - (T)2 * e0 * du[i] * C1 + du[i] * du[i] * C2);
         }
     };
-    for (int k = 0; k < Tn; ++k) {
+    // Outer loop: knot segments; inner loop: the steps of one segment.  Knot
+    // a+2 is loaded when a segment starts and first used when it ends, and
+    // nothing merges into its registers in between, so the wait for that
+    // load falls at the segment's end rather than right after the load.
+    int k = 0;
+    for (;;) {
+        load_knot(a + 2, un);
+        bool adv = false;
+        do {
         const T c = (T)rem * inv_den;
         C1 += c;
         C2 += c * c;
@@ -268,30 +299,38 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
             const T eq = gq[i] - q[i], ev = gv[i] - v[i];
             Sq[i] += eq * eq;
             Sv[i] += ev * ev;
+            if (box) {
+                Pq[i] += box_pen(q[i], loq[i], hiq[i]);
+                Pv[i] += box_pen(v[i], lov[i], hiv[i]);
+            }
         }
         // advance the knot position to step k + 1 (uniform)
         if (p > 1 && Tn > 1) {
             rem += p - 1;
-            if (rem >= den && k + 1 < Tn) {
-                flush_input();
-                C1 = C2 = 0;
-                nseg = 0;
-                rem -= den;
-                ++a;
+            adv = rem >= den && k + 1 < Tn;
+        }
+        ++k;
+        } while (!adv && k < Tn);
+        if (!adv) break;  // k == Tn
+        flush_input();
+        C1 = C2 = 0;
+        nseg = 0;
+        rem -= den;
+        ++a;
 #pragma unroll
-                for (int i = 0; i < J; ++i) {
-                    ua[i] = ub[i];
-                    ub[i] = un[i];
-                    du[i] = ub[i] - ua[i];
-                }
-                load_knot(a + 2, un);
-            }
+        for (int i = 0; i < J; ++i) {
+            ua[i] = ub[i];
+            ub[i] = un[i];
+            du[i] = ub[i] - ua[i];
         }
     }
     flush_input();
     T J_ = Ju;
 #pragma unroll
     for (int i = 0; i < J; ++i) J_ += wq[i] * Sq[i] + wv[i] * Sv[i];
+    if (box)
+#pragma unroll
+        for (int i = 0; i < J; ++i) J_ += bq[i] * Pq[i] + bv[i] * Pv[i];
     T jt = 0;
 #pragma unroll
     for (int i = 0; i < J; ++i) {
@@ -310,13 +349,13 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
     if (r == 0 && valid) cost[cand] = tot;
 }
 
-template <typename T, int J>
+template <typename T, int J, bool BOX>
 __global__ __launch_bounds__(256) void roll_chain_rows(ProbView<T> P, const T *__restrict__ x0,
                                                        const T *__restrict__ knots, int64_t ld,
                                                        int64_t ncand, T *__restrict__ cost) {
     const int64_t cand0 = xcd_swizzle(blockIdx.x, gridDim.x) * 16;  // 16 rows per block
     if (cand0 + (threadIdx.x >> 6) * 4 >= ncand) return;  // whole wavefront past the end
-    chain_row_candidate<T, J>(P, x0, knots, ld, ncand, cost, cand0 + (threadIdx.x >> 4),
+    chain_row_candidate<T, J, BOX>(P, x0, knots, ld, ncand, cost, cand0 + (threadIdx.x >> 4),
                               threadIdx.x & 15);
 }
 

@@ -72,7 +72,10 @@ struct Mfma<double> {
 // with the two sums over c_k accumulated by the step loop (two VALU
 // operations per step, off the MFMA chain).
 // One wavefront: candidates 16*tile .. 16*tile+15 of one problem.
-template <typename T, int NT, int NU, bool HAS_XG>
+// BOX: the problem has a state box penalty (P.qb non-NULL); it is summed per
+// state row like the stage cost, from the state at the start of each step,
+// corrected for x_0 and completed with x_T at the end.
+template <typename T, int NT, int NU, bool HAS_XG, bool BOX = false>
 __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__restrict__ x0,
                                             const T *__restrict__ knots, int64_t ld,
                                             int64_t ncand, T *__restrict__ cost, int64_t tile) {
@@ -109,6 +112,7 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
     }
     // State, disturbance and goal in accumulator layout: row 16mt + R(grp, v).
     v4 X[NT], Wd[NT], Xg[NT];
+    v4 Lo[BOX ? NT : 1], Hi[BOX ? NT : 1], Pn[BOX ? NT : 1];
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
@@ -118,6 +122,11 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
             X[mt][v] = in ? x0[row] : (T)0;
             Wd[mt][v] = (in && P.wd) ? P.wd[row] : (T)0;
             Xg[mt][v] = (in && HAS_XG && P.xg) ? P.xg[row] : (T)0;
+            if (BOX) {  // padding rows: a box around their zero state
+                Lo[mt][v] = in ? P.xlo[row] : (T)-1;
+                Hi[mt][v] = in ? P.xhi[row] : (T)1;
+                Pn[mt][v] = -box_pen(X[mt][v], Lo[mt][v], Hi[mt][v]);
+            }
         }
 
     // the model operands and the initial state are needed by the first
@@ -239,6 +248,7 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
                     }
                     const T e = HAS_XG ? X[i][v] - Xg[i][v] : X[i][v];
                     S[i][v] += e * e;
+                    if (BOX) Pn[i][v] += box_pen(X[i][v], Lo[i][v], Hi[i][v]);
                     __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
@@ -280,6 +290,10 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
             const T q = in ? P.q[row] : (T)0;
             const T qf = (in && P.qf) ? P.qf[row] : (T)0;
             Jm += q * (S[mt][v] + e * e) + qf * e * e;
+            if (BOX) {
+                const T qb = in ? P.qb[row] : (T)0;
+                Jm += qb * (Pn[mt][v] + box_pen(X[mt][v], Lo[mt][v], Hi[mt][v]));
+            }
         }
         Jm += __shfl_xor(Jm, 16, 64);
         Jm += __shfl_xor(Jm, 32, 64);
@@ -288,13 +302,13 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
     if (grp == 0 && valid) cost[cand] = J;
 }
 
-template <typename T, int NT, int NU, int WPB, bool HAS_XG>
+template <typename T, int NT, int NU, int WPB, bool HAS_XG, bool BOX>
 __global__ __launch_bounds__(64 * WPB) void roll_linear_mfma(ProbView<T> P,
                                                              const T *__restrict__ x0,
                                                              const T *__restrict__ knots,
                                                              int64_t ld, int64_t ncand,
                                                              T *__restrict__ cost) {
-    linear_tile<T, NT, NU, HAS_XG>(P, x0, knots, ld, ncand, cost,
+    linear_tile<T, NT, NU, HAS_XG, BOX>(P, x0, knots, ld, ncand, cost,
                                    xcd_swizzle(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6));
 }
 
@@ -326,7 +340,7 @@ __device__ inline void lds_barrier() {
 // One workgroup of 64 NT threads: candidates 16*tile .. 16*tile+15 (tile
 // must hold at least one candidate: the whole workgroup takes part in every
 // barrier).
-template <typename T, int NT, int NU, bool HAS_XG>
+template <typename T, int NT, int NU, bool HAS_XG, bool BOX = false>
 __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T *__restrict__ x0,
                                                   const T *__restrict__ knots, int64_t ld,
                                                   int64_t ncand, T *__restrict__ cost,
@@ -372,12 +386,18 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
             X[i][v] = row < n ? x0[row] : (T)0;
         }
     }
+    v4 Lo, Hi, Pn;  // state box penalty of the own rows (BOX)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int row = 16 * w + Mfma<T>::row(grp, v);
         const bool in = row < n;
         Wd[v] = (in && P.wd) ? P.wd[row] : (T)0;
         Xg[v] = (in && HAS_XG && P.xg) ? P.xg[row] : (T)0;
+        if (BOX) {  // padding rows: a box around their zero state
+            Lo[v] = in ? P.xlo[row] : (T)-1;
+            Hi[v] = in ? P.xhi[row] : (T)1;
+            Pn[v] = -box_pen(X[0][v], Lo[v], Hi[v]);
+        }
     }
 
     // the model operands and the initial state are needed by the first
@@ -471,6 +491,7 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
                     if (i == 0) {
                         const T e = HAS_XG ? X[0][v] - Xg[v] : X[0][v];
                         S[v] += e * e;
+                        if (BOX) Pn[v] += box_pen(X[0][v], Lo[v], Hi[v]);
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -507,6 +528,10 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
         const T q = in ? P.q[row] : (T)0;
         const T qf = (in && P.qf) ? P.qf[row] : (T)0;
         J += q * (S[v] + e * e) + qf * e * e;
+        if (BOX) {
+            const T qb = in ? P.qb[row] : (T)0;
+            J += qb * (Pn[v] + box_pen(X[0][v], Lo[v], Hi[v]));
+        }
     }
     J += __shfl_xor(J, 16, 64);
     J += __shfl_xor(J, 32, 64);
@@ -524,14 +549,14 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
     }
 }
 
-template <typename T, int NT, int NU, bool HAS_XG>
+template <typename T, int NT, int NU, bool HAS_XG, bool BOX>
 __global__ __launch_bounds__(64 * NT) void roll_linear_split(ProbView<T> P,
                                                              const T *__restrict__ x0,
                                                              const T *__restrict__ knots,
                                                              int64_t ld, int64_t ncand,
                                                              T *__restrict__ cost) {
-    linear_tile_split<T, NT, NU, HAS_XG>(P, x0, knots, ld, ncand, cost,
-                                         xcd_swizzle(blockIdx.x, gridDim.x));
+    linear_tile_split<T, NT, NU, HAS_XG, BOX>(P, x0, knots, ld, ncand, cost,
+                                              xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
 // Launch through hipExtLaunchKernelGGL when timing events are given: the
@@ -552,25 +577,28 @@ static hipError_t launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipS
 // forms round identically, so the choice never changes a result.
 constexpr int64_t SPLIT_MAX_TILES = 1024;
 
+template <typename T, int NT, int NU, bool HAS_XG, bool BOX>
+static hipError_t go_linear_forms(const ProbView<T> &P, const T *x0, const T *knots,
+                                  int64_t ncand, int64_t ld, T *cost, hipStream_t s,
+                                  const Events &ev) {
+    constexpr int WPB = 4;
+    const int64_t tiles = (ncand + 15) / 16;
+    if (NT > 1 && tiles < SPLIT_MAX_TILES)
+        return launch_timed(roll_linear_split<T, NT, NU, HAS_XG, BOX>, dim3((unsigned)tiles),
+                            dim3(64 * NT), 0, s, ev, P, x0, knots, ld, ncand, cost);
+    return launch_timed(roll_linear_mfma<T, NT, NU, WPB, HAS_XG, BOX>,
+                        dim3((unsigned)((tiles + WPB - 1) / WPB)), dim3(64 * WPB), 0, s, ev, P, x0,
+                        knots, ld, ncand, cost);
+}
+
+// goal and state box variants: (no goal, no box), (goal, no box), (box, with
+// or without a goal: a NULL goal reads as 0)
 template <typename T, int NT, int NU>
 static hipError_t go_linear(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
                             int64_t ld, T *cost, hipStream_t s, const Events &ev) {
-    constexpr int WPB = 4;
-    const int64_t tiles = (ncand + 15) / 16;
-    if (NT > 1 && tiles < SPLIT_MAX_TILES) {
-        const dim3 grid((unsigned)tiles), block(64 * NT);
-        if (P.xg)
-            return launch_timed(roll_linear_split<T, NT, NU, true>, grid, block, 0, s, ev, P, x0,
-                                knots, ld, ncand, cost);
-        return launch_timed(roll_linear_split<T, NT, NU, false>, grid, block, 0, s, ev, P, x0,
-                            knots, ld, ncand, cost);
-    }
-    const dim3 grid((unsigned)((tiles + WPB - 1) / WPB)), block(64 * WPB);
-    if (P.xg)
-        return launch_timed(roll_linear_mfma<T, NT, NU, WPB, true>, grid, block, 0, s, ev, P, x0,
-                            knots, ld, ncand, cost);
-    return launch_timed(roll_linear_mfma<T, NT, NU, WPB, false>, grid, block, 0, s, ev, P, x0,
-                        knots, ld, ncand, cost);
+    if (P.qb) return go_linear_forms<T, NT, NU, true, true>(P, x0, knots, ncand, ld, cost, s, ev);
+    if (P.xg) return go_linear_forms<T, NT, NU, true, false>(P, x0, knots, ncand, ld, cost, s, ev);
+    return go_linear_forms<T, NT, NU, false, false>(P, x0, knots, ncand, ld, cost, s, ev);
 }
 
 template <typename T, int NT>

@@ -186,3 +186,35 @@ def test_large_population_single_matches_batched(E):
         assert torch.equal(bs.u_of(0), u), tick
         assert torch.equal(bs.best_cost[0:1], J), tick
     bs.close()
+
+
+def test_batched_box_penalty_equals_single(E):
+    """Problems of both models carry a state box penalty (their own kernel
+    classes, beside box-free problems of the same shapes): batch and single
+    solves agree bit for bit."""
+    boxed, probs = mixed_problems(5), mixed_problems(6)
+    rng = np.random.default_rng(5)
+    for i, p in enumerate(boxed):
+        if i % 4 < 2:  # both models at 2, 14 and 36 degrees of freedom
+            hw = 0.1 * rng.uniform(0.5, 1.5, p.n)
+            p.x_min, p.x_max = -hw, hw
+            p.qb = rng.uniform(1.0, 4.0, p.n)
+    probs = [p.cast(np.float32) for p in boxed + probs]
+    ga = W.GA(pop=128, n_elite=8, generations=2, sigma=0.1, seed=77)
+    dps = [E.DeviceProblem(p, F32) for p in probs]
+    bs = E.BatchSolver(dps, ga)
+    assert len(bs.classes()) == 16  # 10 shape classes, 6 of them also with a box
+    singles = [E.Solver(dp, W.dataclasses.replace(ga, seed=ga.seed ^ (i << 32)))
+               for i, dp in enumerate(dps)]
+    x0s = [W.draw_x0(p.n, 3 + i).astype(np.float32) for i, p in enumerate(probs)]
+    for i, x in enumerate(x0s):
+        bs.set_x0(i, x)
+    for tick in range(2):
+        bs.solve()
+        torch.cuda.synchronize()
+        for i, s in enumerate(singles):
+            u, J = s.solve(torch.tensor(x0s[i], device="cuda"), tick)
+            torch.cuda.synchronize()
+            assert torch.equal(bs.u_of(i), u), (tick, i)
+            assert torch.equal(bs.best_cost[i:i + 1], J), (tick, i)
+    bs.close()

@@ -82,6 +82,22 @@ def test_grad_fp32_matches_oracle(oracle_lib, E, kind, d, T, p):
     np.testing.assert_allclose(cost, wcost, rtol=1e-4)
 
 
+@pytest.mark.parametrize("kind,d,T,p", [("linear", 14, 50, 10), ("linear", 2, 20, 5),
+                                         ("chain", 6, 40, 5), ("chain", 20, 30, 4)])
+def test_grad_fp64_box_penalty_matches_oracle(oracle_lib, E, kind, d, T, p):
+    # the state box penalty enters the cost and every adjoint step
+    prob = make(kind, d, T, p)
+    rng = np.random.default_rng(d)
+    hw = 0.05 * rng.uniform(0.5, 1.5, prob.n)
+    prob.x_min, prob.x_max = prob.x_goal - hw, prob.x_goal + hw
+    prob.qb = 3.0 * rng.uniform(0.5, 2.0, prob.n)
+    prob, x0, knots = setup(prob, 9, F64, ld=12)
+    dJ, cost = gpu_grad(E, prob, x0, knots, 9, F64)
+    want, wcost = oracle_lib.grad(prob, x0, knots, 9)
+    assert rel_err_cols(dJ[:, :9], want[:, :9]) < 1e-9
+    np.testing.assert_allclose(cost, wcost, rtol=1e-10)
+
+
 @pytest.mark.parametrize("kind,d,T,p", [("linear", 14, 50, 10), ("chain", 6, 40, 5)])
 def test_grad_fp64_central_differences(E, kind, d, T, p):
     prob, x0, knots = setup(make(kind, d, T, p), 2, F64)

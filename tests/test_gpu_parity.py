@@ -119,6 +119,63 @@ def test_rollout_pendulum_c3_shape(oracle_lib, E):
     check_costs(oracle_lib, E, prob, ncand=70, ld=70, dtype=F32)
 
 
+def with_box(prob, half_width, weight, seed=0):
+    """The problem with a state box around the goal, tight enough that many
+    states leave it: x_goal -/+ half_width (per state, jittered), weights
+    qb."""
+    rng = np.random.default_rng(seed)
+    out = W.dataclasses.replace(prob)
+    g = prob.x_goal if prob.x_goal is not None else np.zeros(prob.n)
+    hw = half_width * rng.uniform(0.5, 1.5, prob.n)
+    out.x_min, out.x_max = g - hw, g + hw
+    out.qb = weight * rng.uniform(0.5, 2.0, prob.n)
+    return out
+
+
+# (model maker, d, T, p, candidates): the linear one-wavefront form (4
+# states), the M-split form (28 and 42 states), the chain's lane form (5
+# joints) and row form (20 joints)
+BOX_CASES = [(W.linear_chain, 2, 20, 5, 70), (W.linear_chain, 14, 50, 10, 300),
+             (W.linear_chain, 21, 30, 6, 100), (W.pendulum_chain, 5, 40, 5, 200),
+             (W.pendulum_chain, 20, 40, 5, 64)]
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("case", range(len(BOX_CASES)))
+def test_rollout_box_penalty_matches_oracle(oracle_lib, E, dtype, case):
+    mk, d, T, p, ncand = BOX_CASES[case]
+    prob = with_box(mk(d, T, p, seed=d), 0.05, 3.0, seed=d)
+    got, want = check_costs(oracle_lib, E, prob, ncand=ncand, ld=ncand + 3, dtype=dtype, seed=d)
+    # the bounds are tight enough that the penalty is active for every candidate
+    plain = rounded(W.dataclasses.replace(prob, x_min=None, x_max=None, qb=None), dtype)
+    x0 = W.draw_x0(prob.n, d).astype(npdt(dtype)).astype(np.float64)
+    knots = W.draw_knots(plain, ncand, d + 1, ld=ncand + 3).astype(npdt(dtype)).astype(np.float64)
+    assert np.all(want > oracle_lib.rollout_cost(plain, x0, knots, ncand))
+
+
+def test_box_penalty_needs_bounds(E):
+    prob = W.linear_chain(2, 10, 3, seed=0)
+    prob.qb = np.ones(prob.n)  # no x_min / x_max
+    cost = torch.empty(4, device="cuda")
+    with pytest.raises(E.EmpcError):
+        E.empc_rollout_cost(E.DeviceProblem(prob, F32), torch.zeros(prob.n, device="cuda"),
+                            torch.zeros((prob.p * prob.m, 4), device="cuda"), 4, 4, cost)
+
+
+def test_solve_fp64_box_matches_oracle(oracle_lib, E):
+    prob = with_box(W.linear_chain(3, 20, 5, seed=2), 0.1, 5.0, seed=3)
+    ga = W.GA(pop=200, n_elite=10, generations=3, sigma=0.1, seed=8)
+    solver = E.Solver(E.DeviceProblem(prob, F64), ga)
+    osolver = oracle_lib.Solver(prob, ga)
+    x = W.draw_x0(prob.n, 5)
+    for tick in range(3):
+        u, J = solver.solve(as_dev(x, F64), tick)
+        uo, Jo, _ = osolver.solve(x, tick)
+        np.testing.assert_allclose(u.cpu().numpy(), uo, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(float(J.item()), Jo, rtol=1e-9)
+        x = oracle_lib.step(prob, x, uo)
+
+
 @pytest.mark.parametrize("model", ["linear", "chain"])
 @pytest.mark.parametrize("T,p", [(1, 1), (9, 1), (12, 12), (50, 2), (2, 2)])
 def test_rollout_knot_edge_cases(oracle_lib, E, model, T, p):
