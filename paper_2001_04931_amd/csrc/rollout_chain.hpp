@@ -95,23 +95,33 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
         q[j] = j < d ? x0[j] : (T)0;
         v[j] = j < d ? x0[d + j] : (T)0;
     }
-    const T inv_den = P.Tn > 1 ? (T)1 / (T)(P.Tn - 1) : (T)0;
+    const int Tn = P.Tn, p = P.p, den = Tn - 1;
+    const T inv_den = Tn > 1 ? (T)1 / (T)den : (T)0;
+    auto load_knot = [&](int kn, T *dst) {
+        const int kc = kn < p ? kn : p - 1;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j)  // joints past d (never used) repeat d-1:
+            // every lane issues the same loads, which keeps the waits countable
+            dst[j] = knots[(int64_t)(kc * d + (j < d ? j : d - 1)) * ld + cand];
+    };
+    // knots a, a+1 (ub) and a+2 (un); the knot position of step k is kept
+    // incrementally, k (p-1) = a (T-1) + rem (p <= T: at most one boundary
+    // per step)
+    T un[DMAX];
+    load_knot(0, ua);
+    load_knot(1, ub);
+    int a = 0, rem = 0, k = 0;
     T J = 0;
-    int cur_a = -1;
-    for (int k = 0; k < P.Tn; ++k) {
+    // outer loop: knot segments; inner loop: the steps of one segment.  Knot
+    // a+2 is loaded when a segment starts and first used when it ends.
+    for (;;) {
+        load_knot(a + 2, un);
+        bool adv = false;
+        do {
         // re-read the per-joint constants from LDS every step instead of
         // letting them be hoisted into (and overflow) registers
         asm volatile("" ::: "memory");
-        const Knot kn = knot_at(P.Tn, P.p, k);
-        if (kn.a != cur_a) {
-            cur_a = kn.a;
-#pragma unroll
-            for (int j = 0; j < DMAX; ++j) {
-                ua[j] = j < d ? knots[(int64_t)(kn.a * d + j) * ld + cand] : (T)0;
-                ub[j] = j < d ? knots[(int64_t)(kn.b * d + j) * ld + cand] : (T)0;
-            }
-        }
-        const T c = (T)kn.rem * inv_den;
+        const T c = (T)rem * inv_den;
         // gravity torque: G_j = sum_{r>=j} cg_r sin(phi_r), phi_r = q_0 + .. + q_r
         T sg[DMAX];
         T phi = 0;
@@ -139,6 +149,20 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
             }
         }
         J += js;
+        if (p > 1 && Tn > 1) {
+            rem += p - 1;
+            adv = rem >= den && k + 1 < Tn;
+        }
+        ++k;
+        } while (!adv && k < Tn);
+        if (!adv) break;  // k == Tn
+        rem -= den;
+        ++a;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+            ua[j] = ub[j];
+            ub[j] = un[j];
+        }
     }
     T jt = 0;
 #pragma unroll
