@@ -14,7 +14,7 @@ namespace empc {
 template <typename T>
 struct JointConst {
     T cg;    // g l_r M_r (gravity coefficient of absolute angle r)
-    T invI;  // 1 / I_j
+    T dtI;   // dt / I_j (the velocity update's factor)
     T kst, dmp;
     T wq, wv, wqf, wvf;  // stage and terminal weights of q_j and qd_j
     T gq, gv;            // goals of q_j and qd_j
@@ -36,7 +36,7 @@ __device__ void chain_constants_lds(const ProbView<T> &P, JointConst<T> *jc) {
         }
         JointConst<T> c;
         c.cg = P.gravity * P.len[j] * tail;
-        c.invI = (T)1 / inert;
+        c.dtI = P.dt / inert;
         c.kst = P.stiff[j];
         c.dmp = P.damp[j];
         c.wq = P.q[j];
@@ -139,8 +139,9 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
                 const JointConst<T> cj = jc[j];
                 G += sg[j];
                 const T u = ((T)1 - c) * ua[j] + c * ub[j];
-                const T acc = (u - cj.kst * q[j] - cj.dmp * v[j] - G) * cj.invI;
-                v[j] = v[j] + dt * acc;
+                // qd += dt (u - k q - b qd - G) / I, with dt / I as one factor
+                const T f = u - cj.kst * q[j] - cj.dmp * v[j] - G;
+                v[j] = v[j] + cj.dtI * f;
                 q[j] = q[j] + dt * v[j];
                 const T eq = cj.gq - q[j], ev = cj.gv - v[j], eu = cj.gu - u;
                 js += cj.wq * eq * eq + cj.wv * ev * ev + cj.wr * eu * eu;
@@ -205,7 +206,7 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
     const bool valid = cand < ncand;
     const int64_t cc = valid ? cand : ncand - 1;  // loads stay in bounds
     // per-joint constants of this lane's joints (zero for joints past d)
-    T q[J], v[J], cg[J], invI[J], kst[J], dmp[J], wq[J], wv[J], gq[J], gv[J], wr[J], gu[J];
+    T q[J], v[J], cg[J], dtI[J], kst[J], dmp[J], wq[J], wv[J], gq[J], gv[J], wr[J], gu[J];
     T ua[J], ub[J];
     // state box penalty: weights, bounds and running sums
     constexpr bool box = BOX;
@@ -223,7 +224,7 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
             }
         }
         cg[i] = in ? P.gravity * P.len[j] * tail : (T)0;
-        invI[i] = in ? (T)1 / inert : (T)0;
+        dtI[i] = in ? P.dt / inert : (T)0;
         kst[i] = in ? P.stiff[j] : (T)0;
         dmp[i] = in ? P.damp[j] : (T)0;
         wq[i] = in ? P.q[j] : (T)0;
@@ -294,9 +295,10 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
         // cumulative angles phi: local prefix over the lane's joints, then
         // the row's exclusive prefix of lane totals
         T loc[J];
-        T run = 0;
+        T run = q[0];
+        loc[0] = run;
 #pragma unroll
-        for (int i = 0; i < J; ++i) {
+        for (int i = 1; i < J; ++i) {
             run += q[i];
             loc[i] = run;
         }
@@ -317,8 +319,9 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
         for (int i = 0; i < J; ++i) {
             const T G = after + sloc[i];
             const T u = ua[i] + c * du[i];
-            const T acc = (u - kst[i] * q[i] - dmp[i] * v[i] - G) * invI[i];
-            v[i] = v[i] + dt * acc;
+            // qd += dt (u - k q - b qd - G) / I, with dt / I as one factor
+            const T f = u - kst[i] * q[i] - dmp[i] * v[i] - G;
+            v[i] = v[i] + dtI[i] * f;
             q[i] = q[i] + dt * v[i];
             const T eq = gq[i] - q[i], ev = gv[i] - v[i];
             Sq[i] += eq * eq;
