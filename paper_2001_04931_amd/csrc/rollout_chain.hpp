@@ -65,19 +65,25 @@ __device__ inline float sin_of<float>(float x) { return sinf(x); }
 template <>
 __device__ inline double sin_of<double>(double x) { return sin(x); }
 
-// sin for the rollout's gravity torques.  FP32: the hardware transcendental
-// (v_sin_f32 takes its argument in revolutions), two instructions instead of
-// the library's range reduction and polynomial; its absolute error (a few
-// 1e-7) is of the order of FP32 rounding of the cumulative angle itself.
-// FP64: the library sin.
+// sin for the rollout's gravity torques, of an angle given in the unit
+// RolloutAngle<T>::per_rad per radian.  FP32: the hardware transcendental
+// (v_sin_f32 takes its argument in revolutions; the rollout sums the
+// cumulative angles in revolutions directly, q / (2 pi) folded into the sum
+// as one fused multiply-add), instead of the library's range reduction and
+// polynomial; its absolute error (a few 1e-7) is of the order of FP32
+// rounding of the cumulative angle itself.  FP64: radians, the library sin.
 template <typename T>
-__device__ inline T sin_rollout(T x);
+struct RolloutAngle;
 template <>
-__device__ inline float sin_rollout<float>(float x) {
-    return __builtin_amdgcn_sinf(x * 0.15915494309189535f);
-}
+struct RolloutAngle<float> {
+    static constexpr float per_rad = 0.15915494309189535f;  // 1 / (2 pi)
+    __device__ static float sin(float rev) { return __builtin_amdgcn_sinf(rev); }
+};
 template <>
-__device__ inline double sin_rollout<double>(double x) { return sin(x); }
+struct RolloutAngle<double> {
+    static constexpr double per_rad = 1.0;
+    __device__ static double sin(double rad) { return ::sin(rad); }
+};
 
 // One thread: candidate `cand` of one problem; jc holds the problem's
 // per-joint constants.  BOX: the problem has a state box penalty.
@@ -123,13 +129,14 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
         asm volatile("" ::: "memory");
         const T c = (T)rem * inv_den;
         // gravity torque: G_j = sum_{r>=j} cg_r sin(phi_r), phi_r = q_0 + .. + q_r
+        // (phi summed in the unit of RolloutAngle<T>)
         T sg[DMAX];
         T phi = 0;
 #pragma unroll
         for (int j = 0; j < DMAX; ++j) {
             if (j < d) {
-                phi += q[j];
-                sg[j] = jc[j].cg * sin_rollout<T>(phi);
+                phi += q[j] * RolloutAngle<T>::per_rad;
+                sg[j] = jc[j].cg * RolloutAngle<T>::sin(phi);
             }
         }
         T G = 0, js = 0;
@@ -302,10 +309,11 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
             run += q[i];
             loc[i] = run;
         }
-        const T before = row_scan_up<T>(run) - run;
+        const T before = (row_scan_up<T>(run) - run) * RolloutAngle<T>::per_rad;
         T sg[J];
 #pragma unroll
-        for (int i = 0; i < J; ++i) sg[i] = cg[i] * sin_rollout<T>(before + loc[i]);
+        for (int i = 0; i < J; ++i)
+            sg[i] = cg[i] * RolloutAngle<T>::sin(loc[i] * RolloutAngle<T>::per_rad + before);
         // gravity torque G_j = sum_{r >= j} cg_r sin(phi_r): local suffix plus
         // the row's exclusive suffix of lane totals
         T srun = 0, sloc[J];
