@@ -119,6 +119,22 @@ def test_rollout_pendulum_c3_shape(oracle_lib, E):
     check_costs(oracle_lib, E, prob, ncand=70, ld=70, dtype=F32)
 
 
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_rollout_pendulum_c3_full_launch_sampled(oracle_lib, E, dtype):
+    # the 36-link chain at its full population (16384 candidates, 1024
+    # workgroups of the row form), every 257th candidate and the last one
+    # against the oracle
+    prob, ga = W.config_c3(0)
+    prob = prob.cast(npdt(dtype))
+    x0 = W.draw_x0(prob.n, 7).astype(npdt(dtype)).astype(np.float64)
+    knots = W.draw_knots(prob, ga.pop, 8).astype(npdt(dtype)).astype(np.float64)
+    full = gpu_costs(E, prob, x0, knots, ga.pop, dtype)
+    idx = np.append(np.arange(0, ga.pop, 257), ga.pop - 1)
+    want = oracle_lib.rollout_cost(prob, x0, np.ascontiguousarray(knots[:, idx]), len(idx))
+    np.testing.assert_allclose(full[idx], want, rtol=RTOL[dtype], atol=0)
+    assert np.all(np.isfinite(full))
+
+
 def with_box(prob, half_width, weight, seed=0):
     """The problem with a state box around the goal, tight enough that many
     states leave it: x_goal -/+ half_width (per state, jittered), weights
