@@ -88,7 +88,10 @@ typedef struct {
      * method admits).  qb NULL: none.  Else x_min, x_max (n each) are
      * required and every state x_1..x_T adds
      *   sum_i qb_i (max(0, x_i - x_max_i)^2 + max(0, x_min_i - x_i)^2)
-     * to the cost (and its derivative to the adjoint). */
+     * to the cost (and its derivative to the adjoint).  The arrays live on
+     * the device and are not read on the host: x_min <= x_max and qb >= 0
+     * are the caller's to keep (infinite bounds are allowed and cost
+     * nothing). */
     const void *x_min;     /* n  state lower bounds (with qb)                    */
     const void *x_max;     /* n  state upper bounds (with qb)                    */
     const void *qb;        /* n  weights of the box penalty; NULL = none         */

@@ -169,6 +169,29 @@ def test_rollout_box_penalty_matches_oracle(oracle_lib, E, dtype, case):
     assert np.all(want > oracle_lib.rollout_cost(plain, x0, knots, ncand))
 
 
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("mk,d", [(W.linear_chain, 2), (W.linear_chain, 14),
+                                  (W.pendulum_chain, 5), (W.pendulum_chain, 20)])
+def test_rollout_box_degenerate_cases(E, dtype, mk, d):
+    prob = mk(d, 30, 6, seed=d)
+    prob.x_goal = np.linspace(-0.1, 0.1, prob.n)
+    prob = prob.cast(npdt(dtype))
+    x0 = W.draw_x0(prob.n, d)
+    knots = W.draw_knots(prob, 100, d + 1)
+    plain = gpu_costs(E, prob, x0, knots, 100, dtype)
+    # infinite bounds: the penalty is exactly zero, the cost bit for bit the plain one
+    inf = W.dataclasses.replace(prob, x_min=np.full(prob.n, -np.inf), x_max=np.full(prob.n, np.inf),
+                                qb=np.full(prob.n, 3.0))
+    np.testing.assert_array_equal(gpu_costs(E, inf, x0, knots, 100, dtype), plain)
+    # a zero-width box at the goal with weight w is w added to the diagonal
+    # of Q (stage terms only); some weights zero
+    w = np.where(np.arange(prob.n) % 3 == 0, 0.0, 0.7).astype(npdt(dtype))
+    point = W.dataclasses.replace(prob, x_min=prob.x_goal.copy(), x_max=prob.x_goal.copy(), qb=w)
+    heavier = W.dataclasses.replace(prob, q=(prob.q + w).astype(npdt(dtype)))
+    np.testing.assert_allclose(gpu_costs(E, point, x0, knots, 100, dtype),
+                               gpu_costs(E, heavier, x0, knots, 100, dtype), rtol=RTOL[dtype] / 10)
+
+
 def test_box_penalty_needs_bounds(E):
     prob = W.linear_chain(2, 10, 3, seed=0)
     prob.qb = np.ones(prob.n)  # no x_min / x_max

@@ -636,6 +636,22 @@ def test_box_penalty_closed_form(oracle_lib):
         np.testing.assert_allclose(J, T * 0.7 * d * d, rtol=1e-14)
 
 
+@pytest.mark.parametrize("mk", [W.linear_chain, W.pendulum_chain])
+def test_box_penalty_point_box_is_extra_state_weight(oracle_lib, mk):
+    # a zero-width box at the goal makes the penalty qb_i (x_i - g_i)^2 on
+    # x_1..x_T: the stage cost with q_i + qb_i and no box (terminal term
+    # untouched), with some weights zero
+    prob = mk(4, 30, 6, seed=6)
+    prob.x_goal = np.linspace(-0.1, 0.1, prob.n)
+    prob.qf = np.linspace(0.5, 1.0, prob.n)
+    w = np.where(np.arange(prob.n) % 3 == 0, 0.0, 0.7)
+    x0 = W.draw_x0(prob.n, 6)
+    knots = W.draw_knots(prob, 20, seed=6)
+    boxed = oracle_lib.rollout_cost(with_box(prob, prob.x_goal, prob.x_goal, w), x0, knots)
+    heavier = oracle_lib.rollout_cost(W.dataclasses.replace(prob, q=prob.q + w), x0, knots)
+    np.testing.assert_allclose(boxed, heavier, rtol=1e-13)
+
+
 @pytest.mark.parametrize("model", ["linear", "chain"])
 def test_box_penalty_gradient_central_differences(oracle_lib, model):
     # the penalty is piecewise quadratic: away from the box faces central
