@@ -12,11 +12,17 @@ hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *k
                              const PopVariant<T> &var) {
     const int pm = P.p * P.m;
     const GaStreams gs = ga_streams(ga.seed, P.m, pm);
-    const int64_t blocks = pop_tiles_s(ga.pop) * pop_tiles_g(pm);
+    // parameter groups per thread: a workgroup's draws shared by its
+    // children (parents, mutation flags, crossover bits) are taken once per
+    // workgroup, so large populations take 32 or 64 parameters per
+    // workgroup instead of 16, as long as thousands of workgroups remain
+    const int64_t wgs1 = pop_tiles_s(ga.pop) * pop_tiles_g(pm);
+    const int R = wgs1 >= 4096 ? 4 : wgs1 >= 2048 ? 2 : 1;
+    const int64_t blocks = pop_tiles_s(ga.pop) * pop_tiles_g(pm, R);
     hipLaunchKernelGGL(population_kernel<T>, dim3((unsigned)blocks), dim3(POP_THREADS), 0, s, P, gs,
                        (int64_t)ga.pop, ga.n_elite, ga.elitism, (T)ga.sigma, knots_in, ld_in,
                        elite_idx, elite_rows, has_elites, cold_mode, knots_out, ld_out, tick, gen,
-                       var);
+                       var, R);
     return hipGetLastError();
 }
 template hipError_t launch_population<float>(const ProbView<float> &, const empc_ga &,

@@ -81,7 +81,8 @@ __device__ __forceinline__ void population_tile(
     const ProbView<T> &P, const GaStreams &gs, int64_t pop, int k, int elitism, T sigma,
     const T *__restrict__ knots_in, int64_t ld_in, const int64_t *__restrict__ elite_idx,
     const T *__restrict__ elite_rows, bool cold, T *__restrict__ knots_out, int64_t ld_out,
-    uint32_t tick, uint32_t gen, int64_t tile_s, int tile_g, const PopVariant<T> &var) {
+    uint32_t tick, uint32_t gen, int64_t tile_s, int tile_g, const PopVariant<T> &var,
+    int R = 1) {
     __shared__ int s_par[POP_SLOTS][2];
     __shared__ int64_t s_eidx[Limits::MAX_ELITE];
     __shared__ uint32_t s_flag[POP_SLOTS][4];
@@ -89,9 +90,12 @@ __device__ __forceinline__ void population_tile(
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = P.m, pm = P.p * P.m;
-    if (tile_g * POP_GROUPS * 4 >= pm) return;  // whole workgroup: no parameter here
+    // the workgroup's parameters: 16 R from jt (R in {1, 2, 4, 8}, so that
+    // they lie in one 128-parameter crossover block); wavefront w takes the
+    // groups of four at jt + 16 r + 4 w, r < R
+    const int jt = tile_g * POP_GROUPS * 4 * R;
+    if (jt >= pm) return;  // whole workgroup: no parameter here
     const int64_t s = tile_s * POP_SLOTS + lane;
-    const int j0 = 4 * (tile_g * POP_GROUPS + w);
     const uint32_t slot = (uint32_t)s;
     // the parents' indices are staged in LDS by the fourth wavefront while
     // the others draw, so no global load waits on a draw
@@ -109,7 +113,7 @@ __device__ __forceinline__ void population_tile(
             s_flag[lane][2] = wf.z;
             s_flag[lane][3] = wf.w;
         } else if (w == 2) {
-            const int xb = (tile_g * POP_GROUPS * 4) / 128;
+            const int xb = jt / 128;
             const U4 wx = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.XB + xb));
             s_xw[lane][0] = wx.x;
             s_xw[lane][1] = wx.y;
@@ -118,7 +122,7 @@ __device__ __forceinline__ void population_tile(
         }
     }
     __syncthreads();
-    if (s >= pop || j0 >= pm) return;
+    if (s >= pop) return;
     // distance-dependent mutation noise (Sec. VII): sigma_min at the goal,
     // growing linearly to sigma at distance sigma_dist (uniform per wavefront)
     if (var.sigma_dist > (T)0) {
@@ -130,80 +134,87 @@ __device__ __forceinline__ void population_tile(
         const T r = sqrt(d2) / var.sigma_dist;
         sigma = var.sigma_min + (sigma - var.sigma_min) * (r < (T)1 ? r : (T)1);
     }
-    T val[4];
-    if (cold) {
-        const U4 wc = ga_draw(gs, slot, gen, tick, 1, (uint32_t)(j0 / 4));
+    for (int rg = 0; rg < R; ++rg) {
+        const int j0 = jt + 16 * rg + 4 * w;
+        if (j0 >= pm) break;
+        T val[4];
+        if (cold) {
+            const U4 wc = ga_draw(gs, slot, gen, tick, 1, (uint32_t)(j0 / 4));
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = (j0 + r) % m;
-            val[r] = P.umin[i] + (P.umax[i] - P.umin[i]) * uni23<T>(word_of(wc, r));
-        }
-    } else {
-        const T *base = elite_rows ? elite_rows : knots_in;
-        const int64_t step = elite_rows ? k : ld_in;
-        // parameter j of the parent stored at src; with the shift, the
-        // carried input one control step later, (1-d) U_a + d U_{a+1} for
-        // knot a < p-1 (d = (p-1)/(T-1), the knot spacing in steps inverted)
-        const T d = P.p > 1 ? (T)(P.p - 1) / (T)(P.Tn - 1) : (T)0;
-        auto parent = [&](int64_t src, int j) -> T {
-            const T v = base[src + (int64_t)j * step];
-            if (!var.shift || j / m >= P.p - 1) return v;
-            return ((T)1 - d) * v + d * base[src + (int64_t)(j + m) * step];
-        };
-        if (elitism && s < k) {
-            const int64_t src = elite_rows ? s : s_eidx[s];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) val[r] = j0 + r < pm ? parent(src, j0 + r) : (T)0;
+            for (int r = 0; r < 4; ++r) {
+                const int i = (j0 + r) % m;
+                val[r] = P.umin[i] + (P.umax[i] - P.umin[i]) * uni23<T>(word_of(wc, r));
+            }
         } else {
-            const int p1 = s_par[lane][0], p2 = s_par[lane][1];
-            const int64_t src1 = elite_rows ? (int64_t)p1 : s_eidx[p1];
-            const int64_t src2 = elite_rows ? (int64_t)p2 : s_eidx[p2];
-            bool flag[4];
-            int ii[4];
+            const T *base = elite_rows ? elite_rows : knots_in;
+            const int64_t step = elite_rows ? k : ld_in;
+            // parameter j of the parent stored at src; with the shift, the
+            // carried input one control step later, (1-d) U_a + d U_{a+1} for
+            // knot a < p-1 (d = (p-1)/(T-1), the knot spacing in steps inverted)
+            const T d = P.p > 1 ? (T)(P.p - 1) / (T)(P.Tn - 1) : (T)0;
+            auto parent = [&](int64_t src, int j) -> T {
+                const T v = base[src + (int64_t)j * step];
+                if (!var.shift || j / m >= P.p - 1) return v;
+                return ((T)1 - d) * v + d * base[src + (int64_t)(j + m) * step];
+            };
+            if (elitism && s < k) {
+                const int64_t src = elite_rows ? s : s_eidx[s];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                ii[r] = (j0 + r) % m;
-                flag[r] = j0 + r < pm && ((s_flag[lane][ii[r] / 32] >> (ii[r] % 32)) & 1u);
-            }
-            T z[4] = {0, 0, 0, 0};
-            if (flag[0] || flag[1] || flag[2] || flag[3]) {
-                const U4 wn = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.NB + j0 / 4));
-                if (flag[0] || flag[1]) box_muller<T>(wn.x, wn.y, z[0], z[1]);
-                if (flag[2] || flag[3]) box_muller<T>(wn.z, wn.w, z[2], z[3]);
-            }
+                for (int r = 0; r < 4; ++r) val[r] = j0 + r < pm ? parent(src, j0 + r) : (T)0;
+            } else {
+                const int p1 = s_par[lane][0], p2 = s_par[lane][1];
+                const int64_t src1 = elite_rows ? (int64_t)p1 : s_eidx[p1];
+                const int64_t src2 = elite_rows ? (int64_t)p2 : s_eidx[p2];
+                bool flag[4];
+                int ii[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = j0 + r, jb = j % 128;
-                if (j >= pm) {
-                    val[r] = 0;
-                    continue;
+                for (int r = 0; r < 4; ++r) {
+                    ii[r] = (j0 + r) % m;
+                    flag[r] = j0 + r < pm && ((s_flag[lane][ii[r] / 32] >> (ii[r] % 32)) & 1u);
                 }
-                const bool from2 = (s_xw[lane][jb / 32] >> (jb % 32)) & 1u;
-                val[r] = mutate_clamp<T>(parent(from2 ? src2 : src1, j), flag[r], sigma, z[r],
-                                         P.umin[ii[r]], P.umax[ii[r]]);
+                T z[4] = {0, 0, 0, 0};
+                if (flag[0] || flag[1] || flag[2] || flag[3]) {
+                    const U4 wn = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.NB + j0 / 4));
+                    if (flag[0] || flag[1]) box_muller<T>(wn.x, wn.y, z[0], z[1]);
+                    if (flag[2] || flag[3]) box_muller<T>(wn.z, wn.w, z[2], z[3]);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = j0 + r, jb = j % 128;
+                    if (j >= pm) {
+                        val[r] = 0;
+                        continue;
+                    }
+                    const bool from2 = (s_xw[lane][jb / 32] >> (jb % 32)) & 1u;
+                    val[r] = mutate_clamp<T>(parent(from2 ? src2 : src1, j), flag[r], sigma, z[r],
+                                             P.umin[ii[r]], P.umax[ii[r]]);
+                }
             }
         }
-    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (j0 + r < pm) knots_out[(int64_t)(j0 + r) * ld_out + s] = val[r];
+        for (int r = 0; r < 4; ++r)
+            if (j0 + r < pm) knots_out[(int64_t)(j0 + r) * ld_out + s] = val[r];
+    }
 }
 
 // tiles of a population of `pop` slots and p m parameters
 __host__ __device__ inline int64_t pop_tiles_s(int64_t pop) { return (pop + POP_SLOTS - 1) / POP_SLOTS; }
-__host__ __device__ inline int pop_tiles_g(int pm) { return ((pm + 3) / 4 + POP_GROUPS - 1) / POP_GROUPS; }
+__host__ __device__ inline int pop_tiles_g(int pm, int R = 1) {
+    return ((pm + 3) / 4 + POP_GROUPS * R - 1) / (POP_GROUPS * R);
+}
 
 template <typename T>
 __global__ __launch_bounds__(POP_THREADS) void population_kernel(
     ProbView<T> P, GaStreams gs, int64_t pop, int k, int elitism, T sigma,
     const T *__restrict__ knots_in, int64_t ld_in, const int64_t *__restrict__ elite_idx,
     const T *__restrict__ elite_rows, const int *__restrict__ has_elites, int cold_mode,
-    T *__restrict__ knots_out, int64_t ld_out, uint32_t tick, uint32_t gen, PopVariant<T> var) {
+    T *__restrict__ knots_out, int64_t ld_out, uint32_t tick, uint32_t gen, PopVariant<T> var,
+    int R) {
     const bool cold = cold_mode == 1 || (cold_mode == 2 && *has_elites == 0);
     const int64_t nts = pop_tiles_s(pop);
     population_tile<T>(P, gs, pop, k, elitism, sigma, knots_in, ld_in, elite_idx, elite_rows, cold,
                        knots_out, ld_out, tick, gen, blockIdx.x % nts, (int)(blockIdx.x / nts),
-                       var);
+                       var, R);
 }
 
 // ---------------------------------------------------------------------------

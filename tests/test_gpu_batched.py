@@ -168,12 +168,14 @@ def test_batch_autotune_keeps_state_and_results(E):
     tuned.close()
 
 
-def test_large_population_single_matches_batched(E):
+@pytest.mark.parametrize("pop", [6000, 12000])
+def test_large_population_single_matches_batched(E, pop):
     """A C3-sized chain (360 parameters) with a large population: the
     single-problem solve (1024-thread selection, parents read in place after
-    the first generation) equals the batched one bit for bit."""
+    the first generation, 32 or 64 parameters per population workgroup)
+    equals the batched one (16 per workgroup) bit for bit."""
     prob = W.pendulum_chain(36, 100, 10, seed=4).cast(np.float32)
-    ga = W.GA(pop=6000, n_elite=64, generations=3, sigma=0.1, seed=0x5EED)
+    ga = W.GA(pop=pop, n_elite=64, generations=3, sigma=0.1, seed=0x5EED)
     dp = E.DeviceProblem(prob, F32)
     bs = E.BatchSolver([dp], ga, autotune=False)
     single = E.Solver(dp, ga)  # problem 0 of a batch uses the seed unchanged
