@@ -27,7 +27,8 @@ __global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<
                                                         int64_t pop, int k, int elitism, T sigma,
                                                         uint32_t seed_lo, int g,
                                                         const uint32_t *__restrict__ tick,
-                                                        int shift, T sigma_min, T sigma_dist) {
+                                                        int shift, T sigma_min, T sigma_dist,
+                                                        int R) {
     const int2 e = popmap[blockIdx.x];  // (problem, tile within the problem)
     const BatchSlot<T> &S = slots[e.x];
     const ProbView<T> P = S.P;
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<
     var.shift = first ? shift : 0;
     population_tile<T>(P, gs, pop, k, elitism, sigma, first ? nullptr : S.knots[(g + 1) & 1], pop,
                        first ? nullptr : S.elite_idx, first ? S.elite_rows : nullptr, cold,
-                       S.knots[g & 1], pop, *tick, (uint32_t)g, e.y % nts, (int)(e.y / nts), var);
+                       S.knots[g & 1], pop, *tick, (uint32_t)g, e.y % nts, (int)(e.y / nts), var,
+                       R);
 }
 
 template <typename T, int NT, int NU, int WPB, bool BOX>
@@ -273,6 +275,7 @@ struct empc_batch {
     BatchSlot<float> *d_slots = nullptr;
     int2 *d_popmap = nullptr;  // population workgroups: (problem, tile)
     int64_t pop_wgs = 0;
+    int pop_r = 1;  // parameter groups per population thread
     int *d_items = nullptr;
     uint32_t *d_tick = nullptr;
     int nstreams = 0;  // side streams in use (all BATCH_STREAMS are created)
@@ -395,9 +398,15 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         S.elite_idx = (int64_t *)(base + off); off += al256(k * 8);
         S.best_idx = (int64_t *)(base + off); off += 256;
     }
+    // parameter groups per population thread, as in the single-problem
+    // launch: 2 or 4 when the plan's population grid is large (the children's
+    // shared draws are then taken by fewer workgroups; the same bits)
+    int64_t wgs1 = 0;
+    for (int i = 0; i < nprob; ++i) wgs1 += pop_tiles_s(ga->pop) * pop_tiles_g(probs[i].p * probs[i].m);
+    b->pop_r = wgs1 >= 4096 ? 4 : wgs1 >= 2048 ? 2 : 1;
     int64_t total_wgs = 0;
     for (int i = 0; i < nprob; ++i)
-        total_wgs += pop_tiles_s(ga->pop) * pop_tiles_g(probs[i].p * probs[i].m);
+        total_wgs += pop_tiles_s(ga->pop) * pop_tiles_g(probs[i].p * probs[i].m, b->pop_r);
     if (total_wgs > INT32_MAX) {
         delete b;
         return empc_fail_internal(EMPC_EUNSUPPORTED, "batch population grid above 2^31 workgroups");
@@ -405,7 +414,7 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
     std::vector<int2> popmap;
     popmap.reserve((size_t)total_wgs);
     for (int i = 0; i < nprob; ++i) {
-        const int64_t wgs = pop_tiles_s(ga->pop) * pop_tiles_g(probs[i].p * probs[i].m);
+        const int64_t wgs = pop_tiles_s(ga->pop) * pop_tiles_g(probs[i].p * probs[i].m, b->pop_r);
         for (int64_t t = 0; t < wgs; ++t) popmap.push_back(make_int2(i, (int)t));
     }
     b->pop_wgs = total_wgs;
@@ -483,7 +492,7 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
         hipLaunchKernelGGL(batch_population<float>, dim3((unsigned)b->pop_wgs), dim3(POP_THREADS), 0,
                            s, b->d_slots, b->d_popmap, pop, G.n_elite, G.elitism, (float)G.sigma,
                            seed_lo, g, (const uint32_t *)b->d_tick, G.shift, (float)G.sigma_min,
-                           (float)G.sigma_dist);
+                           (float)G.sigma_dist, b->pop_r);
         const hipError_t fe = rollout_phase(b, g, s);
         if (fe != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(fe));
         if (per <= 4)
@@ -513,7 +522,7 @@ empc_status empc_batch_autotune(empc_batch *b, int32_t reps, void *stream) {
     hipLaunchKernelGGL(batch_population<float>, dim3((unsigned)b->pop_wgs), dim3(POP_THREADS), 0, s,
                        b->d_slots, b->d_popmap, b->pop, G.n_elite, G.elitism,
                        (float)G.sigma, (uint32_t)G.seed, 0, (const uint32_t *)b->d_tick, G.shift,
-                       (float)G.sigma_min, (float)G.sigma_dist);
+                       (float)G.sigma_min, (float)G.sigma_dist, b->pop_r);
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventCreate(&t0);

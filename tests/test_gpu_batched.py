@@ -173,7 +173,7 @@ def test_large_population_single_matches_batched(E, pop):
     """A C3-sized chain (360 parameters) with a large population: the
     single-problem solve (1024-thread selection, parents read in place after
     the first generation, 32 or 64 parameters per population workgroup)
-    equals the batched one (16 per workgroup) bit for bit."""
+    equals the batched one bit for bit."""
     prob = W.pendulum_chain(36, 100, 10, seed=4).cast(np.float32)
     ga = W.GA(pop=pop, n_elite=64, generations=3, sigma=0.1, seed=0x5EED)
     dp = E.DeviceProblem(prob, F32)
@@ -216,6 +216,31 @@ def test_batched_box_penalty_equals_single(E):
         torch.cuda.synchronize()
         for i, s in enumerate(singles):
             u, J = s.solve(torch.tensor(x0s[i], device="cuda"), tick)
+            torch.cuda.synchronize()
+            assert torch.equal(bs.u_of(i), u), (tick, i)
+            assert torch.equal(bs.best_cost[i:i + 1], J), (tick, i)
+    bs.close()
+
+
+def test_population_grouping_keeps_the_bits(E):
+    """Six 36-link chains at population 2048: alone, each population launch
+    has 736 workgroups of 16 parameters; the batch has 4416 and takes 64
+    parameters per workgroup.  Every draw keeps its counter, so the batched
+    and the single solves agree bit for bit."""
+    probs = [W.pendulum_chain(36, 100, 10, seed=20 + i).cast(np.float32) for i in range(6)]
+    ga = W.GA(pop=2048, n_elite=32, generations=2, sigma=0.1, seed=0xC0FFEE)
+    dps = [E.DeviceProblem(p, F32) for p in probs]
+    bs = E.BatchSolver(dps, ga, autotune=False)
+    singles = [E.Solver(dp, W.dataclasses.replace(ga, seed=ga.seed ^ (i << 32)))
+               for i, dp in enumerate(dps)]
+    x0s = [W.draw_x0(p.n, 40 + i).astype(np.float32) for i, p in enumerate(probs)]
+    for i, x in enumerate(x0s):
+        bs.set_x0(i, x)
+    for tick in range(2):
+        bs.solve()
+        torch.cuda.synchronize()
+        for i, sv in enumerate(singles):
+            u, J = sv.solve(torch.tensor(x0s[i], device="cuda"), tick)
             torch.cuda.synchronize()
             assert torch.equal(bs.u_of(i), u), (tick, i)
             assert torch.equal(bs.best_cost[i:i + 1], J), (tick, i)
