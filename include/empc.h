@@ -5,7 +5,7 @@
  * Williams, Killpack, "Parameterized and GPU-Parallelized Real-Time Model
  * Predictive Control for High Degree of Freedom Robots" (2020): a population
  * of candidate input trajectories, each described by p knots per input
- * (Sec. III-B, interpolation of Sec. IV-D), is simulated through the discrete
+ * (Sec. III-B, interpolation of Sec. IV-C), is simulated through the discrete
  * model (eq. 2), scored by the quadratic cost of eq. 3, and evolved by
  * selection, crossover and mutation (Sec. V, Alg. 1).
  *
@@ -51,12 +51,16 @@ typedef enum { EMPC_F32 = 0, EMPC_F64 = 1 } empc_dtype;
 
 /* EMPC_LINEAR: x_{k+1} = A_d x_k + B_d u_k + w_d (eq. 2).
  * EMPC_PENDULUM_CHAIN: d = m joints, state x = [q; qd] (n = 2d), relative
- *   angles from the downward vertical; the single pendulum of eq. 7 extended
+ *   angles from the downward vertical; the single pendulum of eq. 5 extended
  *   joint by joint with joint stiffness, gravity torque of the cumulative
  *   angles G_j = g sum_{r>=j} l_r (sum_{i>=r} m_i) sin(q_0 + ... + q_r), and
  *   the constant diagonal inertia of the straight chain
  *   I_j = sum_{i>=j} m_i (l_j + ... + l_i)^2;
- *   qdd = (u - k q - b qd - G) / I, semi-implicit Euler with step dt. */
+ *   qdd = (u - k q - b qd - G) / I, semi-implicit Euler with step dt.
+ *   FP32 rollouts take the sine from the hardware instruction, whose input
+ *   domain is +-256 revolutions: each cumulative angle q_0 + ... + q_r must
+ *   stay within +-1608 rad (FP64 rollouts, the adjoint and the plant use
+ *   the library sine and have no such limit). */
 typedef enum { EMPC_LINEAR = 0, EMPC_PENDULUM_CHAIN = 1 } empc_model;
 
 /* The MPC problem of eq. 3 with diagonal weights.  Pointers are device
@@ -181,8 +185,9 @@ empc_status empc_grad(const empc_problem *prob, const void *x0, const void *knot
 /* Gradient refinement: `steps` Adam updates (beta1 0.9, beta2 0.999, eps
  * 1e-8, learning rate lr) of each candidate's knots, each followed by a clamp
  * to [u_min, u_max]; a refined candidate replaces the original only if its
- * cost is lower.  knots [p*m][ld] and cost (ncand, the current costs on
- * entry) are updated in place. */
+ * cost is lower than the cost of its entry knots (both evaluated by the
+ * refinement's own forward pass).  knots [p*m][ld] and cost (ncand) are
+ * updated in place; cost is written only for replaced candidates. */
 empc_status empc_refine(const empc_problem *prob, const void *x0, void *knots, int64_t ncand,
                         int64_t ld, void *cost, double lr, int32_t steps, void *stream);
 

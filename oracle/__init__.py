@@ -5,7 +5,7 @@ benchmark's CPU-baseline leg are the only callers.  Nothing here is shared
 with, or imported by, the HIP library or its binding.
 
 The oracle follows the paper (Hyatt, Williams, Killpack 2020): eq. 2 for the
-linear step, eq. 3 for the cost, Sec. IV-D for the knot interpolation,
+linear step, eq. 3 for the cost, Sec. IV-C for the knot interpolation,
 Sec. V / Alg. 1 for the evolutionary step.  See empc_oracle.h for how each
 function is pinned.
 """

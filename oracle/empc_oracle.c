@@ -4,10 +4,10 @@
  *
  * Conventions taken where the paper is silent or inconsistent (each one is
  * listed with its reason in the design notes of the repository):
- *  - cost (eq. 3 vs Alg. 1 vs the small-matrix form of Sec. IV-C): the stage
+ *  - cost (eq. 3 vs Alg. 1 vs the small-matrix form of Sec. IV-B): the stage
  *    cost is charged on x_1..x_T with u_0..u_{T-1}; a diagonal terminal
  *    weight Q_f (default 0) stands for the undefined terminal_cost;
- *  - knot interpolation (Sec. IV-D): idx1 and c are computed in exact integer
+ *  - knot interpolation (Sec. IV-C): idx1 and c are computed in exact integer
  *    arithmetic (k*(p-1) against T-1) because Delta T is rarely
  *    representable; idx2 is clamped to p-1 where c = 0; p = 1 holds the
  *    single knot constant;
@@ -81,7 +81,7 @@ static int64_t draw_index(uint32_t w, int k) { return (int64_t)(((uint64_t)w * (
 static int bit_of(const uint32_t blk[4], int j) { return (int)((blk[(j / 32) % 4] >> (j % 32)) & 1u); }
 
 /* ---------------------------------------------------------------------------
- * Knot interpolation, Sec. IV-D: Delta T = (T-1)/(p-1), idx1 = floor(k /
+ * Knot interpolation, Sec. IV-C: Delta T = (T-1)/(p-1), idx1 = floor(k /
  * Delta T), idx2 = idx1 + 1, c = (k - idx1 Delta T) / Delta T and
  * u = (1-c) U_idx1 + c U_idx2.  Multiplying through by (p-1) keeps idx1 exact:
  * k / Delta T = k (p-1) / (T-1). */
@@ -116,7 +116,7 @@ void or_input_at(const or_problem *P, const double *knots, int64_t ld, int64_t c
 /* ---------------------------------------------------------------------------
  * Dynamics.
  * Linear: eq. 2, x_{k+1} = A_d x_k + B_d u_k + w_d.
- * Pendulum chain (the paper's single pendulum of eq. 7, m l^2 qdd + b qd +
+ * Pendulum chain (the paper's single pendulum of eq. 5, m l^2 qdd + b qd +
  * m g l sin q = tau, extended joint by joint): relative joint angles q_j
  * measured from the downward vertical, absolute angle phi_r = sum_{s<=r} q_s,
  * tail mass M_r = sum_{i>=r} m_i, gravity torque
@@ -289,17 +289,23 @@ void or_rollout_cost(const or_problem *P, const double *x0, const double *knots,
 
 /* ---------------------------------------------------------------------------
  * Parent selection (Sec. V): the numParents candidates of lowest cost.
- * Total order (J, index) with NaN ranked as +infinity.  elite_idx receives the
- * selected indices in ascending index order; *best the first in (J, index)
- * order. */
+ * Total order (isnan(J), J, index): every NaN ranks after every number,
+ * +infinity included, numbers in numeric order (-0 and +0 tie), ties by
+ * index.  elite_idx receives the selected indices in ascending index order;
+ * *best the first in that order. */
+static int cost_cmp(double a, int64_t ia, double b, int64_t ib) {
+    int na = isnan(a) != 0, nb = isnan(b) != 0;
+    if (na != nb) return na - nb;
+    if (!na) {
+        if (a < b) return -1;
+        if (a > b) return 1;
+    }
+    return (ia > ib) - (ia < ib);
+}
 static const double *g_sort_cost;
-static double sort_key(double J) { return isnan(J) ? INFINITY : J; }
 static int cmp_cost_idx(const void *pa, const void *pb) {
     int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
-    double ka = sort_key(g_sort_cost[a]), kb = sort_key(g_sort_cost[b]);
-    if (ka < kb) return -1;
-    if (ka > kb) return 1;
-    return (a > b) - (a < b);
+    return cost_cmp(g_sort_cost[a], a, g_sort_cost[b], b);
 }
 static int cmp_i64(const void *pa, const void *pb) {
     int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
@@ -601,13 +607,11 @@ int or_solve(const or_problem *P, const or_ga *G, double *elite_knots, int *has_
             or_refine(P, x0, ek, k, k, ec, lr, adam_steps);
             for (int s = 0; s < k; ++s)
                 for (int j = 0; j < pm; ++j) elite_knots[(size_t)s * pm + j] = ek[(int64_t)j * k + s];
-            /* best after refinement: lowest (J, slot) among the elites */
+            /* best after refinement: first in (isnan(J), J, slot) order among
+             * the elites */
             best_slot = 0;
-            for (int s = 1; s < k; ++s) {
-                double a = isnan(ec[s]) ? INFINITY : ec[s];
-                double b = isnan(ec[best_slot]) ? INFINITY : ec[best_slot];
-                if (a < b) best_slot = s;
-            }
+            for (int s = 1; s < k; ++s)
+                if (cost_cmp(ec[s], s, ec[best_slot], best_slot) < 0) best_slot = s;
         }
         *has_elites = 1;
         if (gen_best) gen_best[g] = ec[best_slot];

@@ -11,13 +11,13 @@
  * Parity status per function (what pins it, see the tests):
  *   or_philox4x32_10   pinned: published Philox known-answer vectors and an
  *                      independent library implementation.
- *   or_knot_weights    pinned: worked example T=5, p=3 of Sec. IV-F.
+ *   or_knot_weights    pinned: worked example T=5, p=3 of Sec. IV-E.
  *   or_rollout_cost    linear: pinned by the small-matrix closed form
- *                      (Sec. IV-C) and the quadratic form of J;
+ *                      (Sec. IV-B) and the quadratic form of J;
  *                      pendulum chain: pinned by energy / equilibrium /
- *                      single-pendulum (eq. 7) special cases and the
+ *                      single-pendulum (eq. 5) special cases and the
  *                      gravity-torque finite-difference check.
- *   or_select          pinned: a library sort on (J, index).
+ *   or_select          pinned: a library sort on (isnan(J), J, index).
  *   or_next_population pinned: statistics of the draws, bounds, elitism.
  *   or_solve           pinned: brute-force box-QP bound on tiny problems;
  *                      multi-generation trajectories beyond one generation
@@ -25,8 +25,12 @@
  *                      no numbers for them).
  *   or_grad            pinned: central finite differences, and 2 P U + 2 q
  *                      of the small-matrix form for linear models.
- *   or_refine          follows Adam (Kingma & Ba 2015); pinned only through
- *                      or_grad and a monotone-acceptance invariant.
+ *   or_refine          pinned: Adam (Kingma & Ba 2015) on a one-parameter
+ *                      quadratic: the first update equals -lr g/(|g|+eps),
+ *                      later updates equal the bias-corrected recursion in
+ *                      high-precision decimal arithmetic, the clamp acts
+ *                      after every update, moments start at zero per call,
+ *                      worse candidates are rejected; plus or_grad's pins.
  */
 #ifndef EMPC_ORACLE_H
 #define EMPC_ORACLE_H

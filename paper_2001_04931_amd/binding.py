@@ -132,6 +132,37 @@ def _cprob(prob):
     return ctypes.byref(prob.c if hasattr(prob, "c") else prob)
 
 
+def _shape(prob):
+    """(torch dtype, n, m, p*m) of a DeviceProblem or a bare EmpcProblem."""
+    c = prob.c if hasattr(prob, "c") else prob
+    dt = torch.float64 if c.dtype == EMPC_F64 else torch.float32
+    return dt, int(c.n), int(c.m), int(c.p) * int(c.m)
+
+
+def _need(t, dtype, numel, name, optional=False):
+    """The library sees only raw pointers, so the binding checks what it
+    cannot: a GPU tensor of the problem's dtype, contiguous, holding at least
+    `numel` elements (every element the kernels will touch); _ptr then
+    rejects host tensors."""
+    if t is None:
+        if optional or numel <= 0:
+            return
+        raise ValueError("%s is required" % name)
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s has dtype %s, the problem needs %s" % (name, t.dtype, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < numel:
+        raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), numel))
+
+
+def _soa_elems(pm, ld, ncand):
+    """Elements a [pm][ld] structure-of-arrays block spans for ncand columns."""
+    return 0 if ncand <= 0 else (pm - 1) * int(ld) + int(ncand)
+
+
 def _cga(ga):
     return ctypes.byref(ga.c if hasattr(ga, "c") else ga)
 
@@ -141,12 +172,27 @@ def _cga(ga):
 
 
 def empc_rollout_cost(prob, x0, knots, ncand, ld, cost, stream=None):
+    dt, n, m, pm = _shape(prob)
+    if ncand > 0 and ld >= ncand:
+        _need(x0, dt, n, "x0")
+        _need(knots, dt, _soa_elems(pm, ld, ncand), "knots")
+        _need(cost, dt, ncand, "cost")
     _check(lib().empc_rollout_cost(_cprob(prob), _ptr(x0), _ptr(knots), int(ncand), int(ld),
                                    _ptr(cost), _stream(stream)))
 
 
 def empc_generation(prob, ga, knots_in, ld_in, cost_in, knots_out, ld_out, elite_idx, best_idx,
                     tick, gen, stream=None):
+    dt, n, m, pm = _shape(prob)
+    g = ga.c if hasattr(ga, "c") else ga
+    pop, k = int(g.pop), int(g.n_elite)
+    if ld_out >= pop:
+        _need(knots_out, dt, _soa_elems(pm, ld_out, pop), "knots_out")
+    if knots_in is not None and ld_in >= pop:
+        _need(knots_in, dt, _soa_elems(pm, ld_in, pop), "knots_in")
+        _need(cost_in, dt, pop, "cost_in")
+        _need(elite_idx, torch.int64, k, "elite_idx")
+    _need(best_idx, torch.int64, 1, "best_idx", optional=True)
     _check(lib().empc_generation(_cprob(prob), _cga(ga), _ptr(knots_in), int(ld_in),
                                  _ptr(cost_in), _ptr(knots_out), int(ld_out), _ptr(elite_idx),
                                  _ptr(best_idx), int(tick), int(gen), _stream(stream)))
@@ -156,29 +202,55 @@ def empc_workspace_bytes(prob, ga) -> int:
     return int(lib().empc_workspace_bytes(_cprob(prob), _cga(ga)))
 
 
+def _need_solve_io(prob, workspace, x0, u_star, best_cost):
+    dt, n, m, _ = _shape(prob)
+    _need(workspace, torch.uint8, 1, "workspace")
+    _need(x0, dt, n, "x0")
+    _need(u_star, dt, m, "u_star")
+    _need(best_cost, dt, 1, "best_cost")
+
+
 def empc_solve(prob, ga, workspace, x0, tick, u_star, best_cost, stream=None):
+    _need_solve_io(prob, workspace, x0, u_star, best_cost)
     _check(lib().empc_solve(_cprob(prob), _cga(ga), _ptr(workspace), workspace.numel(),
                             _ptr(x0), int(tick), _ptr(u_star), _ptr(best_cost), _stream(stream)))
 
 
 def empc_solve_refined(prob, ga, workspace, x0, tick, lr, adam_steps, u_star, best_cost,
                        stream=None):
+    _need_solve_io(prob, workspace, x0, u_star, best_cost)
     _check(lib().empc_solve_refined(_cprob(prob), _cga(ga), _ptr(workspace), workspace.numel(),
                                     _ptr(x0), int(tick), float(lr), int(adam_steps), _ptr(u_star),
                                     _ptr(best_cost), _stream(stream)))
 
 
 def empc_grad(prob, x0, knots, ncand, ld, dJ, cost, stream=None):
+    dt, n, m, pm = _shape(prob)
+    if ncand > 0 and ld >= ncand:
+        _need(x0, dt, n, "x0")
+        _need(knots, dt, _soa_elems(pm, ld, ncand), "knots")
+        _need(dJ, dt, _soa_elems(pm, ld, ncand), "dJ")
+        _need(cost, dt, ncand, "cost", optional=True)
     _check(lib().empc_grad(_cprob(prob), _ptr(x0), _ptr(knots), int(ncand), int(ld), _ptr(dJ),
                            _ptr(cost), _stream(stream)))
 
 
 def empc_refine(prob, x0, knots, ncand, ld, cost, lr, steps, stream=None):
+    dt, n, m, pm = _shape(prob)
+    if ncand > 0 and ld >= ncand and steps > 0:
+        _need(x0, dt, n, "x0")
+        _need(knots, dt, _soa_elems(pm, ld, ncand), "knots")
+        _need(cost, dt, ncand, "cost")
     _check(lib().empc_refine(_cprob(prob), _ptr(x0), _ptr(knots), int(ncand), int(ld),
                              _ptr(cost), float(lr), int(steps), _stream(stream)))
 
 
 def empc_plant_step(prob, x, u, noise, x_next, stream=None):
+    dt, n, m, _ = _shape(prob)
+    _need(x, dt, n, "x")
+    _need(u, dt, m, "u")
+    _need(noise, dt, n, "noise", optional=True)
+    _need(x_next, dt, n, "x_next")
     _check(lib().empc_plant_step(_cprob(prob), _ptr(x), _ptr(u), _ptr(noise), _ptr(x_next),
                                  _stream(stream)))
 
@@ -188,6 +260,12 @@ def empc_batch_workspace_bytes(cprobs, nprob, ga) -> int:
 
 
 def empc_batch_create(cprobs, nprob, ga, workspace, x0_packed, u_star_packed, best_cost):
+    nsum = sum(int(cprobs[i].n) for i in range(int(nprob)))
+    msum = sum(int(cprobs[i].m) for i in range(int(nprob)))
+    _need(workspace, torch.uint8, 1, "workspace")
+    _need(x0_packed, torch.float32, nsum, "x0_packed")
+    _need(u_star_packed, torch.float32, msum, "u_star_packed")
+    _need(best_cost, torch.float32, int(nprob), "best_cost")
     plan = ctypes.c_void_p()
     _check(lib().empc_batch_create(cprobs, int(nprob), _cga(ga), _ptr(workspace),
                                    workspace.numel(), _ptr(x0_packed), _ptr(u_star_packed),
@@ -341,6 +419,10 @@ class EmpcCost(torch.autograd.Function):
         knots = knots.contiguous()
         ncand = knots.shape[1]
         cost = torch.empty(ncand, dtype=knots.dtype, device=knots.device)
+        if not ctx.needs_input_grad[0]:
+            # forward only: the rollout kernel, no adjoint pass
+            empc_rollout_cost(dprob, x0.contiguous(), knots, ncand, ncand, cost)
+            return cost
         dJ = torch.empty_like(knots)
         empc_grad(dprob, x0.contiguous(), knots, ncand, ncand, dJ, cost)
         ctx.save_for_backward(dJ)

@@ -409,8 +409,12 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
     // Adam (Kingma & Ba 2015), bias-corrected, clamp after each update
     const T b1 = (T)0.9, b2 = (T)0.999, eps = (T)1e-8;
     T b1t = 1, b2t = 1;
+    T J0 = 0;  // cost of the entry knots by this kernel's own forward pass
     for (int t = 1; t <= steps; ++t) {
-        if (wave == 0) forward(true, xi, qj, vj);
+        if (wave == 0) {
+            const T Jt = forward(true, xi, qj, vj);
+            if (t == 1) J0 = Jt;
+        }
         __syncthreads();  // checkpoints and input tables
         backward(xi, qj, vj);
         b1t *= b1;
@@ -431,8 +435,12 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
         __syncthreads();
     }
     if (wave == 0) {
+        // accept the refined knots only if they cost less: both costs come
+        // from the same forward pass code (in FP32 the rollout kernels take
+        // the hardware sine, this pass the library one, so cost_io is not
+        // the value to compare against)
         const T Jn = forward(false, xi, qj, vj);
-        if (Jn < cost_io[cand]) {  // uniform: Jn is a wave sum
+        if (Jn < J0) {  // uniform: Jn and J0 are wave sums
             for (int j = lane; j < pm; j += 64) knots_io[(int64_t)j * ld + cand] = sU[j];
             if (lane == 0) cost_io[cand] = Jn;
         }

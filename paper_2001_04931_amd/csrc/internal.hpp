@@ -52,7 +52,7 @@ __host__ __device__ inline T box_pen_grad(T x, T lo, T hi, T w) {
     return o > (T)0 ? (T)2 * w * o : (u > (T)0 ? (T)-2 * w * u : (T)0);
 }
 
-// Knot interpolation of Sec. IV-D in exact integers: with num = k (p-1) and
+// Knot interpolation of Sec. IV-C in exact integers: with num = k (p-1) and
 // den = T-1, idx1 = num / den, c = (num mod den) / den, idx2 = min(idx1+1, p-1).
 struct Knot {
     int a, b;

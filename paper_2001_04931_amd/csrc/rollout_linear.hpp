@@ -62,7 +62,7 @@ struct Mfma<double> {
 // problem has a state goal (else (x - g) is x itself).
 //
 // Work per step.  The input enters a step as B_d u_k + w_d with
-// u_k = (1-c) U_a + c U_b (Sec. IV-D), so with V_j = B_d U_j + w_d computed
+// u_k = (1-c) U_a + c U_b (Sec. IV-C), so with V_j = B_d U_j + w_d computed
 // once per knot j the step is x_{k+1} = A_d x_k + V_a + c (V_b - V_a): the
 // accumulators start from that (NT fused multiply-adds of 4-vectors) and only
 // the 4 NT^2 MFMAs of A_d x_k remain in the step.  The stage cost is summed

@@ -172,8 +172,11 @@ def test_batch_autotune_keeps_state_and_results(E):
 def test_large_population_single_matches_batched(E, pop):
     """A C3-sized chain (360 parameters) with a large population: the
     single-problem solve (1024-thread selection, parents read in place after
-    the first generation, 32 or 64 parameters per population workgroup)
-    equals the batched one bit for bit."""
+    the first generation) equals the batched one bit for bit.  Both sides
+    size their population grid the same way here (32 parameters per
+    workgroup at 6000, 64 at 12000), so this checks the two launch paths,
+    not the grouping; test_population_grouping_matches_oracle in the parity
+    tests checks the grouped populations against the oracle."""
     prob = W.pendulum_chain(36, 100, 10, seed=4).cast(np.float32)
     ga = W.GA(pop=pop, n_elite=64, generations=3, sigma=0.1, seed=0x5EED)
     dp = E.DeviceProblem(prob, F32)
@@ -241,6 +244,35 @@ def test_population_grouping_keeps_the_bits(E):
         torch.cuda.synchronize()
         for i, sv in enumerate(singles):
             u, J = sv.solve(torch.tensor(x0s[i], device="cuda"), tick)
+            torch.cuda.synchronize()
+            assert torch.equal(bs.u_of(i), u), (tick, i)
+            assert torch.equal(bs.best_cost[i:i + 1], J), (tick, i)
+    bs.close()
+
+
+def test_c5_plan_sampled_against_single_solves(E):
+    """The full batching configuration (512 problems, population 1024,
+    autotuned launch shapes, one HIP-graph replay per tick): 16 sampled
+    problems equal their single-problem solves bit for bit over two ticks."""
+    probs, ga = W.config_c5(512, 0)
+    probs = [p.cast(np.float32) for p in probs]
+    dps = [E.DeviceProblem(p, F32) for p in probs]
+    bs = E.BatchSolver(dps, ga)
+    x0s = [W.draw_x0(p.n, i).astype(np.float32) for i, p in enumerate(probs)]
+    for i, x in enumerate(x0s):
+        bs.set_x0(i, x)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        bs.solve()
+    sample = np.random.default_rng(0).choice(len(probs), 16, replace=False)
+    singles = {int(i): E.Solver(dps[i], W.dataclasses.replace(ga, seed=ga.seed ^ (int(i) << 32)))
+               for i in sample}
+    for tick in range(2):
+        graph.replay()
+        torch.cuda.synchronize()
+        for i, s in singles.items():
+            u, J = s.solve(torch.tensor(x0s[i], device="cuda"), tick)
             torch.cuda.synchronize()
             assert torch.equal(bs.u_of(i), u), (tick, i)
             assert torch.equal(bs.best_cost[i:i + 1], J), (tick, i)

@@ -182,6 +182,26 @@ def test_refined_solve_fp64_matches_oracle(oracle_lib, E, shift):
         x = oracle_lib.step(prob, x, uo)
 
 
+@pytest.mark.parametrize("case", ["chain5", "chain16_rows"])
+def test_refined_solve_fp64_chain_matches_oracle(oracle_lib, E, case):
+    # the pendulum chain through the refined tick: lane-form rollout (5
+    # joints) and row-form rollout (16 joints), the chain adjoint and Adam on
+    # the parents; FP64 keeps every parent set identical over ticks
+    d, T, p = (5, 20, 4) if case == "chain5" else (16, 25, 5)
+    prob = W.pendulum_chain(d, T, p, seed=d)
+    ga = W.GA(pop=128, n_elite=8, generations=2, sigma=0.1, seed=17)
+    dp = E.DeviceProblem(prob, F64)
+    s = E.Solver(dp, ga)
+    o = oracle_lib.Solver(prob, ga, refine=True, lr=0.01, adam_steps=3)
+    x = W.draw_x0(prob.n, 5) * 0.5
+    for tick in range(3):
+        u, J = s.solve(dev(x, F64), tick, refine_steps=3, lr=0.01)
+        uo, Jo, _ = o.solve(x, tick)
+        np.testing.assert_allclose(u.cpu().numpy(), uo, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(float(J.item()), Jo, rtol=1e-9)
+        x = oracle_lib.step(prob, x, uo)
+
+
 def test_refined_solve_fp32_c2_not_worse(E):
     prob, ga = W.config_c2(0)
     ga = W.dataclasses.replace(ga, generations=5)

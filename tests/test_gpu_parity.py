@@ -114,6 +114,25 @@ def test_rollout_pendulum_chain_shapes(oracle_lib, E, dtype, d):
     check_costs(oracle_lib, E, prob, ncand=300, ld=301, dtype=dtype, seed=d)
 
 
+@pytest.mark.parametrize("d", [4, 20])
+def test_rollout_pendulum_winding_angles(oracle_lib, E, d):
+    # cumulative angles of tens of revolutions (low stiffness, wide inputs):
+    # the FP32 rollout's hardware sine inside its documented domain
+    prob = W.pendulum_chain(d, 30, 5, seed=d)
+    prob.stiffness = np.full(d, 0.5)
+    prob.u_min, prob.u_max = np.full(d, -20.0), np.full(d, 20.0)
+    prob = rounded(prob, F32)
+    x0 = np.r_[np.random.default_rng(d).uniform(20, 40, d), np.zeros(d)]
+    x0 = x0.astype(np.float32).astype(np.float64)
+    knots = W.draw_knots(prob, 80, d).astype(np.float32).astype(np.float64)
+    _, traj = oracle_lib.rollout_one(prob, x0, knots, 0)
+    phi = np.abs(np.cumsum(traj[:, :d], axis=1))
+    assert phi.max() > 2 * np.pi * 10 and phi.max() < 1608  # within +-256 revolutions
+    got = gpu_costs(E, prob, x0, knots, 80, F32)
+    want = oracle_lib.rollout_cost(prob, x0, knots)
+    np.testing.assert_allclose(got, want, rtol=1e-4)
+
+
 def test_rollout_pendulum_c3_shape(oracle_lib, E):
     prob, _ = W.config_c3(0)
     check_costs(oracle_lib, E, prob, ncand=70, ld=70, dtype=F32)
@@ -341,11 +360,52 @@ def test_selection_ties_nan_inf(oracle_lib, E, dtype):
         assert best == want_best
 
 
+@pytest.mark.parametrize("pop", [600, 6000, 12000])
+@pytest.mark.parametrize("cold", [True, False])
+def test_population_grouping_matches_oracle(oracle_lib, E, pop, cold):
+    # 360 parameters: a single launch takes 16 parameters per workgroup at
+    # pop 600, 32 at 6000 and 64 at 12000; every grouping must give the
+    # oracle's children (sampled slots, parents and elitism included)
+    prob = W.pendulum_chain(36, 100, 10, seed=4).cast(np.float32)
+    ga = W.GA(pop=pop, n_elite=64, generations=1, sigma=0.1, seed=0xC0FFEE)
+    rng = np.random.default_rng(pop)
+    knots = W.draw_knots(prob, pop, 9).astype(np.float32).astype(np.float64)
+    cost = rng.uniform(0, 10, pop).astype(np.float32).astype(np.float64)
+    if cold:
+        got, _, _ = gpu_generation(E, prob, ga, None, None, tick=0, gen=0, dtype=F32)
+        want = oracle_lib.next_population(prob, ga, None, cold=True, tick=0, gen=0)
+    else:
+        got, eidx, _ = gpu_generation(E, prob, ga, knots, cost, tick=4, gen=2, dtype=F32)
+        want_idx, _ = oracle_lib.select(cost, ga.n_elite)
+        np.testing.assert_array_equal(eidx, want_idx)
+        want = oracle_lib.next_population(prob, ga, knots[:, want_idx].T.copy(), cold=False,
+                                          tick=4, gen=2)
+    slots = np.r_[np.arange(70), rng.choice(pop, 300, replace=False), pop - 1]
+    np.testing.assert_allclose(got[:, slots], want[:, slots], rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_selection_nan_after_inf(oracle_lib, E, dtype):
+    # the k boundary between a NaN and a later +inf: NaN ranks last
+    prob = W.linear_chain(2, 10, 3, seed=0)
+    cases = [([np.nan, np.inf, 1.0], 2, [1, 2], 2), ([np.nan, np.inf], 1, [1], 1),
+             ([np.nan, np.nan, -np.inf], 2, [0, 2], 2), ([np.inf, np.nan, np.inf], 2, [0, 2], 0)]
+    for cost, k, want_idx, want_best in cases:
+        cost = np.array(cost)
+        ga = W.GA(pop=len(cost), n_elite=k, generations=1, sigma=0.1, seed=1)
+        knots = W.draw_knots(prob, len(cost), 1)
+        _, eidx, best = gpu_generation(E, prob, ga, knots, cost, 0, 0, dtype)
+        assert list(eidx) == want_idx and best == want_best, (cost, k)
+        oidx, obest = oracle_lib.select(cost, k)
+        assert list(oidx) == want_idx and obest == want_best
+
+
 @pytest.mark.parametrize("dtype", [F32, F64])
 def test_selection_small_populations(oracle_lib, E, dtype):
-    # populations of at most 256 take the rank-based path (every key counts
-    # the keys ordered before it): heavy ties, NaN / inf / signed zeros, every
-    # k from 1 to pop on a few sizes, exact equality with the oracle
+    # populations of at most 256 run the 256-thread radix select with at
+    # most one key per thread (most threads hold none): heavy ties, NaN / inf
+    # / signed zeros, every k from 1 to pop on a few sizes, exact equality
+    # with the oracle
     prob = W.linear_chain(2, 10, 3, seed=0)
     rng = np.random.default_rng(11)
     cases = [(pop, k) for pop in (2, 16, 63, 64, 65, 200, 256) for k in sorted({1, 2, pop // 3 or 1, pop})]
@@ -405,6 +465,75 @@ def test_selection_random_bands(oracle_lib, E, dtype):
         want_idx, want_best = oracle_lib.select(cost, k)
         np.testing.assert_array_equal(eidx, want_idx, err_msg="trial %d" % trial)
         assert best == want_best, trial
+
+
+# ---------------------------------------------------------------------------
+# FP32 selection on real rollout costs against the FP64 oracle's selection
+
+
+def check_fp32_elites(oracle_lib, E, prob, knots, x0, k, rtol=1e-4):
+    """The GPU selects from its own FP32 costs; the oracle from FP64 costs of
+    the same (rounded) knots.  The two elite sets may differ only by swaps
+    whose oracle costs lie within rtol of the k-th smallest oracle cost (a
+    tie group at the boundary); every other index must agree."""
+    pop = knots.shape[1]
+    dp = E.DeviceProblem(prob, F32)
+    K = as_dev(knots, F32)
+    cost = torch.empty(pop, dtype=F32, device="cuda")
+    E.empc_rollout_cost(dp, as_dev(x0, F32), K, pop, pop, cost)
+    ga = W.GA(pop=pop, n_elite=k, generations=1, sigma=0.1, seed=1)
+    g = E.make_ga(ga)
+    out = torch.empty((prob.p * prob.m, pop), dtype=F32, device="cuda")
+    eidx = torch.empty(k, dtype=torch.int64, device="cuda")
+    best = torch.empty(1, dtype=torch.int64, device="cuda")
+    E.empc_generation(dp, g, K, pop, cost, out, pop, eidx, best, 0, 1)
+    torch.cuda.synchronize()
+    got = set(eidx.cpu().numpy().tolist())
+    J = oracle_lib.rollout_cost(prob, x0, knots)
+    np.testing.assert_allclose(cost.cpu().numpy(), J, rtol=rtol)
+    want_idx, want_best = oracle_lib.select(J, k)
+    want = set(want_idx.tolist())
+    thr = np.sort(J)[k - 1]
+    tol = rtol * abs(thr)
+    for i in got - want:
+        assert J[i] <= thr + tol, (i, J[i], thr)
+    for i in want - got:
+        assert J[i] >= thr - tol, (i, J[i], thr)
+    b = int(best.item())
+    assert J[b] <= J[want_best] * (1 + rtol)
+    return len(got ^ want) // 2
+
+
+def warm_population(oracle_lib, prob, pop, seed):
+    """A population bred from 64 random parents (crossover and mutation with
+    sigma 0.1): costs in the narrow band of a real generation."""
+    rng = np.random.default_rng(seed)
+    parents = rng.uniform(-1, 1, (64, prob.p * prob.m))
+    ga = W.GA(pop=pop, n_elite=64, generations=1, sigma=0.1, seed=seed)
+    return oracle_lib.next_population(prob, ga, parents, cold=False, tick=1, gen=0)
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_fp32_elites_c2(oracle_lib, E, warm):
+    prob, ga = W.config_c2(0)
+    prob = rounded(prob, F32)
+    x0 = W.draw_x0(prob.n, 0).astype(np.float32).astype(np.float64)
+    knots = (warm_population(oracle_lib, prob, ga.pop, 3) if warm
+             else W.draw_knots(prob, ga.pop, 3))
+    knots = knots.astype(np.float32).astype(np.float64)
+    check_fp32_elites(oracle_lib, E, prob, knots, x0, ga.n_elite)
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_fp32_elites_c3(oracle_lib, E, warm):
+    prob, ga = W.config_c3(0)
+    prob = rounded(prob, F32)
+    x0 = W.draw_x0(prob.n, 0).astype(np.float32).astype(np.float64)
+    pop = 4096  # a quarter of the configured population keeps the oracle fast
+    knots = (warm_population(oracle_lib, prob, pop, 5) if warm
+             else W.draw_knots(prob, pop, 5))
+    knots = knots.astype(np.float32).astype(np.float64)
+    check_fp32_elites(oracle_lib, E, prob, knots, x0, ga.n_elite)
 
 
 # ---------------------------------------------------------------------------
@@ -471,10 +600,11 @@ def test_solve_fp64_edge_shapes(oracle_lib, E, case):
 
 
 @pytest.mark.parametrize("d,T,p", [(9, 30, 6), (20, 25, 5)])
-def test_solve_fp64_generating_rollout_matches_oracle(oracle_lib, E, d, T, p):
-    # linear chains of more than 16 states generate each tile's children
-    # inside the rollout kernel: whole FP64 ticks must still follow the
-    # oracle (ragged last tile: pop is not a multiple of 16)
+def test_solve_fp64_split_rollout_matches_oracle(oracle_lib, E, d, T, p):
+    # linear chains of more than 16 states at a population of fewer than
+    # 1024 tiles run the M-split rollout (one wavefront per 16-state tile,
+    # rows exchanged through LDS every step): whole FP64 ticks must still
+    # follow the oracle (ragged last tile: pop is not a multiple of 16)
     prob = W.linear_chain(d, T, p, seed=d)
     ga = W.GA(pop=600, n_elite=24, generations=3, sigma=0.1, seed=11)
     solver = E.Solver(E.DeviceProblem(prob, F64), ga)

@@ -147,3 +147,71 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+# ---------------------------------------------------------------------------
+# the binding's own checks of torch tensors (dtype, size, contiguity): the
+# library sees raw pointers only, so these are caught before any call
+
+
+def _torch_problem(E, dtype=0, n=4, m=2, p=3):
+    c = _problem(E, n=n, m=m, p=p, dtype=dtype)
+    return c
+
+
+@pytest.mark.parametrize("case", ["dtype", "knots_short", "x0_short", "cost_short",
+                                  "noncontig", "cpu"])
+def test_binding_rejects_bad_tensors(E, case):
+    import torch
+
+    c = _torch_problem(E, dtype=1)  # FP64 problem, n = 4, m = 2, p = 3
+    f64 = torch.float64
+    x0 = torch.zeros(4, dtype=f64)
+    knots = torch.zeros(6, 10, dtype=f64)
+    cost = torch.zeros(10, dtype=f64)
+    if case == "dtype":
+        knots = knots.float()  # 4-byte elements where the kernels read 8
+        msg = "dtype"
+    elif case == "knots_short":
+        knots = torch.zeros(5, 10, dtype=f64)  # fewer than p*m rows
+        msg = "knots holds"
+    elif case == "x0_short":
+        x0 = torch.zeros(3, dtype=f64)
+        msg = "x0 holds"
+    elif case == "cost_short":
+        cost = torch.zeros(9, dtype=f64)
+        msg = "cost holds"
+    elif case == "noncontig":
+        knots = torch.zeros(10, 6, dtype=f64).t()
+        msg = "contiguous"
+    else:
+        msg = "GPU tensor"  # right sizes, but host memory
+    with pytest.raises(ValueError, match=msg):
+        E.empc_rollout_cost(c, x0, knots, 10, 10, cost)
+
+
+def test_binding_rejects_bad_solve_and_plant_tensors(E):
+    import torch
+
+    c = _torch_problem(E, dtype=0)  # FP32, n = 4, m = 2
+    g = E.EmpcGA()
+    g.pop, g.n_elite, g.generations, g.sigma = 32, 4, 1, 0.1
+    ws = torch.zeros(64, dtype=torch.uint8)
+    x0 = torch.zeros(4)
+    u = torch.zeros(2)
+    b = torch.zeros(1)
+    with pytest.raises(ValueError, match="u_star holds"):
+        E.empc_solve(c, g, ws, x0, 0, torch.zeros(1), b)
+    with pytest.raises(ValueError, match="dtype"):
+        E.empc_solve(c, g, ws, x0.double(), 0, u, b)
+    with pytest.raises(ValueError, match="workspace has dtype"):
+        E.empc_solve(c, g, torch.zeros(16), x0, 0, u, b)
+    with pytest.raises(ValueError, match="x_next holds"):
+        E.empc_plant_step(c, x0, u, None, torch.zeros(2))
+    with pytest.raises(ValueError, match="noise holds"):
+        E.empc_plant_step(c, x0, u, torch.zeros(3), torch.zeros(4))
+    with pytest.raises(ValueError, match="dJ holds"):
+        E.empc_grad(c, x0, torch.zeros(6, 5), 5, 5, torch.zeros(6, 4), None)
+    with pytest.raises(ValueError, match="elite_idx has dtype"):
+        E.empc_generation(c, g, torch.zeros(6, 32), 32, torch.zeros(32), torch.zeros(6, 32), 32,
+                          torch.zeros(4, dtype=torch.int32), None, 0, 1)

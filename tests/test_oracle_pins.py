@@ -1,8 +1,8 @@
 """Pins of the FP64 oracle against what the paper and the mathematics fix.
 
 Every check here compares the oracle with something other than itself: the
-paper's worked examples (Sec. IV-E/F), its small-matrix closed form
-(Sec. IV-C), published Philox known-answer vectors, an independent Philox
+paper's worked examples (Sec. IV-D/E), its small-matrix closed form
+(Sec. IV-B), published Philox known-answer vectors, an independent Philox
 implementation, library sorts, brute force over tiny problems, invariants of
 the dynamics, and finite differences.
 """
@@ -37,7 +37,7 @@ def hat_weights(T, p):
 
 def small_matrix(A, B, w, x0, T, p):
     """S (nT x pm), v (nT), Phi (Tm x pm) with [x_1..x_T] = S z + v and
-    [u_0..u_{T-1}] = Phi z, z[j*m + i] = knot j of input i (Sec. IV-C/F)."""
+    [u_0..u_{T-1}] = Phi z, z[j*m + i] = knot j of input i (Sec. IV-B/E)."""
     n, m = B.shape
     Wt = hat_weights(T, p)
     powers = [np.eye(n)]
@@ -120,7 +120,7 @@ def test_philox_matches_rocrand(oracle_lib, tmp_path):
 
 
 # ---------------------------------------------------------------------------
-# knot interpolation and the parameterized matrices (Sec. IV-D/E/F)
+# knot interpolation and the parameterized matrices (Sec. IV-C/D/E)
 
 
 def test_knot_weights_worked_example(oracle_lib):
@@ -180,7 +180,7 @@ def test_parameterized_S_worked_example(oracle_lib):
 
 
 # ---------------------------------------------------------------------------
-# linear rollout and cost against the closed forms of Sec. IV-C
+# linear rollout and cost against the closed forms of Sec. IV-B
 
 
 @pytest.mark.parametrize("n,m,T,p", [(5, 3, 12, 4), (4, 2, 20, 5), (6, 6, 9, 9), (3, 1, 7, 1),
@@ -358,11 +358,26 @@ def test_select_matches_library_sort(oracle_lib):
         cost = np.round(rng.normal(0, 1, pop), 1)  # many exact ties
         cost[rng.random(pop) < 0.05] = np.nan
         cost[rng.random(pop) < 0.02] = np.inf
-        key = np.where(np.isnan(cost), np.inf, cost)
-        order = np.lexsort((np.arange(pop), key))
+        # library sort on (isnan, J, index): NaN after every number, +inf
+        # included (np.lexsort sorts by its last key first)
+        isnan = np.isnan(cost)
+        order = np.lexsort((np.arange(pop), np.where(isnan, 0.0, cost), isnan))
         idx, best = oracle_lib.select(cost, k)
         np.testing.assert_array_equal(idx, np.sort(order[:k]))
         assert best == order[0]
+
+
+def test_select_nan_ranks_after_inf(oracle_lib):
+    # a NaN at a lower index than a +inf still ranks after it
+    idx, best = oracle_lib.select([np.nan, np.inf], 1)
+    assert list(idx) == [1] and best == 1
+    idx, best = oracle_lib.select([np.nan, np.inf, 1.0], 2)
+    assert list(idx) == [1, 2] and best == 2
+    idx, best = oracle_lib.select([np.nan, np.nan, -np.inf], 2)
+    assert list(idx) == [0, 2] and best == 2
+    # -0 and +0 tie, broken by index
+    idx, best = oracle_lib.select([0.0, -0.0, 1.0], 1)
+    assert list(idx) == [0] and best == 0
 
 
 # ---------------------------------------------------------------------------
@@ -519,7 +534,7 @@ def test_solve_warm_start_and_elitism_over_ticks(oracle_lib):
 def test_shift_samples_the_carried_input_one_step_later(oracle_lib, T, p):
     # knot a sits at step a (T-1)/(p-1), an integer for these (T, p); the moved
     # knot must be the carried piecewise-linear input at that step plus one,
-    # evaluated with the interpolation weights of Sec. IV-D (pinned above by
+    # evaluated with the interpolation weights of Sec. IV-C (pinned above by
     # the worked example), and the last knot is held
     m = 3
     prob = W.linear_chain(m, T, p, seed=1)
@@ -727,6 +742,124 @@ def test_refine_never_increases_cost(oracle_lib):
     assert np.sum(c2 < cost) >= 4  # convex problem: Adam makes progress
     np.testing.assert_allclose(oracle_lib.rollout_cost(prob, x0, k2), c2, rtol=1e-12)
     assert np.all(np.abs(k2) <= 1.0)
+
+
+# Adam (Kingma & Ba 2015, Algorithm 1) on a one-parameter quadratic: n = m =
+# T = p = 1, A_d = 0, B_d = 1, goal 1, so x_1 = u and J(u) = q (u - 1)^2,
+# dJ/du = 2 q (u - 1).
+
+
+def _scalar_quadratic(q=1.0, lo=-10.0, hi=10.0, goal=1.0):
+    one = np.ones(1)
+    return W.Problem(model=W.LINEAR, n=1, m=1, T=1, p=1, q=q * one, r=0 * one, qf=0 * one,
+                     x_goal=goal * one, u_goal=0 * one, u_min=lo * one, u_max=hi * one,
+                     Ad=np.zeros((1, 1)), Bd=np.ones((1, 1)), wd=np.zeros(1))
+
+
+def _adam_decimal(u0, q, lr, steps, lo, hi, goal=1.0, clamp_each=True):
+    """The bias-corrected Adam recursion on q (u - goal)^2, with a clamp after
+    every update (or, clamp_each=False, once at the end), evaluated in
+    40-digit decimal arithmetic (independent of the oracle's binary64 code
+    path)."""
+    from decimal import Decimal as D, getcontext
+
+    getcontext().prec = 40
+    b1, b2, eps = D("0.9"), D("0.999"), D("1e-8")
+    u, m, v = D(repr(u0)), D(0), D(0)
+    for t in range(1, steps + 1):
+        g = 2 * D(repr(q)) * (u - D(repr(goal)))
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        mh, vh = m / (1 - b1 ** t), v / (1 - b2 ** t)
+        u = u - D(repr(lr)) * mh / (vh.sqrt() + eps)
+        if clamp_each:
+            u = min(max(u, D(repr(lo))), D(repr(hi)))
+    return float(min(max(u, D(repr(lo))), D(repr(hi))))
+
+
+def _refine1(oracle_lib, prob, u0, lr, steps):
+    knots = np.array([[u0]])
+    cost = oracle_lib.rollout_cost(prob, np.zeros(1), knots)
+    k2, c2 = oracle_lib.refine(prob, np.zeros(1), knots, cost, lr=lr, steps=steps)
+    return float(k2[0, 0]), float(c2[0]), float(cost[0])
+
+
+def test_adam_first_step_is_lr_times_sign(oracle_lib):
+    # from zero moments the bias corrections make m_hat = g and v_hat = g^2,
+    # whatever beta1 and beta2 are: the first update is exactly
+    # -lr g / (|g| + eps).  A missing correction would move by about
+    # lr (1 - b1) / sqrt(1 - b2) = 3.16 lr.
+    prob = _scalar_quadratic()
+    for u0, lr in [(0.0, 0.1), (0.3, 0.01), (2.5, 0.2)]:
+        g = 2 * (u0 - 1)
+        u1, _, _ = _refine1(oracle_lib, prob, u0, lr, 1)
+        assert abs(u1 - (u0 - lr * g / (abs(g) + 1e-8))) < 1e-15
+
+
+def test_adam_steps_follow_the_recursion(oracle_lib):
+    # steps 2 and 3 carry the moments: their values depend on beta1, beta2
+    # and the bias corrections separately (swapped betas or a dropped
+    # correction change them at the 1e-3 level)
+    prob = _scalar_quadratic(q=3.0)
+    for u0, lr, steps in [(0.0, 0.1, 2), (0.0, 0.1, 3), (-0.7, 0.05, 5)]:
+        got, _, _ = _refine1(oracle_lib, prob, u0, lr, steps)
+        assert abs(got - _adam_decimal(u0, 3.0, lr, steps, -10, 10)) < 1e-14
+    # the second step from u0 = 0, lr = 0.1 (q = 1) by hand: g1 = -2,
+    # u1 = 0.2 / (2 + eps) (= 0.1 up to 5e-10); g2 = 2 (u1 - 1) (about -1.8);
+    # m = 0.9 (0.1 g1) + 0.1 g2, v = 0.999 (0.001 g1^2) + 0.001 g2^2;
+    # m_hat = m / (1 - 0.81), v_hat = v / (1 - 0.998001)
+    u1 = 0.2 / (2 + 1e-8)
+    g2 = 2 * (u1 - 1)
+    m = 0.9 * 0.1 * -2 + 0.1 * g2
+    v = 0.999 * 0.001 * 4 + 0.001 * g2 * g2
+    u2 = u1 - 0.1 * (m / 0.19) / (np.sqrt(v / 0.001999) + 1e-8)
+    got, _, _ = _refine1(oracle_lib, _scalar_quadratic(), 0.0, 0.1, 2)
+    assert abs(got - u2) < 1e-14
+    assert abs(got - 0.1995877718) < 1e-9
+    # swapped betas (m with 0.999, v with 0.9) would move u2 to about 0.1997
+    m_sw = 0.999 * 0.001 * -2 + 0.001 * g2
+    v_sw = 0.9 * 0.1 * 4 + 0.1 * g2 * g2
+    u2_sw = u1 - 0.1 * (m_sw / 0.001999) / (np.sqrt(v_sw / 0.19) + 1e-8)
+    assert abs(got - u2_sw) > 1e-5
+
+
+def test_adam_clamp_binds_mid_sequence(oracle_lib):
+    # the clamp acts on the parameter after every update, not once at the
+    # end: goal 0.12, u_max = 0.15, from 0 with lr = 0.1 the momentum carries
+    # steps 2..5 past the bound (cut to 0.15 each time, gradients then taken
+    # at 0.15) before the iterate turns back; the moments keep their own
+    # history
+    prob = _scalar_quadratic(hi=0.15, goal=0.12)
+    got, c, c0 = _refine1(oracle_lib, prob, 0.0, 0.1, 7)
+    want = _adam_decimal(0.0, 1.0, 0.1, 7, -10, 0.15, goal=0.12)
+    assert abs(got - want) < 1e-14
+    assert abs(want - 0.1278793876) < 1e-9
+    end_only = _adam_decimal(0.0, 1.0, 0.1, 7, -10, 0.15, goal=0.12, clamp_each=False)
+    assert abs(got - end_only) > 0.03
+    assert c < c0  # and the refined candidate is accepted
+
+
+def test_adam_moments_reset_per_call_and_scale_invariance(oracle_lib):
+    # each call starts from zero moments: two one-step calls are two first
+    # steps
+    prob = _scalar_quadratic()
+    u1, _, _ = _refine1(oracle_lib, prob, 0.0, 0.1, 1)
+    u2, _, _ = _refine1(oracle_lib, prob, u1, 0.1, 1)
+    g1 = 2 * (u1 - 1)
+    assert abs(u2 - (u1 - 0.1 * g1 / (abs(g1) + 1e-8))) < 1e-15
+    # Adam's update does not depend on the gradient's scale (up to eps)
+    a, _, _ = _refine1(oracle_lib, _scalar_quadratic(q=1.0), 0.2, 0.05, 4)
+    b, _, _ = _refine1(oracle_lib, _scalar_quadratic(q=1000.0), 0.2, 0.05, 4)
+    assert abs(a - b) < 1e-8  # eps = 1e-8 against gradients of order 1
+
+
+def test_adam_rejects_a_worse_candidate(oracle_lib):
+    # an update that raises the cost is not accepted: knots and cost stay
+    prob = _scalar_quadratic()
+    u, c, c0 = _refine1(oracle_lib, prob, 0.9, 5.0, 1)  # overshoots to 5.9
+    assert u == 0.9 and c == c0
+    u, c, c0 = _refine1(oracle_lib, prob, 0.0, 0.5, 1)  # 0 -> 0.5: better
+    assert abs(u - 0.5) < 1e-8 and c < c0
 
 
 # ---------------------------------------------------------------------------
