@@ -176,6 +176,26 @@ empc_status empc_solve_refined(const empc_problem *prob, const empc_ga *ga, void
                                size_t ws_bytes, const void *x0, uint32_t tick, double lr,
                                int32_t adam_steps, void *u_star, void *best_cost, void *stream);
 
+/* empc_solve without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  The workspace is a static device array of
+ * EMPC_STATIC_SCRATCH_BYTES bytes inside the library, one per GPU, held from
+ * the library's load to the end of the process; the call itself allocates
+ * nothing.  The array keeps the last call's contents, which is what carries
+ * the parents from tick to tick: cold = 1 clears the warm-start state first
+ * (a cold start, as a zero-filled workspace does for empc_solve), cold = 0
+ * continues from whatever solve ran last on this GPU.  Every call on one GPU
+ * shares the array, so calls that overlap on one GPU (other streams, other
+ * threads) race, and a warm call after a solve of a different problem shape
+ * reads that solve's parents: use cold = 1 whenever the shape or ga changes.
+ * Arguments as empc_solve.  A problem whose workspace (empc_workspace_bytes)
+ * exceeds the array returns EMPC_EUNSUPPORTED; cold outside {0, 1} returns
+ * EMPC_EINVAL. */
+#define EMPC_STATIC_SCRATCH_BYTES (64ull << 20)
+empc_status empc_solve_static(const empc_problem *prob, const empc_ga *ga, const void *x0,
+                              uint32_t tick, int32_t cold, void *u_star, void *best_cost,
+                              void *stream);
+
 /* Gradient of the rollout cost with respect to the knots by a hand-written
  * adjoint pass (states recomputed from checkpoints every ceil(sqrt(T))
  * steps).  dJ: [p*m][ld].  cost: ncand (may be NULL). */

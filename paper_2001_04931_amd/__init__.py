@@ -6,4 +6,5 @@ include/empc.h); `binding` marshals torch GPU tensors into it.
 from .binding import (BatchSolver, DeviceProblem, EmpcCost, EmpcError, EmpcGA, EmpcProblem, Solver,  # noqa: F401
                       empc_generation, empc_grad, empc_plant_step, empc_profile_begin,
                       empc_profile_end, empc_refine,
-                      empc_rollout_cost, empc_solve, empc_workspace_bytes, lib, make_ga)
+                      empc_rollout_cost, empc_solve, empc_solve_static, empc_workspace_bytes, lib,
+                      make_ga)

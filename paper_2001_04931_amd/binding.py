@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
             "empc_solve": ([P, G, _vp, sz, _vp, u32, _vp, _vp, _vp], ctypes.c_int),
             "empc_solve_refined": ([P, G, _vp, sz, _vp, u32, ctypes.c_double, ctypes.c_int32, _vp,
                                     _vp, _vp], ctypes.c_int),
+            "empc_solve_static": ([P, G, _vp, u32, ctypes.c_int32, _vp, _vp, _vp], ctypes.c_int),
             "empc_grad": ([P, _vp, _vp, i64, i64, _vp, _vp, _vp], ctypes.c_int),
             "empc_refine": ([P, _vp, _vp, i64, i64, _vp, ctypes.c_double, ctypes.c_int32, _vp],
                             ctypes.c_int),
@@ -101,7 +102,8 @@ def lib() -> ctypes.CDLL:
 
 def exported_symbols():
     return ["empc_status_str", "empc_last_error", "empc_rollout_cost", "empc_generation",
-            "empc_workspace_bytes", "empc_solve", "empc_solve_refined", "empc_grad", "empc_refine", "empc_plant_step",
+            "empc_workspace_bytes", "empc_solve", "empc_solve_refined", "empc_solve_static",
+            "empc_grad", "empc_refine", "empc_plant_step",
             "empc_batch_workspace_bytes", "empc_batch_create", "empc_solve_batched",
             "empc_batch_destroy", "empc_batch_autotune", "empc_batch_classes",
             "empc_batch_class_info", "empc_batch_class_times", "empc_batch_set_variant",
@@ -222,6 +224,15 @@ def empc_solve_refined(prob, ga, workspace, x0, tick, lr, adam_steps, u_star, be
     _check(lib().empc_solve_refined(_cprob(prob), _cga(ga), _ptr(workspace), workspace.numel(),
                                     _ptr(x0), int(tick), float(lr), int(adam_steps), _ptr(u_star),
                                     _ptr(best_cost), _stream(stream)))
+
+
+def empc_solve_static(prob, ga, x0, tick, cold, u_star, best_cost, stream=None):
+    dt, n, m, _ = _shape(prob)
+    _need(x0, dt, n, "x0")
+    _need(u_star, dt, m, "u_star")
+    _need(best_cost, dt, 1, "best_cost")
+    _check(lib().empc_solve_static(_cprob(prob), _cga(ga), _ptr(x0), int(tick), int(cold),
+                                   _ptr(u_star), _ptr(best_cost), _stream(stream)))
 
 
 def empc_grad(prob, x0, knots, ncand, ld, dJ, cost, stream=None):

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -210,6 +211,39 @@ empc_status solve_t(const empc_problem *P, const empc_ga *G, const Workspace &w,
     return EMPC_OK;
 }
 
+// Workspace of empc_solve_static: one array per GPU, held from the load of
+// the library's code object to the end of the process.  In host code the
+// symbol is only a host-side stand-in; its device address is looked up once
+// per device (with that device current) and used everywhere instead.
+__device__ __align__(256) unsigned char scratch[EMPC_STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};
+
+empc_status static_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_status(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(EMPC_EUNSUPPORTED, "device %d above %d", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return device_status(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(EMPC_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return EMPC_OK;
+}
+
+// Clears the warm-start words of a solve workspace header (a kernel, not a
+// memset, so that a captured graph replays it as it was recorded).
+__global__ void clear_header_kernel(int *head) {
+    if (threadIdx.x < 2) head[threadIdx.x] = 0;
+}
+
 }  // namespace
 
 empc_status empc_validate_problem_internal(const empc_problem *P) { return validate_problem(P); }
@@ -336,6 +370,32 @@ empc_status empc_solve_refined(const empc_problem *prob, const empc_ga *ga, void
     return prob->dtype == EMPC_F32
                ? solve_t<float>(prob, ga, w, x0, tick, u_star, best_cost, s, adam_steps, lr)
                : solve_t<double>(prob, ga, w, x0, tick, u_star, best_cost, s, adam_steps, lr);
+}
+
+empc_status empc_solve_static(const empc_problem *prob, const empc_ga *ga, const void *x0,
+                              uint32_t tick, int32_t cold, void *u_star, void *best_cost,
+                              void *stream) {
+    empc_status st = validate_problem(prob);
+    if (st) return st;
+    if ((st = validate_ga(ga))) return st;
+    if (cold != 0 && cold != 1) return fail(EMPC_EINVAL, "cold=%d must be 0 or 1", cold);
+    if (!x0 || !u_star || !best_cost) return fail(EMPC_EINVAL, "x0, u_star and best_cost are required");
+    const size_t need = layout(prob, ga, nullptr).bytes;
+    if (need > EMPC_STATIC_SCRATCH_BYTES)
+        return fail(EMPC_EUNSUPPORTED, "solve needs %zu bytes of workspace, above the static %zu",
+                    need, (size_t)EMPC_STATIC_SCRATCH_BYTES);
+    if ((st = check_prior())) return st;
+    void *base = nullptr;
+    if ((st = static_scratch(&base))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const Workspace w = layout(prob, ga, base);
+    if (cold) {
+        hipLaunchKernelGGL(clear_header_kernel, dim3(1), dim3(64), 0, s, w.has_elites);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return device_status(e, "clear launch");
+    }
+    return prob->dtype == EMPC_F32 ? solve_t<float>(prob, ga, w, x0, tick, u_star, best_cost, s)
+                                   : solve_t<double>(prob, ga, w, x0, tick, u_star, best_cost, s);
 }
 
 empc_status empc_grad(const empc_problem *prob, const void *x0, const void *knots, int64_t ncand,

@@ -103,6 +103,25 @@ def test_ga_validation_and_workspace_size(E):
     assert st == 4
 
 
+def test_static_solve_validation(E):
+    # the no-allocation solve refuses bad arguments and workspaces above its
+    # static array on the host, before it looks up the array or launches
+    c = _problem(E)
+    g = E.EmpcGA()
+    g.pop, g.n_elite, g.generations, g.elitism, g.sigma, g.seed = 100, 10, 2, 1, 0.1, 0
+    L = E.lib()
+    fake = ctypes.c_void_p(0x3000)
+    assert L.empc_solve_static(ctypes.byref(c), ctypes.byref(g), fake, 0, 2, fake, fake, None) == 1
+    assert L.empc_solve_static(ctypes.byref(c), ctypes.byref(g), None, 0, 1, fake, fake, None) == 1
+    assert L.empc_solve_static(None, ctypes.byref(g), fake, 0, 1, fake, fake, None) == 1
+    big = E.EmpcGA.from_buffer_copy(g)
+    big.pop = 1 << 22  # 30 parameters x 2^22 candidates x 2 buffers x 4 B > 64 MiB
+    assert L.empc_workspace_bytes(ctypes.byref(c), ctypes.byref(big)) > (64 << 20)
+    assert L.empc_solve_static(ctypes.byref(c), ctypes.byref(big), fake, 0, 1, fake, fake,
+                               None) == 3
+    assert "static" in L.empc_last_error().decode()
+
+
 def test_generation_validation(E):
     c = _problem(E)
     g = E.EmpcGA()
