@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "empc_oracle.c")
+_SRC_NLINK = os.path.join(_HERE, "nlink_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -31,7 +32,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-o", tmp, _SRC,
-                        "-lm"], check=True)
+                        _SRC_NLINK, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -89,6 +90,14 @@ def lib():
                               ctypes.c_int64, _dp, _dp]
         L.or_refine.argtypes = [ctypes.POINTER(_OrProblem), _dp, _dp, ctypes.c_int64,
                                 ctypes.c_int64, _dp, ctypes.c_double, ctypes.c_int]
+        L.or_nlink_mass_matrix.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_nlink_kinetic.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+        L.or_nlink_kinetic.restype = ctypes.c_double
+        L.or_nlink_deriv.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _dp, _dp, _dp]
+        L.or_nlink_jacobian.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _dp, _dp, _dp,
+                                        _dp, _dp]
+        L.or_nlink_rk4.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _dp, _dp,
+                                   ctypes.c_double, ctypes.c_int, _dp]
         _lib = L
     return _lib
 
@@ -274,3 +283,77 @@ class Solver:
                                         self.idx_ws.ctypes.data_as(_i64p),
                                         1 if self.refine else 0, self.lr, self.adam_steps)
         return u, best.value, gen_best
+
+
+# ---------------------------------------------------------------------------
+# N-link planar robot (nlink_oracle.c): point masses at the link ends, plane
+# perpendicular to gravity, M(q) qdd + C(q, qd) + b qd = tau.
+
+
+def _nl_check(rc):
+    if rc != 0:
+        raise ValueError("N-link oracle: links outside [1, 16] or bad substeps")
+
+
+def nlink_mass_matrix(mass, length, q, qd=None):
+    """(M(q) [N][N], C(q, qd) [N] or None)."""
+    mass, length, q = _f64(mass), _f64(length), _f64(q)
+    N = mass.shape[0]
+    M = np.zeros((N, N))
+    C = np.zeros(N) if qd is not None else None
+    qd = None if qd is None else _f64(qd)
+    _nl_check(lib().or_nlink_mass_matrix(N, _ptr(mass), _ptr(length), _ptr(q), _ptr(M), _ptr(C),
+                                         _ptr(qd)))
+    return M, C
+
+
+def nlink_kinetic(mass, length, q, qd):
+    mass, length, q, qd = _f64(mass), _f64(length), _f64(q), _f64(qd)
+    return float(lib().or_nlink_kinetic(mass.shape[0], _ptr(mass), _ptr(length), _ptr(q),
+                                        _ptr(qd)))
+
+
+def nlink_deriv(mass, length, b, x, tau):
+    """State derivative [qd; qdd] of x = [q; qd]."""
+    mass, length, x, tau = _f64(mass), _f64(length), _f64(x), _f64(tau)
+    f = np.zeros(x.shape[0])
+    _nl_check(lib().or_nlink_deriv(mass.shape[0], _ptr(mass), _ptr(length), float(b), _ptr(x),
+                                   _ptr(tau), _ptr(f)))
+    return f
+
+
+def nlink_jacobian(mass, length, b, x, tau):
+    """(A = df/dx [2N][2N], B = df/dtau [2N][N], f(x, tau)) by the complex step."""
+    mass, length, x, tau = _f64(mass), _f64(length), _f64(x), _f64(tau)
+    N = mass.shape[0]
+    A = np.zeros((2 * N, 2 * N))
+    B = np.zeros((2 * N, N))
+    f0 = np.zeros(2 * N)
+    _nl_check(lib().or_nlink_jacobian(N, _ptr(mass), _ptr(length), float(b), _ptr(x), _ptr(tau),
+                                      _ptr(A), _ptr(B), _ptr(f0)))
+    return A, B, f0
+
+
+def nlink_rk4(mass, length, b, x, tau, dt, substeps):
+    """The simulated robot over dt: `substeps` RK4 steps, tau held."""
+    mass, length, x, tau = _f64(mass), _f64(length), _f64(x), _f64(tau)
+    out = np.zeros(x.shape[0])
+    _nl_check(lib().or_nlink_rk4(mass.shape[0], _ptr(mass), _ptr(length), float(b), _ptr(x),
+                                 _ptr(tau), float(dt), int(substeps), _ptr(out)))
+    return out
+
+
+def nlink_linearize(mass, length, b, x, tau, dt):
+    """Discrete affine model (A_d, B_d, w_d) of the robot at (x, tau): the
+    exact Jacobians A, B and the offset w = f(x, tau) - A x - B tau of the
+    first-order expansion, held over dt by the zero-order hold, i.e. the
+    matrix exponential of [[A, B, w], [0, 0, 0]] dt (scipy's expm)."""
+    import scipy.linalg
+
+    A, B, f0 = nlink_jacobian(mass, length, b, x, tau)
+    n, m = A.shape[0], B.shape[1]
+    w = f0 - A @ _f64(x) - B @ _f64(tau)
+    Z = np.zeros((n + m + 1, n + m + 1))
+    Z[:n, :n], Z[:n, n:n + m], Z[:n, n + m] = A, B, w
+    E = scipy.linalg.expm(Z * dt)
+    return E[:n, :n].copy(), E[:n, n:n + m].copy(), E[:n, n + m].copy()

@@ -31,6 +31,16 @@
  *                      high-precision decimal arithmetic, the clamp acts
  *                      after every update, moments start at zero per call,
  *                      worse candidates are rejected; plus or_grad's pins.
+ *   or_nlink_*         (nlink_oracle.c, the N-link planar robot of the
+ *                      paper's Sec. IV-F setup) pinned: the two-link
+ *                      closed form of M and C, eq. 5 without gravity for one
+ *                      link (and its zero-order-hold closed form), kinetic
+ *                      energy from the mass points' velocities, energy
+ *                      conservation, power balance and Lagrange's equation
+ *                      by differences in time, the complex-step Jacobian by
+ *                      central differences, the hold against a fine RK4 of
+ *                      the affine expansion, third-order local error of the
+ *                      linearized step, fourth-order convergence of RK4.
  */
 #ifndef EMPC_ORACLE_H
 #define EMPC_ORACLE_H
