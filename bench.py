@@ -154,7 +154,7 @@ def summary(rate, lats, **extra):
     return d
 
 
-WORKLOADS = ("c1", "c3", "c4", "c5", "c2v")
+WORKLOADS = ("c1", "c3", "c4", "c5", "c2v", "nlink")
 
 
 def other_workloads(E, W, names=WORKLOADS):
@@ -177,7 +177,74 @@ def other_workloads(E, W, names=WORKLOADS):
         out.update(batched_workload(E, W))
     if "c2v" in names:
         out.update(variants_workload(E, W))
+    if "nlink" in names:
+        out.update(nlink_workload(E, W))
     return out
+
+
+def nlink_closed_loop(E, W, N, generations, ticks, dtype, seed=0):
+    """The paper's N-link robot experiment on the GPU: every tick relinearize
+    the robot at its state (and last torque), one EMPC solve on that model,
+    u* to the host, RK4 step of the robot (4 substeps).  Returns (solve
+    latencies ms, relinearization+solve latencies ms, rollouts/s, final
+    distance to the goal)."""
+    import torch
+
+    robot, prob, x0, ga = W.config_nlink(N, seed, generations)
+    R = E.NLinkRobot(robot.mass, robot.length, robot.damping, dtype)
+    dp = E.DeviceProblem(prob, dtype, keep=("wd",))
+    solver = E.Solver(dp, ga)
+    x = torch.tensor(x0, dtype=dtype, device="cuda")
+    u = torch.zeros(N, dtype=dtype, device="cuda")
+    u_host = torch.empty(N, dtype=dtype).pin_memory()
+    done = torch.cuda.Event()
+    lin_ev = torch.cuda.Event()
+    lats, tot = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for t in range(ticks):
+        t0 = time.perf_counter()
+        E.empc_nlink_linearize(R, 0.01, x, u, dp.tensors["Ad"], dp.tensors["Bd"],
+                               dp.tensors["wd"])
+        lin_ev.record()
+        lin_ev.synchronize()
+        t1 = time.perf_counter()
+        us, _ = solver.solve(x, t)
+        u_host.copy_(us, non_blocking=True)
+        done.record()
+        done.synchronize()
+        t2 = time.perf_counter()
+        lats.append((t2 - t1) * 1e3)
+        tot.append((t2 - t0) * 1e3)
+        u.copy_(us)
+        E.empc_nlink_step(R, 0.01, 4, x, u, x)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    dist = float(torch.linalg.vector_norm(x - torch.tensor(prob.x_goal, dtype=dtype,
+                                                           device="cuda")).item())
+    return np.array(lats), np.array(tot), ga.pop * generations * ticks / wall, dist
+
+
+def nlink_workload(E, W, links=range(1, 14), ticks=1000):
+    """The paper's EMPC experiment: N-link planar robots of 1..13 links, 1 kg
+    and 0.25 m per link, |tau| <= 2 N m, horizon 100, 3 knots, control at
+    100 Hz for 10 s (1000 ticks), 1 and 3 generations per tick; FP32 EMPC on
+    the model relinearized (in FP64) every tick."""
+    import torch
+
+    out = {}
+    for G in (1, 3):
+        rows = {}
+        for N in links:
+            lats, tot, rate, dist = nlink_closed_loop(E, W, N, G, ticks, torch.float32)
+            rows[str(N)] = {"solve_ms": {"p50": float(np.percentile(lats, 50)),
+                                         "p99": float(np.percentile(lats, 99))},
+                            "relinearize_and_solve_ms": {"p50": float(np.percentile(tot, 50)),
+                                                         "p99": float(np.percentile(tot, 99))},
+                            "rollouts_per_s": rate, "final_goal_distance": dist}
+        out["G%d" % G] = rows
+    return {"nlink_robot_relinearized": {"ticks": ticks, "horizon": 100, "knots": 3,
+                                         "pop": 1024, "dtype": "f32", "links": out}}
 
 
 def variants_workload(E, W):

@@ -216,6 +216,38 @@ empc_status empc_refine(const empc_problem *prob, const void *x0, void *knots, i
 empc_status empc_plant_step(const empc_problem *prob, const void *x, const void *u,
                             const void *noise, void *x_next, void *stream);
 
+/* The N-link planar robot of the paper's convex-solver and EMPC experiments
+ * (Sec. IV-F setup, used again in Sec. VI-A): N revolute joints in a plane
+ * perpendicular to gravity, M(q) qdd + C(q, qd) + b qd = tau, each link
+ * massless with a point mass at its far end (N = 1 is the pendulum of eq. 5
+ * with g = 0), relative joint angles, state x = [q; qd] (2N), input tau (N).
+ * EMPC controls it through the linear model of eq. 2, relinearized at the
+ * current state every tick (Sec. VI-A: the dynamics matrices are computed
+ * from the current conditions).  Every array of the robot, x, u and the
+ * outputs has robot->dtype elements; the kernels compute in FP64. */
+typedef struct {
+    int32_t links;      /* N, 1 <= N <= 16 (more: EMPC_EUNSUPPORTED)            */
+    int32_t dtype;      /* empc_dtype                                           */
+    const void *mass;   /* N point masses (device)                              */
+    const void *length; /* N link lengths (device)                              */
+    double damping;     /* viscous joint damping b                              */
+} empc_nlink;
+
+/* Discrete affine model x_{k+1} = A_d x_k + B_d u_k + w_d (eq. 2) of the robot
+ * at (x, u): the exact Jacobians A = df/dx, B = df/du of f = [qd; qdd], the
+ * offset w = f(x, u) - A x - B u of the first-order expansion, and the
+ * zero-order hold over dt (the exponential of [[A, B, w], [0, 0, 0]] dt).
+ * Ad: 2N x 2N, Bd: 2N x N row-major, wd: 2N, ready to be pointed at by an
+ * empc_problem of model EMPC_LINEAR.  dt finite and > 0. */
+empc_status empc_nlink_linearize(const empc_nlink *robot, double dt, const void *x,
+                                 const void *u, void *Ad, void *Bd, void *wd, void *stream);
+
+/* The robot itself over dt with u held: `substeps` classical Runge-Kutta
+ * steps (the simulated plant of a closed loop).  x, x_next: 2N (x_next may
+ * be x: the state is read before anything is written); u: N. */
+empc_status empc_nlink_step(const empc_nlink *robot, double dt, int32_t substeps, const void *x,
+                            const void *u, void *x_next, void *stream);
+
 /* Batched solve: many independent problems (each its own empc_problem, all
  * FP32, possibly of different model, size, horizon and knot count) advance
  * one control tick together under one empc_ga.  Problem i draws from the

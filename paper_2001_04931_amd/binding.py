@@ -49,6 +49,11 @@ class EmpcGA(ctypes.Structure):
                 ("sigma_dist", ctypes.c_double)]
 
 
+class EmpcNLink(ctypes.Structure):
+    _fields_ = [("links", ctypes.c_int32), ("dtype", ctypes.c_int32), ("mass", _vp),
+                ("length", _vp), ("damping", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -88,6 +93,10 @@ def lib() -> ctypes.CDLL:
             "empc_batch_class_times": ([_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)],
                                        ctypes.c_int),
             "empc_batch_set_variant": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+            "empc_nlink_linearize": ([ctypes.POINTER(EmpcNLink), ctypes.c_double, _vp, _vp, _vp,
+                                      _vp, _vp, _vp], ctypes.c_int),
+            "empc_nlink_step": ([ctypes.POINTER(EmpcNLink), ctypes.c_double, ctypes.c_int32, _vp,
+                                 _vp, _vp, _vp], ctypes.c_int),
             "empc_profile_begin": ([ctypes.c_int32], ctypes.c_int),
             "empc_profile_end": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
                                  ctypes.c_int),
@@ -107,7 +116,7 @@ def exported_symbols():
             "empc_batch_workspace_bytes", "empc_batch_create", "empc_solve_batched",
             "empc_batch_destroy", "empc_batch_autotune", "empc_batch_classes",
             "empc_batch_class_info", "empc_batch_class_times", "empc_batch_set_variant",
-            "empc_profile_begin",
+            "empc_nlink_linearize", "empc_nlink_step", "empc_profile_begin",
             "empc_profile_end"]
 
 
@@ -345,7 +354,10 @@ class DeviceProblem:
     # when all zero (x_min / x_max are bounds: a zero bound is kept)
     _OPTIONAL = ("wd", "qf", "x_goal", "u_goal", "qb")
 
-    def __init__(self, prob, dtype=torch.float32, device="cuda"):
+    def __init__(self, prob, dtype=torch.float32, device="cuda", keep=()):
+        """keep: names of optional arrays to place on the device even when
+        they are all zero (a model rewritten in place later, e.g. the w_d of
+        a relinearized robot)."""
         self.prob, self.dtype, self.device = prob, dtype, torch.device(device)
         self.tensors = {}
         c = EmpcProblem()
@@ -356,7 +368,8 @@ class DeviceProblem:
             v = getattr(prob, name, None)
             # optional arrays that are all zero are passed as NULL (= 0 by the
             # ABI), which lets the kernels skip them
-            if v is None or (name in self._OPTIONAL and not np.any(np.asarray(v))):
+            if v is None or (name in self._OPTIONAL and name not in keep and
+                             not np.any(np.asarray(v))):
                 setattr(c, name, None)
                 continue
             t = torch.as_tensor(v, dtype=dtype).contiguous().to(self.device)
@@ -506,3 +519,44 @@ class BatchSolver:
             self.close()
         except Exception:
             pass
+
+
+class NLinkRobot:
+    """The N-link planar robot's parameters on the GPU plus the C struct.
+
+    mass, length: host arrays (N,); damping: b."""
+
+    def __init__(self, mass, length, damping, dtype=torch.float64, device="cuda"):
+        self.dtype = dtype
+        self.mass = torch.as_tensor(np.asarray(mass), dtype=dtype).contiguous().to(device)
+        self.length = torch.as_tensor(np.asarray(length), dtype=dtype).contiguous().to(device)
+        c = EmpcNLink()
+        c.links = int(self.mass.numel())
+        c.dtype = EMPC_F64 if dtype == torch.float64 else EMPC_F32
+        c.mass, c.length = self.mass.data_ptr(), self.length.data_ptr()
+        c.damping = float(damping)
+        self.c = c
+
+    @property
+    def links(self):
+        return self.c.links
+
+
+def empc_nlink_linearize(robot, dt, x, u, Ad, Bd, wd, stream=None):
+    N, dt_ = robot.links, robot.dtype
+    _need(x, dt_, 2 * N, "x")
+    _need(u, dt_, N, "u")
+    _need(Ad, dt_, 4 * N * N, "Ad")
+    _need(Bd, dt_, 2 * N * N, "Bd")
+    _need(wd, dt_, 2 * N, "wd")
+    _check(lib().empc_nlink_linearize(ctypes.byref(robot.c), float(dt), _ptr(x), _ptr(u),
+                                      _ptr(Ad), _ptr(Bd), _ptr(wd), _stream(stream)))
+
+
+def empc_nlink_step(robot, dt, substeps, x, u, x_next, stream=None):
+    N, dt_ = robot.links, robot.dtype
+    _need(x, dt_, 2 * N, "x")
+    _need(u, dt_, N, "u")
+    _need(x_next, dt_, 2 * N, "x_next")
+    _check(lib().empc_nlink_step(ctypes.byref(robot.c), float(dt), int(substeps), _ptr(x),
+                                 _ptr(u), _ptr(x_next), _stream(stream)))

@@ -356,4 +356,13 @@ template <typename T>
 hipError_t launch_plant(const ProbView<T> &P, int model, const T *x, const T *u, const T *noise,
                         T *x_next, hipStream_t s);
 
+// N-link planar robot (nlink.hip): links per robot of this build
+constexpr int NLINK_MAX = 16;
+template <typename T>
+hipError_t launch_nlink_linearize(int N, const T *mass, const T *len, double b, double dt,
+                                  const T *x, const T *u, T *Ad, T *Bd, T *wd, hipStream_t s);
+template <typename T>
+hipError_t launch_nlink_step(int N, const T *mass, const T *len, double b, double dt, int sub,
+                             const T *x, const T *u, T *x_next, hipStream_t s);
+
 }  // namespace empc

@@ -122,6 +122,26 @@ def test_static_solve_validation(E):
     assert "static" in L.empc_last_error().decode()
 
 
+def test_nlink_validation(E):
+    # the N-link robot's calls check the robot and the step on the host
+    L = E.lib()
+    fake = ctypes.c_void_p(0x4000)
+    R = E.binding.EmpcNLink()
+    R.links, R.dtype, R.mass, R.length, R.damping = 3, 1, fake, fake, 0.01
+    assert L.empc_nlink_step(ctypes.byref(R), 0.01, 0, fake, fake, fake, None) == 1
+    assert L.empc_nlink_step(ctypes.byref(R), 0.0, 1, fake, fake, fake, None) == 1
+    assert L.empc_nlink_linearize(ctypes.byref(R), float("nan"), fake, fake, fake, fake, fake,
+                                  None) == 1
+    assert L.empc_nlink_linearize(ctypes.byref(R), 0.01, fake, fake, None, fake, fake, None) == 1
+    R.links = 17
+    assert L.empc_nlink_linearize(ctypes.byref(R), 0.01, fake, fake, fake, fake, fake, None) == 3
+    R.links = 0
+    assert L.empc_nlink_step(ctypes.byref(R), 0.01, 1, fake, fake, fake, None) == 1
+    R.links, R.dtype = 3, 5
+    assert L.empc_nlink_step(ctypes.byref(R), 0.01, 1, fake, fake, fake, None) == 1
+    assert L.empc_nlink_step(None, 0.01, 1, fake, fake, fake, None) == 1
+
+
 def test_generation_validation(E):
     c = _problem(E)
     g = E.EmpcGA()

@@ -228,6 +228,55 @@ def config_c3(seed: int = 0):
     return prob, GA(pop=16384, n_elite=64, generations=30, sigma=0.1, seed=seed)
 
 
+# ---------------------------------------------------------------------------
+# The N-link planar robot of the paper's Sec. IV-F setup and Sec. VI-A EMPC
+# experiments: every link 1 kg at 0.25 m, viscous damping 0.01, torques
+# within +-2 N m, control at 100 Hz (dt = 0.01 s), horizon 100, 3 knots,
+# from rest at an initial position to rest at a goal position, both drawn
+# uniformly (here each joint angle in [-1, 1] rad).  The linear model of each
+# tick comes from relinearizing the robot at its current state (the method's
+# own step, done by each side), so the Problem carries placeholder matrices.
+
+@dataclasses.dataclass
+class NLink:
+    mass: np.ndarray
+    length: np.ndarray
+    damping: float
+
+
+def nlink_robot(N: int) -> NLink:
+    return NLink(mass=np.ones(N), length=np.full(N, 0.25), damping=0.01)
+
+
+def nlink_problem(N: int, T: int = 100, p: int = 3, x_goal=None) -> Problem:
+    """Linear-model MPC problem of an N-link robot (n = 2N, m = N); A_d, B_d,
+    w_d are placeholders that the relinearization overwrites."""
+    n = 2 * N
+    cb = _cost_and_bounds(N, n)
+    cb["u_min"], cb["u_max"] = np.full(N, -2.0), np.full(N, 2.0)
+    if x_goal is not None:
+        cb["x_goal"] = np.asarray(x_goal, dtype=np.float64)
+    return Problem(model=LINEAR, n=n, m=N, T=T, p=p, Ad=np.eye(n), Bd=np.zeros((n, N)),
+                   wd=np.zeros(n), dt=0.01, **cb)
+
+
+def nlink_start_goal(N: int, seed: int):
+    """(x0, x_goal): rest at joint angles ~ U[-1, 1] rad, both."""
+    rng = np.random.default_rng([seed, 8, N])
+    q0, qg = rng.uniform(-1.0, 1.0, N), rng.uniform(-1.0, 1.0, N)
+    return (np.concatenate([q0, np.zeros(N)]), np.concatenate([qg, np.zeros(N)]))
+
+
+def config_nlink(N: int, seed: int = 0, generations: int = 1):
+    """N-link robot EMPC at 100 Hz: T = 100, 3 knots, pop 1024, top-32,
+    sigma 0.2 (a tenth of the torque range), `generations` per tick (the
+    paper runs 1 and 3)."""
+    x0, xg = nlink_start_goal(N, seed)
+    prob = nlink_problem(N, 100, 3, xg)
+    return (nlink_robot(N), prob, x0,
+            GA(pop=1024, n_elite=32, generations=generations, sigma=0.2, seed=seed))
+
+
 C5_DOFS = (2, 7, 14, 21, 36)
 
 
