@@ -154,7 +154,7 @@ def summary(rate, lats, **extra):
     return d
 
 
-WORKLOADS = ("c1", "c3", "c4", "c5", "c2v", "nlink")
+WORKLOADS = ("c1", "c3", "c4", "c5", "c2v", "nlink", "convex")
 
 
 def other_workloads(E, W, names=WORKLOADS):
@@ -179,7 +179,61 @@ def other_workloads(E, W, names=WORKLOADS):
         out.update(variants_workload(E, W))
     if "nlink" in names:
         out.update(nlink_workload(E, W))
+    if "convex" in names:
+        out.update(convex_workload(E, W))
     return out
+
+
+def convex_workload(E, W, reps=50):
+    """The paper's other method on the GPU: parameterized small-matrix convex
+    MPC (form P, q, c, then the box QP) for the 2-DoF and 14-DoF linear
+    chains and the 13-link robot linearized at rest-to-goal start (horizon
+    50 and 100, 5 knots as in the paper's convex experiments), FP64; the
+    solve time, active-set iterations, and the gap of EMPC's best cost after
+    the configuration's generations to the convex optimum."""
+    import torch
+
+    out = {}
+    cases = {"c1_2dof": W.config_c1(0), "c2_14dof": W.config_c2(0)}
+    for T in (50, 100):
+        robot, prob, x0, ga = W.config_nlink(13, 0)
+        prob = W.nlink_problem(13, T, 5, prob.x_goal)
+        cases["nlink13_T%d" % T] = (prob, ga, robot, x0)
+    for name, c in cases.items():
+        prob, ga = c[0], c[1]
+        dp = E.DeviceProblem(prob, torch.float64, keep=("wd",))
+        if len(c) == 4:
+            robot, x0 = c[2], c[3]
+            R = E.NLinkRobot(robot.mass, robot.length, robot.damping, torch.float64)
+            x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+            E.empc_nlink_linearize(R, 0.01, x, torch.zeros(prob.m, dtype=torch.float64,
+                                                           device="cuda"),
+                                   dp.tensors["Ad"], dp.tensors["Bd"], dp.tensors["wd"])
+        else:
+            x = torch.tensor(W.draw_x0(prob.n, 0), dtype=torch.float64, device="cuda")
+        cs = E.ConvexSolver(dp)
+        cs.solve(x)
+        torch.cuda.synchronize()
+        lats = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            cs.solve(x)
+            torch.cuda.synchronize()
+            lats.append((time.perf_counter() - t0) * 1e3)
+        info = cs.info.cpu().numpy()
+        Jstar = float(cs.cost.item())
+        entry = {"pm": prob.p * prob.m, "T": prob.T, "n": prob.n,
+                 "solve_ms": {"p50": float(np.percentile(lats, 50)),
+                              "p99": float(np.percentile(lats, 99))},
+                 "active_set_iterations": int(info[0]), "converged": bool(info[1]),
+                 "optimum": Jstar}
+        if len(c) == 2:
+            s = E.Solver(dp, ga)
+            _, J = s.solve(x, 0)
+            entry["empc_best_cost"] = float(J.item())
+            entry["empc_gap"] = float(J.item()) / Jstar - 1.0
+        out[name] = entry
+    return {"convex_small_matrix_fp64": out}
 
 
 def nlink_closed_loop(E, W, N, generations, ticks, dtype, seed=0):

@@ -216,6 +216,35 @@ empc_status empc_refine(const empc_problem *prob, const void *x0, void *knots, i
 empc_status empc_plant_step(const empc_problem *prob, const void *x, const void *u,
                             const void *noise, void *x_next, void *stream);
 
+/* Parameterized small-matrix convex MPC (Sec. IV-B small-matrix formulation
+ * with the knot parameterization of Sec. IV-E), the paper's other method,
+ * for EMPC_LINEAR problems without the state box penalty: with z the knot
+ * vector [p*m] (z[j*m + i] = knot j of input i), the states x_1..x_T are
+ * S z + v and the cost of eq. 3 is J(z) = z^T P z + 2 q^T z + c;
+ * u_min <= z <= u_max (each input's bounds on each of its knots) keeps
+ * every interpolated input in bounds, so the MPC is a box-constrained QP.
+ * Limits: p*m <= 1024 (more: EMPC_EUNSUPPORTED); FP64 arithmetic inside,
+ * arrays in the problem dtype.
+ * empc_qp_workspace_bytes(prob): device workspace of both calls (0 for an
+ *   invalid or unsupported problem).
+ * empc_qp_form: P [p*m][p*m] row-major, q [p*m], c [1] at state x0 [n] (the
+ *   "MPC solve time" matrix formation: S from the responses to unit knots,
+ *   then S^T Qb S plus the input term).
+ * empc_qp_solve: the minimizer z [p*m] of z^T P z + 2 q^T z over the box by
+ *   the projected Newton method (Bertsekas 1982: Newton steps on the
+ *   variables off their bounds by Cholesky solves of P restricted to them,
+ *   an Armijo search along the projection arc), stopping when the projected
+ *   gradient vanishes to rounding or after max_iter iterations; cost [1] =
+ *   J(z) including c; info (device, int32[2]) = {iterations, converged}.
+ *   P must be positive definite (r > 0 for every input suffices).  u* is
+ *   the first m entries of z (knot 0). */
+size_t empc_qp_workspace_bytes(const empc_problem *prob);
+empc_status empc_qp_form(const empc_problem *prob, const void *x0, void *workspace,
+                         size_t ws_bytes, void *P, void *q, void *c, void *stream);
+empc_status empc_qp_solve(const empc_problem *prob, const void *P, const void *q, const void *c,
+                          void *workspace, size_t ws_bytes, int32_t max_iter, void *z, void *cost,
+                          int32_t *info, void *stream);
+
 /* The N-link planar robot of the paper's convex-solver and EMPC experiments
  * (Sec. IV-F setup, used again in Sec. VI-A): N revolute joints in a plane
  * perpendicular to gravity, M(q) qdd + C(q, qd) + b qd = tau, each link

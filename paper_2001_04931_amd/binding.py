@@ -93,6 +93,10 @@ def lib() -> ctypes.CDLL:
             "empc_batch_class_times": ([_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)],
                                        ctypes.c_int),
             "empc_batch_set_variant": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+            "empc_qp_workspace_bytes": ([P], sz),
+            "empc_qp_form": ([P, _vp, _vp, sz, _vp, _vp, _vp, _vp], ctypes.c_int),
+            "empc_qp_solve": ([P, _vp, _vp, _vp, _vp, sz, ctypes.c_int32, _vp, _vp, _vp, _vp],
+                              ctypes.c_int),
             "empc_nlink_linearize": ([ctypes.POINTER(EmpcNLink), ctypes.c_double, _vp, _vp, _vp,
                                       _vp, _vp, _vp], ctypes.c_int),
             "empc_nlink_step": ([ctypes.POINTER(EmpcNLink), ctypes.c_double, ctypes.c_int32, _vp,
@@ -116,6 +120,7 @@ def exported_symbols():
             "empc_batch_workspace_bytes", "empc_batch_create", "empc_solve_batched",
             "empc_batch_destroy", "empc_batch_autotune", "empc_batch_classes",
             "empc_batch_class_info", "empc_batch_class_times", "empc_batch_set_variant",
+            "empc_qp_workspace_bytes", "empc_qp_form", "empc_qp_solve",
             "empc_nlink_linearize", "empc_nlink_step", "empc_profile_begin",
             "empc_profile_end"]
 
@@ -560,3 +565,61 @@ def empc_nlink_step(robot, dt, substeps, x, u, x_next, stream=None):
     _need(x_next, dt_, 2 * N, "x_next")
     _check(lib().empc_nlink_step(ctypes.byref(robot.c), float(dt), int(substeps), _ptr(x),
                                  _ptr(u), _ptr(x_next), _stream(stream)))
+
+
+def empc_qp_workspace_bytes(prob) -> int:
+    return int(lib().empc_qp_workspace_bytes(_cprob(prob)))
+
+
+def empc_qp_form(prob, x0, workspace, P, q, c, stream=None):
+    dt, n, m, pm = _shape(prob)
+    _need(x0, dt, n, "x0")
+    _need(workspace, torch.uint8, 1, "workspace")
+    _need(P, dt, pm * pm, "P")
+    _need(q, dt, pm, "q")
+    _need(c, dt, 1, "c")
+    _check(lib().empc_qp_form(_cprob(prob), _ptr(x0), _ptr(workspace), workspace.numel(),
+                              _ptr(P), _ptr(q), _ptr(c), _stream(stream)))
+
+
+def empc_qp_solve(prob, P, q, c, workspace, max_iter, z, cost, info, stream=None):
+    dt, n, m, pm = _shape(prob)
+    _need(P, dt, pm * pm, "P")
+    _need(q, dt, pm, "q")
+    _need(c, dt, 1, "c")
+    _need(workspace, torch.uint8, 1, "workspace")
+    _need(z, dt, pm, "z")
+    _need(cost, dt, 1, "cost")
+    _need(info, torch.int32, 2, "info")
+    _check(lib().empc_qp_solve(_cprob(prob), _ptr(P), _ptr(q), _ptr(c), _ptr(workspace),
+                               workspace.numel(), int(max_iter), _ptr(z), _ptr(cost), _ptr(info),
+                               _stream(stream)))
+
+
+class ConvexSolver:
+    """Parameterized small-matrix convex MPC of one linear problem on the
+    GPU: form P, q, c at x0, then the box QP; owns the buffers."""
+
+    def __init__(self, dprob, max_iter=100):
+        self.dprob = dprob
+        dt, n, m, pm = _shape(dprob)
+        nbytes = empc_qp_workspace_bytes(dprob)
+        if nbytes == 0:
+            _check(EMPC_EUNSUPPORTED)
+        dev = dprob.device
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.P = torch.empty(pm, pm, dtype=dt, device=dev)
+        self.q = torch.empty(pm, dtype=dt, device=dev)
+        self.c = torch.empty(1, dtype=dt, device=dev)
+        self.z = torch.empty(pm, dtype=dt, device=dev)
+        self.cost = torch.empty(1, dtype=dt, device=dev)
+        self.info = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.max_iter = max_iter
+
+    def solve(self, x0, stream=None):
+        """(z [p*m], J(z) [1], info [iterations, converged]) device tensors;
+        u* = z[:m]."""
+        empc_qp_form(self.dprob, x0, self.workspace, self.P, self.q, self.c, stream)
+        empc_qp_solve(self.dprob, self.P, self.q, self.c, self.workspace, self.max_iter, self.z,
+                      self.cost, self.info, stream)
+        return self.z, self.cost, self.info

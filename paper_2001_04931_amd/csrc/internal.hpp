@@ -356,6 +356,15 @@ template <typename T>
 hipError_t launch_plant(const ProbView<T> &P, int model, const T *x, const T *u, const T *noise,
                         T *x_next, hipStream_t s);
 
+// Parameterized small-matrix convex MPC (convex.hip)
+size_t qp_workspace_bytes(int n, int T, int pm);
+template <typename T>
+hipError_t launch_qp_form(const ProbView<T> &P, const T *x0, void *ws, T *Pout, T *qout, T *cout,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_qp_solve(const ProbView<T> &P, const T *Pm, const T *q, const T *c, void *ws,
+                           int max_iter, T *z, T *cost, int *info, hipStream_t s);
+
 // N-link planar robot (nlink.hip): links per robot of this build
 constexpr int NLINK_MAX = 16;
 template <typename T>

@@ -122,6 +122,27 @@ def test_static_solve_validation(E):
     assert "static" in L.empc_last_error().decode()
 
 
+def test_qp_validation(E):
+    # the convex path takes linear problems without the box penalty, at most
+    # 1024 knot parameters, and checks its workspace and iteration limit
+    L = E.lib()
+    fake = ctypes.c_void_p(0x5000)
+    c = _problem(E)
+    nb = L.empc_qp_workspace_bytes(ctypes.byref(c))
+    assert nb >= 8 * (c.T * c.n * c.p * c.m + (c.p * c.m) ** 2)
+    info = ctypes.c_void_p(0x6000)
+    assert L.empc_qp_solve(ctypes.byref(c), fake, fake, fake, fake, nb, 0, fake, fake, info,
+                           None) == 1
+    assert L.empc_qp_solve(ctypes.byref(c), fake, fake, fake, fake, nb - 1, 10, fake, fake, info,
+                           None) == 4
+    assert L.empc_qp_form(ctypes.byref(c), fake, fake, nb, None, fake, fake, None) == 1
+    boxed = _problem(E, qb=fake, x_min=fake, x_max=fake)
+    assert L.empc_qp_workspace_bytes(ctypes.byref(boxed)) == 0
+    assert L.empc_qp_form(ctypes.byref(boxed), fake, fake, nb, fake, fake, fake, None) == 3
+    big = _problem(E, m=40, T=40, p=30)
+    assert L.empc_qp_workspace_bytes(ctypes.byref(big)) == 0
+
+
 def test_nlink_validation(E):
     # the N-link robot's calls check the robot and the step on the host
     L = E.lib()
