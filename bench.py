@@ -175,6 +175,7 @@ def other_workloads(E, W, names=WORKLOADS):
         out.update(refined_workload(E, W))
     if "c5" in names:
         out.update(batched_workload(E, W))
+        out.update(batched_workload(E, W, mode=1))
     if "c2v" in names:
         out.update(variants_workload(E, W))
     if "nlink" in names:
@@ -338,15 +339,17 @@ def refined_workload(E, W):
     return out
 
 
-def batched_workload(E, W):
-    """C5: 512 uneven problems, one tick per HIP-graph replay."""
+def batched_workload(E, W, mode=0, ticks=200):
+    """C5: 512 uneven problems, one tick per HIP-graph replay; mode 0 the
+    per-class launches (autotuned), 1 the persistent work-queue form."""
     import torch
 
     out = {}
     probs, ga = W.config_c5(512, 0)
     dps = [E.DeviceProblem(p.cast(np.float32), torch.float32) for p in probs]
     t_tune = time.perf_counter()
-    bs = E.BatchSolver(dps, ga)  # autotunes the launch shapes
+    bs = E.BatchSolver(dps, ga, autotune=mode == 0)  # autotunes the launch shapes
+    bs.set_mode(mode)
     t_tune = time.perf_counter() - t_tune
     for i, p in enumerate(probs):
         bs.set_x0(i, W.draw_x0(p.n, i))
@@ -356,7 +359,7 @@ def batched_workload(E, W):
         bs.solve()
     u_host = torch.empty(bs.u_star.numel(), dtype=torch.float32).pin_memory()
     done = torch.cuda.Event()
-    ticks, warm = 200, 10
+    warm = 10
     lats = []
     for t in range(warm + ticks):
         if t == warm:
@@ -371,7 +374,7 @@ def batched_workload(E, W):
             lats.append((time.perf_counter() - t0) * 1e3)
     wall = time.perf_counter() - t_start
     lats = np.array(lats)
-    out["c5_fp32_512_problems"] = summary(
+    out["c5_fp32_512_problems" + ("_persistent" if mode else "")] = summary(
         len(probs) * ga.pop * ga.generations * ticks / wall, lats, ticks=ticks, dtype="f32",
         problems=len(probs), within_2ms=float(np.mean(lats <= 2.0)),
         plan_and_autotune_s=round(t_tune, 3),

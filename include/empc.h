@@ -336,6 +336,22 @@ empc_status empc_batch_class_info(const empc_batch *plan, int32_t cls, int32_t *
 empc_status empc_batch_class_times(const empc_batch *plan, int32_t cls, float *us);
 empc_status empc_batch_set_variant(empc_batch *plan, int32_t cls, int32_t variant);
 
+/* Launch form of a batch plan's ticks.  Mode 0 (the default): per
+ * generation, one population launch, one rollout launch per class (on side
+ * streams), one selection launch over all problems, then a tick-advance
+ * launch.  Mode 1, the persistent work-queue form: per generation, one
+ * population launch and one persistent kernel per register tier (linear
+ * problems of more than 32 states; of 17..32 states; of at most 16 states;
+ * pendulum chains), whose one-wavefront workgroups
+ * take (problem, candidate tile) items from an atomic queue, the heaviest
+ * problems first; the wave that finishes a problem's last tile runs its
+ * selection, and the one that finishes the last selection advances the
+ * tick, so no wave ever waits for another.  Both forms give the same bits.
+ * Mode 1 takes populations of at most 1024 and problems without the state
+ * box penalty (else EMPC_EUNSUPPORTED); EMPC_EINVAL for a NULL plan or
+ * another mode. */
+empc_status empc_batch_set_mode(empc_batch *plan, int32_t mode);
+
 /* Kernel timing.  empc_profile_begin(max_launches) creates a pool of HIP
  * event pairs (host call, may allocate); until empc_profile_end, every
  * rollout launch made by empc_rollout_cost and empc_solve (at most

@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
             "empc_batch_class_times": ([_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)],
                                        ctypes.c_int),
             "empc_batch_set_variant": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+            "empc_batch_set_mode": ([_vp, ctypes.c_int32], ctypes.c_int),
             "empc_qp_workspace_bytes": ([P], sz),
             "empc_qp_form": ([P, _vp, _vp, sz, _vp, _vp, _vp, _vp], ctypes.c_int),
             "empc_qp_solve": ([P, _vp, _vp, _vp, _vp, sz, ctypes.c_int32, _vp, _vp, _vp, _vp],
@@ -120,6 +121,7 @@ def exported_symbols():
             "empc_batch_workspace_bytes", "empc_batch_create", "empc_solve_batched",
             "empc_batch_destroy", "empc_batch_autotune", "empc_batch_classes",
             "empc_batch_class_info", "empc_batch_class_times", "empc_batch_set_variant",
+            "empc_batch_set_mode",
             "empc_qp_workspace_bytes", "empc_qp_form", "empc_qp_solve",
             "empc_nlink_linearize", "empc_nlink_step", "empc_profile_begin",
             "empc_profile_end"]
@@ -502,6 +504,11 @@ class BatchSolver:
 
     def set_variant(self, cls, variant):
         empc_batch_set_variant(self.plan, cls, variant)
+
+    def set_mode(self, mode):
+        """0: a launch per kernel class (default); 1: the persistent
+        work-queue form (same results)."""
+        _check(lib().empc_batch_set_mode(self.plan, int(mode)))
 
     def set_x0(self, i, x):
         self.x0[int(self.x_off[i]):int(self.x_off[i + 1])] = torch.as_tensor(

@@ -28,7 +28,12 @@ __global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<
                                                         uint32_t seed_lo, int g,
                                                         const uint32_t *__restrict__ tick,
                                                         int shift, T sigma_min, T sigma_dist,
-                                                        int R) {
+                                                        int R, unsigned *__restrict__ counters,
+                                                        int ncounters) {
+    // the persistent form's work-queue heads and completion counters start
+    // every generation at zero (its kernels run after this one)
+    if (counters && blockIdx.x == 0)
+        for (int c = threadIdx.x; c < ncounters; c += blockDim.x) counters[c] = 0;
     const int2 e = popmap[blockIdx.x];  // (problem, tile within the problem)
     const BatchSlot<T> &S = slots[e.x];
     const ProbView<T> P = S.P;
@@ -112,6 +117,143 @@ __global__ __launch_bounds__(SEL_THREADS) void batch_select(const BatchSlot<T> *
 
 __global__ void batch_tick_advance(uint32_t *tick) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *tick += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form: per register tier one kernel of one-wavefront workgroups
+// that pull (problem, unit) items from a work queue (an atomic head); a unit
+// is a 16-candidate tile (linear, MFMA), 16 candidates in four passes of four
+// 16-lane rows (chains of more than 8 joints) or 64 candidates (chains of at
+// most 8 joints, one per lane).  The wave that completes the last unit of a
+// problem (an atomic count per problem) runs that problem's selection; the
+// wave that completes the last selection of a tick's last generation
+// advances the tick.  Nothing waits on anything: a wave only ever takes the
+// next item or finds the queue empty and exits, so the grid always drains.
+// The kernels of different tiers run concurrently on side streams; within a
+// tier every problem uses the same compiled code paths, so the register
+// allocation of a tier is that of its largest class, not of the whole batch.
+// Tiers: 0 linear of more than 32 states, 1 linear of 17..32, 2 linear of at
+// most 16, 3 pendulum chains.
+// Counters (reset by the population kernel): head[4], probs_done, done[nprob].
+constexpr int PTIERS = 4;
+enum { PC_LIN = 0, PC_LANE = 1, PC_ROW = 2 };
+
+struct PersistArgs {
+    const BatchSlot<float> *slots;
+    const int2 *items;       // (problem, unit), this tier's, heaviest first
+    const int *units;        // per problem: its number of units
+    const int *code;         // per problem: kind * 256 + shape (see pcode)
+    unsigned *head;          // this tier's queue head
+    unsigned *done;          // per problem: units completed
+    unsigned *probs_done;    // selections completed (all tiers)
+    uint32_t *tick;
+    int nitems, nprob, k, g, last;
+    int64_t pop;
+};
+
+__host__ __device__ inline int pcode(int kind, int a, int b) { return kind * 256 + a * 16 + b; }
+
+template <int NT, int NU>
+__device__ __forceinline__ void p_linear(const BatchSlot<float> &S, int64_t pop, int g, int unit) {
+    linear_tile<float, NT, NU, true, false>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost, unit);
+}
+template <int NT>
+__device__ __forceinline__ bool p_linear_nu(int nu, const BatchSlot<float> &S, int64_t pop, int g,
+                                            int unit) {
+    switch (nu) {
+        case 1: p_linear<NT, 1>(S, pop, g, unit); return true;
+        case 2: p_linear<NT, 2>(S, pop, g, unit); return true;
+        case 4: p_linear<NT, 4>(S, pop, g, unit); return true;
+        case 6: p_linear<NT, 6>(S, pop, g, unit); return true;
+        case 8: p_linear<NT, 8>(S, pop, g, unit); return true;
+        case 10: p_linear<NT, 10>(S, pop, g, unit); return true;
+    }
+    return false;
+}
+template <int J>
+__device__ __forceinline__ void p_rows(const BatchSlot<float> &S, int64_t pop, int g, int unit) {
+    const int lane = threadIdx.x & 63;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int64_t c0 = (int64_t)unit * 16 + pass * 4;
+        if (c0 >= pop) break;  // wave-uniform
+        chain_row_candidate<float, J, false>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
+                                             c0 + (lane >> 4), lane & 15);
+    }
+}
+template <int DMAX>
+__device__ __forceinline__ void p_lane(const BatchSlot<float> &S, JointConst<float> *jc,
+                                       int64_t pop, int g, int unit) {
+    __syncthreads();  // the previous item's readers of jc are done
+    chain_constants_lds(S.P, jc);
+    __syncthreads();
+    const int64_t cand = (int64_t)unit * 64 + (threadIdx.x & 63);
+    if (cand < pop) chain_candidate<float, DMAX, false>(S.P, jc, S.x0, S.knots[g & 1], pop, S.cost, cand);
+}
+
+template <int TIER>
+__device__ __forceinline__ void p_item(int code, const BatchSlot<float> &S, JointConst<float> *jc,
+                                       int64_t pop, int g, int unit) {
+    const int kind = code >> 8, a = (code >> 4) & 15, b = code & 15;
+    if constexpr (TIER == 0) {
+        if (a == 3) p_linear_nu<3>(b, S, pop, g, unit);
+        else if (a == 4) p_linear_nu<4>(b, S, pop, g, unit);
+        else p_linear_nu<5>(b, S, pop, g, unit);
+    } else if constexpr (TIER == 1) {
+        p_linear_nu<2>(b, S, pop, g, unit);
+    } else if constexpr (TIER == 2) {
+        p_linear_nu<1>(b, S, pop, g, unit);
+    } else {
+        if (kind == PC_LANE) {
+            if (a == 4) p_lane<4>(S, jc, pop, g, unit);
+            else p_lane<8>(S, jc, pop, g, unit);
+        } else {
+            if (a == 1) p_rows<1>(S, pop, g, unit);
+            else if (a == 2) p_rows<2>(S, pop, g, unit);
+            else p_rows<3>(S, pop, g, unit);
+        }
+    }
+}
+
+// waves per SIMD each tier's kernel is compiled for (bounds its registers):
+// the register need of the tier's largest class decides
+template <int TIER>
+constexpr int persist_waves() { return TIER == 0 ? 1 : (TIER == 3 ? 3 : 2); }
+
+template <int TIER>
+__global__ __launch_bounds__(64, persist_waves<TIER>()) void batch_persist(PersistArgs A) {
+    constexpr int CACHE = 16;  // keys per lane: populations of at most 1024
+    __shared__ JointConst<float> jc[8];
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned it = 0;
+        if (lane == 0) it = atomicAdd(A.head, 1u);
+        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
+        if (it >= (unsigned)A.nitems) break;
+        const int2 e = A.items[it];
+        const BatchSlot<float> &S = A.slots[e.x];
+        p_item<TIER>(A.code[e.x], S, jc, A.pop, A.g, e.y);
+        // publish this unit's costs, then count it; the wave that completes
+        // a problem sees every other unit's costs after its acquire fence
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        unsigned prev = 0;
+        if (lane == 0) prev = atomicAdd(&A.done[e.x], 1u);
+        prev = __builtin_amdgcn_readfirstlane(__shfl(prev, 0, 64));
+        if (prev + 1 != (unsigned)A.units[e.x]) continue;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        select_body<float, uint32_t, CACHE, 64, 1>(
+            S.cost, A.pop, A.k, S.knots[A.g & 1], A.pop, S.P.p * S.P.m, S.P.m, S.elite_idx,
+            S.best_idx, A.last ? S.elite_rows : nullptr, S.elite_cost, S.has_elites, nullptr,
+            A.last ? S.u_star : nullptr, A.last ? S.best_cost : nullptr);
+        if (A.last) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            unsigned pd = 0;
+            if (lane == 0) pd = atomicAdd(A.probs_done, 1u);
+            pd = __builtin_amdgcn_readfirstlane(__shfl(pd, 0, 64));
+            if (pd + 1 == (unsigned)A.nprob && lane == 0) *A.tick += 1;
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -282,6 +424,13 @@ struct empc_batch {
     hipStream_t side[BATCH_STREAMS] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[BATCH_STREAMS] = {};
+    // persistent form (mode 1)
+    int mode = 0;
+    bool persist_ok = false;       // every problem box-free
+    int2 *d_pitems = nullptr;      // all tiers' items, tier after tier
+    int *d_units = nullptr, *d_code = nullptr;
+    unsigned *d_counters = nullptr;  // head[3], probs_done, done[nprob]
+    int pfirst[PTIERS] = {}, pcount[PTIERS] = {}, pgrid[PTIERS] = {};
 };
 
 namespace {
@@ -318,6 +467,117 @@ hipError_t rollout_phase(empc_batch *b, int g, hipStream_t s) {
         if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[i], 0);
     }
     if (e == hipSuccess) e = hipGetLastError();
+    return e;
+}
+
+// One generation's rollouts and selections in the persistent form: the
+// tiers' kernels on side streams forked from s and joined back into it.
+hipError_t persist_phase(empc_batch *b, int g, int last, hipStream_t s) {
+    hipError_t e = hipEventRecord(b->fork, s);
+    int used = 0;
+    for (int t = 0; t < PTIERS && e == hipSuccess; ++t) {
+        if (!b->pcount[t]) continue;
+        hipStream_t st = b->side[used];
+        e = hipStreamWaitEvent(st, b->fork, 0);
+        if (e != hipSuccess) break;
+        PersistArgs A;
+        A.slots = b->d_slots;
+        A.items = b->d_pitems + b->pfirst[t];
+        A.units = b->d_units;
+        A.code = b->d_code;
+        A.head = b->d_counters + t;
+        A.probs_done = b->d_counters + PTIERS;
+        A.done = b->d_counters + PTIERS + 1;
+        A.tick = b->d_tick;
+        A.nitems = b->pcount[t];
+        A.nprob = b->nprob;
+        A.k = b->ga.n_elite;
+        A.g = g;
+        A.last = last;
+        A.pop = b->pop;
+        const dim3 grid(b->pgrid[t]), block(64);
+        void (*kern)(PersistArgs) =
+            t == 0 ? batch_persist<0>
+                   : (t == 1 ? batch_persist<1> : (t == 2 ? batch_persist<2> : batch_persist<3>));
+        hipLaunchKernelGGL(kern, grid, block, 0, st, A);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(b->join[used], st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[used], 0);
+        ++used;
+    }
+    return e;
+}
+
+// Work items of the persistent form: tier, kind and units of every problem,
+// items of a tier heaviest problem first; grids sized so that the tiers'
+// kernels share the chip in proportion to their work.
+hipError_t build_persistent(empc_batch *b, const empc_problem *probs) {
+    const int nprob = b->nprob;
+    const int64_t pop = b->pop;
+    std::vector<int> units(nprob), code(nprob), tier(nprob);
+    std::vector<double> wunit(nprob);
+    b->persist_ok = pop <= 1024;  // the one-wavefront selection caches 16 keys per lane
+    for (int i = 0; i < nprob; ++i) {
+        const empc_problem &P = probs[i];
+        if (P.qb) b->persist_ok = false;
+        if (P.model == EMPC_LINEAR) {
+            const int NT = (P.n + 15) / 16;
+            code[i] = pcode(PC_LIN, NT, nu_bucket(P.m));
+            tier[i] = NT >= 3 ? 0 : (NT == 2 ? 1 : 2);
+            units[i] = (int)((pop + 15) / 16);
+            wunit[i] = (double)P.T * NT * NT;
+        } else if (P.m <= 8) {
+            code[i] = pcode(PC_LANE, P.m <= 4 ? 4 : 8, 0);
+            tier[i] = 3;
+            units[i] = (int)((pop + 63) / 64);
+            wunit[i] = (double)P.T * P.m;
+        } else {
+            code[i] = pcode(PC_ROW, (P.m + 15) / 16, 0);
+            tier[i] = 3;
+            units[i] = (int)((pop + 15) / 16);
+            wunit[i] = (double)P.T * ((P.m + 15) / 16) * 4.0;
+        }
+    }
+    std::vector<int2> items;
+    double twork[PTIERS] = {0, 0, 0, 0}, total = 0;
+    for (int t = 0; t < PTIERS; ++t) {
+        std::vector<int> ps;
+        for (int i = 0; i < nprob; ++i)
+            if (tier[i] == t) ps.push_back(i);
+        std::stable_sort(ps.begin(), ps.end(), [&](int x, int y) { return wunit[x] > wunit[y]; });
+        b->pfirst[t] = (int)items.size();
+        for (int i : ps) {
+            for (int u = 0; u < units[i]; ++u) items.push_back(make_int2(i, u));
+            twork[t] += wunit[i] * units[i];
+        }
+        b->pcount[t] = (int)items.size() - b->pfirst[t];
+        total += twork[t];
+    }
+    int dev = 0, cus = 256;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int occ[PTIERS] = {1, 1, 1, 1};
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], batch_persist<0>, 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], batch_persist<1>, 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], batch_persist<2>, 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], batch_persist<3>, 64, 0);
+    if (e != hipSuccess) return e;
+    for (int t = 0; t < PTIERS; ++t) {
+        const double share = total > 0 ? twork[t] / total : 0.0;
+        int grid = (int)(share * cus * (occ[t] > 0 ? occ[t] : 1) + 0.5);
+        grid = std::max(grid, 64);
+        b->pgrid[t] = std::min(grid, std::max(b->pcount[t], 1));
+    }
+    const size_t ncounters = PTIERS + 1 + nprob;
+    e = hipMalloc(&b->d_pitems, sizeof(int2) * std::max<size_t>(items.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&b->d_units, sizeof(int) * nprob);
+    if (e == hipSuccess) e = hipMalloc(&b->d_code, sizeof(int) * nprob);
+    if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(unsigned) * ncounters);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(b->d_pitems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_units, units.data(), sizeof(int) * nprob, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_code, code.data(), sizeof(int) * nprob, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->d_counters, 0, sizeof(unsigned) * ncounters);
     return e;
 }
 
@@ -464,10 +724,15 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming);
     }
+    if (e == hipSuccess) e = build_persistent(b, probs);
     if (e != hipSuccess) {
         (void)hipFree(b->d_slots);
         (void)hipFree(b->d_items);
         (void)hipFree(b->d_popmap);
+        (void)hipFree(b->d_pitems);
+        (void)hipFree(b->d_units);
+        (void)hipFree(b->d_code);
+        (void)hipFree(b->d_counters);
         for (int i = 0; i < BATCH_STREAMS; ++i) {
             if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
             if (b->join[i]) (void)hipEventDestroy(b->join[i]);
@@ -487,12 +752,26 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
     const int64_t pop = b->pop;
     const uint32_t seed_lo = (uint32_t)G.seed;
     const int64_t per = (pop + SEL_THREADS - 1) / SEL_THREADS;
+    if (b->mode == 1) {
+        const int ncounters = PTIERS + 1 + b->nprob;
+        for (int g = 0; g < G.generations; ++g) {
+            const int last = g == G.generations - 1;
+            hipLaunchKernelGGL(batch_population<float>, dim3((unsigned)b->pop_wgs),
+                               dim3(POP_THREADS), 0, s, b->d_slots, b->d_popmap, pop, G.n_elite,
+                               G.elitism, (float)G.sigma, seed_lo, g, (const uint32_t *)b->d_tick,
+                               G.shift, (float)G.sigma_min, (float)G.sigma_dist, b->pop_r,
+                               b->d_counters, ncounters);
+            const hipError_t fe = persist_phase(b, g, last, s);
+            if (fe != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(fe));
+        }
+        return EMPC_OK;
+    }
     for (int g = 0; g < G.generations; ++g) {
         const int last = g == G.generations - 1;
         hipLaunchKernelGGL(batch_population<float>, dim3((unsigned)b->pop_wgs), dim3(POP_THREADS), 0,
                            s, b->d_slots, b->d_popmap, pop, G.n_elite, G.elitism, (float)G.sigma,
                            seed_lo, g, (const uint32_t *)b->d_tick, G.shift, (float)G.sigma_min,
-                           (float)G.sigma_dist, b->pop_r);
+                           (float)G.sigma_dist, b->pop_r, (unsigned *)nullptr, 0);
         const hipError_t fe = rollout_phase(b, g, s);
         if (fe != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(fe));
         if (per <= 4)
@@ -522,7 +801,7 @@ empc_status empc_batch_autotune(empc_batch *b, int32_t reps, void *stream) {
     hipLaunchKernelGGL(batch_population<float>, dim3((unsigned)b->pop_wgs), dim3(POP_THREADS), 0, s,
                        b->d_slots, b->d_popmap, b->pop, G.n_elite, G.elitism,
                        (float)G.sigma, (uint32_t)G.seed, 0, (const uint32_t *)b->d_tick, G.shift,
-                       (float)G.sigma_min, (float)G.sigma_dist, b->pop_r);
+                       (float)G.sigma_min, (float)G.sigma_dist, b->pop_r, (unsigned *)nullptr, 0);
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventCreate(&t0);
@@ -621,7 +900,22 @@ empc_status empc_batch_destroy(empc_batch *b) {
     (void)hipFree(b->d_slots);
     (void)hipFree(b->d_items);
     (void)hipFree(b->d_popmap);
+    (void)hipFree(b->d_pitems);
+    (void)hipFree(b->d_units);
+    (void)hipFree(b->d_code);
+    (void)hipFree(b->d_counters);
     delete b;
+    return EMPC_OK;
+}
+
+empc_status empc_batch_set_mode(empc_batch *b, int32_t mode) {
+    if (!b) return empc_fail_internal(EMPC_EINVAL, "batch is NULL");
+    if (mode != 0 && mode != 1) return empc_fail_internal(EMPC_EINVAL, "mode must be 0 or 1");
+    if (mode == 1 && !b->persist_ok)
+        return empc_fail_internal(EMPC_EUNSUPPORTED,
+                                  "the persistent form takes populations of at most 1024 and "
+                                  "problems without the state box penalty");
+    b->mode = mode;
     return EMPC_OK;
 }
 

@@ -305,13 +305,15 @@ __device__ inline double key_value(uint64_t k) {
         (long long)((k & 0x8000000000000000ull) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k));
 }
 
-template <typename T, typename K, int CACHE, int NTHR = SEL_THREADS>
+// NREP: histogram replicas (a power of two <= 16); a one-wavefront selection
+// inside the persistent batched kernel takes 1 to keep its LDS small.
+template <typename T, typename K, int CACHE, int NTHR = SEL_THREADS, int NREP = HREP>
 __device__ __forceinline__ void select_body(
     const T *__restrict__ cost, int64_t pop, int k, const T *__restrict__ knots, int64_t ld,
     int pm, int m, int64_t *__restrict__ elite_idx_out, int64_t *__restrict__ best_idx_out,
     T *__restrict__ elite_rows, T *__restrict__ elite_cost, int *__restrict__ has_elites,
     int *__restrict__ best_slot_out, T *__restrict__ u_star, T *__restrict__ best_cost) {
-    __shared__ int hist[2][HREP * HSTRIDE];
+    __shared__ int hist[2][NREP * HSTRIDE];
     __shared__ int tot[256];
     __shared__ int wsum[(NTHR / 64)];
     __shared__ K s_lo[(NTHR / 64)], s_hi[(NTHR / 64)];
@@ -320,7 +322,7 @@ __device__ __forceinline__ void select_body(
     __shared__ int s_best_slot;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int b = tid; b < HREP * HSTRIDE; b += NTHR) hist[0][b] = 0;
+    for (int b = tid; b < NREP * HSTRIDE; b += NTHR) hist[0][b] = 0;
 
     const int64_t per = (pop + NTHR - 1) / NTHR;
     const int64_t i0 = (int64_t)tid * per;
@@ -385,18 +387,18 @@ __device__ __forceinline__ void select_body(
     int remaining = k;
     int buf = 0;
     for (int shift = top; shift >= 0; shift -= 8) {
-        int *myh = hist[buf] + (lane & (HREP - 1)) * HSTRIDE;
+        int *myh = hist[buf] + (lane & (NREP - 1)) * HSTRIDE;
         for_each_key([&](int64_t, K key) {
             if ((key & mask) == prefix) atomicAdd(&myh[(int)((key >> shift) & 255)], 1);
         });
         // clear the other buffer for the next pass
-        for (int b = tid; b < HREP * HSTRIDE; b += NTHR) hist[buf ^ 1][b] = 0;
+        for (int b = tid; b < NREP * HSTRIDE; b += NTHR) hist[buf ^ 1][b] = 0;
         __syncthreads();
-        if (tid < 256) {  // one bin per thread
+        for (int bin = tid; bin < 256; bin += NTHR) {  // one bin per thread
             int sum = 0;
 #pragma unroll
-            for (int rep = 0; rep < HREP; ++rep) sum += hist[buf][rep * HSTRIDE + tid];
-            tot[tid] = sum;
+            for (int rep = 0; rep < NREP; ++rep) sum += hist[buf][rep * HSTRIDE + bin];
+            tot[bin] = sum;
         }
         __syncthreads();
         // every wavefront finds the digit itself: lane owns bins 4 lane .. +3

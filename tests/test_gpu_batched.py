@@ -250,14 +250,17 @@ def test_population_grouping_keeps_the_bits(E):
     bs.close()
 
 
-def test_c5_plan_sampled_against_single_solves(E):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_c5_plan_sampled_against_single_solves(E, mode):
     """The full batching configuration (512 problems, population 1024,
-    autotuned launch shapes, one HIP-graph replay per tick): 16 sampled
-    problems equal their single-problem solves bit for bit over two ticks."""
+    autotuned launch shapes or the persistent form, one HIP-graph replay per
+    tick): 16 sampled problems equal their single-problem solves bit for bit
+    over two ticks."""
     probs, ga = W.config_c5(512, 0)
     probs = [p.cast(np.float32) for p in probs]
     dps = [E.DeviceProblem(p, F32) for p in probs]
-    bs = E.BatchSolver(dps, ga)
+    bs = E.BatchSolver(dps, ga, autotune=mode == 0)
+    bs.set_mode(mode)
     x0s = [W.draw_x0(p.n, i).astype(np.float32) for i, p in enumerate(probs)]
     for i, x in enumerate(x0s):
         bs.set_x0(i, x)
@@ -276,4 +279,79 @@ def test_c5_plan_sampled_against_single_solves(E):
             torch.cuda.synchronize()
             assert torch.equal(bs.u_of(i), u), (tick, i)
             assert torch.equal(bs.best_cost[i:i + 1], J), (tick, i)
+    bs.close()
+
+
+def test_persistent_form_equals_class_launches(E):
+    """The persistent work-queue form (one kernel per register tier, the last
+    tile of a problem selecting for it) gives the bits of the per-class
+    launches, tick after tick, for every kernel class, ragged populations
+    (units of 16 and 64 candidates with tails) and two generations per
+    tick."""
+    probs = mixed_problems(3)
+    for pop in (256, 200):
+        ga = W.GA(pop=pop, n_elite=16, generations=2, sigma=0.1, seed=77)
+        dps = [E.DeviceProblem(p, F32) for p in probs]
+        a = E.BatchSolver(dps, ga)
+        b = E.BatchSolver(dps, ga, autotune=False)
+        b.set_mode(1)
+        x0s = [W.draw_x0(p.n, 40 + i).astype(np.float32) for i, p in enumerate(probs)]
+        ra = _run_ticks(a, x0s, 3)
+        rb = _run_ticks(b, x0s, 3)
+        for t, ((ua, ja), (ub, jb)) in enumerate(zip(ra, rb)):
+            assert torch.equal(ua, ub), (pop, t)
+            assert torch.equal(ja, jb), (pop, t)
+        a.close()
+        b.close()
+
+
+def test_persistent_form_graph_replay(E):
+    """A HIP graph of the persistent form's tick (its counters are cleared by
+    the population kernel, the tick advanced by the last selection) replays
+    tick after tick like eager ticks of the per-class form."""
+    probs = mixed_problems(4)
+    ga = W.GA(pop=128, n_elite=8, generations=1, sigma=0.1, seed=21)
+    dps = [E.DeviceProblem(p, F32) for p in probs]
+    eager = E.BatchSolver(dps, ga, autotune=False)
+    graphed = E.BatchSolver(dps, ga, autotune=False)
+    graphed.set_mode(1)
+    for i, p in enumerate(probs):
+        x = W.draw_x0(p.n, i)
+        eager.set_x0(i, x)
+        graphed.set_x0(i, x)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        graphed.solve()
+    for tick in range(4):
+        eager.solve()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(eager.u_star, graphed.u_star), tick
+        assert torch.equal(eager.best_cost, graphed.best_cost), tick
+        _ = eager.u_star.cpu()
+    eager.close()
+    graphed.close()
+
+
+def test_persistent_form_limits(E):
+    # the box penalty and populations above 1024 stay on the per-class form
+    probs = mixed_problems(5)[:3]
+    ga = W.GA(pop=64, n_elite=8, generations=1, sigma=0.1, seed=1)
+    boxed = probs[0]
+    boxed = W.dataclasses.replace(boxed, x_min=np.full(boxed.n, -1.0), x_max=np.full(boxed.n, 1.0),
+                                  qb=np.ones(boxed.n))
+    bs = E.BatchSolver([E.DeviceProblem(p, F32) for p in [boxed] + probs[1:]], ga,
+                       autotune=False)
+    with pytest.raises(E.EmpcError) as ei:
+        bs.set_mode(1)
+    assert ei.value.status == E.binding.EMPC_EUNSUPPORTED
+    bs.close()
+    big = W.dataclasses.replace(ga, pop=2048)
+    bs = E.BatchSolver([E.DeviceProblem(p, F32) for p in probs], big, autotune=False)
+    with pytest.raises(E.EmpcError):
+        bs.set_mode(1)
+    with pytest.raises(E.EmpcError):
+        bs.set_mode(2)
     bs.close()
