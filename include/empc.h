@@ -196,6 +196,39 @@ empc_status empc_solve_static(const empc_problem *prob, const empc_ga *ga, const
                               uint32_t tick, int32_t cold, void *u_star, void *best_cost,
                               void *stream);
 
+/* Autotuner of the single-problem path.  empc_autotune times, on a
+ * cold-start population of (prob, ga), every rollout launch shape of the
+ * problem's kernel family (linear: one wavefront per 16-candidate tile with
+ * 1, 2 or 4 per workgroup, the M-split form for more than 16 states, and,
+ * if allow_valu, the vector-ALU form with one lane per candidate for n, m <=
+ * 16; pendulum chain: three workgroup sizes) and the population kernel's
+ * 16, 32 or 64 parameters per workgroup, then records the fastest in a
+ * process-wide tuning table keyed by the problem's shape (model, dtype, n,
+ * m, T, p, which optional terms are present) and the population.  Later
+ * empc_solve, empc_solve_refined, empc_solve_static and empc_rollout_cost
+ * calls of that shape (rollout_cost: with ncand equal to the population)
+ * use the recorded choice; other shapes keep the fixed rules.  The
+ * matrix-core shapes and the population choices give the same bits as the
+ * rules; the vector-ALU form sums the cost in another order, so its costs
+ * differ by rounding (within the FP32 / FP64 parity tolerances), which is
+ * why it is only tried with allow_valu.  info (host, float[5], may be NULL):
+ * the chosen rollout form (RolloutForm codes: 1..3 one wavefront per tile
+ * with 1/2/4 per workgroup, 4 M-split, 5/6 vector-ALU in workgroups of
+ * 256/64, 11..13 chain workgroups of 64/128/256), the chosen parameter
+ * groups, its mean rollout time and the fixed rule's (us), and the chosen
+ * population time (us).  A host call that allocates scratch buffers,
+ * launches on `stream` and blocks until the timing is done.
+ * empc_autotune_set records a choice by hand (form one of the codes above
+ * or 0 for the fixed rule; groups 1, 2, 4 or 0 for the rule): EMPC_EINVAL
+ * for a code the model does not have, EMPC_EUNSUPPORTED for the vector-ALU
+ * form above 16 states or inputs or the M-split form at 16 states or less.
+ * empc_autotune_reset clears the table. */
+empc_status empc_autotune(const empc_problem *prob, const empc_ga *ga, int32_t reps,
+                          int32_t allow_valu, float *info, void *stream);
+empc_status empc_autotune_set(const empc_problem *prob, const empc_ga *ga, int32_t form,
+                              int32_t groups);
+empc_status empc_autotune_reset(void);
+
 /* Gradient of the rollout cost with respect to the knots by a hand-written
  * adjoint pass (states recomputed from checkpoints every ceil(sqrt(T))
  * steps).  dJ: [p*m][ld].  cost: ncand (may be NULL). */

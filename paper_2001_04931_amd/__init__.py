@@ -4,7 +4,8 @@ The compute lives in libempc.so (hand-written HIP kernels behind the C ABI of
 include/empc.h); `binding` marshals torch GPU tensors into it.
 """
 from .binding import (BatchSolver, ConvexSolver, DeviceProblem, EmpcCost, EmpcError, EmpcGA, EmpcProblem,  # noqa: F401
-                      NLinkRobot, Solver, empc_generation, empc_grad, empc_nlink_linearize,
+                      NLinkRobot, Solver, empc_autotune, empc_autotune_reset,
+                      empc_autotune_set, empc_generation, empc_grad, empc_nlink_linearize,
                       empc_nlink_step, empc_plant_step, empc_profile_begin,
                       empc_profile_end, empc_refine,
                       empc_rollout_cost, empc_solve, empc_solve_static, empc_workspace_bytes, lib,

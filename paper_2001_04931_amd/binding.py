@@ -77,6 +77,10 @@ def lib() -> ctypes.CDLL:
             "empc_solve_refined": ([P, G, _vp, sz, _vp, u32, ctypes.c_double, ctypes.c_int32, _vp,
                                     _vp, _vp], ctypes.c_int),
             "empc_solve_static": ([P, G, _vp, u32, ctypes.c_int32, _vp, _vp, _vp], ctypes.c_int),
+            "empc_autotune": ([P, G, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_float), _vp], ctypes.c_int),
+            "empc_autotune_set": ([P, G, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+            "empc_autotune_reset": ([], ctypes.c_int),
             "empc_grad": ([P, _vp, _vp, i64, i64, _vp, _vp, _vp], ctypes.c_int),
             "empc_refine": ([P, _vp, _vp, i64, i64, _vp, ctypes.c_double, ctypes.c_int32, _vp],
                             ctypes.c_int),
@@ -117,6 +121,7 @@ def lib() -> ctypes.CDLL:
 def exported_symbols():
     return ["empc_status_str", "empc_last_error", "empc_rollout_cost", "empc_generation",
             "empc_workspace_bytes", "empc_solve", "empc_solve_refined", "empc_solve_static",
+            "empc_autotune", "empc_autotune_set", "empc_autotune_reset",
             "empc_grad", "empc_refine", "empc_plant_step",
             "empc_batch_workspace_bytes", "empc_batch_create", "empc_solve_batched",
             "empc_batch_destroy", "empc_batch_autotune", "empc_batch_classes",
@@ -240,6 +245,29 @@ def empc_solve_refined(prob, ga, workspace, x0, tick, lr, adam_steps, u_star, be
     _check(lib().empc_solve_refined(_cprob(prob), _cga(ga), _ptr(workspace), workspace.numel(),
                                     _ptr(x0), int(tick), float(lr), int(adam_steps), _ptr(u_star),
                                     _ptr(best_cost), _stream(stream)))
+
+
+def empc_autotune(prob, ga, reps=5, allow_valu=True, stream=None):
+    """Tune the single-problem launch shapes of (prob, ga); returns a dict of
+    the choice and its measured times (microseconds)."""
+    info = (ctypes.c_float * 5)()
+    _check(lib().empc_autotune(_cprob(prob), _cga(ga), int(reps), 1 if allow_valu else 0, info,
+                               _stream(stream)))
+    return {"rollout_form": int(info[0]), "pop_groups": int(info[1]), "rollout_us": info[2],
+            "rule_rollout_us": info[3], "population_us": info[4]}
+
+
+def empc_autotune_set(prob, ga, form, groups=0):
+    _check(lib().empc_autotune_set(_cprob(prob), _cga(ga), int(form), int(groups)))
+
+
+def empc_autotune_reset():
+    _check(lib().empc_autotune_reset())
+
+
+# rollout form codes of empc_autotune / empc_autotune_set
+RF_RULE, RF_ONE1, RF_ONE2, RF_ONE4, RF_SPLIT, RF_VALU256, RF_VALU64 = 0, 1, 2, 3, 4, 5, 6
+RF_CH64, RF_CH128, RF_CH256 = 11, 12, 13
 
 
 def empc_solve_static(prob, ga, x0, tick, cold, u_star, best_cost, stream=None):

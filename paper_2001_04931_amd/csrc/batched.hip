@@ -2,9 +2,10 @@
 // sizes advance one control tick together.  Per generation: one population
 // launch over all problems, one rollout launch per kernel shape class (the
 // problems whose state and input counts select the same register tiling),
-// one selection launch over all problems; then one tiny launch advances the
-// device tick counter, so the same launch sequence, captured once as a HIP
-// graph, replays tick after tick.
+// on up to four side streams, one selection launch over all problems; then
+// one tiny launch advances the device tick counter, so the same launch
+// sequence, captured once as a HIP graph, replays tick after tick.  A
+// persistent work-queue form is below as well.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -105,10 +106,12 @@ __global__ __launch_bounds__(64 * WPB) void batch_roll_chain_rows(const BatchSlo
                               cand0 + (threadIdx.x >> 4), threadIdx.x & 15);
 }
 
+// one workgroup per problem: problem items[blockIdx.x] (items NULL: blockIdx.x)
 template <typename T, typename K, int CACHE>
 __global__ __launch_bounds__(SEL_THREADS) void batch_select(const BatchSlot<T> *__restrict__ slots,
+                                                            const int *__restrict__ items,
                                                             int64_t pop, int k, int g, int last) {
-    const BatchSlot<T> &S = slots[blockIdx.x];
+    const BatchSlot<T> &S = slots[items ? items[blockIdx.x] : (int)blockIdx.x];
     select_body<T, K, CACHE, SEL_THREADS>(S.cost, pop, k, S.knots[g & 1], pop, S.P.p * S.P.m, S.P.m,
                              S.elite_idx, S.best_idx, last ? S.elite_rows : nullptr, S.elite_cost,
                              S.has_elites, nullptr, last ? S.u_star : nullptr,
@@ -470,6 +473,22 @@ hipError_t rollout_phase(empc_batch *b, int g, hipStream_t s) {
     return e;
 }
 
+// selection launch over `count` problems (items NULL: problems 0..count-1)
+void launch_batch_select(const empc_batch *b, const int *items, int count, int g, int last,
+                         hipStream_t st) {
+    const int64_t pop = b->pop, per = (pop + SEL_THREADS - 1) / SEL_THREADS;
+    const int k = b->ga.n_elite;
+    if (per <= 4)
+        hipLaunchKernelGGL((batch_select<float, uint32_t, 4>), dim3(count), dim3(SEL_THREADS), 0, st,
+                           b->d_slots, items, pop, k, g, last);
+    else if (per <= 16)
+        hipLaunchKernelGGL((batch_select<float, uint32_t, 16>), dim3(count), dim3(SEL_THREADS), 0,
+                           st, b->d_slots, items, pop, k, g, last);
+    else
+        hipLaunchKernelGGL((batch_select<float, uint32_t, 0>), dim3(count), dim3(SEL_THREADS), 0, st,
+                           b->d_slots, items, pop, k, g, last);
+}
+
 // One generation's rollouts and selections in the persistent form: the
 // tiers' kernels on side streams forked from s and joined back into it.
 hipError_t persist_phase(empc_batch *b, int g, int last, hipStream_t s) {
@@ -671,12 +690,6 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         delete b;
         return empc_fail_internal(EMPC_EUNSUPPORTED, "batch population grid above 2^31 workgroups");
     }
-    std::vector<int2> popmap;
-    popmap.reserve((size_t)total_wgs);
-    for (int i = 0; i < nprob; ++i) {
-        const int64_t wgs = pop_tiles_s(ga->pop) * pop_tiles_g(probs[i].p * probs[i].m, b->pop_r);
-        for (int64_t t = 0; t < wgs; ++t) popmap.push_back(make_int2(i, (int)t));
-    }
     b->pop_wgs = total_wgs;
     // group problems by kernel shape class
     std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
@@ -707,6 +720,12 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
                      ((ga->pop + 15) / 16) * c.count < SPLIT_MAX_TILES) ? 3 : 0;
         items.insert(items.end(), kv.second.begin(), kv.second.end());
         b->classes.push_back(c);
+    }
+    std::vector<int2> popmap;
+    popmap.reserve((size_t)total_wgs);
+    for (int i = 0; i < nprob; ++i) {
+        const int64_t wgs = pop_tiles_s(ga->pop) * pop_tiles_g(probs[i].p * probs[i].m, b->pop_r);
+        for (int64_t t = 0; t < wgs; ++t) popmap.push_back(make_int2(i, (int)t));
     }
     assign_streams(b, BATCH_STREAMS);
     b->d_tick = (uint32_t *)base;
@@ -751,7 +770,6 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
     const empc_ga &G = b->ga;
     const int64_t pop = b->pop;
     const uint32_t seed_lo = (uint32_t)G.seed;
-    const int64_t per = (pop + SEL_THREADS - 1) / SEL_THREADS;
     if (b->mode == 1) {
         const int ncounters = PTIERS + 1 + b->nprob;
         for (int g = 0; g < G.generations; ++g) {
@@ -767,22 +785,13 @@ empc_status empc_solve_batched(empc_batch *b, void *stream) {
         return EMPC_OK;
     }
     for (int g = 0; g < G.generations; ++g) {
-        const int last = g == G.generations - 1;
         hipLaunchKernelGGL(batch_population<float>, dim3((unsigned)b->pop_wgs), dim3(POP_THREADS), 0,
                            s, b->d_slots, b->d_popmap, pop, G.n_elite, G.elitism, (float)G.sigma,
                            seed_lo, g, (const uint32_t *)b->d_tick, G.shift, (float)G.sigma_min,
                            (float)G.sigma_dist, b->pop_r, (unsigned *)nullptr, 0);
         const hipError_t fe = rollout_phase(b, g, s);
         if (fe != hipSuccess) return empc_fail_internal(EMPC_EDEVICE, hipGetErrorString(fe));
-        if (per <= 4)
-            hipLaunchKernelGGL((batch_select<float, uint32_t, 4>), dim3(b->nprob), dim3(SEL_THREADS), 0,
-                               s, b->d_slots, pop, G.n_elite, g, last);
-        else if (per <= 16)
-            hipLaunchKernelGGL((batch_select<float, uint32_t, 16>), dim3(b->nprob), dim3(SEL_THREADS), 0,
-                               s, b->d_slots, pop, G.n_elite, g, last);
-        else
-            hipLaunchKernelGGL((batch_select<float, uint32_t, 0>), dim3(b->nprob), dim3(SEL_THREADS), 0,
-                               s, b->d_slots, pop, G.n_elite, g, last);
+        launch_batch_select(b, nullptr, b->nprob, g, g == G.generations - 1, s);
     }
     hipLaunchKernelGGL(batch_tick_advance, dim3(1), dim3(64), 0, s, b->d_tick);
     hipError_t e = hipGetLastError();

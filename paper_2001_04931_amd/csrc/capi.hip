@@ -4,7 +4,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "internal.hpp"
@@ -147,10 +149,32 @@ Events next_events() {
     return ev;
 }
 
+// Tuning table of the single-problem path (empc_autotune): per problem
+// shape and candidate count, the rollout form and the population's
+// parameter groups per workgroup.  Shapes not in the table use the fixed
+// rules.  Every lookup and update holds the mutex.
+typedef std::tuple<int, int, int, int, int, int, int64_t, int, int, int> TuneKey;
+struct Tuned {
+    int form = RF_RULE;
+    int R = 0;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuned> g_tune;
+
+TuneKey tune_key(const empc_problem *P, int64_t ncand) {
+    return TuneKey(P->model, P->dtype, P->n, P->m, P->T, P->p, ncand, P->qb ? 1 : 0,
+                   P->x_goal ? 1 : 0, P->wd ? 1 : 0);
+}
+Tuned tuned_for(const empc_problem *P, int64_t ncand) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(tune_key(P, ncand));
+    return it == g_tune.end() ? Tuned() : it->second;
+}
+
 template <typename T>
 hipError_t timed_rollout(const ProbView<T> &V, int model, const T *x0, const T *knots,
-                         int64_t ncand, int64_t ld, T *cost, hipStream_t s) {
-    return launch_rollout<T>(V, model, x0, knots, ncand, ld, cost, s, next_events());
+                         int64_t ncand, int64_t ld, T *cost, hipStream_t s, int form = RF_RULE) {
+    return launch_rollout<T>(V, model, x0, knots, ncand, ld, cost, s, next_events(), form);
 }
 
 // Gradient refinement of the parents after a selection: gather them, run
@@ -178,6 +202,7 @@ empc_status solve_t(const empc_problem *P, const empc_ga *G, const Workspace &w,
     const ProbView<T> V = view_of<T>(*P);
     const int64_t pop = G->pop;
     const bool refine = adam_steps > 0;
+    const Tuned tu = tuned_for(P, pop);
     for (int g = 0; g < G->generations; ++g) {
         const bool last = g == G->generations - 1;
         T *cur = (T *)w.knots[g & 1];
@@ -191,11 +216,12 @@ empc_status solve_t(const empc_problem *P, const empc_ga *G, const Workspace &w,
                            ? launch_population<T>(V, *G, nullptr, 0, nullptr,
                                                   (const T *)w.elite_rows, w.has_elites,
                                                   g == 0 ? 2 : 0, cur, pop, tick, (uint32_t)g, s,
-                                                  var)
+                                                  var, tu.R)
                            : launch_population<T>(V, *G, prev, pop, w.elite_idx, nullptr,
-                                                  nullptr, 0, cur, pop, tick, (uint32_t)g, s, var);
+                                                  nullptr, 0, cur, pop, tick, (uint32_t)g, s, var,
+                                                  tu.R);
         if (e != hipSuccess) return device_status(e, "population launch");
-        e = timed_rollout<T>(V, P->model, (const T *)x0, cur, pop, pop, (T *)w.cost, s);
+        e = timed_rollout<T>(V, P->model, (const T *)x0, cur, pop, pop, (T *)w.cost, s, tu.form);
         if (e != hipSuccess) return device_status(e, "rollout launch");
         e = launch_select<T>(V, (const T *)w.cost, cur, pop, pop, G->n_elite, w.elite_idx,
                              w.best_idx, (last && !refine) ? (T *)w.elite_rows : nullptr,
@@ -207,6 +233,115 @@ empc_status solve_t(const empc_problem *P, const empc_ga *G, const Workspace &w,
             e = refine_parents<T>(P, G, w, x0, cur, lr, adam_steps, last, u_star, best_cost, s);
             if (e != hipSuccess) return device_status(e, "refine launch");
         }
+    }
+    return EMPC_OK;
+}
+
+// Mean launch time (us) of `enqueue` over reps launches after one untimed.
+template <typename F>
+hipError_t time_us(F &&enqueue, int reps, hipStream_t s, hipEvent_t t0, hipEvent_t t1, float *us) {
+    hipError_t e = enqueue();
+    if (e == hipSuccess) e = hipEventRecord(t0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = enqueue();
+    if (e == hipSuccess) e = hipEventRecord(t1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    *us = ms * 1e3f / (float)reps;
+    return e;
+}
+
+// The single-problem autotuner: time every rollout form of the shape on a
+// cold-start population, then the population kernel's parameter groups per
+// workgroup, and record the fastest in the tuning table.
+template <typename T>
+empc_status autotune_t(const empc_problem *P, const empc_ga *G, int reps, int allow_valu,
+                       float *info, hipStream_t s) {
+    const ProbView<T> V = view_of<T>(*P);
+    const int64_t pop = G->pop;
+    const int pm = P->p * P->m, k = G->n_elite;
+    T *knots = nullptr, *knots2 = nullptr, *cost = nullptr, *x0 = nullptr;
+    int64_t *eidx = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipMalloc(&knots, sizeof(T) * pm * pop);
+    if (e == hipSuccess) e = hipMalloc(&knots2, sizeof(T) * pm * pop);
+    if (e == hipSuccess) e = hipMalloc(&cost, sizeof(T) * pop);
+    if (e == hipSuccess) e = hipMalloc(&x0, sizeof(T) * P->n);
+    if (e == hipSuccess) e = hipMalloc(&eidx, sizeof(int64_t) * k);
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e == hipSuccess) e = hipMemsetAsync(x0, 0, sizeof(T) * P->n, s);
+    if (e == hipSuccess) {
+        std::vector<int64_t> idx(k);
+        for (int i = 0; i < k; ++i) idx[i] = (int64_t)i * (pop / k);
+        e = hipMemcpyAsync(eidx, idx.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (e == hipSuccess)
+        e = launch_population<T>(V, *G, nullptr, 0, nullptr, nullptr, nullptr, 1, knots, pop, 0, 0, s);
+    std::vector<int> forms;
+    if (P->model == EMPC_LINEAR) {
+        forms = {RF_ONE1, RF_ONE2, RF_ONE4};
+        if (P->n > 16) forms.push_back(RF_SPLIT);
+        if (allow_valu && P->n <= 16 && P->m <= 16) {
+            forms.push_back(RF_VALU256);
+            forms.push_back(RF_VALU64);
+        }
+    } else {
+        forms = {RF_CH64, RF_CH128, RF_CH256};
+    }
+    float rule_us = 0.f, best_us = 0.f;
+    int best_form = RF_RULE;
+    auto rollout = [&](int form) {
+        return launch_rollout<T>(V, P->model, x0, knots, pop, pop, cost, s, Events(), form);
+    };
+    if (e == hipSuccess) e = time_us([&]() { return rollout(RF_RULE); }, reps, s, t0, t1, &rule_us);
+    best_us = rule_us;
+    for (int f : forms) {
+        if (e != hipSuccess) break;
+        float us = 0.f;
+        e = time_us([&]() { return rollout(f); }, reps, s, t0, t1, &us);
+        if (e == hipSuccess && us < best_us) {
+            best_us = us;
+            best_form = f;
+        }
+    }
+    // population: parameter groups per workgroup (the same bits for each)
+    float pop_best = 0.f;
+    int best_R = 0;
+    for (int R : {1, 2, 4}) {
+        if (e != hipSuccess) break;
+        float us = 0.f;
+        e = time_us([&]() {
+                return launch_population<T>(V, *G, knots, pop, eidx, nullptr, nullptr, 0, knots2,
+                                            pop, 1, 1, s, PopVariant<T>(), R);
+            }, reps, s, t0, t1, &us);
+        if (e == hipSuccess && (best_R == 0 || us < pop_best)) {
+            pop_best = us;
+            best_R = R;
+        }
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    (void)hipFree(knots);
+    (void)hipFree(knots2);
+    (void)hipFree(cost);
+    (void)hipFree(x0);
+    (void)hipFree(eidx);
+    if (e != hipSuccess) return device_status(e, "autotune");
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        Tuned t;
+        t.form = best_form;
+        t.R = best_R;
+        g_tune[tune_key(P, pop)] = t;
+    }
+    if (info) {
+        info[0] = (float)best_form;
+        info[1] = (float)best_R;
+        info[2] = best_us;
+        info[3] = rule_us;
+        info[4] = pop_best;
     }
     return EMPC_OK;
 }
@@ -275,12 +410,14 @@ empc_status empc_rollout_cost(const empc_problem *prob, const void *x0, const vo
     if (!x0 || !knots || !cost) return fail(EMPC_EINVAL, "x0, knots and cost are required");
     if ((st = check_prior())) return st;
     hipStream_t s = (hipStream_t)stream;
+    const int form = tuned_for(prob, ncand).form;
     hipError_t e = prob->dtype == EMPC_F32
                        ? timed_rollout<float>(view_of<float>(*prob), prob->model, (const float *)x0,
-                                              (const float *)knots, ncand, ld, (float *)cost, s)
+                                              (const float *)knots, ncand, ld, (float *)cost, s,
+                                              form)
                        : timed_rollout<double>(view_of<double>(*prob), prob->model,
                                                 (const double *)x0, (const double *)knots, ncand, ld,
-                                                (double *)cost, s);
+                                                (double *)cost, s, form);
     return device_status(e, "rollout launch");
 }
 
@@ -396,6 +533,49 @@ empc_status empc_solve_static(const empc_problem *prob, const empc_ga *ga, const
     }
     return prob->dtype == EMPC_F32 ? solve_t<float>(prob, ga, w, x0, tick, u_star, best_cost, s)
                                    : solve_t<double>(prob, ga, w, x0, tick, u_star, best_cost, s);
+}
+
+empc_status empc_autotune(const empc_problem *prob, const empc_ga *ga, int32_t reps,
+                          int32_t allow_valu, float *info, void *stream) {
+    empc_status st = validate_problem(prob);
+    if (st) return st;
+    if ((st = validate_ga(ga))) return st;
+    if (reps < 1) return fail(EMPC_EINVAL, "reps must be >= 1");
+    if ((st = check_prior())) return st;
+    hipStream_t s = (hipStream_t)stream;
+    return prob->dtype == EMPC_F32 ? autotune_t<float>(prob, ga, reps, allow_valu, info, s)
+                                   : autotune_t<double>(prob, ga, reps, allow_valu, info, s);
+}
+
+empc_status empc_autotune_set(const empc_problem *prob, const empc_ga *ga, int32_t form,
+                              int32_t groups) {
+    empc_status st = validate_problem(prob);
+    if (st) return st;
+    if ((st = validate_ga(ga))) return st;
+    const bool lin = prob->model == EMPC_LINEAR;
+    const bool ok = form == RF_RULE ||
+                    (lin && (form == RF_ONE1 || form == RF_ONE2 || form == RF_ONE4 ||
+                             form == RF_SPLIT || form == RF_VALU256 || form == RF_VALU64)) ||
+                    (!lin && (form == RF_CH64 || form == RF_CH128 || form == RF_CH256));
+    if (!ok) return fail(EMPC_EINVAL, "rollout form %d does not exist for this model", form);
+    if (groups != 0 && groups != 1 && groups != 2 && groups != 4)
+        return fail(EMPC_EINVAL, "groups=%d must be 0, 1, 2 or 4", groups);
+    if ((form == RF_VALU256 || form == RF_VALU64) && (prob->n > 16 || prob->m > 16))
+        return fail(EMPC_EUNSUPPORTED, "the vector-ALU form takes n, m <= 16");
+    if (form == RF_SPLIT && prob->n <= 16)
+        return fail(EMPC_EUNSUPPORTED, "the M-split form needs more than 16 states");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    Tuned t;
+    t.form = form;
+    t.R = groups;
+    g_tune[tune_key(prob, ga->pop)] = t;
+    return EMPC_OK;
+}
+
+empc_status empc_autotune_reset(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+    return EMPC_OK;
 }
 
 empc_status empc_grad(const empc_problem *prob, const void *x0, const void *knots, int64_t ncand,

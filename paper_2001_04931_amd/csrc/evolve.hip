@@ -9,7 +9,7 @@ hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *k
                              int64_t ld_in, const int64_t *elite_idx, const T *elite_rows,
                              const int *has_elites, int cold_mode, T *knots_out, int64_t ld_out,
                              uint32_t tick, uint32_t gen, hipStream_t s,
-                             const PopVariant<T> &var) {
+                             const PopVariant<T> &var, int R_override) {
     const int pm = P.p * P.m;
     const GaStreams gs = ga_streams(ga.seed, P.m, pm);
     // parameter groups per thread: a workgroup's draws shared by its
@@ -17,7 +17,9 @@ hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *k
     // workgroup, so large populations take 32 or 64 parameters per
     // workgroup instead of 16, as long as thousands of workgroups remain
     const int64_t wgs1 = pop_tiles_s(ga.pop) * pop_tiles_g(pm);
-    const int R = wgs1 >= 4096 ? 4 : wgs1 >= 2048 ? 2 : 1;
+    const int R = (R_override == 1 || R_override == 2 || R_override == 4)
+                      ? R_override
+                      : (wgs1 >= 4096 ? 4 : wgs1 >= 2048 ? 2 : 1);
     const int64_t blocks = pop_tiles_s(ga.pop) * pop_tiles_g(pm, R);
     hipLaunchKernelGGL(population_kernel<T>, dim3((unsigned)blocks), dim3(POP_THREADS), 0, s, P, gs,
                        (int64_t)ga.pop, ga.n_elite, ga.elitism, (T)ga.sigma, knots_in, ld_in,
@@ -29,12 +31,12 @@ template hipError_t launch_population<float>(const ProbView<float> &, const empc
                                              const float *, int64_t, const int64_t *,
                                              const float *, const int *, int, float *, int64_t,
                                              uint32_t, uint32_t, hipStream_t,
-                                             const PopVariant<float> &);
+                                             const PopVariant<float> &, int);
 template hipError_t launch_population<double>(const ProbView<double> &, const empc_ga &,
                                               const double *, int64_t, const int64_t *,
                                               const double *, const int *, int, double *,
                                               int64_t, uint32_t, uint32_t, hipStream_t,
-                                              const PopVariant<double> &);
+                                              const PopVariant<double> &, int);
 
 template <typename T>
 hipError_t launch_select(const ProbView<T> &P, const T *cost, const T *knots, int64_t ld,

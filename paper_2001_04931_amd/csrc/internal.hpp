@@ -290,15 +290,28 @@ struct Events {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 
+// Rollout launch shapes.  RF_RULE: the fixed rule (linear: the M-split form
+// below 1024 tiles of 16 candidates, else one wavefront per tile and four
+// per workgroup; chains: 256-thread workgroups).  Linear: RF_ONE1/2/4 one
+// wavefront per tile, 1 / 2 / 4 per workgroup; RF_SPLIT the M-split form
+// (more than 16 states); RF_VALU256 / RF_VALU64 one lane per candidate on the
+// vector ALUs (n, m <= 16) in workgroups of 256 / 64.  Chains: RF_CH64 /
+// RF_CH128 / RF_CH256 workgroup sizes.  All matrix-core forms give the same
+// bits, and all chain forms; the VALU forms sum in another order.
+enum RolloutForm {
+    RF_RULE = 0, RF_ONE1 = 1, RF_ONE2 = 2, RF_ONE4 = 3, RF_SPLIT = 4, RF_VALU256 = 5,
+    RF_VALU64 = 6, RF_CH64 = 11, RF_CH128 = 12, RF_CH256 = 13
+};
+
 template <typename T>
 hipError_t launch_rollout(const ProbView<T> &P, int model, const T *x0, const T *knots,
                           int64_t ncand, int64_t ld, T *cost, hipStream_t s,
-                          const Events &ev = Events());
+                          const Events &ev = Events(), int form = RF_RULE);
 
 // Linear model only (defined per dtype in rollout_linear_f32.hip / _f64.hip).
 template <typename T>
 hipError_t launch_linear(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
-                         int64_t ld, T *cost, hipStream_t s, const Events &ev);
+                         int64_t ld, T *cost, hipStream_t s, const Events &ev, int form);
 
 // Warm-start and exploration variants of a population launch (empc_ga):
 // shift the carried parents one control step later (parents read from
@@ -319,12 +332,15 @@ inline PopVariant<T> pop_variant(const empc_ga &ga, const void *x0, bool shift_n
     return v;
 }
 
+// R_override: parameter groups of 16 per population workgroup (1, 2 or 4;
+// 0 = the rule: 2 or 4 when the launch would have 2048 / 4096 or more
+// workgroups).  Every choice gives the same bits.
 template <typename T>
 hipError_t launch_population(const ProbView<T> &P, const empc_ga &ga, const T *knots_in,
                              int64_t ld_in, const int64_t *elite_idx, const T *elite_rows,
                              const int *has_elites, int cold_mode, T *knots_out, int64_t ld_out,
                              uint32_t tick, uint32_t gen, hipStream_t s,
-                             const PopVariant<T> &var = PopVariant<T>());
+                             const PopVariant<T> &var = PopVariant<T>(), int R_override = 0);
 
 // Selection writes elite indices (ascending), best index, and optionally the
 // elite knots [pm][k] (parameter-major), elite costs [k], the warm-start flag, u* and the

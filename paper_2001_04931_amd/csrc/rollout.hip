@@ -26,21 +26,27 @@ static hipError_t launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipS
 
 template <typename T, int DMAX, bool BOX>
 static hipError_t go_chain(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
-                           int64_t ld, T *cost, hipStream_t s, const Events &ev) {
-    const int64_t blocks = (ncand + 255) / 256;
-    return launch_timed(roll_chain<T, DMAX, BOX>, dim3((unsigned)blocks), dim3(256), 0, s, ev, P,
-                        x0, knots, ld, ncand, cost);
+                           int64_t ld, T *cost, hipStream_t s, const Events &ev, int threads) {
+    const int64_t blocks = (ncand + threads - 1) / threads;
+    return launch_timed(roll_chain<T, DMAX, BOX>, dim3((unsigned)blocks), dim3(threads), 0, s, ev,
+                        P, x0, knots, ld, ncand, cost);
+}
+
+// workgroup size of a chain form (RF_RULE: 256)
+static int chain_threads(int form) {
+    return form == RF_CH64 ? 64 : (form == RF_CH128 ? 128 : 256);
 }
 
 template <typename T, bool BOX>
 static hipError_t go_chain_forms(const ProbView<T> &P, const T *x0, const T *knots,
                                  int64_t ncand, int64_t ld, T *cost, hipStream_t s,
-                                 const Events &ev) {
-    const int d = P.m;
-    if (d <= 4) return go_chain<T, 4, BOX>(P, x0, knots, ncand, ld, cost, s, ev);
-    if (d <= 8) return go_chain<T, 8, BOX>(P, x0, knots, ncand, ld, cost, s, ev);
-    // one candidate per 16-lane row for larger chains
-    const dim3 rows((unsigned)((ncand + 15) / 16)), blk(256);
+                                 const Events &ev, int form) {
+    const int d = P.m, threads = chain_threads(form);
+    if (d <= 4) return go_chain<T, 4, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    if (d <= 8) return go_chain<T, 8, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    // one candidate per 16-lane row for larger chains (threads / 16 per
+    // workgroup)
+    const dim3 rows((unsigned)((ncand + threads / 16 - 1) / (threads / 16))), blk(threads);
     if (d <= 16)
         return launch_timed(roll_chain_rows<T, 1, BOX>, rows, blk, 0, s, ev, P, x0, knots, ld,
                             ncand, cost);
@@ -53,19 +59,22 @@ static hipError_t go_chain_forms(const ProbView<T> &P, const T *x0, const T *kno
 
 template <typename T>
 hipError_t launch_rollout(const ProbView<T> &P, int model, const T *x0, const T *knots,
-                          int64_t ncand, int64_t ld, T *cost, hipStream_t s, const Events &ev) {
+                          int64_t ncand, int64_t ld, T *cost, hipStream_t s, const Events &ev,
+                          int form) {
     if (ncand <= 0) return hipSuccess;
-    if (model == EMPC_LINEAR) return launch_linear<T>(P, x0, knots, ncand, ld, cost, s, ev);
-    if (P.qb) return go_chain_forms<T, true>(P, x0, knots, ncand, ld, cost, s, ev);
-    return go_chain_forms<T, false>(P, x0, knots, ncand, ld, cost, s, ev);
+    if (model == EMPC_LINEAR)
+        return launch_linear<T>(P, x0, knots, ncand, ld, cost, s, ev, form >= RF_CH64 ? RF_RULE : form);
+    const int cf = form >= RF_CH64 ? form : RF_RULE;
+    if (P.qb) return go_chain_forms<T, true>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+    return go_chain_forms<T, false>(P, x0, knots, ncand, ld, cost, s, ev, cf);
 }
 
 template hipError_t launch_rollout<float>(const ProbView<float> &, int, const float *,
                                           const float *, int64_t, int64_t, float *, hipStream_t,
-                                          const Events &);
+                                          const Events &, int);
 template hipError_t launch_rollout<double>(const ProbView<double> &, int, const double *,
                                            const double *, int64_t, int64_t, double *,
-                                           hipStream_t, const Events &);
+                                           hipStream_t, const Events &, int);
 
 // ---------------------------------------------------------------------------
 // Plant: one model step of a single state vector (closed-loop simulation).

@@ -388,7 +388,8 @@ template <typename T, int J, bool BOX>
 __global__ __launch_bounds__(256) void roll_chain_rows(ProbView<T> P, const T *__restrict__ x0,
                                                        const T *__restrict__ knots, int64_t ld,
                                                        int64_t ncand, T *__restrict__ cost) {
-    const int64_t cand0 = xcd_swizzle(blockIdx.x, gridDim.x) * 16;  // 16 rows per block
+    // blockDim.x / 16 rows (candidates) per block
+    const int64_t cand0 = xcd_swizzle(blockIdx.x, gridDim.x) * (int64_t)(blockDim.x >> 4);
     if (cand0 + (threadIdx.x >> 6) * 4 >= ncand) return;  // whole wavefront past the end
     chain_row_candidate<T, J, BOX>(P, x0, knots, ld, ncand, cost, cand0 + (threadIdx.x >> 4),
                               threadIdx.x & 15);

@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include "internal.hpp"
+#include "rollout_valu.hpp"
 
 namespace empc {
 
@@ -577,52 +578,89 @@ static hipError_t launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipS
 // forms round identically, so the choice never changes a result.
 constexpr int64_t SPLIT_MAX_TILES = 1024;
 
+template <typename T, int NM, int MM, bool BOX>
+static hipError_t go_valu_box(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
+                              int64_t ld, T *cost, hipStream_t s, const Events &ev, int threads) {
+    return launch_timed(roll_linear_valu<T, NM, MM, BOX>,
+                        dim3((unsigned)((ncand + threads - 1) / threads)), dim3(threads), 0, s, ev,
+                        P, x0, knots, ld, ncand, cost);
+}
+template <typename T, int NM, bool BOX>
+static hipError_t go_valu_m(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
+                            int64_t ld, T *cost, hipStream_t s, const Events &ev, int threads) {
+    if (P.m <= 4) return go_valu_box<T, NM, 4, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    if (P.m <= 8) return go_valu_box<T, NM, 8, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    return go_valu_box<T, NM, 16, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+}
+template <typename T, bool BOX>
+static hipError_t go_valu(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
+                          int64_t ld, T *cost, hipStream_t s, const Events &ev, int threads) {
+    if (P.n <= 4) return go_valu_m<T, 4, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    if (P.n <= 8) return go_valu_m<T, 8, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    return go_valu_m<T, 16, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+}
+
+// form: one of RolloutForm (internal.hpp); RF_RULE takes the M-split form
+// below SPLIT_MAX_TILES tiles, else one wavefront per tile, four per
+// workgroup.  Every matrix-core form rounds identically; the VALU forms
+// (n, m <= 16 only) round differently.
 template <typename T, int NT, int NU, bool HAS_XG, bool BOX>
 static hipError_t go_linear_forms(const ProbView<T> &P, const T *x0, const T *knots,
                                   int64_t ncand, int64_t ld, T *cost, hipStream_t s,
-                                  const Events &ev) {
-    constexpr int WPB = 4;
+                                  const Events &ev, int form) {
     const int64_t tiles = (ncand + 15) / 16;
-    if (NT > 1 && tiles < SPLIT_MAX_TILES)
+    if ((form == RF_VALU256 || form == RF_VALU64) && P.n <= VALU_MAX && P.m <= VALU_MAX)
+        return go_valu<T, BOX>(P, x0, knots, ncand, ld, cost, s, ev,
+                               form == RF_VALU256 ? 256 : 64);
+    if ((form == RF_RULE && NT > 1 && tiles < SPLIT_MAX_TILES) || (form == RF_SPLIT && NT > 1))
         return launch_timed(roll_linear_split<T, NT, NU, HAS_XG, BOX>, dim3((unsigned)tiles),
                             dim3(64 * NT), 0, s, ev, P, x0, knots, ld, ncand, cost);
-    return launch_timed(roll_linear_mfma<T, NT, NU, WPB, HAS_XG, BOX>,
-                        dim3((unsigned)((tiles + WPB - 1) / WPB)), dim3(64 * WPB), 0, s, ev, P, x0,
-                        knots, ld, ncand, cost);
+    if (form == RF_ONE1)
+        return launch_timed(roll_linear_mfma<T, NT, NU, 1, HAS_XG, BOX>, dim3((unsigned)tiles),
+                            dim3(64), 0, s, ev, P, x0, knots, ld, ncand, cost);
+    if (form == RF_ONE2)
+        return launch_timed(roll_linear_mfma<T, NT, NU, 2, HAS_XG, BOX>,
+                            dim3((unsigned)((tiles + 1) / 2)), dim3(128), 0, s, ev, P, x0, knots,
+                            ld, ncand, cost);
+    return launch_timed(roll_linear_mfma<T, NT, NU, 4, HAS_XG, BOX>,
+                        dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, ev, P, x0, knots, ld,
+                        ncand, cost);
 }
 
 // goal and state box variants: (no goal, no box), (goal, no box), (box, with
 // or without a goal: a NULL goal reads as 0)
 template <typename T, int NT, int NU>
 static hipError_t go_linear(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
-                            int64_t ld, T *cost, hipStream_t s, const Events &ev) {
-    if (P.qb) return go_linear_forms<T, NT, NU, true, true>(P, x0, knots, ncand, ld, cost, s, ev);
-    if (P.xg) return go_linear_forms<T, NT, NU, true, false>(P, x0, knots, ncand, ld, cost, s, ev);
-    return go_linear_forms<T, NT, NU, false, false>(P, x0, knots, ncand, ld, cost, s, ev);
+                            int64_t ld, T *cost, hipStream_t s, const Events &ev, int form) {
+    if (P.qb)
+        return go_linear_forms<T, NT, NU, true, true>(P, x0, knots, ncand, ld, cost, s, ev, form);
+    if (P.xg)
+        return go_linear_forms<T, NT, NU, true, false>(P, x0, knots, ncand, ld, cost, s, ev, form);
+    return go_linear_forms<T, NT, NU, false, false>(P, x0, knots, ncand, ld, cost, s, ev, form);
 }
 
 template <typename T, int NT>
 static hipError_t go_linear_nu(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
-                               int64_t ld, T *cost, hipStream_t s, const Events &ev) {
+                               int64_t ld, T *cost, hipStream_t s, const Events &ev, int form) {
     const int nu = (P.m + 3) / 4;
-    if (nu <= 1) return go_linear<T, NT, 1>(P, x0, knots, ncand, ld, cost, s, ev);
-    if (nu <= 2) return go_linear<T, NT, 2>(P, x0, knots, ncand, ld, cost, s, ev);
-    if (nu <= 4) return go_linear<T, NT, 4>(P, x0, knots, ncand, ld, cost, s, ev);
-    if (nu <= 6) return go_linear<T, NT, 6>(P, x0, knots, ncand, ld, cost, s, ev);
-    if (nu <= 8) return go_linear<T, NT, 8>(P, x0, knots, ncand, ld, cost, s, ev);
-    return go_linear<T, NT, 10>(P, x0, knots, ncand, ld, cost, s, ev);
+    if (nu <= 1) return go_linear<T, NT, 1>(P, x0, knots, ncand, ld, cost, s, ev, form);
+    if (nu <= 2) return go_linear<T, NT, 2>(P, x0, knots, ncand, ld, cost, s, ev, form);
+    if (nu <= 4) return go_linear<T, NT, 4>(P, x0, knots, ncand, ld, cost, s, ev, form);
+    if (nu <= 6) return go_linear<T, NT, 6>(P, x0, knots, ncand, ld, cost, s, ev, form);
+    if (nu <= 8) return go_linear<T, NT, 8>(P, x0, knots, ncand, ld, cost, s, ev, form);
+    return go_linear<T, NT, 10>(P, x0, knots, ncand, ld, cost, s, ev, form);
 }
 
 template <typename T>
 hipError_t launch_linear(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
-                         int64_t ld, T *cost, hipStream_t s, const Events &ev) {
+                         int64_t ld, T *cost, hipStream_t s, const Events &ev, int form) {
     const int nt = (P.n + 15) / 16;
     switch (nt) {
-        case 1: return go_linear_nu<T, 1>(P, x0, knots, ncand, ld, cost, s, ev);
-        case 2: return go_linear_nu<T, 2>(P, x0, knots, ncand, ld, cost, s, ev);
-        case 3: return go_linear_nu<T, 3>(P, x0, knots, ncand, ld, cost, s, ev);
-        case 4: return go_linear_nu<T, 4>(P, x0, knots, ncand, ld, cost, s, ev);
-        default: return go_linear_nu<T, 5>(P, x0, knots, ncand, ld, cost, s, ev);
+        case 1: return go_linear_nu<T, 1>(P, x0, knots, ncand, ld, cost, s, ev, form);
+        case 2: return go_linear_nu<T, 2>(P, x0, knots, ncand, ld, cost, s, ev, form);
+        case 3: return go_linear_nu<T, 3>(P, x0, knots, ncand, ld, cost, s, ev, form);
+        case 4: return go_linear_nu<T, 4>(P, x0, knots, ncand, ld, cost, s, ev, form);
+        default: return go_linear_nu<T, 5>(P, x0, knots, ncand, ld, cost, s, ev, form);
     }
 }
 

@@ -3,5 +3,5 @@
 
 namespace empc {
 template hipError_t launch_linear<float>(const ProbView<float> &, const float *, const float *, int64_t,
-                                        int64_t, float *, hipStream_t, const Events &);
+                                        int64_t, float *, hipStream_t, const Events &, int);
 }  // namespace empc

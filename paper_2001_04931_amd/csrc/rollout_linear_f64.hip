@@ -3,5 +3,5 @@
 
 namespace empc {
 template hipError_t launch_linear<double>(const ProbView<double> &, const double *, const double *, int64_t,
-                                        int64_t, double *, hipStream_t, const Events &);
+                                        int64_t, double *, hipStream_t, const Events &, int);
 }  // namespace empc

@@ -163,6 +163,24 @@ def test_nlink_validation(E):
     assert L.empc_nlink_step(None, 0.01, 1, fake, fake, fake, None) == 1
 
 
+def test_autotune_table_validation(E):
+    # recording choices by hand is a host operation: bad codes and shapes are
+    # refused, good ones recorded, and the table cleared
+    L = E.lib()
+    c = _problem(E)
+    g = E.EmpcGA()
+    g.pop, g.n_elite, g.generations, g.elitism, g.sigma, g.seed = 100, 10, 2, 1, 0.1, 0
+    assert L.empc_autotune(ctypes.byref(c), ctypes.byref(g), 0, 0, None, None) == 1
+    assert L.empc_autotune_set(ctypes.byref(c), ctypes.byref(g), 9, 0) == 1
+    assert L.empc_autotune_set(ctypes.byref(c), ctypes.byref(g), 11, 0) == 1   # chain code
+    assert L.empc_autotune_set(ctypes.byref(c), ctypes.byref(g), 1, 3) == 1
+    assert L.empc_autotune_set(ctypes.byref(c), ctypes.byref(g), 4, 0) == 3    # n = 4: no split
+    big = _problem(E, n=20)
+    assert L.empc_autotune_set(ctypes.byref(big), ctypes.byref(g), 5, 0) == 3  # VALU: n <= 16
+    assert L.empc_autotune_set(ctypes.byref(c), ctypes.byref(g), 5, 2) == 0
+    assert L.empc_autotune_reset() == 0
+
+
 def test_generation_validation(E):
     c = _problem(E)
     g = E.EmpcGA()
