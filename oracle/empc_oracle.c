@@ -302,7 +302,9 @@ static int cost_cmp(double a, int64_t ia, double b, int64_t ib) {
     }
     return (ia > ib) - (ia < ib);
 }
-static const double *g_sort_cost;
+/* comparator context of or_select; one per thread, so that concurrent
+ * selections (the all-cores baseline runs one oracle per thread) do not mix */
+static _Thread_local const double *g_sort_cost;
 static int cmp_cost_idx(const void *pa, const void *pb) {
     int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
     return cost_cmp(g_sort_cost[a], a, g_sort_cost[b], b);
