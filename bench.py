@@ -1,37 +1,44 @@
 #!/usr/bin/env python3
-"""EMPC benchmark on one MI355X: closed-loop control of the 14-DoF linear
-mass-spring-damper chain (n = 28 states, m = 14 inputs), FP32, horizon 50,
-10 knots per input, population 4096, 64 elites, 20 generations per control
-tick, N(0, 1e-3^2) process noise on the simulated plant.
+"""EMPC benchmark on one MI355X.
 
-A step is one control tick: the EMPC solve (20 x {population, rollout +
-cost, selection}), the copy of u* and the best cost to the host, then the
-plant step.  Printed as one JSON line:
-  value       candidate rollouts per second over the timed ticks
-              (population x generations x ticks / wall time);
-  latency_ms  per-tick solve latency (submit to u* on the host) p50 / p99;
-  roofline    rollout kernel: algorithmic FLOP of the rollout and cost per
-              launch over the mean launch time from HIP events recorded
-              around every rollout launch of up to 20 further ticks of the
-              same closed loop (the event markers slow the tick down, so the
-              throughput ticks run without them), against the FP32
-              matrix-core peak;
-  cpu_baseline the FP64 oracle on a bounded sample of the same workload;
-  workloads   the other configurations measured the same way: 2-DoF chain
-              in FP64, 36-link pendulum chain, the gradient-refined form of
-              the 14-DoF run beside plain EMPC, 512 uneven problems solved
-              together, one HIP-graph replay per tick, and the 14-DoF loop
-              with 1 / 3 / 20 generations per tick and the warm-start
-              variants.
+Headline workload: 512 independent MPC problems solved together (degrees of
+freedom drawn from {2, 7, 14, 21, 36}, linear mass-spring-damper or
+nonlinear pendulum chains, horizon 20..100, 5..10 knots, population 1024,
+32 parents, one generation per tick, FP32), one HIP-graph replay per
+control tick.  A step is one tick for all 512 problems: the graph replay
+(population, rollout + cost of every class, selection) and the copy of the
+packed u* to the host.  Printed as one JSON line:
+  value        candidate rollouts per second over the timed ticks
+               (problems x population x generations x ticks / wall time);
+  latency_ms   per-tick latency (submit to u* on the host) p50 / p99;
+  roofline     one tick on the GPU (the graph replay, timed with HIP events on
+               its stream over further ticks): algorithmic FLOP of every
+               problem's rollouts (linear: the knot-precompute count; chain:
+               25 d FLOP per candidate-step, sines not counted) over the mean
+               tick time, against the matrix-core FP32 peak for the linear
+               problems' share and the plain-VALU FP32 peak for the chains'
+               (their time-weighted blend);
+  cpu_baseline the FP64 oracle (one thread) on a bounded sample of the same
+               workload, scaled per rollout;
+  workloads    every other configuration measured the same way, each with
+               its own roofline and oracle baselines on one core and on all
+               cores: the 14-DoF closed loop (C2), the 2-DoF FP64 chain (C1),
+               the 36-link pendulum chain (C3), the gradient-refined form
+               against plain EMPC at equal final cost (C4, 14-DoF linear and
+               36-DoF chain), the batch in its persistent form and as 512
+               single solves, the N-link robot relinearized every tick, the
+               parameterized convex MPC, and the 14-DoF loop's variants.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--only NAME]
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -42,9 +49,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("candidate rollouts/sec and EMPC solve latency p50/p99 (ms) at fixed DoF/horizon")
 PEAK_FP32_MFMA = 157.3e12  # MI355X dense FP32 matrix peak, FLOP/s
+PEAK_FP32_VALU = 78.6e12   # MI355X FP32 vector peak without packed math, FLOP/s
+PEAK_FP64 = 78.6e12        # MI355X FP64 (vector and matrix), FLOP/s
+CSRC = os.path.join(ROOT, "paper_2001_04931_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rollout_linear_c2_traffic.md")
-ROLLOUT_SRC = os.path.join(ROOT, "paper_2001_04931_amd", "csrc", "rollout_linear.hpp")
+ROLLOUT_SRC = os.path.join(CSRC, "rollout_linear.hpp")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_tick_c5_traffic.md")
+BATCH_SRCS = [os.path.join(CSRC, f) for f in ("batched.hip", "rollout_linear.hpp",
+                                               "rollout_chain.hpp", "evolve_body.hpp")]
 
+
+# ---------------------------------------------------------------------------
+# algorithmic work
 
 def linear_flop_per_candidate(n, m, T, p):
     """Algorithmic FLOP of one linear rollout with the knot precompute
@@ -54,22 +70,57 @@ def linear_flop_per_candidate(n, m, T, p):
     return T * (2 * n * n + 6 * n + 6 * m) + 2 * p * n * m
 
 
-def traffic_entry():
-    """HBM bytes per rollout launch from the committed counter summary, or
-    None when absent or taken on a different rollout kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def chain_flop_per_candidate(d, T):
+    """Per candidate-step 25 d FLOP (interpolation 3d, prefix d, gravity
+    coefficient d, suffix d, acceleration 6d, two updates 4d, cost 9d); the
+    d sines are counted separately, not as FLOP."""
+    return 25 * d * T
+
+
+def flop_per_candidate(prob):
+    import workloads as W
+
+    if prob.model == W.LINEAR:
+        return linear_flop_per_candidate(prob.n, prob.m, prob.T, prob.p)
+    return chain_flop_per_candidate(prob.m, prob.T)
+
+
+def roofline(flop, seconds, peak, bound="mfma", **extra):
+    achieved = flop / seconds
+    d = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+         "frac": achieved / peak}
+    d.update(extra)
+    return d
+
+
+def _counted_bytes(summary, sources, hash_key, bytes_key):
+    """HBM bytes from a committed counter summary, or None when it is absent
+    or was taken on other kernel sources than the current ones."""
+    if not os.path.exists(summary):
         return None
     t = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(summary) as f:
         for line in f:
             key, sep, val = line.strip().strip("`").partition(": ")
-            if sep and key in ("rollout_src_sha256", "bytes_per_launch"):
+            if sep and key in (hash_key, bytes_key):
                 t[key] = val.strip()
-    with open(ROLLOUT_SRC, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()
-    if t.get("rollout_src_sha256") != h or "bytes_per_launch" not in t:
+    h = hashlib.sha256()
+    for src in sources:
+        with open(src, "rb") as f:
+            h.update(f.read())
+    if t.get(hash_key) != h.hexdigest() or bytes_key not in t:
         return None
-    return float(t["bytes_per_launch"])
+    return float(t[bytes_key])
+
+
+def traffic_entry():
+    """HBM bytes per C2 rollout launch (FETCH_SIZE + WRITE_SIZE, scaled)."""
+    return _counted_bytes(TRAFFIC_FILE, [ROLLOUT_SRC], "rollout_src_sha256", "bytes_per_launch")
+
+
+def batch_traffic_entry():
+    """HBM bytes per tick of the 512-problem batch (every kernel of a tick)."""
+    return _counted_bytes(BATCH_TRAFFIC_FILE, BATCH_SRCS, "batch_src_sha256", "bytes_per_tick")
 
 
 def copy_calibration(mib, reps):
@@ -87,35 +138,86 @@ def copy_calibration(mib, reps):
           flush=True)
 
 
-def cpu_baseline(prob, ga, ticks):
-    """The FP64 oracle as it stands, single-threaded, on `ticks` closed-loop
-    ticks of the same workload."""
+# ---------------------------------------------------------------------------
+# the oracle as CPU baseline (one thread, and one oracle per core)
+
+def host_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_baseline(jobs, sample, unit="rollouts/s"):
+    """Runs the first job alone on one thread, then jobs[1:] at once, one
+    thread each (the oracle's C calls release the interpreter lock).  Each
+    job returns the rollouts it did.  Returns the one-core and all-core
+    baseline objects."""
     import oracle
-    import workloads as W
 
     oracle.build(force=False)
-    s = oracle.Solver(prob, ga)
-    x = W.draw_x0(prob.n, 0)
-    noise = W.process_noise(prob.n, ticks, 0)
     t0 = time.perf_counter()
-    for t in range(ticks):
-        u, _, _ = s.solve(x, t)
-        x = oracle.step(prob, x, u, noise[t])
-    dt = time.perf_counter() - t0
-    return {"value": ga.pop * ga.generations * ticks / dt, "unit": "rollouts/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "%d closed-loop ticks of the same workload (%d generations x %d candidates "
-                      "each), FP64, one thread, %.1f s" % (ticks, ga.generations, ga.pop, dt)}
+    n1 = jobs[0]()
+    t1 = time.perf_counter() - t0
+    one = {"value": n1 / t1, "unit": unit, "cores": 1, "kind": "oracle",
+           "sample": "%s; one thread, %.1f s" % (sample, t1), "cpu": cpu_model()}
+    rest = jobs[1:][:host_cores()]
+    cores = len(rest)
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=cores) as ex:
+        counts = list(ex.map(lambda f: f(), rest))
+    ta = time.perf_counter() - t0
+    allc = {"value": sum(counts) / ta, "unit": unit, "cores": cores, "kind": "oracle",
+            "sample": "%s; %d independent copies on %d threads, %.1f s" % (sample, cores, cores,
+                                                                            ta),
+            "cpu": cpu_model()}
+    return one, allc
 
 
-def closed_loop(E, W, prob, ga, dtype, ticks, warmup, noise_std=0.0, refine_steps=0):
+def closed_loop_job(prob, ga, ticks, seed, noise_std=0.0, refine=False):
+    """One oracle closed loop (its own solver and start state)."""
+    def job():
+        import oracle
+        import workloads as W
+
+        s = oracle.Solver(prob, ga, refine=refine)
+        x = W.draw_x0(prob.n, seed)
+        noise = W.process_noise(prob.n, ticks, seed, noise_std) if noise_std > 0 else None
+        for t in range(ticks):
+            u, _, _ = s.solve(x, t)
+            x = oracle.step(prob, x, u, None if noise is None else noise[t])
+        return ga.pop * ga.generations * ticks
+    return job
+
+
+# ---------------------------------------------------------------------------
+# GPU measurement helpers
+
+def closed_loop(E, W, prob, ga, dtype, ticks, warmup, noise_std=0.0, refine_steps=0,
+                profile=0, tune=False):
     """Closed-loop ticks on one problem: solve, u* and best cost to the host,
-    plant step.  Returns (rollouts/s, per-tick latencies in ms, best costs)."""
+    plant step.  Returns (rollouts/s, per-tick latencies in ms, best costs,
+    (launches, kernel ms) of `profile` further ticks with HIP events stamped
+    by every rollout launch, or None)."""
     import torch
 
     dp = E.DeviceProblem(prob, dtype)
+    if tune:
+        E.empc_autotune(dp, E.make_ga(ga), reps=10, allow_valu=True)
     solver = E.Solver(dp, ga)
-    total = warmup + ticks
+    total = warmup + ticks + profile
     x = torch.tensor(W.draw_x0(prob.n, 0), dtype=dtype, device="cuda")
     x_next = torch.empty_like(x)
     noise = None
@@ -126,115 +228,345 @@ def closed_loop(E, W, prob, ga, dtype, ticks, warmup, noise_std=0.0, refine_step
     j_host = torch.empty(1, dtype=dtype).pin_memory()
     done = torch.cuda.Event()
     lats, costs = [], []
-    t_start = None
+    t_start = wall = None
+    prof = None
     for t in range(total):
         if t == warmup:
             torch.cuda.synchronize()
             t_start = time.perf_counter()
+        if t == warmup + ticks:
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t_start
+            if profile:
+                E.empc_profile_begin(profile * ga.generations)
         t0 = time.perf_counter()
         u, J = solver.solve(x, t, refine_steps=refine_steps)
         u_host.copy_(u, non_blocking=True)
         j_host.copy_(J, non_blocking=True)
         done.record()
         done.synchronize()
-        if t >= warmup:
+        if warmup <= t < warmup + ticks:
             lats.append((time.perf_counter() - t0) * 1e3)
             costs.append(float(j_host.item()))
         E.empc_plant_step(dp, x, u, None if noise is None else noise[t], x_next)
         x, x_next = x_next, x
     torch.cuda.synchronize()
+    if wall is None:
+        wall = time.perf_counter() - t_start
+    if profile:
+        prof = E.empc_profile_end()
+    return ga.pop * ga.generations * ticks / wall, np.array(lats), costs, prof
+
+
+def lat_summary(lats):
+    return {"p50": float(np.percentile(lats, 50)), "p99": float(np.percentile(lats, 99)),
+            "mean": float(np.mean(lats)), "max": float(np.max(lats))}
+
+
+def kernel_roofline(prof, flop_launch, peak, name, bound="mfma", **extra):
+    launches, kernel_ms = prof
+    mean_s = kernel_ms * 1e-3 / max(launches, 1)
+    return roofline(flop_launch, mean_s, peak, bound, kernel=name, launches=int(launches),
+                    mean_us=mean_s * 1e6, flop_per_launch=flop_launch, **extra)
+
+
+# ---------------------------------------------------------------------------
+# the batch (headline) and its other forms
+
+def c5_problems(W):
+    probs, ga = W.config_c5(512, 0)
+    return [p.cast(np.float32) for p in probs], ga
+
+
+def c5_flop(probs, ga):
+    """(linear FLOP, chain FLOP) of one generation of every problem."""
+    import workloads as W
+
+    lin = sum(ga.pop * flop_per_candidate(p) for p in probs if p.model == W.LINEAR)
+    ch = sum(ga.pop * flop_per_candidate(p) for p in probs if p.model != W.LINEAR)
+    return lin, ch
+
+
+def blended_roofline(lin, ch, seconds, **extra):
+    """Linear FLOP against the matrix-core peak, chain FLOP against the
+    plain-VALU peak: `peak` is the blended rate (total FLOP over the time
+    both shares would take at their peaks), `frac` that time over the
+    measured one."""
+    t_peak = lin / PEAK_FP32_MFMA + ch / PEAK_FP32_VALU
+    peak = (lin + ch) / t_peak
+    return roofline(lin + ch, seconds, peak, "mfma+valu", linear_flop=lin, chain_flop=ch, **extra)
+
+
+def batched_run(E, W, probs, ga, mode, ticks, warm, event_ticks=50):
+    """One BatchSolver over `probs`, one graph replay per tick.  Returns a
+    summary (throughput, host latency, GPU tick time by HIP events)."""
+    import torch
+
+    dps = [E.DeviceProblem(p, torch.float32) for p in probs]
+    t_tune = time.perf_counter()
+    bs = E.BatchSolver(dps, ga, autotune=mode == 0)
+    bs.set_mode(mode)
+    t_tune = time.perf_counter() - t_tune
+    for i, p in enumerate(probs):
+        bs.set_x0(i, W.draw_x0(p.n, i))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bs.solve()
+    u_host = torch.empty(bs.u_star.numel(), dtype=torch.float32).pin_memory()
+    done = torch.cuda.Event()
+    lats = []
+    for t in range(warm + ticks):
+        if t == warm:
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+        t0 = time.perf_counter()
+        g.replay()
+        u_host.copy_(bs.u_star, non_blocking=True)
+        done.record()
+        done.synchronize()
+        if t >= warm:
+            lats.append((time.perf_counter() - t0) * 1e3)
     wall = time.perf_counter() - t_start
-    return ga.pop * ga.generations * ticks / wall, np.array(lats), costs
+    # GPU time of a tick: events on the replay's stream around each replay
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(event_ticks)]
+    for a, b in ev:
+        a.record(st)
+        g.replay()
+        b.record(st)
+    torch.cuda.synchronize()
+    gpu_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    classes = bs.classes() if mode == 0 else None
+    bs.close()
+    lats = np.array(lats)
+    n = len(probs)
+    return {"rollouts_per_s": n * ga.pop * ga.generations * ticks / wall,
+            "latency_ms": lat_summary(lats), "ticks": ticks, "problems": n,
+            "within_2ms": float(np.mean(lats <= 2.0)), "gpu_tick_ms": gpu_ms, "wall_s": wall,
+            "plan_and_autotune_s": round(t_tune, 3),
+            "mode": "persistent work queue" if mode else "per-class launches, autotuned",
+            "classes": None if classes is None else [
+                "%s%s x%d: shape %d of us %s, stream %d" % (
+                    "lin" if c["model"] == "linear" else "chain", list(c["shape"]),
+                    c["problems"], c["variant"], c["tuned_us"], c["stream"]) for c in classes]}
 
 
-def summary(rate, lats, **extra):
-    d = {"rollouts_per_s": rate, "latency_ms": {"p50": float(np.percentile(lats, 50)),
-                                                "p99": float(np.percentile(lats, 99))}}
-    d.update(extra)
-    return d
+def c5_oracle_jobs(probs, ga, cores):
+    """Oracle jobs on a 32-problem sample of the batch, one tick each (cold
+    start, one generation of 1024): the first job does the whole sample, the
+    others a share each."""
+    import workloads as W
+
+    sample = [int(i) for i in np.random.default_rng(0).choice(len(probs), 32, replace=False)]
+
+    def job_for(idx):
+        def job():
+            import oracle
+
+            for i in idx:
+                s = oracle.Solver(probs[i], W.dataclasses.replace(ga, seed=ga.seed ^ (i << 32)))
+                s.solve(W.draw_x0(probs[i].n, i), 0)
+            return len(idx) * ga.pop * ga.generations
+        return job
+    per = max(1, -(-len(sample) // cores))
+    return [job_for(sample)] + [job_for(sample[i:i + per]) for i in range(0, len(sample), per)]
 
 
-WORKLOADS = ("c1", "c3", "c4", "c5", "c2v", "nlink", "convex")
+def c5_workload(E, W, ticks, warm, with_cpu=True):
+    """The headline: 512 uneven problems, one graph replay per tick."""
+    probs, ga = c5_problems(W)
+    r = batched_run(E, W, probs, ga, 0, ticks, warm)
+    lin, ch = c5_flop(probs, ga)
+    r["roofline"] = blended_roofline(lin, ch, r["gpu_tick_ms"] * 1e-3,
+                                     unit_of_work="one tick (graph replay), all 512 problems",
+                                     traffic=batch_traffic_entry())
+    r["flop_per_tick"] = lin + ch
+    if with_cpu:
+        r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
+            c5_oracle_jobs(probs, ga, host_cores()),
+            "one tick (cold start, 1 generation of 1024) of 32 of the 512 problems, FP64")
+    return r, probs, ga
 
 
-def other_workloads(E, W, names=WORKLOADS):
-    """The remaining benchmark configurations, measured the same way."""
+def c5_extra(E, W, probs, ga, ticks, warm):
+    """The batch in its persistent form, and the same 512 problems as
+    single-problem solves one after another."""
     import torch
 
     out = {}
-    if "c1" in names:
-        prob, ga = W.config_c1(0)
-        rate, lats, _ = closed_loop(E, W, prob, ga, torch.float64, 100, 5)
-        out["c1_fp64_2dof"] = summary(rate, lats, ticks=100, dtype="f64")
-
-    if "c3" in names:
-        prob, ga = W.config_c3(0)
-        rate, lats, _ = closed_loop(E, W, prob, ga, torch.float32, 10, 2)
-        out["c3_fp32_36link_chain"] = summary(rate, lats, ticks=10, dtype="f32")
-    if "c4" in names:
-        out.update(refined_workload(E, W))
-    if "c5" in names:
-        out.update(batched_workload(E, W))
-        out.update(batched_workload(E, W, mode=1))
-    if "c2v" in names:
-        out.update(variants_workload(E, W))
-    if "nlink" in names:
-        out.update(nlink_workload(E, W))
-    if "convex" in names:
-        out.update(convex_workload(E, W))
+    r = batched_run(E, W, probs, ga, 1, ticks, warm)
+    lin, ch = c5_flop(probs, ga)
+    r["roofline"] = blended_roofline(lin, ch, r["gpu_tick_ms"] * 1e-3,
+                                     unit_of_work="one tick (graph replay), all 512 problems")
+    out["c5_persistent_form"] = r
+    dps = [E.DeviceProblem(p, torch.float32) for p in probs]
+    solvers = [E.Solver(dp, W.dataclasses.replace(ga, seed=ga.seed ^ (i << 32)))
+               for i, dp in enumerate(dps)]
+    xs = [torch.tensor(W.draw_x0(p.n, i), dtype=torch.float32, device="cuda")
+          for i, p in enumerate(probs)]
+    reps = 5
+    for t in range(reps + 1):
+        if t == 1:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        for s, x in zip(solvers, xs):
+            s.solve(x, t)
+    torch.cuda.synchronize()
+    per_tick = (time.perf_counter() - t0) / reps
+    out["c5_as_single_solves"] = {"tick_ms": per_tick * 1e3,
+                                  "rollouts_per_s": len(probs) * ga.pop / per_tick,
+                                  "ticks": reps, "launches_per_tick": 3 * len(probs)}
     return out
 
 
-def convex_workload(E, W, reps=50):
-    """The paper's other method on the GPU: parameterized small-matrix convex
-    MPC (form P, q, c, then the box QP) for the 2-DoF and 14-DoF linear
-    chains and the 13-link robot linearized at rest-to-goal start (horizon
-    50 and 100, 5 knots as in the paper's convex experiments), FP64; the
-    solve time, active-set iterations, and the gap of EMPC's best cost after
-    the configuration's generations to the convex optimum."""
+# ---------------------------------------------------------------------------
+# single-problem workloads
+
+def c2_workload(E, W, ticks, warm, with_cpu=True):
+    """C2: 14-DoF linear chain, FP32, closed loop with process noise."""
+    import torch
+
+    prob, ga = W.config_c2(0)
+    rate, lats, costs, prof = closed_loop(E, W, prob, ga, torch.float32, ticks, warm,
+                                          noise_std=1e-3, profile=min(ticks, 20))
+    flop = ga.pop * linear_flop_per_candidate(prob.n, prob.m, prob.T, prob.p)
+    r = {"rollouts_per_s": rate, "latency_ms": lat_summary(lats), "ticks": ticks, "dtype": "f32",
+         "final_best_cost": costs[-1],
+         "roofline": kernel_roofline(prof, flop, PEAK_FP32_MFMA, "roll_linear_split<float,2,4>",
+                                     traffic=traffic_entry())}
+    if with_cpu:
+        jobs = [closed_loop_job(prob, ga, 2, s, 1e-3) for s in range(1 + host_cores())]
+        r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
+            jobs, "2 closed-loop ticks (20 generations x 4096 candidates each), FP64")
+    return r
+
+
+def c1_workload(E, W, ticks=1000, with_cpu=True):
+    """C1: 2-DoF linear chain, FP64, 1000 closed-loop solves, launch shapes
+    picked by the single-problem autotuner."""
+    import torch
+
+    prob, ga = W.config_c1(0)
+    dp = E.DeviceProblem(prob, torch.float64)
+    tuned = E.empc_autotune(dp, E.make_ga(ga), reps=10, allow_valu=True)
+    rate, lats, _, prof = closed_loop(E, W, prob, ga, torch.float64, ticks, 20, profile=20)
+    flop = ga.pop * linear_flop_per_candidate(prob.n, prob.m, prob.T, prob.p)
+    r = {"rollouts_per_s": rate, "latency_ms": lat_summary(lats), "ticks": ticks, "dtype": "f64",
+         "autotuned": tuned,
+         "roofline": kernel_roofline(prof, flop, PEAK_FP64, "tuned linear rollout (FP64)",
+                                     bound="latency")}
+    E.empc_autotune_reset()
+    if with_cpu:
+        jobs = [closed_loop_job(prob, ga, 100, s) for s in range(1 + host_cores())]
+        r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
+            jobs, "100 closed-loop ticks (10 generations x 256 candidates each), FP64")
+    return r
+
+
+def c3_workload(E, W, ticks=100, with_cpu=True):
+    """C3: 36-link pendulum chain, FP32, pop 16384, 30 generations."""
+    import torch
+
+    prob, ga = W.config_c3(0)
+    rate, lats, _, prof = closed_loop(E, W, prob, ga, torch.float32, ticks, 2, profile=5)
+    flop = ga.pop * chain_flop_per_candidate(prob.m, prob.T)
+    r = {"rollouts_per_s": rate, "latency_ms": lat_summary(lats), "ticks": ticks, "dtype": "f32",
+         "roofline": kernel_roofline(prof, flop, PEAK_FP32_VALU, "roll_chain_rows<float,3>",
+                                     bound="valu", sines_per_launch=ga.pop * prob.m * prob.T)}
+    if with_cpu:
+        one_gen = W.dataclasses.replace(ga, generations=1, pop=2048)
+        jobs = [closed_loop_job(prob, one_gen, 1, s) for s in range(1 + host_cores())]
+        r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
+            jobs, "1 tick of 1 generation of 2048 candidates of the same chain, FP64")
+    return r
+
+
+def equal_cost(E, W, prob, ga, dtype, refine_steps, x0, max_gen=2560):
+    """The refined solve's best cost after ga.generations at x0 (cold start),
+    and plain EMPC's with the generations doubled until plain comes within
+    1e-4 (relative) of the refined cost; solve times of both."""
+    import torch
+
+    dp = E.DeviceProblem(prob, dtype)
+    x = torch.tensor(x0, dtype=dtype, device="cuda")
+
+    def solve_once(g, steps):
+        s = E.Solver(dp, W.dataclasses.replace(ga, generations=g))
+        s.solve(x, 0, refine_steps=steps)  # first call: kernels loaded
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, J = s.solve(x, 0, refine_steps=steps)
+        torch.cuda.synchronize()
+        return float(J.item()), (time.perf_counter() - t0) * 1e3
+
+    J_ref, t_ref = solve_once(ga.generations, refine_steps)
+    g = ga.generations
+    J_plain, t_plain = solve_once(g, 0)
+    trail = [(g, J_plain, t_plain)]
+    while J_plain > J_ref * (1 + 1e-4) and g < max_gen:
+        g *= 2
+        J_plain, t_plain = solve_once(g, 0)
+        trail.append((g, J_plain, t_plain))
+    return {"refined": {"generations": ga.generations, "adam_steps": refine_steps,
+                        "best_cost": J_ref, "solve_ms": t_ref},
+            "plain_equal_cost": {"generations": g, "best_cost": J_plain, "solve_ms": t_plain,
+                                 "reached": bool(J_plain <= J_ref * (1 + 1e-4))},
+            "plain_trail": [{"generations": a, "best_cost": b, "solve_ms": c}
+                            for a, b, c in trail]}
+
+
+def c4_workload(E, W, ticks=100, with_cpu=True):
+    """C4: gradient refinement (5 Adam steps on the 64 parents after every
+    selection) on the 14-DoF linear loop and the 36-DoF pendulum chain,
+    against plain EMPC at equal final cost."""
     import torch
 
     out = {}
-    cases = {"c1_2dof": W.config_c1(0), "c2_14dof": W.config_c2(0)}
-    for T in (50, 100):
-        robot, prob, x0, ga = W.config_nlink(13, 0)
-        prob = W.nlink_problem(13, T, 5, prob.x_goal)
-        cases["nlink13_T%d" % T] = (prob, ga, robot, x0)
-    for name, c in cases.items():
-        prob, ga = c[0], c[1]
-        dp = E.DeviceProblem(prob, torch.float64, keep=("wd",))
-        if len(c) == 4:
-            robot, x0 = c[2], c[3]
-            R = E.NLinkRobot(robot.mass, robot.length, robot.damping, torch.float64)
-            x = torch.tensor(x0, dtype=torch.float64, device="cuda")
-            E.empc_nlink_linearize(R, 0.01, x, torch.zeros(prob.m, dtype=torch.float64,
-                                                           device="cuda"),
-                                   dp.tensors["Ad"], dp.tensors["Bd"], dp.tensors["wd"])
-        else:
-            x = torch.tensor(W.draw_x0(prob.n, 0), dtype=torch.float64, device="cuda")
-        cs = E.ConvexSolver(dp)
-        cs.solve(x)
-        torch.cuda.synchronize()
-        lats = []
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            cs.solve(x)
-            torch.cuda.synchronize()
-            lats.append((time.perf_counter() - t0) * 1e3)
-        info = cs.info.cpu().numpy()
-        Jstar = float(cs.cost.item())
-        entry = {"pm": prob.p * prob.m, "T": prob.T, "n": prob.n,
-                 "solve_ms": {"p50": float(np.percentile(lats, 50)),
-                              "p99": float(np.percentile(lats, 99))},
-                 "active_set_iterations": int(info[0]), "converged": bool(info[1]),
-                 "optimum": Jstar}
-        if len(c) == 2:
-            s = E.Solver(dp, ga)
-            _, J = s.solve(x, 0)
-            entry["empc_best_cost"] = float(J.item())
-            entry["empc_gap"] = float(J.item()) / Jstar - 1.0
-        out[name] = entry
-    return {"convex_small_matrix_fp64": out}
+    prob, ga = W.config_c2(0)
+    rate_r, lats_r, _, _ = closed_loop(E, W, prob, ga, torch.float32, ticks, 2,
+                                       noise_std=1e-3, refine_steps=5)
+    rate_p, lats_p, _, _ = closed_loop(E, W, prob, ga, torch.float32, ticks, 2, noise_std=1e-3)
+    r = {"rollouts_per_s": rate_r, "latency_ms": lat_summary(lats_r), "ticks": ticks,
+         "dtype": "f32", "plain_rollouts_per_s": rate_p, "plain_latency_ms": lat_summary(lats_p),
+         "equal_cost": equal_cost(E, W, prob.cast(np.float32), ga, torch.float32, 5,
+                                  W.draw_x0(prob.n, 0))}
+    if with_cpu:
+        one_gen = W.dataclasses.replace(ga, generations=1)
+        jobs = [closed_loop_job(prob, one_gen, 1, s, refine=True)
+                for s in range(1 + host_cores())]
+        r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
+            jobs, "1 tick of 1 refined generation (4096 candidates, 5 Adam steps on 64 parents), "
+                  "FP64", unit="rollouts/s (refinement included)")
+    out["c4_fp32_14dof_refined"] = r
+    prob, ga = W.config_c3(0)
+    out["c4_fp32_36dof_chain_refined"] = {
+        "dtype": "f32", "equal_cost": equal_cost(E, W, prob.cast(np.float32), ga, torch.float32,
+                                                 5, W.draw_x0(prob.n, 0), max_gen=480)}
+    return out
+
+
+def variants_workload(E, W):
+    """The 14-DoF closed loop with fewer generations per tick (the paper's one
+    and three iterations per control step) and with the warm-start variants
+    (carried parents moved one step later per tick, noise growing with the
+    distance to the goal): throughput, latency and the mean best cost of
+    the ticks (lower: the loop holds the chain nearer the goal)."""
+    import torch
+
+    prob, ga = W.config_c2(0)
+    runs = {"G1": dict(generations=1), "G3": dict(generations=3), "G20": {},
+            "G20_shift_noise_schedule": dict(shift=True, sigma_min=0.01, sigma_dist=1.0)}
+    out = {}
+    for name, kw in runs.items():
+        g = W.dataclasses.replace(ga, **kw)
+        rate, lats, costs, _ = closed_loop(E, W, prob, g, torch.float32, 30, 2, noise_std=1e-3)
+        out[name] = {"rollouts_per_s": rate, "latency_ms": lat_summary(lats), "ticks": 30,
+                     "generations": g.generations, "mean_best_cost": float(np.mean(costs)),
+                     "last_best_cost": float(costs[-1])}
+    return {"c2_variants": out}
 
 
 def nlink_closed_loop(E, W, N, generations, ticks, dtype, seed=0):
@@ -280,7 +612,7 @@ def nlink_closed_loop(E, W, N, generations, ticks, dtype, seed=0):
     return np.array(lats), np.array(tot), ga.pop * generations * ticks / wall, dist
 
 
-def nlink_workload(E, W, links=range(1, 14), ticks=1000):
+def nlink_workload(E, W, links=range(1, 14), ticks=1000, with_cpu=True):
     """The paper's EMPC experiment: N-link planar robots of 1..13 links, 1 kg
     and 0.25 m per link, |tau| <= 2 N m, horizon 100, 3 knots, control at
     100 Hz for 10 s (1000 ticks), 1 and 3 generations per tick; FP32 EMPC on
@@ -298,105 +630,130 @@ def nlink_workload(E, W, links=range(1, 14), ticks=1000):
                                                          "p99": float(np.percentile(tot, 99))},
                             "rollouts_per_s": rate, "final_goal_distance": dist}
         out["G%d" % G] = rows
-    return {"nlink_robot_relinearized": {"ticks": ticks, "horizon": 100, "knots": 3,
-                                         "pop": 1024, "dtype": "f32", "links": out}}
+    r = {"ticks": ticks, "horizon": 100, "knots": 3, "pop": 1024, "dtype": "f32", "links": out}
+    if with_cpu:
+        def job_for(seed):
+            def job():
+                import dataclasses
+
+                import oracle
+
+                robot, prob, x0, ga = W.config_nlink(13, seed, 1)
+                s = oracle.Solver(prob, ga)
+                x, u = x0.copy(), np.zeros(13)
+                for t in range(5):
+                    Ad, Bd, wd = oracle.nlink_linearize(robot.mass, robot.length, robot.damping,
+                                                        x, u, 0.01)
+                    s.P = oracle.OracleProblem(dataclasses.replace(prob, Ad=Ad, Bd=Bd, wd=wd))
+                    u, _, _ = s.solve(x, t)
+                    x = oracle.nlink_rk4(robot.mass, robot.length, robot.damping, x, u, 0.01, 4)
+                return ga.pop * 5
+            return job
+        r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
+            [job_for(s) for s in range(1 + host_cores())],
+            "5 relinearize-solve-step ticks of the 13-link robot (1 generation of 1024), FP64")
+    return {"nlink_robot_relinearized": r}
 
 
-def variants_workload(E, W):
-    """The 14-DoF closed loop with fewer generations per tick (the paper's one
-    and three iterations per control step) and with the warm-start variants
-    (carried parents moved one step later per tick, noise growing with the
-    distance to the goal): throughput, latency and the mean best cost of
-    the ticks (lower: the loop holds the chain nearer the goal)."""
-    import torch
-
-    prob, ga = W.config_c2(0)
-    runs = {"G1": dict(generations=1), "G3": dict(generations=3), "G20": {},
-            "G20_shift_noise_schedule": dict(shift=True, sigma_min=0.01, sigma_dist=1.0)}
-    out = {}
-    for name, kw in runs.items():
-        g = W.dataclasses.replace(ga, **kw)
-        rate, lats, costs = closed_loop(E, W, prob, g, torch.float32, 30, 2, noise_std=1e-3)
-        out[name] = summary(rate, lats, ticks=30, dtype="f32", generations=g.generations,
-                            mean_best_cost=float(np.mean(costs)),
-                            last_best_cost=float(costs[-1]))
-    return {"c2_variants": out}
-
-
-def refined_workload(E, W):
-    """C4: the gradient-refined form beside plain EMPC on the same ticks."""
-    import torch
-
-    out = {}
-    prob, ga = W.config_c2(0)
-    rate_p, lats_p, costs_p = closed_loop(E, W, prob, ga, torch.float32, 10, 1, noise_std=1e-3)
-    rate_r, lats_r, costs_r = closed_loop(E, W, prob, ga, torch.float32, 10, 1, noise_std=1e-3,
-                                          refine_steps=5)
-    out["c4_fp32_14dof_refined"] = summary(
-        rate_r, lats_r, ticks=10, dtype="f32", adam_steps_per_generation=5, elites_refined=64,
-        plain_rollouts_per_s=rate_p,
-        first_tick_best_cost={"plain": costs_p[0], "refined": costs_r[0]})
-    return out
-
-
-def batched_workload(E, W, mode=0, ticks=200):
-    """C5: 512 uneven problems, one tick per HIP-graph replay; mode 0 the
-    per-class launches (autotuned), 1 the persistent work-queue form."""
+def convex_workload(E, W, reps=50, with_cpu=True):
+    """The paper's other method on the GPU: parameterized small-matrix convex
+    MPC (form P, q, c, then the box QP) for the 2-DoF and 14-DoF linear
+    chains and the 13-link robot linearized at its start (horizon 50 and
+    100, 5 knots as in the paper's convex experiments), FP64; the solve
+    time, the solver's iterations, and the gap of EMPC's best cost after the
+    configuration's generations to the convex optimum."""
     import torch
 
     out = {}
-    probs, ga = W.config_c5(512, 0)
-    dps = [E.DeviceProblem(p.cast(np.float32), torch.float32) for p in probs]
-    t_tune = time.perf_counter()
-    bs = E.BatchSolver(dps, ga, autotune=mode == 0)  # autotunes the launch shapes
-    bs.set_mode(mode)
-    t_tune = time.perf_counter() - t_tune
-    for i, p in enumerate(probs):
-        bs.set_x0(i, W.draw_x0(p.n, i))
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        bs.solve()
-    u_host = torch.empty(bs.u_star.numel(), dtype=torch.float32).pin_memory()
-    done = torch.cuda.Event()
-    warm = 10
-    lats = []
-    for t in range(warm + ticks):
-        if t == warm:
+    cases = {"c1_2dof": W.config_c1(0), "c2_14dof": W.config_c2(0)}
+    for T in (50, 100):
+        robot, prob, x0, ga = W.config_nlink(13, 0)
+        prob = W.nlink_problem(13, T, 5, prob.x_goal)
+        cases["nlink13_T%d" % T] = (prob, ga, robot, x0)
+    for name, c in cases.items():
+        prob, ga = c[0], c[1]
+        dp = E.DeviceProblem(prob, torch.float64, keep=("wd",))
+        if len(c) == 4:
+            robot, x0 = c[2], c[3]
+            R = E.NLinkRobot(robot.mass, robot.length, robot.damping, torch.float64)
+            x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+            E.empc_nlink_linearize(R, 0.01, x, torch.zeros(prob.m, dtype=torch.float64,
+                                                           device="cuda"),
+                                   dp.tensors["Ad"], dp.tensors["Bd"], dp.tensors["wd"])
+        else:
+            x = torch.tensor(W.draw_x0(prob.n, 0), dtype=torch.float64, device="cuda")
+        cs = E.ConvexSolver(dp)
+        cs.solve(x)
+        torch.cuda.synchronize()
+        lats = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            cs.solve(x)
             torch.cuda.synchronize()
-            t_start = time.perf_counter()
-        t0 = time.perf_counter()
-        g.replay()
-        u_host.copy_(bs.u_star, non_blocking=True)
-        done.record()
-        done.synchronize()
-        if t >= warm:
             lats.append((time.perf_counter() - t0) * 1e3)
-    wall = time.perf_counter() - t_start
-    lats = np.array(lats)
-    out["c5_fp32_512_problems" + ("_persistent" if mode else "")] = summary(
-        len(probs) * ga.pop * ga.generations * ticks / wall, lats, ticks=ticks, dtype="f32",
-        problems=len(probs), within_2ms=float(np.mean(lats <= 2.0)),
-        plan_and_autotune_s=round(t_tune, 3),
-        shapes=["%s%s x%d: shape %d of us %s, stream %d" % (
-            "lin" if c["model"] == "linear" else "chain", list(c["shape"]), c["problems"],
-            c["variant"], c["tuned_us"], c["stream"]) for c in bs.classes()])
-    bs.close()
+        info = cs.info.cpu().numpy()
+        Jstar = float(cs.cost.item())
+        entry = {"pm": prob.p * prob.m, "T": prob.T, "n": prob.n,
+                 "solve_ms": lat_summary(np.array(lats)),
+                 "iterations": int(info[0]), "converged": bool(info[1]), "optimum": Jstar}
+        if len(c) == 2:
+            s = E.Solver(dp, ga)
+            _, J = s.solve(x, 0)
+            entry["empc_best_cost"] = float(J.item())
+            entry["empc_gap"] = float(J.item()) / Jstar - 1.0
+            if with_cpu and name == "c2_14dof":
+                from oracle import convex
+
+                x0 = W.draw_x0(prob.n, 0)
+                t0 = time.perf_counter()
+                P, q, cc = convex.qp_form(prob, x0)
+                lo, hi = convex.knot_bounds(prob)
+                convex.qp_solve(P, q, lo, hi)
+                entry["cpu_baseline"] = {"value": (time.perf_counter() - t0) * 1e3, "unit": "ms",
+                                         "cores": 1, "kind": "oracle",
+                                         "sample": "one convex solve (form + bvls), FP64",
+                                         "cpu": cpu_model()}
+        out[name] = entry
+    return {"convex_small_matrix_fp64": out}
+
+
+WORKLOADS = ("c2", "c1", "c3", "c4", "c5x", "c2v", "nlink", "convex")
+
+
+def other_workloads(E, W, names, with_cpu, c5_state=None):
+    out = {}
+    if "c2" in names:
+        out["c2_fp32_14dof_closed_loop"] = c2_workload(E, W, 100, 5, with_cpu)
+    if "c1" in names:
+        out["c1_fp64_2dof"] = c1_workload(E, W, 1000, with_cpu)
+    if "c3" in names:
+        out["c3_fp32_36link_chain"] = c3_workload(E, W, 100, with_cpu)
+    if "c4" in names:
+        out.update(c4_workload(E, W, 100, with_cpu))
+    if "c5x" in names:
+        if c5_state is None:
+            c5_state = c5_problems(W)
+        out.update(c5_extra(E, W, c5_state[0], c5_state[1], 200, 10))
+    if "c2v" in names:
+        out.update(variants_workload(E, W))
+    if "nlink" in names:
+        out.update(nlink_workload(E, W, with_cpu=with_cpu))
+    if "convex" in names:
+        out.update(convex_workload(E, W, with_cpu=with_cpu))
     return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100, help="timed control ticks")
-    ap.add_argument("--warmup", type=int, default=5, help="untimed control ticks")
-    ap.add_argument("--cpu-ticks", type=int, default=8, help="oracle ticks for cpu_baseline")
+    ap.add_argument("--steps", type=int, default=1000, help="timed control ticks (headline)")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed control ticks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-workloads", action="store_true",
-                    help="skip the other configurations (C1, C3, C4, C5, C2 variants)")
-    ap.add_argument("--only", choices=WORKLOADS, default=None,
-                    help="run only this other configuration (for profiling) and print "
-                         "its summary instead of the benchmark line")
+                    help="skip the other configurations")
+    ap.add_argument("--only", choices=WORKLOADS + ("c5",), default=None,
+                    help="run only this configuration (for profiling) and print its summary "
+                         "instead of the benchmark line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain MIB-MiB device copy (traffic-counter scale)")
     args = ap.parse_args()
@@ -416,101 +773,46 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    if args.only:
-        print(json.dumps(other_workloads(E, W, (args.only,))), flush=True)
+    with_cpu = not args.no_cpu_baseline
+    if args.only == "c5":
+        r, _, _ = c5_workload(E, W, args.steps, args.warmup, with_cpu)
+        print(json.dumps(r), flush=True)
         return
-    prob, ga = W.config_c2(0)
-    dtype = torch.float32
-    dp = E.DeviceProblem(prob, dtype)
-    solver = E.Solver(dp, ga)
-    prof_ticks = min(args.steps, 20)
-    total = args.warmup + args.steps
-    x = torch.tensor(W.draw_x0(prob.n, 0), dtype=dtype, device="cuda")
-    x_next = torch.empty_like(x)
-    noise = torch.tensor(W.process_noise(prob.n, total + prof_ticks, 0), dtype=dtype,
-                         device="cuda")
-    u_host = torch.empty(prob.m, dtype=dtype).pin_memory()
-    j_host = torch.empty(1, dtype=dtype).pin_memory()
-    done = torch.cuda.Event()
-
-    def tick(t):
-        nonlocal x, x_next
-        t0 = time.perf_counter()
-        u, J = solver.solve(x, t)
-        u_host.copy_(u, non_blocking=True)
-        j_host.copy_(J, non_blocking=True)
-        done.record()
-        done.synchronize()
-        lat = time.perf_counter() - t0
-        E.empc_plant_step(dp, x, u, noise[t], x_next)
-        x, x_next = x_next, x
-        return lat
-
-    for t in range(args.warmup):
-        tick(t)
-    # timed ticks: no timing markers in the stream
-    lats = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for t in range(args.warmup, total):
-        lats.append(tick(t))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    final_cost = float(j_host.item())
-    # the same closed loop continued with HIP events around every rollout
-    # launch (the start / stop markers add dispatch latency to the tick, so
-    # they stay out of the throughput figure)
-    E.empc_profile_begin(prof_ticks * ga.generations)
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    for t in range(total, total + prof_ticks):
-        tick(t)
-    torch.cuda.synchronize()
-    prof_wall = time.perf_counter() - tp
-    launches, kernel_ms = E.empc_profile_end()
-
-    rollouts = ga.pop * ga.generations * args.steps
-    lat_ms = np.array(lats) * 1e3
-    flop_launch = ga.pop * linear_flop_per_candidate(prob.n, prob.m, prob.T, prob.p)
-    avg_launch_s = kernel_ms * 1e-3 / max(launches, 1)
-    achieved = flop_launch / avg_launch_s
-    traffic = traffic_entry()
+    if args.only:
+        print(json.dumps(other_workloads(E, W, (args.only,), with_cpu)), flush=True)
+        return
+    r, probs, ga = c5_workload(E, W, args.steps, args.warmup, with_cpu)
     out = {
         "metric": METRIC,
-        "value": rollouts / wall,
+        "value": r["rollouts_per_s"],
         "unit": "rollouts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": r["wall_s"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "EMPC closed loop, 14-DoF linear mass-spring-damper chain "
-                               "(n=28, m=14), ZOH dt=0.01, horizon 50, 10 knots, pop 4096, "
-                               "64 elites, 20 generations/tick, sigma 0.1, seed 0",
-                   "n": prob.n, "m": prob.m, "T": prob.T, "p": prob.p, "pop": ga.pop,
-                   "n_elite": ga.n_elite, "generations": ga.generations,
-                   "ticks": args.steps},
-        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
-                       "p99": float(np.percentile(lat_ms, 99)),
-                       "mean": float(lat_ms.mean()), "max": float(lat_ms.max())},
-        "kernel": {"name": "roll_linear_split", "launches": launches,
-                   "timed_ticks": prof_ticks,
-                   "ms_per_step_with_events": prof_wall * 1e3 / prof_ticks,
-                   "mean_us": avg_launch_s * 1e6,
-                   "rollouts_per_s": ga.pop / avg_launch_s,
-                   "flop_per_launch": flop_launch},
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic},
-        "final_best_cost": final_cost,
+        "config": {"workload": "EMPC batch: 512 independent problems, DoF ~ U{2,7,14,21,36}, "
+                               "linear mass-spring-damper or nonlinear pendulum chain ~ "
+                               "Bernoulli(1/2), horizon U{20..100}, knots U{5..10}, pop 1024, "
+                               "32 parents, 1 generation/tick, sigma 0.1, seed 0, one HIP-graph "
+                               "replay per tick",
+                   "problems": len(probs), "pop": ga.pop, "n_elite": ga.n_elite,
+                   "generations": ga.generations, "ticks": args.steps},
+        "latency_ms": r["latency_ms"],
+        "within_2ms": r["within_2ms"],
+        "gpu_tick_ms": r["gpu_tick_ms"],
+        "roofline": r["roofline"],
+        "classes": r["classes"],
     }
+    if with_cpu:
+        out["cpu_baseline"] = r["cpu_baseline"]
+        out["cpu_baseline_all_cores"] = r["cpu_baseline_all_cores"]
     if not args.no_workloads:
-        out["workloads"] = other_workloads(E, W)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, ga, args.cpu_ticks)
+        out["workloads"] = other_workloads(E, W, WORKLOADS, with_cpu, (probs, ga))
     print(json.dumps(out), flush=True)
 
 
