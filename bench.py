@@ -354,12 +354,14 @@ def batched_run(E, W, probs, ga, mode, ticks, warm, event_ticks=50):
 
 
 def c5_oracle_jobs(probs, ga, cores):
-    """Oracle jobs on a 32-problem sample of the batch, one tick each (cold
-    start, one generation of 1024): the first job does the whole sample, the
+    """Oracle jobs on a 128-problem sample of the batch (every fourth
+    problem), three ticks each (a cold start and two warm ticks, one
+    generation of 1024 per tick): the first job does the whole sample, the
     others a share each."""
     import workloads as W
 
-    sample = [int(i) for i in np.random.default_rng(0).choice(len(probs), 32, replace=False)]
+    sample = list(range(0, len(probs), 4))
+    ticks = 3
 
     def job_for(idx):
         def job():
@@ -367,8 +369,10 @@ def c5_oracle_jobs(probs, ga, cores):
 
             for i in idx:
                 s = oracle.Solver(probs[i], W.dataclasses.replace(ga, seed=ga.seed ^ (i << 32)))
-                s.solve(W.draw_x0(probs[i].n, i), 0)
-            return len(idx) * ga.pop * ga.generations
+                x = W.draw_x0(probs[i].n, i)
+                for t in range(ticks):
+                    s.solve(x, t)
+            return len(idx) * ga.pop * ga.generations * ticks
         return job
     per = max(1, -(-len(sample) // cores))
     return [job_for(sample)] + [job_for(sample[i:i + per]) for i in range(0, len(sample), per)]
@@ -386,7 +390,8 @@ def c5_workload(E, W, ticks, warm, with_cpu=True):
     if with_cpu:
         r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
             c5_oracle_jobs(probs, ga, host_cores()),
-            "one tick (cold start, 1 generation of 1024) of 32 of the 512 problems, FP64")
+            "3 ticks (cold start + 2 warm, 1 generation of 1024 each) of 128 of the 512 "
+            "problems (every fourth), FP64")
     return r, probs, ga
 
 
@@ -459,9 +464,9 @@ def c1_workload(E, W, ticks=1000, with_cpu=True):
                                      bound="latency")}
     E.empc_autotune_reset()
     if with_cpu:
-        jobs = [closed_loop_job(prob, ga, 100, s) for s in range(1 + host_cores())]
+        jobs = [closed_loop_job(prob, ga, 1000, s) for s in range(1 + host_cores())]
         r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
-            jobs, "100 closed-loop ticks (10 generations x 256 candidates each), FP64")
+            jobs, "1000 closed-loop ticks (10 generations x 256 candidates each), FP64")
     return r
 
 
@@ -476,10 +481,10 @@ def c3_workload(E, W, ticks=100, with_cpu=True):
          "roofline": kernel_roofline(prof, flop, PEAK_FP32_VALU, "roll_chain_rows<float,3>",
                                      bound="valu", sines_per_launch=ga.pop * prob.m * prob.T)}
     if with_cpu:
-        one_gen = W.dataclasses.replace(ga, generations=1, pop=2048)
+        one_gen = W.dataclasses.replace(ga, generations=1)
         jobs = [closed_loop_job(prob, one_gen, 1, s) for s in range(1 + host_cores())]
         r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
-            jobs, "1 tick of 1 generation of 2048 candidates of the same chain, FP64")
+            jobs, "1 tick of 1 generation of 16384 candidates of the same chain, FP64")
     return r
 
 
@@ -534,12 +539,12 @@ def c4_workload(E, W, ticks=100, with_cpu=True):
          "equal_cost": equal_cost(E, W, prob.cast(np.float32), ga, torch.float32, 5,
                                   W.draw_x0(prob.n, 0))}
     if with_cpu:
-        one_gen = W.dataclasses.replace(ga, generations=1)
-        jobs = [closed_loop_job(prob, one_gen, 1, s, refine=True)
+        five_gen = W.dataclasses.replace(ga, generations=5)
+        jobs = [closed_loop_job(prob, five_gen, 1, s, refine=True)
                 for s in range(1 + host_cores())]
         r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
-            jobs, "1 tick of 1 refined generation (4096 candidates, 5 Adam steps on 64 parents), "
-                  "FP64", unit="rollouts/s (refinement included)")
+            jobs, "1 tick of 5 refined generations (4096 candidates, 5 Adam steps on 64 parents "
+                  "each), FP64", unit="rollouts/s (refinement included)")
     out["c4_fp32_14dof_refined"] = r
     prob, ga = W.config_c3(0)
     out["c4_fp32_36dof_chain_refined"] = {
@@ -641,17 +646,17 @@ def nlink_workload(E, W, links=range(1, 14), ticks=1000, with_cpu=True):
                 robot, prob, x0, ga = W.config_nlink(13, seed, 1)
                 s = oracle.Solver(prob, ga)
                 x, u = x0.copy(), np.zeros(13)
-                for t in range(5):
+                for t in range(50):
                     Ad, Bd, wd = oracle.nlink_linearize(robot.mass, robot.length, robot.damping,
                                                         x, u, 0.01)
                     s.P = oracle.OracleProblem(dataclasses.replace(prob, Ad=Ad, Bd=Bd, wd=wd))
                     u, _, _ = s.solve(x, t)
                     x = oracle.nlink_rk4(robot.mass, robot.length, robot.damping, x, u, 0.01, 4)
-                return ga.pop * 5
+                return ga.pop * 50
             return job
         r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
             [job_for(s) for s in range(1 + host_cores())],
-            "5 relinearize-solve-step ticks of the 13-link robot (1 generation of 1024), FP64")
+            "50 relinearize-solve-step ticks of the 13-link robot (1 generation of 1024), FP64")
     return {"nlink_robot_relinearized": r}
 
 
@@ -721,25 +726,23 @@ WORKLOADS = ("c2", "c1", "c3", "c4", "c5x", "c2v", "nlink", "convex")
 
 
 def other_workloads(E, W, names, with_cpu, c5_state=None):
+    runs = {
+        "c2": lambda: {"c2_fp32_14dof_closed_loop": c2_workload(E, W, 100, 5, with_cpu)},
+        "c1": lambda: {"c1_fp64_2dof": c1_workload(E, W, 1000, with_cpu)},
+        "c3": lambda: {"c3_fp32_36link_chain": c3_workload(E, W, 100, with_cpu)},
+        "c4": lambda: c4_workload(E, W, 100, with_cpu),
+        "c5x": lambda: c5_extra(E, W, *(c5_state or c5_problems(W)), 200, 10),
+        "c2v": lambda: variants_workload(E, W),
+        "nlink": lambda: nlink_workload(E, W, with_cpu=with_cpu),
+        "convex": lambda: convex_workload(E, W, with_cpu=with_cpu),
+    }
     out = {}
-    if "c2" in names:
-        out["c2_fp32_14dof_closed_loop"] = c2_workload(E, W, 100, 5, with_cpu)
-    if "c1" in names:
-        out["c1_fp64_2dof"] = c1_workload(E, W, 1000, with_cpu)
-    if "c3" in names:
-        out["c3_fp32_36link_chain"] = c3_workload(E, W, 100, with_cpu)
-    if "c4" in names:
-        out.update(c4_workload(E, W, 100, with_cpu))
-    if "c5x" in names:
-        if c5_state is None:
-            c5_state = c5_problems(W)
-        out.update(c5_extra(E, W, c5_state[0], c5_state[1], 200, 10))
-    if "c2v" in names:
-        out.update(variants_workload(E, W))
-    if "nlink" in names:
-        out.update(nlink_workload(E, W, with_cpu=with_cpu))
-    if "convex" in names:
-        out.update(convex_workload(E, W, with_cpu=with_cpu))
+    for name in WORKLOADS:
+        if name in names:
+            t0 = time.perf_counter()
+            out.update(runs[name]())
+            print("bench: workload %s done in %.1f s" % (name, time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
     return out
 
 
@@ -781,7 +784,10 @@ def main():
     if args.only:
         print(json.dumps(other_workloads(E, W, (args.only,), with_cpu)), flush=True)
         return
+    t0 = time.perf_counter()
     r, probs, ga = c5_workload(E, W, args.steps, args.warmup, with_cpu)
+    print("bench: headline done in %.1f s" % (time.perf_counter() - t0), file=sys.stderr,
+          flush=True)
     out = {
         "metric": METRIC,
         "value": r["rollouts_per_s"],
