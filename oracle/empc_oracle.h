@@ -11,7 +11,7 @@
  * Parity status per function (what pins it, see the tests):
  *   or_philox4x32_10   pinned: published Philox known-answer vectors and an
  *                      independent library implementation.
- *   or_knot_weights    pinned: worked example T=5, p=3 of Sec. IV-E.
+ *   or_knot_weights    pinned: worked example T=5, p=3 of Sec. IV-D.
  *   or_rollout_cost    linear: pinned by the small-matrix closed form
  *                      (Sec. IV-B) and the quadratic form of J;
  *                      pendulum chain: pinned by energy / equilibrium /

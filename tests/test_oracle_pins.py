@@ -248,7 +248,7 @@ def chain_positions(prob, q):
     return x, y
 
 
-def test_chain_single_link_is_eq7(oracle_lib):
+def test_chain_single_link_is_eq5(oracle_lib):
     # one link: m l^2 qdd + b qd + m g l sin q + k q = tau, semi-implicit Euler
     prob = W.pendulum_chain(1, 10, 2, seed=4)
     ml2 = prob.mass[0] * prob.length[0] ** 2
