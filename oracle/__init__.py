@@ -44,7 +44,9 @@ class _OrProblem(ctypes.Structure):
                 ("stiff", _dp), ("damp", _dp), ("mass", _dp), ("len", _dp),
                 ("gravity", ctypes.c_double), ("dt", ctypes.c_double),
                 ("q", _dp), ("r", _dp), ("qf", _dp), ("x_goal", _dp), ("u_goal", _dp),
-                ("u_min", _dp), ("u_max", _dp), ("x_min", _dp), ("x_max", _dp), ("qb", _dp)]
+                ("u_min", _dp), ("u_max", _dp), ("x_min", _dp), ("x_max", _dp), ("qb", _dp),
+                ("sb", _dp), ("q_min", _dp), ("q_max", _dp), ("restitution", ctypes.c_double),
+                ("Q", _dp), ("R", _dp), ("Qf", _dp)]
 
 
 class _OrGA(ctypes.Structure):
@@ -122,7 +124,9 @@ class OracleProblem:
                             ("damping", "damp"), ("mass", "mass"), ("length", "len"),
                             ("q", "q"), ("r", "r"), ("qf", "qf"), ("x_goal", "x_goal"),
                             ("u_goal", "u_goal"), ("u_min", "u_min"), ("u_max", "u_max"),
-                            ("x_min", "x_min"), ("x_max", "x_max"), ("qb", "qb")):
+                            ("x_min", "x_min"), ("x_max", "x_max"), ("qb", "qb"),
+                            ("sb", "sb"), ("q_min", "q_min"), ("q_max", "q_max"),
+                            ("Q", "Q"), ("R", "R"), ("Qf", "Qf")):
             v = getattr(prob, name, None)
             if v is not None:
                 v = _f64(v)
@@ -130,6 +134,7 @@ class OracleProblem:
                 setattr(s, cname, _ptr(v))
         s.gravity = float(prob.gravity)
         s.dt = float(prob.dt)
+        s.restitution = float(getattr(prob, "restitution", 0.0) or 0.0)
         self.s = s
 
     @property
@@ -231,8 +236,18 @@ def next_population(prob, ga, elite_knots, cold, tick, gen, pop=None):
     return out
 
 
+def _smooth_diagonal(prob):
+    """The adjoint covers diagonal weights and smooth dynamics only: full Q,
+    R, Qf and joint limits with impacts have no gradient here (the step
+    charge sb has derivative zero off the box faces and is allowed)."""
+    for name in ("Q", "R", "Qf", "q_min", "q_max"):
+        if getattr(prob, name, None) is not None:
+            raise ValueError("the adjoint does not cover %s" % name)
+
+
 def grad(prob, x0, knots, ncand=None):
     """(dJ/dknots [p*m][ld], cost [ncand]) by the adjoint, full storage."""
+    _smooth_diagonal(prob)
     P = OracleProblem(prob)
     x0, knots = _f64(x0), _f64(knots)
     ld = knots.shape[1]
@@ -245,6 +260,7 @@ def grad(prob, x0, knots, ncand=None):
 
 def refine(prob, x0, knots, cost, lr=0.01, steps=5):
     """Adam refinement of candidates in place of copies; returns (knots, cost)."""
+    _smooth_diagonal(prob)
     P = OracleProblem(prob)
     x0 = _f64(x0)
     knots = _f64(knots).copy()
@@ -258,6 +274,8 @@ class Solver:
     """Warm-started EMPC controller state for one problem (oracle side)."""
 
     def __init__(self, prob, ga, refine=False, lr=0.01, adam_steps=5):
+        if refine:
+            _smooth_diagonal(prob)
         self.prob, self.ga = prob, ga
         self.P = OracleProblem(prob)
         self.G = _ga_struct(ga)

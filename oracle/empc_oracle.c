@@ -160,8 +160,18 @@ static void chain_step(const or_problem *P, const double *tail_mass, const doubl
         G *= P->gravity;
         double qdd = (u[j] - P->stiff[j] * q[j] - P->damp[j] * qd[j] - G) / inertia[j];
         double qd_new = qd[j] + P->dt * qdd;
+        double q_new = q[j] + P->dt * qd_new;
+        /* joint limits with impacts: an if/else branch inside the
+         * simulation of the kind Sec. V-A names (contact, impacts) */
+        if (P->q_max && q_new > P->q_max[j]) {
+            q_new = P->q_max[j];
+            if (qd_new > 0.0) qd_new = -P->restitution * qd_new;
+        } else if (P->q_min && q_new < P->q_min[j]) {
+            q_new = P->q_min[j];
+            if (qd_new < 0.0) qd_new = -P->restitution * qd_new;
+        }
         x_next[d + j] = qd_new;
-        x_next[j] = q[j] + P->dt * qd_new;
+        x_next[j] = q_new;
     }
     free(sphi);
 }
@@ -214,7 +224,18 @@ static double box_penalty(const or_problem *P, const double *x) {
         double over = x[i] - P->x_max[i], under = P->x_min[i] - x[i];
         if (over > 0.0) J += P->qb[i] * over * over;
         if (under > 0.0) J += P->qb[i] * under * under;
+        /* a constant charge for being outside at all: discontinuous at the
+         * bounds (Sec. V-A: costs need not be continuous) */
+        if (P->sb && (x[i] > P->x_max[i] || x[i] < P->x_min[i])) J += P->sb[i];
     }
+    return J;
+}
+
+/* e^T W e for a symmetric n x n row-major W */
+static double quad_form(const double *W, const double *e, int n) {
+    double J = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) J += e[i] * W[i * n + j] * e[j];
     return J;
 }
 
@@ -229,19 +250,32 @@ static double box_penalty_grad(const or_problem *P, const double *x, int i) {
 
 static double stage_cost(const or_problem *P, const double *x, const double *u) {
     double J = box_penalty(P, x);
-    for (int i = 0; i < P->n; ++i) {
-        double e = x_goal_at(P, i) - x[i];
-        J += P->q[i] * e * e;
+    double *e = (double *)malloc(sizeof(double) * (size_t)(P->n > P->m ? P->n : P->m));
+    for (int i = 0; i < P->n; ++i) e[i] = x_goal_at(P, i) - x[i];
+    if (P->Q) {
+        J += quad_form(P->Q, e, P->n);
+    } else {
+        for (int i = 0; i < P->n; ++i) J += P->q[i] * e[i] * e[i];
     }
-    for (int i = 0; i < P->m; ++i) {
-        double e = u_goal_at(P, i) - u[i];
-        J += P->r[i] * e * e;
+    for (int i = 0; i < P->m; ++i) e[i] = u_goal_at(P, i) - u[i];
+    if (P->R) {
+        J += quad_form(P->R, e, P->m);
+    } else {
+        for (int i = 0; i < P->m; ++i) J += P->r[i] * e[i] * e[i];
     }
+    free(e);
     return J;
 }
 
 static double terminal_cost(const or_problem *P, const double *x) {
     double J = 0.0;
+    if (P->Qf) {
+        double *e = (double *)malloc(sizeof(double) * (size_t)P->n);
+        for (int i = 0; i < P->n; ++i) e[i] = x_goal_at(P, i) - x[i];
+        J = quad_form(P->Qf, e, P->n);
+        free(e);
+        return J;
+    }
     if (!P->qf) return 0.0;
     for (int i = 0; i < P->n; ++i) {
         double e = x_goal_at(P, i) - x[i];

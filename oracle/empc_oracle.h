@@ -73,6 +73,20 @@ typedef struct {
     /* state box as a soft constraint (NULL qb: none): each of x_1..x_T adds
      * sum_i qb_i (max(0, x_i - x_max_i)^2 + max(0, x_min_i - x_i)^2)      */
     const double *x_min, *x_max, *qb; /* n                                     */
+    /* non-smooth terms (Sec. V-A: branches in the simulation and costs that
+     * need not be continuous), NULL = none:
+     * sb (with the state box): sb_i for every state x_1..x_T outside
+     *   [x_min_i, x_max_i], a discontinuous cost;
+     * q_min, q_max (chain, d each): joint limits with impacts; after each
+     *   step a joint past a limit is put back on it and its rate, if it
+     *   still points outward, reversed and scaled by the restitution.      */
+    const double *sb;                 /* n                                     */
+    const double *q_min, *q_max;      /* d                                     */
+    double restitution;               /* in [0, 1]                             */
+    /* full symmetric weights (linear model), row-major, replacing the
+     * diagonal q, r, qf when given: (x-g)^T Q (x-g) + (u-ug)^T R (u-ug) per
+     * stage and (x_T-g)^T Qf (x_T-g) at the end (eq. 3 with full Q, R).   */
+    const double *Q, *R, *Qf;         /* n*n, m*m, n*n                          */
 } or_problem;
 
 /* Tunables of Alg. 1: numSims (pop), numParents (n_elite), sigma_noise. */

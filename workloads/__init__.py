@@ -69,6 +69,17 @@ class Problem:
     x_min: Optional[np.ndarray] = None
     x_max: Optional[np.ndarray] = None
     qb: Optional[np.ndarray] = None
+    # non-smooth terms (None: none): sb_i charged for every state x_1..x_T
+    # outside [x_min_i, x_max_i] (needs the box, qb may be zeros); chain
+    # joint limits [q_min_j, q_max_j] with impacts of the given restitution
+    sb: Optional[np.ndarray] = None
+    q_min: Optional[np.ndarray] = None
+    q_max: Optional[np.ndarray] = None
+    restitution: float = 0.0
+    # full symmetric weights of the linear model (None: the diagonals q, r, qf)
+    Q: Optional[np.ndarray] = None
+    R: Optional[np.ndarray] = None
+    Qf: Optional[np.ndarray] = None
     gravity: float = GRAVITY
     dt: float = 0.0
 
@@ -86,6 +97,7 @@ class Problem:
         if dtype == np.float32:
             out.gravity = float(np.float32(self.gravity))
             out.dt = float(np.float32(self.dt))
+            out.restitution = float(np.float32(self.restitution))
         return out
 
 
