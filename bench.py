@@ -27,7 +27,10 @@ packed u* to the host.  Printed as one JSON line:
                against plain EMPC at equal final cost (C4, 14-DoF linear and
                36-DoF chain), the batch in its persistent form and as 512
                single solves, the N-link robot relinearized every tick, the
-               parameterized convex MPC, and the 14-DoF loop's variants.
+               parameterized convex MPC, the 14-DoF loop's variants, and the
+               non-smooth forms (full weights with a settling-band charge on
+               a 7-DoF chain; joint limits with impacts on the 36-link
+               chain).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--only NAME]
 """
@@ -193,7 +196,7 @@ def closed_loop_job(prob, ga, ticks, seed, noise_std=0.0, refine=False):
         import workloads as W
 
         s = oracle.Solver(prob, ga, refine=refine)
-        x = W.draw_x0(prob.n, seed)
+        x = W.start_inside_limits(prob, W.draw_x0(prob.n, seed))
         noise = W.process_noise(prob.n, ticks, seed, noise_std) if noise_std > 0 else None
         for t in range(ticks):
             u, _, _ = s.solve(x, t)
@@ -218,7 +221,8 @@ def closed_loop(E, W, prob, ga, dtype, ticks, warmup, noise_std=0.0, refine_step
         E.empc_autotune(dp, E.make_ga(ga), reps=10, allow_valu=True)
     solver = E.Solver(dp, ga)
     total = warmup + ticks + profile
-    x = torch.tensor(W.draw_x0(prob.n, 0), dtype=dtype, device="cuda")
+    x = torch.tensor(W.start_inside_limits(prob, W.draw_x0(prob.n, 0)), dtype=dtype,
+                     device="cuda")
     x_next = torch.empty_like(x)
     noise = None
     if noise_std > 0:
@@ -553,6 +557,54 @@ def c4_workload(E, W, ticks=100, with_cpu=True):
     return out
 
 
+def full_weight_flop_per_candidate(n, m, T):
+    """Per step: dynamics 2n^2 + 2nm, the state quadratic form 2n^2 + 2n
+    and its error n, the input quadratic form 2m^2 + 2m, the knot blend and
+    input error 4m, the band indicator n; the terminal form once."""
+    return T * (4 * n * n + 2 * n * m + 2 * m * m + 4 * n + 6 * m) + 2 * n * n + 3 * n
+
+
+def nonsmooth_workload(E, W, ticks=100, with_cpu=True):
+    """Sec. V-A's flexibility on the GPU: full Q, R, Qf with a settling-band
+    charge on the 7-DoF linear chain (vector-ALU rollout), and joint limits
+    with impacts plus a settling-band charge on the 36-joint pendulum chain
+    (C3's shape), each in a closed loop whose plant has the same effects."""
+    import torch
+
+    out = {}
+    prob, ga = W.config_nonsmooth_linear(0)
+    dp = E.DeviceProblem(prob, torch.float32)
+    tuned = E.empc_autotune(dp, E.make_ga(ga), reps=10, allow_valu=True)
+    rate, lats, costs, prof = closed_loop(E, W, prob, ga, torch.float32, ticks, 5,
+                                          noise_std=1e-3, profile=10)
+    E.empc_autotune_reset()
+    flop = ga.pop * full_weight_flop_per_candidate(prob.n, prob.m, prob.T)
+    r = {"rollouts_per_s": rate, "latency_ms": lat_summary(lats), "ticks": ticks,
+         "dtype": "f32", "autotuned": tuned, "final_best_cost": costs[-1],
+         "roofline": kernel_roofline(prof, flop, PEAK_FP32_VALU, "roll_linear_valu<full>",
+                                     bound="valu")}
+    if with_cpu:
+        jobs = [closed_loop_job(prob, W.dataclasses.replace(ga, generations=5), 1, s, 1e-3)
+                for s in range(1 + host_cores())]
+        r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
+            jobs, "1 closed-loop tick of 5 generations x 4096 candidates, FP64")
+    out["nonsmooth_7dof_full_weights_band"] = r
+    prob, ga = W.config_nonsmooth_chain(0)
+    rate, lats, costs, prof = closed_loop(E, W, prob, ga, torch.float32, ticks, 2, profile=5)
+    flop = ga.pop * chain_flop_per_candidate(prob.m, prob.T)
+    r = {"rollouts_per_s": rate, "latency_ms": lat_summary(lats), "ticks": ticks,
+         "dtype": "f32", "final_best_cost": costs[-1],
+         "roofline": kernel_roofline(prof, flop, PEAK_FP32_VALU, "roll_chain_rows<limits, box>",
+                                     bound="valu", sines_per_launch=ga.pop * prob.m * prob.T)}
+    if with_cpu:
+        one_gen = W.dataclasses.replace(ga, generations=1)
+        jobs = [closed_loop_job(prob, one_gen, 1, s) for s in range(1 + host_cores())]
+        r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
+            jobs, "1 tick of 1 generation of 16384 candidates of the same chain, FP64")
+    out["nonsmooth_36link_limits_band"] = r
+    return out
+
+
 def variants_workload(E, W):
     """The 14-DoF closed loop with fewer generations per tick (the paper's one
     and three iterations per control step) and with the warm-start variants
@@ -722,7 +774,7 @@ def convex_workload(E, W, reps=50, with_cpu=True):
     return {"convex_small_matrix_fp64": out}
 
 
-WORKLOADS = ("c2", "c1", "c3", "c4", "c5x", "c2v", "nlink", "convex")
+WORKLOADS = ("c2", "c1", "c3", "c4", "c5x", "c2v", "nlink", "convex", "nonsmooth")
 
 
 def other_workloads(E, W, names, with_cpu, c5_state=None):
@@ -735,6 +787,7 @@ def other_workloads(E, W, names, with_cpu, c5_state=None):
         "c2v": lambda: variants_workload(E, W),
         "nlink": lambda: nlink_workload(E, W, with_cpu=with_cpu),
         "convex": lambda: convex_workload(E, W, with_cpu=with_cpu),
+        "nonsmooth": lambda: nonsmooth_workload(E, W, 100, with_cpu),
     }
     out = {}
     for name in WORKLOADS:

@@ -63,8 +63,9 @@ typedef enum { EMPC_F32 = 0, EMPC_F64 = 1 } empc_dtype;
  *   the library sine and have no such limit). */
 typedef enum { EMPC_LINEAR = 0, EMPC_PENDULUM_CHAIN = 1 } empc_model;
 
-/* The MPC problem of eq. 3 with diagonal weights.  Pointers are device
- * pointers of problem->dtype elements. */
+/* The MPC problem of eq. 3 (diagonal weights, or full Q, R, Qf below) with
+ * the optional non-smooth terms below.  Pointers are device pointers of
+ * problem->dtype elements. */
 typedef struct {
     int32_t n, m;          /* states, inputs                                     */
     int32_t T;             /* horizon steps                                      */
@@ -99,6 +100,34 @@ typedef struct {
     const void *x_min;     /* n  state lower bounds (with qb)                    */
     const void *x_max;     /* n  state upper bounds (with qb)                    */
     const void *qb;        /* n  weights of the box penalty; NULL = none         */
+    /* Non-smooth terms: Sec. V-A names effects placed in if/else branches
+     * of the simulation (contact, impacts) and costs that need not be
+     * continuous as what the evolutionary method admits.  NULL: none.
+     * sb (needs the state box: qb, x_min, x_max; qb may be zeros): a
+     *   constant sb_i for every state x_1..x_T outside [x_min_i, x_max_i],
+     *   a discontinuous cost (with a box around the goal: the number of
+     *   steps spent outside a tolerance band, a settling-time cost).  The
+     *   adjoint takes its derivative as zero (it has none off the faces).
+     * q_min, q_max (PENDULUM_CHAIN, d each, both or neither): joint limits
+     *   with impacts.  After every step a joint past a limit is put back on
+     *   it and its rate, if it still points outward, reversed and scaled by
+     *   `restitution` (0 plastic, 1 elastic; [0, 1] is checked).  The
+     *   adjoint, refinement and the batched plan refuse such problems
+     *   (EMPC_EUNSUPPORTED); FP32 rollouts decide each impact in FP32. */
+    const void *sb;        /* n  charge per step outside the box; NULL = none    */
+    const void *q_min;     /* CHAIN: d joint lower limits; NULL = none           */
+    const void *q_max;     /* CHAIN: d joint upper limits; NULL = none           */
+    double restitution;    /* CHAIN: impact restitution in [0, 1]                */
+    /* Full weights of eq. 3 (LINEAR only): symmetric row-major Q (n*n),
+     * R (m*m), Qf (n*n) replacing q, r, qf respectively when non-NULL
+     * (q, r may then be NULL); each stage adds (x-g)^T Q (x-g) +
+     * (u-ug)^T R (u-ug), the end (x_T-g)^T Qf (x_T-g).  Such problems
+     * run on the vector-ALU rollout (n, m <= 16, else EMPC_EUNSUPPORTED);
+     * the adjoint, refinement, the convex solver and the batched plan
+     * refuse them (EMPC_EUNSUPPORTED). */
+    const void *Q;         /* LINEAR: n*n full stage state weight; NULL = q      */
+    const void *R;         /* LINEAR: m*m full stage input weight; NULL = r      */
+    const void *Qf;        /* LINEAR: n*n full terminal weight; NULL = qf        */
 } empc_problem;
 
 /* Tunables of Alg. 1: numSims = pop, numParents = n_elite, sigma_noise. */

@@ -10,3 +10,6 @@ from .binding import (BatchSolver, ConvexSolver, DeviceProblem, EmpcCost, EmpcEr
                       empc_profile_end, empc_refine,
                       empc_rollout_cost, empc_solve, empc_solve_static, empc_workspace_bytes, lib,
                       empc_qp_form, empc_qp_solve, empc_qp_workspace_bytes, make_ga)
+from .binding import (EMPC_EDEVICE, EMPC_EINVAL, EMPC_EUNSUPPORTED, EMPC_EWORKSPACE,  # noqa: F401
+                      EMPC_OK, RF_CH64, RF_CH128, RF_CH256, RF_ONE1, RF_ONE2, RF_ONE4, RF_RULE,
+                      RF_SPLIT, RF_VALU64, RF_VALU256)

@@ -38,7 +38,9 @@ class EmpcProblem(ctypes.Structure):
                 ("stiffness", _vp), ("damping", _vp), ("mass", _vp), ("length", _vp),
                 ("gravity", ctypes.c_double), ("dt", ctypes.c_double),
                 ("q", _vp), ("r", _vp), ("qf", _vp), ("x_goal", _vp), ("u_goal", _vp),
-                ("u_min", _vp), ("u_max", _vp), ("x_min", _vp), ("x_max", _vp), ("qb", _vp)]
+                ("u_min", _vp), ("u_max", _vp), ("x_min", _vp), ("x_max", _vp), ("qb", _vp),
+                ("sb", _vp), ("q_min", _vp), ("q_max", _vp), ("restitution", ctypes.c_double),
+                ("Q", _vp), ("R", _vp), ("Qf", _vp)]
 
 
 class EmpcGA(ctypes.Structure):
@@ -380,14 +382,16 @@ class DeviceProblem:
     `prob` is any object with the fields of the C struct: model, n, m, T, p,
     Ad, Bd, wd (linear) or stiffness, damping, mass, length, gravity, dt
     (chain), and q, r, qf, x_goal, u_goal, u_min, u_max, and optionally the
-    state box x_min, x_max, qb (host arrays).
+    state box x_min, x_max, qb with its step charge sb, chain joint limits
+    q_min, q_max with restitution, full weights Q, R, Qf (host arrays).
     """
 
     _ARRAYS = ("Ad", "Bd", "wd", "stiffness", "damping", "mass", "length", "q", "r", "qf",
-               "x_goal", "u_goal", "u_min", "u_max", "x_min", "x_max", "qb")
+               "x_goal", "u_goal", "u_min", "u_max", "x_min", "x_max", "qb", "sb", "q_min",
+               "q_max", "Q", "R", "Qf")
     # may be None (NULL); the zero-droppable ones are also passed as NULL
     # when all zero (x_min / x_max are bounds: a zero bound is kept)
-    _OPTIONAL = ("wd", "qf", "x_goal", "u_goal", "qb")
+    _OPTIONAL = ("wd", "qf", "x_goal", "u_goal", "qb", "sb")
 
     def __init__(self, prob, dtype=torch.float32, device="cuda", keep=()):
         """keep: names of optional arrays to place on the device even when
@@ -399,6 +403,9 @@ class DeviceProblem:
         c.n, c.m, c.T, c.p = int(prob.n), int(prob.m), int(prob.T), int(prob.p)
         c.dtype = EMPC_F64 if dtype == torch.float64 else EMPC_F32
         c.model = int(prob.model)
+        sb = getattr(prob, "sb", None)
+        if sb is not None and np.any(np.asarray(sb)):
+            keep = tuple(keep) + ("qb",)  # the step charge needs the box, zero weights or not
         for name in self._ARRAYS:
             v = getattr(prob, name, None)
             # optional arrays that are all zero are passed as NULL (= 0 by the
@@ -412,6 +419,7 @@ class DeviceProblem:
             setattr(c, name, t.data_ptr())
         c.gravity = float(getattr(prob, "gravity", 0.0) or 0.0)
         c.dt = float(getattr(prob, "dt", 0.0) or 0.0)
+        c.restitution = float(getattr(prob, "restitution", 0.0) or 0.0)
         self.c = c
 
     @property

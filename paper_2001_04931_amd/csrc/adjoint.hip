@@ -82,6 +82,7 @@ struct Lane {
     T cg, invI, kst, dmp, wq, wv, wqf, wvf, gq, gv, wr, gu;  // chain joint j
     T lo, hi, bq;                         // state box penalty: linear state i, chain q_j
     T lov, hiv, bv;                       // chain qd_j
+    T sq, sv;                             // step charges outside the box (no derivative)
 };
 
 // LIN: linear model with NMAX >= n and MMAX >= m (register operand
@@ -138,6 +139,8 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
         L.bq = bx ? P.qb[lane] : (T)0;
         L.lo = bx ? P.xlo[lane] : (T)0;
         L.hi = bx ? P.xhi[lane] : (T)0;
+        L.sq = (bx && P.sb) ? P.sb[lane] : (T)0;
+        L.sv = 0;
     } else {
         const int d = m;
         const bool in = lane < d;
@@ -168,6 +171,8 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
         L.bv = bx ? P.qb[d + lane] : (T)0;
         L.lov = bx ? P.xlo[d + lane] : (T)0;
         L.hiv = bx ? P.xhi[d + lane] : (T)0;
+        L.sq = (bx && P.sb) ? P.sb[lane] : (T)0;
+        L.sv = (bx && P.sb) ? P.sb[d + lane] : (T)0;
     }
     __syncthreads();
 
@@ -256,12 +261,15 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
                 xi = lin_step(xi, k);
                 const T e = L.xg - xi, eu = L.ug - u;
                 J += L.q * e * e + L.r * eu * eu;
-                if (box) J += L.bq * box_pen(xi, L.lo, L.hi);
+                if (box) J += L.bq * box_pen(xi, L.lo, L.hi) + L.sq * box_out(xi, L.lo, L.hi);
             } else {
                 chain_step(qj, vj, u);
                 const T eq = L.gq - qj, ev = L.gv - vj, eu = L.gu - u;
                 J += L.wq * eq * eq + L.wv * ev * ev + L.wr * eu * eu;
-                if (box) J += L.bq * box_pen(qj, L.lo, L.hi) + L.bv * box_pen(vj, L.lov, L.hiv);
+                if (box) {
+                    J += L.bq * box_pen(qj, L.lo, L.hi) + L.bv * box_pen(vj, L.lov, L.hiv);
+                    J += L.sq * box_out(qj, L.lo, L.hi) + L.sv * box_out(vj, L.lov, L.hiv);
+                }
             }
         }
         if (lin) {

@@ -48,15 +48,28 @@ empc_status validate_problem(const empc_problem *P) {
     if (P->n < 1 || P->m < 1) return fail(EMPC_EINVAL, "n=%d, m=%d must be >= 1", P->n, P->m);
     if (P->T < 1 || P->T > 100000) return fail(EMPC_EINVAL, "T=%d outside [1, 100000]", P->T);
     if (P->p < 1 || P->p > P->T) return fail(EMPC_EINVAL, "p=%d outside [1, T=%d]", P->p, P->T);
-    if (!P->q || !P->r || !P->u_min || !P->u_max)
-        return fail(EMPC_EINVAL, "q, r, u_min and u_max are required");
+    if ((!P->q && !P->Q) || (!P->r && !P->R) || !P->u_min || !P->u_max)
+        return fail(EMPC_EINVAL, "q (or Q), r (or R), u_min and u_max are required");
     if (P->qb && (!P->x_min || !P->x_max))
         return fail(EMPC_EINVAL, "the state box penalty (qb) needs x_min and x_max");
+    if (P->sb && !P->qb)
+        return fail(EMPC_EINVAL, "the step charge (sb) needs the state box (qb, x_min, x_max)");
+    if (!P->q_min != !P->q_max) return fail(EMPC_EINVAL, "q_min and q_max go together");
+    if (P->q_min && P->model != EMPC_PENDULUM_CHAIN)
+        return fail(EMPC_EINVAL, "joint limits (q_min, q_max) belong to the pendulum chain");
+    if (P->q_min && !(P->restitution >= 0.0 && P->restitution <= 1.0))
+        return fail(EMPC_EINVAL, "restitution must lie in [0, 1]");
+    const bool full = P->Q || P->R || P->Qf;
+    if (full && P->model != EMPC_LINEAR)
+        return fail(EMPC_EINVAL, "full weights (Q, R, Qf) belong to the linear model");
     if (P->model == EMPC_LINEAR) {
         if (!P->Ad || !P->Bd) return fail(EMPC_EINVAL, "linear model needs Ad and Bd");
         if (P->n > Limits::MAX_N_LINEAR || P->m > Limits::MAX_M_LINEAR)
             return fail(EMPC_EUNSUPPORTED, "linear n=%d, m=%d above %d, %d", P->n, P->m,
                         Limits::MAX_N_LINEAR, Limits::MAX_M_LINEAR);
+        if (full && (P->n > VALU_FULL_NMAX || P->m > VALU_FULL_MMAX))
+            return fail(EMPC_EUNSUPPORTED, "full weights take n <= %d, m <= %d (n=%d, m=%d)",
+                        VALU_FULL_NMAX, VALU_FULL_MMAX, P->n, P->m);
     } else {
         if (P->n != 2 * P->m) return fail(EMPC_EINVAL, "chain needs n = 2m (n=%d, m=%d)", P->n, P->m);
         if (!P->stiffness || !P->damping || !P->mass || !P->length)
@@ -70,6 +83,10 @@ empc_status validate_problem(const empc_problem *P) {
 }
 
 empc_status validate_grad(const empc_problem *P) {
+    if (P->Q || P->R || P->Qf)
+        return fail(EMPC_EUNSUPPORTED, "the adjoint takes diagonal weights (no Q, R, Qf)");
+    if (P->q_min)
+        return fail(EMPC_EUNSUPPORTED, "the adjoint has no derivative through impacts (q_min, q_max)");
     if (P->model == EMPC_LINEAR ? P->n > 64 : P->m > 64)
         return fail(EMPC_EUNSUPPORTED, "adjoint supports n <= 64 (linear) or d <= 64 (chain)");
     const size_t b = grad_smem_bytes(P->model, P->n, P->m, P->T, P->p, esize(P));
@@ -153,7 +170,7 @@ Events next_events() {
 // shape and candidate count, the rollout form and the population's
 // parameter groups per workgroup.  Shapes not in the table use the fixed
 // rules.  Every lookup and update holds the mutex.
-typedef std::tuple<int, int, int, int, int, int, int64_t, int, int, int> TuneKey;
+typedef std::tuple<int, int, int, int, int, int, int64_t, int, int, int, int> TuneKey;
 struct Tuned {
     int form = RF_RULE;
     int R = 0;
@@ -163,7 +180,8 @@ std::map<TuneKey, Tuned> g_tune;
 
 TuneKey tune_key(const empc_problem *P, int64_t ncand) {
     return TuneKey(P->model, P->dtype, P->n, P->m, P->T, P->p, ncand, P->qb ? 1 : 0,
-                   P->x_goal ? 1 : 0, P->wd ? 1 : 0);
+                   P->x_goal ? 1 : 0, P->wd ? 1 : 0,
+                   ((P->Q || P->R || P->Qf) ? 1 : 0) | (P->q_min ? 2 : 0));
 }
 Tuned tuned_for(const empc_problem *P, int64_t ncand) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -280,7 +298,9 @@ empc_status autotune_t(const empc_problem *P, const empc_ga *G, int reps, int al
     if (e == hipSuccess)
         e = launch_population<T>(V, *G, nullptr, 0, nullptr, nullptr, nullptr, 1, knots, pop, 0, 0, s);
     std::vector<int> forms;
-    if (P->model == EMPC_LINEAR) {
+    if (P->model == EMPC_LINEAR && (P->Q || P->R || P->Qf)) {
+        forms = {RF_VALU256, RF_VALU64};  // full weights run the VALU form only
+    } else if (P->model == EMPC_LINEAR) {
         forms = {RF_ONE1, RF_ONE2, RF_ONE4};
         if (P->n > 16) forms.push_back(RF_SPLIT);
         if (allow_valu && P->n <= 16 && P->m <= 16) {
@@ -560,8 +580,11 @@ empc_status empc_autotune_set(const empc_problem *prob, const empc_ga *ga, int32
     if (!ok) return fail(EMPC_EINVAL, "rollout form %d does not exist for this model", form);
     if (groups != 0 && groups != 1 && groups != 2 && groups != 4)
         return fail(EMPC_EINVAL, "groups=%d must be 0, 1, 2 or 4", groups);
-    if ((form == RF_VALU256 || form == RF_VALU64) && (prob->n > 16 || prob->m > 16))
+    const bool full = prob->Q || prob->R || prob->Qf;
+    if ((form == RF_VALU256 || form == RF_VALU64) && !full && (prob->n > 16 || prob->m > 16))
         return fail(EMPC_EUNSUPPORTED, "the vector-ALU form takes n, m <= 16");
+    if (full && form != RF_RULE && form != RF_VALU256 && form != RF_VALU64)
+        return fail(EMPC_EUNSUPPORTED, "full weights run the vector-ALU form only");
     if (form == RF_SPLIT && prob->n <= 16)
         return fail(EMPC_EUNSUPPORTED, "the M-split form needs more than 16 states");
     std::lock_guard<std::mutex> lock(g_tune_mu);

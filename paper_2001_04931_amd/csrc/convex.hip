@@ -374,6 +374,8 @@ empc_status check_qp_problem(const empc_problem *P) {
     if (P->model != EMPC_LINEAR)
         return empc_fail_internal(EMPC_EUNSUPPORTED, "the convex form needs a linear model");
     if (P->qb) return empc_fail_internal(EMPC_EUNSUPPORTED, "the state box penalty is not quadratic");
+    if (P->Q || P->R || P->Qf)
+        return empc_fail_internal(EMPC_EUNSUPPORTED, "the convex form takes diagonal weights");
     if (P->p * P->m > QP_MAX_PM)
         return empc_fail_internal(EMPC_EUNSUPPORTED, "more than 1024 knot parameters");
     return EMPC_OK;

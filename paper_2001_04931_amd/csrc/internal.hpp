@@ -22,6 +22,10 @@ struct ProbView {
     T gravity, dt;
     const T *q, *r, *qf, *xg, *ug, *umin, *umax;
     const T *xlo, *xhi, *qb;  // state box penalty (qb NULL: none)
+    const T *sb;              // charge per step outside the box (NULL: none)
+    const T *qlo, *qhi;       // chain joint limits with impacts (NULL: none)
+    T rest;                   // impact restitution
+    const T *Qm, *Rm, *Qfm;   // full weights (NULL: the diagonals)
 };
 
 template <typename T>
@@ -36,7 +40,16 @@ inline ProbView<T> view_of(const empc_problem &P) {
     v.xg = (const T *)P.x_goal; v.ug = (const T *)P.u_goal;
     v.umin = (const T *)P.u_min; v.umax = (const T *)P.u_max;
     v.xlo = (const T *)P.x_min; v.xhi = (const T *)P.x_max; v.qb = (const T *)P.qb;
+    v.sb = (const T *)P.sb;
+    v.qlo = (const T *)P.q_min; v.qhi = (const T *)P.q_max; v.rest = (T)P.restitution;
+    v.Qm = (const T *)P.Q; v.Rm = (const T *)P.R; v.Qfm = (const T *)P.Qf;
     return v;
+}
+
+// the problem has full weights (the vector-ALU rollout handles them)
+template <typename T>
+__host__ __device__ inline bool full_weights(const ProbView<T> &P) {
+    return P.Qm || P.Rm || P.Qfm;
 }
 
 // State box penalty of one state: squared distance to [lo, hi] (unweighted),
@@ -45,6 +58,23 @@ template <typename T>
 __host__ __device__ inline T box_pen(T x, T lo, T hi) {
     const T o = x - hi, u = lo - x;
     return (o > (T)0 ? o * o : (T)0) + (u > (T)0 ? u * u : (T)0);
+}
+// 1 if x lies outside [lo, hi], else 0 (the step charge's indicator)
+template <typename T>
+__host__ __device__ inline T box_out(T x, T lo, T hi) {
+    return (x > hi || x < lo) ? (T)1 : (T)0;
+}
+// Joint limit with an impact: a joint past a limit is put back on it and its
+// rate, if it still points outward, reversed and scaled by e.
+template <typename T>
+__host__ __device__ inline void joint_limit(T &q, T &v, T lo, T hi, T e) {
+    if (q > hi) {
+        q = hi;
+        if (v > (T)0) v = -e * v;
+    } else if (q < lo) {
+        q = lo;
+        if (v < (T)0) v = -e * v;
+    }
 }
 template <typename T>
 __host__ __device__ inline T box_pen_grad(T x, T lo, T hi, T w) {
@@ -165,6 +195,8 @@ struct Limits {
     static constexpr int MAX_D_CHAIN = 40;
     static constexpr int MAX_ELITE = 256;
 };
+constexpr int VALU_FULL_NMAX = 16;  // largest n with full weights (VALU rollout)
+constexpr int VALU_FULL_MMAX = 16;  // largest m with full weights
 
 // Optional start / stop events stamped by a kernel's dispatch.
 // Workgroups are dispatched to the chip's 8 XCDs round-robin (linear

@@ -24,11 +24,11 @@ static hipError_t launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipS
     return hipGetLastError();
 }
 
-template <typename T, int DMAX, bool BOX>
+template <typename T, int DMAX, int FEAT>
 static hipError_t go_chain(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
                            int64_t ld, T *cost, hipStream_t s, const Events &ev, int threads) {
     const int64_t blocks = (ncand + threads - 1) / threads;
-    return launch_timed(roll_chain<T, DMAX, BOX>, dim3((unsigned)blocks), dim3(threads), 0, s, ev,
+    return launch_timed(roll_chain<T, DMAX, FEAT>, dim3((unsigned)blocks), dim3(threads), 0, s, ev,
                         P, x0, knots, ld, ncand, cost);
 }
 
@@ -37,23 +37,23 @@ static int chain_threads(int form) {
     return form == RF_CH64 ? 64 : (form == RF_CH128 ? 128 : 256);
 }
 
-template <typename T, bool BOX>
+template <typename T, int FEAT>
 static hipError_t go_chain_forms(const ProbView<T> &P, const T *x0, const T *knots,
                                  int64_t ncand, int64_t ld, T *cost, hipStream_t s,
                                  const Events &ev, int form) {
     const int d = P.m, threads = chain_threads(form);
-    if (d <= 4) return go_chain<T, 4, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
-    if (d <= 8) return go_chain<T, 8, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    if (d <= 4) return go_chain<T, 4, FEAT>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    if (d <= 8) return go_chain<T, 8, FEAT>(P, x0, knots, ncand, ld, cost, s, ev, threads);
     // one candidate per 16-lane row for larger chains (threads / 16 per
     // workgroup)
     const dim3 rows((unsigned)((ncand + threads / 16 - 1) / (threads / 16))), blk(threads);
     if (d <= 16)
-        return launch_timed(roll_chain_rows<T, 1, BOX>, rows, blk, 0, s, ev, P, x0, knots, ld,
+        return launch_timed(roll_chain_rows<T, 1, FEAT>, rows, blk, 0, s, ev, P, x0, knots, ld,
                             ncand, cost);
     if (d <= 32)
-        return launch_timed(roll_chain_rows<T, 2, BOX>, rows, blk, 0, s, ev, P, x0, knots, ld,
+        return launch_timed(roll_chain_rows<T, 2, FEAT>, rows, blk, 0, s, ev, P, x0, knots, ld,
                             ncand, cost);
-    return launch_timed(roll_chain_rows<T, 3, BOX>, rows, blk, 0, s, ev, P, x0, knots, ld, ncand,
+    return launch_timed(roll_chain_rows<T, 3, FEAT>, rows, blk, 0, s, ev, P, x0, knots, ld, ncand,
                         cost);  // d <= 48
 }
 
@@ -65,8 +65,14 @@ hipError_t launch_rollout(const ProbView<T> &P, int model, const T *x0, const T 
     if (model == EMPC_LINEAR)
         return launch_linear<T>(P, x0, knots, ncand, ld, cost, s, ev, form >= RF_CH64 ? RF_RULE : form);
     const int cf = form >= RF_CH64 ? form : RF_RULE;
-    if (P.qb) return go_chain_forms<T, true>(P, x0, knots, ncand, ld, cost, s, ev, cf);
-    return go_chain_forms<T, false>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+    const int feat = (P.qb ? CF_BOX : 0) | (P.qhi ? CF_LIMIT : 0);
+    switch (feat) {
+        case CF_BOX: return go_chain_forms<T, CF_BOX>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+        case CF_LIMIT: return go_chain_forms<T, CF_LIMIT>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+        case CF_BOX | CF_LIMIT:
+            return go_chain_forms<T, CF_BOX | CF_LIMIT>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+        default: return go_chain_forms<T, 0>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+    }
 }
 
 template hipError_t launch_rollout<float>(const ProbView<float> &, int, const float *,
@@ -122,9 +128,11 @@ __global__ void plant_kernel(ProbView<T> P, int model, const T *__restrict__ x,
             inert += P.mass[i] * dist * dist;
         }
         const T acc = (u[j] - P.stiff[j] * xs[j] - P.damp[j] * xs[d + j] - G) / inert;
-        const T vn = xs[d + j] + P.dt * acc;
+        T vn = xs[d + j] + P.dt * acc;
+        T qn = xs[j] + P.dt * vn;
+        if (P.qhi) joint_limit(qn, vn, P.qlo[j], P.qhi[j], P.rest);
         x_next[d + j] = vn + (noise ? noise[d + j] : (T)0);
-        x_next[j] = xs[j] + P.dt * vn + (noise ? noise[j] : (T)0);
+        x_next[j] = qn + (noise ? noise[j] : (T)0);
     }
 }
 

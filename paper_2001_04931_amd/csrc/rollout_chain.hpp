@@ -21,7 +21,13 @@ struct JointConst {
     T wr, gu;            // input weight and goal
     T bq, bv;            // state box penalty weights of q_j and qd_j (0: none)
     T loq, hiq, lov, hiv;  // and its bounds
+    T sq, sv;            // step charges outside the box (0: none)
+    T qmn, qmx;          // joint limits (with impacts)
 };
+
+// Compile-time features of the chain forms: the state box penalty with its
+// step charge, and joint limits with impacts.
+constexpr int CF_BOX = 1, CF_LIMIT = 2;
 
 template <typename T>
 __device__ void chain_constants_lds(const ProbView<T> &P, JointConst<T> *jc) {
@@ -54,6 +60,10 @@ __device__ void chain_constants_lds(const ProbView<T> &P, JointConst<T> *jc) {
         c.hiq = box ? P.xhi[j] : (T)0;
         c.lov = box ? P.xlo[d + j] : (T)0;
         c.hiv = box ? P.xhi[d + j] : (T)0;
+        c.sq = (box && P.sb) ? P.sb[j] : (T)0;
+        c.sv = (box && P.sb) ? P.sb[d + j] : (T)0;
+        c.qmn = P.qlo ? P.qlo[j] : (T)0;
+        c.qmx = P.qhi ? P.qhi[j] : (T)0;
         jc[j] = c;
     }
 }
@@ -86,15 +96,17 @@ struct RolloutAngle<double> {
 };
 
 // One thread: candidate `cand` of one problem; jc holds the problem's
-// per-joint constants.  BOX: the problem has a state box penalty.
-template <typename T, int DMAX, bool BOX>
+// per-joint constants.  FEAT: CF_BOX (state box penalty and step charge),
+// CF_LIMIT (joint limits with impacts).
+template <typename T, int DMAX, int FEAT>
 __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const JointConst<T> *jc,
                                                 const T *__restrict__ x0,
                                                 const T *__restrict__ knots, int64_t ld,
                                                 T *__restrict__ cost, int64_t cand) {
     const int d = P.m;
     const T dt = P.dt;
-    constexpr bool box = BOX;
+    constexpr bool box = (FEAT & CF_BOX) != 0, limit = (FEAT & CF_LIMIT) != 0;
+    const T rest = P.rest;
     T q[DMAX], v[DMAX], ua[DMAX], ub[DMAX];
 #pragma unroll
     for (int j = 0; j < DMAX; ++j) {
@@ -150,10 +162,13 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
                 const T f = u - cj.kst * q[j] - cj.dmp * v[j] - G;
                 v[j] = v[j] + cj.dtI * f;
                 q[j] = q[j] + dt * v[j];
+                if (limit) joint_limit(q[j], v[j], cj.qmn, cj.qmx, rest);
                 const T eq = cj.gq - q[j], ev = cj.gv - v[j], eu = cj.gu - u;
                 js += cj.wq * eq * eq + cj.wv * ev * ev + cj.wr * eu * eu;
-                if (box)
+                if (box) {
                     js += cj.bq * box_pen(q[j], cj.loq, cj.hiq) + cj.bv * box_pen(v[j], cj.lov, cj.hiv);
+                    js += cj.sq * box_out(q[j], cj.loq, cj.hiq) + cj.sv * box_out(v[j], cj.lov, cj.hiv);
+                }
             }
         }
         J += js;
@@ -183,7 +198,7 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
     cost[cand] = J + jt;
 }
 
-template <typename T, int DMAX, bool BOX>
+template <typename T, int DMAX, int FEAT>
 __global__ __launch_bounds__(256) void roll_chain(ProbView<T> P, const T *__restrict__ x0,
                                                   const T *__restrict__ knots, int64_t ld,
                                                   int64_t ncand, T *__restrict__ cost) {
@@ -192,7 +207,7 @@ __global__ __launch_bounds__(256) void roll_chain(ProbView<T> P, const T *__rest
     __syncthreads();
     const int64_t cand = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (cand >= ncand) return;
-    chain_candidate<T, DMAX, BOX>(P, jc, x0, knots, ld, cost, cand);
+    chain_candidate<T, DMAX, FEAT>(P, jc, x0, knots, ld, cost, cand);
 }
 
 // ---------------------------------------------------------------------------
@@ -202,9 +217,9 @@ __global__ __launch_bounds__(256) void roll_chain(ProbView<T> P, const T *__rest
 // over the lane's J joints plus a scan over the 16 lanes of the row with DPP
 // row shifts (which never cross a row).
 // One candidate per 16-lane row.  `cand` is the row's candidate; r the lane
-// in the row.  Every lane of the wavefront must call this (DPP).  BOX: the
-// problem has a state box penalty.
-template <typename T, int J, bool BOX>
+// in the row.  Every lane of the wavefront must call this (DPP).  FEAT:
+// CF_BOX, CF_LIMIT as for the lane form.
+template <typename T, int J, int FEAT>
 __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const T *__restrict__ x0,
                                                     const T *__restrict__ knots, int64_t ld,
                                                     int64_t ncand, T *__restrict__ cost,
@@ -215,9 +230,13 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
     // per-joint constants of this lane's joints (zero for joints past d)
     T q[J], v[J], cg[J], dtI[J], kst[J], dmp[J], wq[J], wv[J], gq[J], gv[J], wr[J], gu[J];
     T ua[J], ub[J];
-    // state box penalty: weights, bounds and running sums
-    constexpr bool box = BOX;
+    // state box penalty: weights, bounds and running sums; step charges and
+    // the running counts of steps outside; joint limits
+    constexpr bool box = (FEAT & CF_BOX) != 0, limit = (FEAT & CF_LIMIT) != 0;
     T bq[J], bv[J], loq[J], hiq[J], lov[J], hiv[J], Pq[J], Pv[J];
+    T sq[box ? J : 1], sv[box ? J : 1], Nq[box ? J : 1], Nv[box ? J : 1];
+    T qmn[limit ? J : 1], qmx[limit ? J : 1];
+    const T rest = P.rest;
 #pragma unroll
     for (int i = 0; i < J; ++i) {
         const int j = r * J + i;
@@ -250,6 +269,15 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
         lov[i] = bx ? P.xlo[d + j] : (T)0;
         hiv[i] = bx ? P.xhi[d + j] : (T)0;
         Pq[i] = Pv[i] = 0;
+        if (box) {
+            sq[i] = (bx && P.sb) ? P.sb[j] : (T)0;
+            sv[i] = (bx && P.sb) ? P.sb[d + j] : (T)0;
+            Nq[i] = Nv[i] = 0;
+        }
+        if (limit) {
+            qmn[i] = in ? P.qlo[j] : (T)0;
+            qmx[i] = in ? P.qhi[j] : (T)0;
+        }
     }
     const T dt = P.dt;
     const int Tn = P.Tn, p = P.p, den = Tn - 1;
@@ -331,12 +359,15 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
             const T f = u - kst[i] * q[i] - dmp[i] * v[i] - G;
             v[i] = v[i] + dtI[i] * f;
             q[i] = q[i] + dt * v[i];
+            if (limit) joint_limit(q[i], v[i], qmn[i], qmx[i], rest);
             const T eq = gq[i] - q[i], ev = gv[i] - v[i];
             Sq[i] += eq * eq;
             Sv[i] += ev * ev;
             if (box) {
                 Pq[i] += box_pen(q[i], loq[i], hiq[i]);
                 Pv[i] += box_pen(v[i], lov[i], hiv[i]);
+                Nq[i] += box_out(q[i], loq[i], hiq[i]);
+                Nv[i] += box_out(v[i], lov[i], hiv[i]);
             }
         }
         // advance the knot position to step k + 1 (uniform)
@@ -365,7 +396,10 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
     for (int i = 0; i < J; ++i) J_ += wq[i] * Sq[i] + wv[i] * Sv[i];
     if (box)
 #pragma unroll
-        for (int i = 0; i < J; ++i) J_ += bq[i] * Pq[i] + bv[i] * Pv[i];
+        for (int i = 0; i < J; ++i) {
+            J_ += bq[i] * Pq[i] + bv[i] * Pv[i];
+            J_ += sq[i] * Nq[i] + sv[i] * Nv[i];
+        }
     T jt = 0;
 #pragma unroll
     for (int i = 0; i < J; ++i) {
@@ -384,14 +418,14 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
     if (r == 0 && valid) cost[cand] = tot;
 }
 
-template <typename T, int J, bool BOX>
+template <typename T, int J, int FEAT>
 __global__ __launch_bounds__(256) void roll_chain_rows(ProbView<T> P, const T *__restrict__ x0,
                                                        const T *__restrict__ knots, int64_t ld,
                                                        int64_t ncand, T *__restrict__ cost) {
     // blockDim.x / 16 rows (candidates) per block
     const int64_t cand0 = xcd_swizzle(blockIdx.x, gridDim.x) * (int64_t)(blockDim.x >> 4);
     if (cand0 + (threadIdx.x >> 6) * 4 >= ncand) return;  // whole wavefront past the end
-    chain_row_candidate<T, J, BOX>(P, x0, knots, ld, ncand, cost, cand0 + (threadIdx.x >> 4),
+    chain_row_candidate<T, J, FEAT>(P, x0, knots, ld, ncand, cost, cand0 + (threadIdx.x >> 4),
                               threadIdx.x & 15);
 }
 

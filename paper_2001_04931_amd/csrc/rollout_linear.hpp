@@ -75,7 +75,8 @@ struct Mfma<double> {
 // One wavefront: candidates 16*tile .. 16*tile+15 of one problem.
 // BOX: the problem has a state box penalty (P.qb non-NULL); it is summed per
 // state row like the stage cost, from the state at the start of each step,
-// corrected for x_0 and completed with x_T at the end.
+// corrected for x_0 and completed with x_T at the end, and so is the count
+// of steps outside the box that the step charge (P.sb) weighs.
 template <typename T, int NT, int NU, bool HAS_XG, bool BOX = false>
 __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__restrict__ x0,
                                             const T *__restrict__ knots, int64_t ld,
@@ -113,7 +114,7 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
     }
     // State, disturbance and goal in accumulator layout: row 16mt + R(grp, v).
     v4 X[NT], Wd[NT], Xg[NT];
-    v4 Lo[BOX ? NT : 1], Hi[BOX ? NT : 1], Pn[BOX ? NT : 1];
+    v4 Lo[BOX ? NT : 1], Hi[BOX ? NT : 1], Pn[BOX ? NT : 1], Cn[BOX ? NT : 1];
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
@@ -127,6 +128,7 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
                 Lo[mt][v] = in ? P.xlo[row] : (T)-1;
                 Hi[mt][v] = in ? P.xhi[row] : (T)1;
                 Pn[mt][v] = -box_pen(X[mt][v], Lo[mt][v], Hi[mt][v]);
+                Cn[mt][v] = -box_out(X[mt][v], Lo[mt][v], Hi[mt][v]);
             }
         }
 
@@ -249,7 +251,10 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
                     }
                     const T e = HAS_XG ? X[i][v] - Xg[i][v] : X[i][v];
                     S[i][v] += e * e;
-                    if (BOX) Pn[i][v] += box_pen(X[i][v], Lo[i][v], Hi[i][v]);
+                    if (BOX) {
+                        Pn[i][v] += box_pen(X[i][v], Lo[i][v], Hi[i][v]);
+                        Cn[i][v] += box_out(X[i][v], Lo[i][v], Hi[i][v]);
+                    }
                     __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
@@ -294,6 +299,8 @@ __device__ __forceinline__ void linear_tile(const ProbView<T> &P, const T *__res
             if (BOX) {
                 const T qb = in ? P.qb[row] : (T)0;
                 Jm += qb * (Pn[mt][v] + box_pen(X[mt][v], Lo[mt][v], Hi[mt][v]));
+                const T sb = (in && P.sb) ? P.sb[row] : (T)0;
+                Jm += sb * (Cn[mt][v] + box_out(X[mt][v], Lo[mt][v], Hi[mt][v]));
             }
         }
         Jm += __shfl_xor(Jm, 16, 64);
@@ -387,7 +394,7 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
             X[i][v] = row < n ? x0[row] : (T)0;
         }
     }
-    v4 Lo, Hi, Pn;  // state box penalty of the own rows (BOX)
+    v4 Lo, Hi, Pn, Cn;  // state box penalty and step charge of the own rows (BOX)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int row = 16 * w + Mfma<T>::row(grp, v);
@@ -398,6 +405,7 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
             Lo[v] = in ? P.xlo[row] : (T)-1;
             Hi[v] = in ? P.xhi[row] : (T)1;
             Pn[v] = -box_pen(X[0][v], Lo[v], Hi[v]);
+            Cn[v] = -box_out(X[0][v], Lo[v], Hi[v]);
         }
     }
 
@@ -492,7 +500,10 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
                     if (i == 0) {
                         const T e = HAS_XG ? X[0][v] - Xg[v] : X[0][v];
                         S[v] += e * e;
-                        if (BOX) Pn[v] += box_pen(X[0][v], Lo[v], Hi[v]);
+                        if (BOX) {
+                            Pn[v] += box_pen(X[0][v], Lo[v], Hi[v]);
+                            Cn[v] += box_out(X[0][v], Lo[v], Hi[v]);
+                        }
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -532,6 +543,8 @@ __device__ __forceinline__ void linear_tile_split(const ProbView<T> &P, const T 
         if (BOX) {
             const T qb = in ? P.qb[row] : (T)0;
             J += qb * (Pn[v] + box_pen(X[0][v], Lo[v], Hi[v]));
+            const T sb = (in && P.sb) ? P.sb[row] : (T)0;
+            J += sb * (Cn[v] + box_out(X[0][v], Lo[v], Hi[v]));
         }
     }
     J += __shfl_xor(J, 16, 64);
@@ -578,10 +591,10 @@ static hipError_t launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipS
 // forms round identically, so the choice never changes a result.
 constexpr int64_t SPLIT_MAX_TILES = 1024;
 
-template <typename T, int NM, int MM, bool BOX>
+template <typename T, int NM, int MM, bool BOX, bool FULL = false>
 static hipError_t go_valu_box(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
                               int64_t ld, T *cost, hipStream_t s, const Events &ev, int threads) {
-    return launch_timed(roll_linear_valu<T, NM, MM, BOX>,
+    return launch_timed(roll_linear_valu<T, NM, MM, BOX, FULL>,
                         dim3((unsigned)((ncand + threads - 1) / threads)), dim3(threads), 0, s, ev,
                         P, x0, knots, ld, ncand, cost);
 }
@@ -598,6 +611,33 @@ static hipError_t go_valu(const ProbView<T> &P, const T *x0, const T *knots, int
     if (P.n <= 4) return go_valu_m<T, 4, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
     if (P.n <= 8) return go_valu_m<T, 8, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
     return go_valu_m<T, 16, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+}
+
+// full weights (n, m <= 16): the VALU form with the matrices in LDS
+template <typename T, int NM, bool BOX>
+static hipError_t go_valu_full_m(const ProbView<T> &P, const T *x0, const T *knots,
+                                 int64_t ncand, int64_t ld, T *cost, hipStream_t s,
+                                 const Events &ev, int threads) {
+    if (P.m <= 4)
+        return go_valu_box<T, NM, 4, BOX, true>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    if (P.m <= 8)
+        return go_valu_box<T, NM, 8, BOX, true>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    return go_valu_box<T, NM, 16, BOX, true>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+}
+template <typename T, bool BOX>
+static hipError_t go_valu_full_n(const ProbView<T> &P, const T *x0, const T *knots,
+                                 int64_t ncand, int64_t ld, T *cost, hipStream_t s,
+                                 const Events &ev, int threads) {
+    if (P.n <= 4) return go_valu_full_m<T, 4, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    if (P.n <= 8) return go_valu_full_m<T, 8, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    return go_valu_full_m<T, 16, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+}
+template <typename T>
+static hipError_t go_valu_full(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
+                               int64_t ld, T *cost, hipStream_t s, const Events &ev, int form) {
+    const int threads = form == RF_VALU64 ? 64 : 256;
+    if (P.qb) return go_valu_full_n<T, true>(P, x0, knots, ncand, ld, cost, s, ev, threads);
+    return go_valu_full_n<T, false>(P, x0, knots, ncand, ld, cost, s, ev, threads);
 }
 
 // form: one of RolloutForm (internal.hpp); RF_RULE takes the M-split form
@@ -654,6 +694,7 @@ static hipError_t go_linear_nu(const ProbView<T> &P, const T *x0, const T *knots
 template <typename T>
 hipError_t launch_linear(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
                          int64_t ld, T *cost, hipStream_t s, const Events &ev, int form) {
+    if (full_weights(P)) return go_valu_full<T>(P, x0, knots, ncand, ld, cost, s, ev, form);
     const int nt = (P.n + 15) / 16;
     switch (nt) {
         case 1: return go_linear_nu<T, 1>(P, x0, knots, ncand, ld, cost, s, ev, form);

@@ -293,3 +293,33 @@ def test_binding_rejects_bad_solve_and_plant_tensors(E):
     with pytest.raises(ValueError, match="elite_idx has dtype"):
         E.empc_generation(c, g, torch.zeros(6, 32), 32, torch.zeros(32), torch.zeros(6, 32), 32,
                           torch.zeros(4, dtype=torch.int32), None, 0, 1)
+
+
+@pytest.mark.parametrize("cname,pyname", [("empc_problem", "EmpcProblem"), ("empc_ga", "EmpcGA"),
+                                          ("empc_nlink", "EmpcNLink")])
+def test_binding_structs_match_the_header(cname, pyname, tmp_path):
+    """Every field of the ctypes mirror sits at the offset the C compiler
+    gives the header's struct, and the sizes agree."""
+    import shutil
+    import subprocess
+
+    from paper_2001_04931_amd import binding
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    py = getattr(binding, pyname)
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "empc.h"', "int main(void) {",
+             '  printf("size %%zu\\n", sizeof(%s));' % cname]
+    for f, _ in py._fields_:
+        lines.append('  printf("%s %%zu\\n", offsetof(%s, %s));' % (f, cname, f))
+    lines.append("  return 0;\n}\n")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = dict(ln.split() for ln in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                   check=True).stdout.splitlines())
+    assert int(out["size"]) == ctypes.sizeof(py)
+    for f, _ in py._fields_:
+        assert int(out[f]) == getattr(py, f).offset, f

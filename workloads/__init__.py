@@ -289,6 +289,50 @@ def config_nlink(N: int, seed: int = 0, generations: int = 1):
             GA(pop=1024, n_elite=32, generations=generations, sigma=0.2, seed=seed))
 
 
+def config_nonsmooth_linear(seed: int = 0):
+    """Full weights and a settling band on the 7-DoF linear chain (n = 14,
+    m = 7), T = 50, p = 10, pop 4096, top-64, 20 generations: Q charges the
+    spring extensions (x_i - x_{i-1})^2 of the positions (plus 0.5 I) and
+    0.1 on the velocities, Qf = 5 Q, R = 0.01 (I + tridiagonal 1/2), and a
+    charge of 1 per step for every position more than 0.05 from its goal."""
+    d = 7
+    prob = linear_chain(d, 50, 10, seed)
+    n = prob.n
+    D = np.eye(d) - np.eye(d, k=-1)
+    Q = np.zeros((n, n))
+    Q[:d, :d] = 0.5 * np.eye(d) + D.T @ D
+    Q[d:, d:] = 0.1 * np.eye(d)
+    prob.Q, prob.Qf = Q, 5.0 * Q
+    prob.R = 0.01 * (np.eye(d) + 0.5 * (np.eye(d, k=1) + np.eye(d, k=-1)))
+    band = np.concatenate([np.full(d, 0.05), np.full(d, np.inf)])
+    prob.x_min, prob.x_max = prob.x_goal - band, prob.x_goal + band
+    prob.qb = np.zeros(n)
+    prob.sb = np.concatenate([np.ones(d), np.zeros(d)])
+    return prob, GA(pop=4096, n_elite=64, generations=20, sigma=0.1, seed=seed)
+
+
+def config_nonsmooth_chain(seed: int = 0):
+    """The 36-joint pendulum chain of the C3 configuration with joint limits
+    of +-0.6 rad (impacts with restitution 0.5) and a charge of 0.1 per step
+    for every joint angle more than 0.05 rad from its goal."""
+    prob, ga = config_c3(seed)
+    d = prob.m
+    prob.q_min, prob.q_max, prob.restitution = np.full(d, -0.6), np.full(d, 0.6), 0.5
+    band = np.concatenate([np.full(d, 0.05), np.full(d, np.inf)])
+    prob.x_min, prob.x_max = prob.x_goal - band, prob.x_goal + band
+    prob.qb = np.zeros(prob.n)
+    prob.sb = np.concatenate([np.full(d, 0.1), np.zeros(d)])
+    return prob, ga
+
+
+def start_inside_limits(prob, x0):
+    """x0 with the joint angles clipped into the problem's joint limits."""
+    x0 = np.array(x0, dtype=np.float64)
+    if prob.q_min is not None:
+        x0[:prob.m] = np.clip(x0[:prob.m], prob.q_min, prob.q_max)
+    return x0
+
+
 C5_DOFS = (2, 7, 14, 21, 36)
 
 
