@@ -647,6 +647,9 @@ def nlink_closed_loop(E, W, N, generations, ticks, dtype, seed=0):
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for t in range(ticks):
+        # the simulated robot's step (the plant, not the controller) has
+        # finished before the controller's time starts
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         E.empc_nlink_linearize(R, 0.01, x, u, dp.tensors["Ad"], dp.tensors["Bd"],
                                dp.tensors["wd"])

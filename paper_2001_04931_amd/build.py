@@ -1,6 +1,6 @@
 """Build libempc.so (HIP, gfx950) in-tree.
 
-    python -m paper_2001_04931_amd.build
+    python -m paper_2001_04931_amd.build [--changed]
 
 Each .hip file under csrc/ is compiled to an object with hipcc, then the
 objects are linked into paper_2001_04931_amd/libempc.so.  Packed FP32 VALU
@@ -53,11 +53,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
+def _stale(src: str, headers) -> bool:
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(f) > t for f in [src, *headers])
+
+
+def build(verbose: bool = True, changed_only: bool = False) -> str:
+    """Compile every source (changed_only: only those whose object is older
+    than the source or any header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    headers = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(
+        os.path.join(HERE, "..", "include", "*.h"))
+    todo = [s for s in srcs if not changed_only or _stale(s, headers)]
+    if todo:
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(todo))) as ex:
+            list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -70,4 +85,4 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(changed_only="--changed" in sys.argv[1:])

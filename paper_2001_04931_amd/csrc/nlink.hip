@@ -11,11 +11,14 @@
 // Inverse dynamics come from a recursive Newton-Euler pass over the chain
 // (O(N) per call): accelerations of the mass points outward, the force and
 // moment carried by each joint inward.  M(q) is N such passes with qd = 0 and
-// qdd = e_j, C(q, qd) one pass with qdd = 0, and the Jacobian of the forward
-// dynamics follows from differentiating RNEA(q, qd, qdd(q, qd, tau)) =
-// tau - b qd: dqdd/dx_s = M^-1 (d(tau - b qd)/dx_s - dRNEA/dx_s |qdd fixed),
-// the last term a forward-mode dual-number pass per direction.  Everything
-// runs in FP64 (the model is tiny); outputs are written in the problem dtype.
+// qdd = e_j (one per thread), C(q, qd) one pass with qdd = 0, M is factored
+// by Cholesky across the workgroup, and the Jacobian of the forward dynamics
+// follows from differentiating RNEA(q, qd, qdd(q, qd, tau)) = tau - b qd:
+// dqdd/dx_s = M^-1 (d(tau - b qd)/dx_s - dRNEA/dx_s |qdd fixed), the last
+// term a forward-mode dual-number pass per direction (one per thread).  The
+// zero-order hold works on the n x n state block (Phi and its integral)
+// rather than on the augmented matrix.  Everything runs in FP64 (the model
+// is tiny); outputs are written in the problem dtype.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -32,13 +35,15 @@ __device__ inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}
 __device__ inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
 __device__ inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.v * b.d + a.d * b.v}; }
 __device__ inline Dual operator*(double s, Dual a) { return {s * a.v, s * a.d}; }
-__device__ inline void sincos_d(Dual a, Dual *s, Dual *c) {
-    double sv, cv;
-    sincos(a.v, &sv, &cv);
-    *s = {sv, cv * a.d};
-    *c = {cv, -sv * a.d};
+// sine and cosine of an angle whose value's sine and cosine are known
+__device__ inline void sincos_at(double, double s0, double c0, double *s, double *c) {
+    *s = s0;
+    *c = c0;
 }
-__device__ inline void sincos_d(double a, double *s, double *c) { sincos(a, s, c); }
+__device__ inline void sincos_at(Dual a, double s0, double c0, Dual *s, Dual *c) {
+    *s = {s0, c0 * a.d};
+    *c = {c0, -s0 * a.d};
+}
 template <typename S>
 __device__ inline S make(double v, double d);
 template <>
@@ -52,116 +57,206 @@ __device__ inline Dual make<Dual>(double v, double d) { return {v, d}; }
 // u_i), u_i = (cos phi_i, sin phi_i), phi/omega/alpha the absolute angle,
 // rate and acceleration of link i; joint i carries the force f_i =
 // sum_{j>=i} m_j a_j and the moment tau_i = tau_{i+1} + l_i u_i x f_i.
-template <typename S>
-__device__ void rnea(int N, const double *mass, const double *len, const S *q, const S *qd,
-                     const S *qdd, S *tau) {
+// Loops run to NLINK_MAX with the links past N skipped, so that the
+// per-link arrays live in registers (every index a compile-time constant).
+// sphi, cphi: sine and cosine of the absolute angles at q (a table shared
+// by all passes at the same q); a dual q carries its directional part into
+// them by the chain rule.
+template <typename S, typename QV, typename DV, typename AV>
+__device__ __forceinline__ void rnea(int N, const double *mass, const double *len,
+                                     const double *sphi, const double *cphi, const QV &q,
+                                     const DV &qd, const AV &qdd, S *tau) {
     S ux[NLINK_MAX], uy[NLINK_MAX], ax[NLINK_MAX], ay[NLINK_MAX];
     S phi = make<S>(0, 0), om = make<S>(0, 0), al = make<S>(0, 0);
     S px = make<S>(0, 0), py = make<S>(0, 0);
-    for (int i = 0; i < N; ++i) {
-        phi = phi + q[i];
-        om = om + qd[i];
-        al = al + qdd[i];
-        S s, c;
-        sincos_d(phi, &s, &c);
-        const S w2 = om * om;
-        px = px + len[i] * (make<S>(0, 0) - al * s - w2 * c);
-        py = py + len[i] * (al * c - w2 * s);
-        ux[i] = c;
-        uy[i] = s;
-        ax[i] = px;
-        ay[i] = py;
+#pragma unroll
+    for (int i = 0; i < NLINK_MAX; ++i) {
+        if (i < N) {
+            phi = phi + q(i);
+            om = om + qd(i);
+            al = al + qdd(i);
+            S sn, c;
+            sincos_at(phi, sphi[i], cphi[i], &sn, &c);
+            const S w2 = om * om;
+            px = px + len[i] * (make<S>(0, 0) - al * sn - w2 * c);
+            py = py + len[i] * (al * c - w2 * sn);
+            ux[i] = c;
+            uy[i] = sn;
+            ax[i] = px;
+            ay[i] = py;
+        }
     }
     S fx = make<S>(0, 0), fy = make<S>(0, 0), t = make<S>(0, 0);
-    for (int i = N - 1; i >= 0; --i) {
-        fx = fx + mass[i] * ax[i];
-        fy = fy + mass[i] * ay[i];
-        t = t + len[i] * (ux[i] * fy - uy[i] * fx);
-        tau[i] = t;
-    }
-}
-
-// In-place Cholesky factor (lower) of the N x N matrix A (row-major); one
-// thread.
-__device__ void cholesky(int N, double *A) {
-    for (int j = 0; j < N; ++j) {
-        double s = A[j * N + j];
-        for (int k = 0; k < j; ++k) s -= A[j * N + k] * A[j * N + k];
-        const double d = sqrt(s);
-        A[j * N + j] = d;
-        for (int i = j + 1; i < N; ++i) {
-            double t = A[i * N + j];
-            for (int k = 0; k < j; ++k) t -= A[i * N + k] * A[j * N + k];
-            A[i * N + j] = t / d;
+#pragma unroll
+    for (int i = NLINK_MAX - 1; i >= 0; --i) {
+        if (i < N) {
+            fx = fx + mass[i] * ax[i];
+            fy = fy + mass[i] * ay[i];
+            t = t + len[i] * (ux[i] * fy - uy[i] * fx);
+            tau[i] = t;
         }
     }
 }
-// y = (L L^T)^-1 r, in place on y (holding r on entry)
-__device__ void chol_solve(int N, const double *L, double *y) {
-    for (int i = 0; i < N; ++i) {
-        double s = y[i];
-        for (int k = 0; k < i; ++k) s -= L[i * N + k] * y[k];
-        y[i] = s / L[i * N + i];
-    }
-    for (int i = N - 1; i >= 0; --i) {
-        double s = y[i];
-        for (int k = i + 1; k < N; ++k) s -= L[k * N + i] * y[k];
-        y[i] = s / L[i * N + i];
+
+// Cholesky factor of the N x N matrix A (row-major, LDS) by every thread of
+// the workgroup: column j is scaled by the threads of its rows, then the
+// trailing block is updated in parallel; the strictly lower part of A
+// receives L, dg the diagonal of L.  Must be reached by every thread.
+__device__ void cholesky_par(int N, double *A, double *dg) {
+    const int t = threadIdx.x;
+    for (int j = 0; j < N; ++j) {
+        const double d = sqrt(A[j * N + j]);
+        if (t == j) dg[j] = d;
+        if (t > j && t < N) A[t * N + j] /= d;
+        __syncthreads();
+        const int rem = N - j - 1;
+        for (int e = t; e < rem * rem; e += blockDim.x) {
+            const int i = j + 1 + e / rem, k = j + 1 + e % rem;
+            if (k <= i) A[i * N + k] -= A[i * N + j] * A[k * N + j];
+        }
+        __syncthreads();
     }
 }
 
-// Forward dynamics qdd = M^-1 (tau - C - b qd) at (q, qd) by threads
-// 0..N of the workgroup (M's columns and C in parallel, the factorisation on
-// thread 0).  Msh: N*N doubles of LDS, qdd: N doubles of LDS (the result).
-// Must be reached by every thread of the workgroup.
-__device__ void forward_dynamics(int N, const double *mass, const double *len, double b,
-                                 const double *q, const double *qd, const double *tau,
-                                 double *Msh, double *qdd) {
-    const int tid = threadIdx.x;
-    double zero[NLINK_MAX], col[NLINK_MAX];
-    for (int i = 0; i < N; ++i) zero[i] = 0.0;
-    if (tid < N) {
-        double e[NLINK_MAX];
-        for (int i = 0; i < N; ++i) e[i] = i == tid ? 1.0 : 0.0;
-        rnea<double>(N, mass, len, q, zero, e, col);
-        for (int i = 0; i < N; ++i) Msh[i * N + tid] = col[i];
-    } else if (tid == N) {
-        rnea<double>(N, mass, len, q, qd, zero, col);
-        for (int i = 0; i < N; ++i) qdd[i] = tau[i] - col[i] - b * qd[i];
+// (L L^T)^-1 r with thread t < N holding r_t in yt (returned as y_t); each
+// step's pivot goes through sh (N doubles of LDS).  Every thread.
+__device__ double chol_solve_par(int N, const double *L, const double *dg, double yt,
+                                 double *sh) {
+    const int t = threadIdx.x;
+    for (int j = 0; j < N; ++j) {  // L z = r
+        if (t == j) {
+            yt /= dg[j];
+            sh[j] = yt;
+        }
+        __syncthreads();
+        if (t > j && t < N) yt -= L[t * N + j] * sh[j];
+    }
+    for (int j = N - 1; j >= 0; --j) {  // L^T y = z
+        if (t == j) {
+            yt /= dg[j];
+            sh[j] = yt;
+        }
+        __syncthreads();
+        if (t < j) yt -= L[j * N + t] * sh[j];
+    }
+    return yt;
+}
+
+// (L L^T)^-1 r for one right-hand side held in registers by one thread (L,
+// dg in LDS, read by every thread at the same address).
+__device__ __forceinline__ void chol_solve_regs(int N, const double *L, const double *dg,
+                                                double *y) {
+#pragma unroll
+    for (int i = 0; i < NLINK_MAX; ++i) {
+        if (i < N) {
+            double s = y[i];
+#pragma unroll
+            for (int k = 0; k < NLINK_MAX; ++k)
+                if (k < i) s -= L[i * N + k] * y[k];
+            y[i] = s / dg[i];
+        }
+    }
+#pragma unroll
+    for (int i = NLINK_MAX - 1; i >= 0; --i) {
+        if (i < N) {
+            double s = y[i];
+#pragma unroll
+            for (int k = 0; k < NLINK_MAX; ++k)
+                if (k > i && k < N) s -= L[k * N + i] * y[k];
+            y[i] = s / dg[i];
+        }
+    }
+}
+
+// Forward dynamics qdd = M^-1 (tau - C - b qd) at (q, qd) (LDS arrays) by the
+// workgroup: threads 0..N-1 build M's columns, thread N the bias C, all of
+// them factor M; the result qdd (LDS, N doubles) and the factor (Msh, dg)
+// are left for the caller.  Must be reached by every thread.
+// Sine and cosine of the absolute angles q_0 + .. + q_i, thread i (LDS).
+// Must be reached by every thread.
+__device__ void angle_table(int N, const double *q, double *sphi, double *cphi) {
+    const int t = threadIdx.x;
+    if (t < N) {
+        double phi = 0.0;
+        for (int i = 0; i <= t; ++i) phi += q[i];
+        sincos(phi, &sphi[t], &cphi[t]);
     }
     __syncthreads();
-    if (tid == 0) {
-        cholesky(N, Msh);
-        chol_solve(N, Msh, qdd);
+}
+
+__device__ void forward_dynamics(int N, const double *mass, const double *len, double b,
+                                 const double *q, const double *qd, const double *tau,
+                                 double *Msh, double *dg, double *sh, double *sphi,
+                                 double *cphi, double *qdd) {
+    const int tid = threadIdx.x;
+    auto zero = [](int) { return 0.0; };
+    auto qv = [&](int i) { return q[i]; };
+    double rhs = 0.0;
+    angle_table(N, q, sphi, cphi);
+    if (tid < N) {
+        double col[NLINK_MAX];
+        rnea<double>(N, mass, len, sphi, cphi, qv, zero,
+                     [&](int i) { return i == tid ? 1.0 : 0.0; }, col);
+#pragma unroll
+        for (int i = 0; i < NLINK_MAX; ++i)
+            if (i < N) Msh[i * N + tid] = col[i];
+    } else if (tid == N) {
+        double col[NLINK_MAX];
+        rnea<double>(N, mass, len, sphi, cphi, qv, [&](int i) { return qd[i]; }, zero, col);
+#pragma unroll
+        for (int i = 0; i < NLINK_MAX; ++i)
+            if (i < N) qdd[i] = tau[i] - col[i] - b * qd[i];
     }
+    __syncthreads();
+    if (tid < N) rhs = qdd[tid];
+    cholesky_par(N, Msh, dg);
+    rhs = chol_solve_par(N, Msh, dg, rhs, sh);
+    __syncthreads();  // every read of sh done before qdd (maybe the same caller buffer) changes
+    if (tid < N) qdd[tid] = rhs;
     __syncthreads();
 }
 
 constexpr int LIN_THREADS = 256;
-constexpr int ZMAX = 3 * NLINK_MAX + 1;  // n + m + 1 of the augmented hold matrix
 
-// C = A B (D x D, row-major, LDS), all threads
-__device__ void matmul_lds(int D, const double *A, const double *B, double *C) {
-    for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
-        const int i = e / D, j = e % D;
-        double s = 0.0;
-        for (int k = 0; k < D; ++k) s += A[i * D + k] * B[k * D + j];
-        C[e] = s;
+// C = A B for n x n matrices in LDS (row-major, leading dimension n), all
+// threads, a 2 x 2 block of C per thread
+__device__ void matmul_lds(int n, const double *A, const double *B, double *C) {
+    const int h = (n + 1) / 2;
+    for (int e = threadIdx.x; e < h * h; e += blockDim.x) {
+        const int i = 2 * (e / h), j = 2 * (e % h);
+        const bool i1 = i + 1 < n, j1 = j + 1 < n;
+        double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double a0 = A[i * n + k], a1 = i1 ? A[(i + 1) * n + k] : 0.0;
+            const double b0 = B[k * n + j], b1 = j1 ? B[k * n + j + 1] : 0.0;
+            c00 += a0 * b0;
+            c01 += a0 * b1;
+            c10 += a1 * b0;
+            c11 += a1 * b1;
+        }
+        C[i * n + j] = c00;
+        if (j1) C[i * n + j + 1] = c01;
+        if (i1) C[(i + 1) * n + j] = c10;
+        if (i1 && j1) C[(i + 1) * n + j + 1] = c11;
     }
     __syncthreads();
 }
+
+constexpr int NS_MAX = 2 * NLINK_MAX;  // states
 
 template <typename T>
 __global__ __launch_bounds__(LIN_THREADS) void nlink_linearize_kernel(
     int N, const T *__restrict__ mass_in, const T *__restrict__ len_in, double b, double dt,
     const T *__restrict__ x_in, const T *__restrict__ u_in, T *__restrict__ Ad,
     T *__restrict__ Bd, T *__restrict__ wd) {
-    __shared__ double mass[NLINK_MAX], len[NLINK_MAX], x[2 * NLINK_MAX], u[NLINK_MAX];
-    __shared__ double Msh[NLINK_MAX * NLINK_MAX], qdd0[NLINK_MAX];
+    __shared__ double mass[NLINK_MAX], len[NLINK_MAX], x[NS_MAX], u[NLINK_MAX];
+    __shared__ double Msh[NLINK_MAX * NLINK_MAX], dg[NLINK_MAX], sh[NLINK_MAX];
+    __shared__ double sphi[NLINK_MAX], cphi[NLINK_MAX], qdd0[NLINK_MAX];
     __shared__ double J[3 * NLINK_MAX][NLINK_MAX];  // dqdd / d(q, qd, tau), column s
-    __shared__ double Z[ZMAX * ZMAX], E[ZMAX * ZMAX], W[ZMAX * ZMAX];
+    __shared__ double Y[NS_MAX * NS_MAX], G[NS_MAX * NS_MAX], W[NS_MAX * NS_MAX];
+    __shared__ double Ph[NS_MAX * NS_MAX], F[NS_MAX * (NLINK_MAX + 1)];
     __shared__ int s_scale;
-    const int tid = threadIdx.x, n = 2 * N, m = N, D = n + m + 1;
+    const int tid = threadIdx.x, n = 2 * N, m = N;
     if (tid < N) {
         mass[tid] = (double)mass_in[tid];
         len[tid] = (double)len_in[tid];
@@ -169,86 +264,114 @@ __global__ __launch_bounds__(LIN_THREADS) void nlink_linearize_kernel(
     }
     if (tid < n) x[tid] = (double)x_in[tid];
     __syncthreads();
-    forward_dynamics(N, mass, len, b, x, x + N, u, Msh, qdd0);
-    // direction s < 2N: state x_s; 2N <= s < 3N: torque s - 2N
+    forward_dynamics(N, mass, len, b, x, x + N, u, Msh, dg, sh, sphi, cphi, qdd0);
+    // direction s < 2N: state x_s; 2N <= s < 3N: torque s - 2N.  The
+    // Jacobian of RNEA(q, qd, qdd0) in direction s by one dual-number pass.
     if (tid < 3 * N) {
         double y[NLINK_MAX];
         if (tid < n) {
-            Dual q[NLINK_MAX], qd[NLINK_MAX], a[NLINK_MAX], t[NLINK_MAX];
-            for (int i = 0; i < N; ++i) {
-                q[i] = {x[i], i == tid ? 1.0 : 0.0};
-                qd[i] = {x[N + i], N + i == tid ? 1.0 : 0.0};
-                a[i] = {qdd0[i], 0.0};
-            }
-            rnea<Dual>(N, mass, len, q, qd, a, t);
-            for (int i = 0; i < N; ++i) y[i] = -t[i].d - (N + i == tid ? b : 0.0);
+            Dual t[NLINK_MAX];
+            rnea<Dual>(
+                N, mass, len, sphi, cphi, [&](int i) { return Dual{x[i], i == tid ? 1.0 : 0.0}; },
+                [&](int i) { return Dual{x[N + i], N + i == tid ? 1.0 : 0.0}; },
+                [&](int i) { return Dual{qdd0[i], 0.0}; }, t);
+#pragma unroll
+            for (int i = 0; i < NLINK_MAX; ++i)
+                if (i < N) y[i] = -t[i].d - (N + i == tid ? b : 0.0);
         } else {
-            for (int i = 0; i < N; ++i) y[i] = i == tid - n ? 1.0 : 0.0;
+#pragma unroll
+            for (int i = 0; i < NLINK_MAX; ++i) y[i] = i == tid - n ? 1.0 : 0.0;
         }
-        chol_solve(N, Msh, y);
-        for (int i = 0; i < N; ++i) J[tid][i] = y[i];
+        chol_solve_regs(N, Msh, dg, y);
+#pragma unroll
+        for (int i = 0; i < NLINK_MAX; ++i)
+            if (i < N) J[tid][i] = y[i];
     }
     __syncthreads();
-    // Z = dt [[A, B, w], [0, 0, 0]]: position rows [0 I | 0 | 0] (their
-    // offset qd - qd is 0), velocity rows from J and the offset
-    // w = qdd0 - A x - B u
-    for (int e = tid; e < D * D; e += blockDim.x) {
-        const int i = e / D, j = e % D;
+    // f(x, u) ~ f0 + A (x' - x) + B (u' - u): A = [[0, I], [Jq, Jqd]],
+    // B = [[0], [Ju]], offset w = f0 - A x - B u (position rows: 0).
+    // F holds [B | w] (n x (m + 1)); Y = A dt first, scaled below.
+    const int m1 = m + 1;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        Y[e] = (i < N ? (j == N + i ? 1.0 : 0.0) : J[j][i - N]) * dt;
+    }
+    for (int e = tid; e < n * m1; e += blockDim.x) {
+        const int i = e / m1, j = e % m1;
         double v = 0.0;
-        if (i < N) {
-            v = (j == N + i) ? 1.0 : 0.0;
-        } else if (i < n) {
+        if (i >= N) {
             const int k = i - N;
-            if (j < n + m) {
-                v = J[j][k];
+            if (j < m) {
+                v = J[n + j][k];
             } else {
-                double w = qdd0[k];
-                for (int s = 0; s < n; ++s) w -= J[s][k] * x[s];
-                for (int s = 0; s < m; ++s) w -= J[n + s][k] * u[s];
-                v = w;
+                v = qdd0[k];
+                for (int s2 = 0; s2 < n; ++s2) v -= J[s2][k] * x[s2];
+                for (int s2 = 0; s2 < m; ++s2) v -= J[n + s2][k] * u[s2];
             }
         }
-        Z[e] = v * dt;
+        F[e] = v;
     }
     __syncthreads();
-    // scaling and squaring: Y = Z / 2^s with |Y|_1 <= 1/4, exp(Y) by the
-    // degree-16 Taylor polynomial in Horner form (truncation below 1e-26 of
-    // |exp(Y)|), then s squarings
-    if (tid == 0) {
-        double nrm = 0.0;
-        for (int j = 0; j < D; ++j) {
-            double c = 0.0;
-            for (int i = 0; i < D; ++i) c += fabs(Z[i * D + j]);
-            nrm = c > nrm ? c : nrm;
+    // Zero-order hold: Phi = exp(A dt), Gamma = int_0^dt exp(A s) ds, then
+    // A_d = Phi, [B_d w_d] = Gamma [B w].  Scaling and squaring on
+    // h = dt / 2^s with |A h|_1 <= 1/4: G = sum_k (A h)^k / (k+1)! by a
+    // degree-14 Horner scheme (truncation below 1e-20), Phi(h) = I + A h G,
+    // Gamma(h) = h G; each squaring Gamma <- Gamma + Phi Gamma,
+    // Phi <- Phi Phi.  The column sums of |Y| and their maximum by the first
+    // wavefront.
+    if (tid < 64) {
+        double c = 0.0;
+        if (tid < n)
+            for (int i = 0; i < n; ++i) c += fabs(Y[i * n + tid]);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) c = fmax(c, __shfl_xor(c, o, 64));
+        if (tid == 0) {
+            int sc = 0;
+            while (c > 0.25 && sc < 64) {
+                c *= 0.5;
+                ++sc;
+            }
+            s_scale = sc;
         }
-        int s = 0;
-        while (nrm > 0.25 && s < 64) {
-            nrm *= 0.5;
-            ++s;
-        }
-        s_scale = s;
     }
     __syncthreads();
-    const double sc = ldexp(1.0, -s_scale);
-    for (int e = tid; e < D * D; e += blockDim.x) {
-        Z[e] *= sc;
-        E[e] = (e / D == e % D ? 1.0 : 0.0) + Z[e] / 16.0;
+    const int sc = s_scale;
+    const double scl = ldexp(1.0, -sc), h = dt * scl;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        Y[e] *= scl;
+        G[e] = (e / n == e % n ? 1.0 : 0.0) + Y[e] / 15.0;
     }
     __syncthreads();
-    for (int k = 15; k >= 1; --k) {
-        matmul_lds(D, Z, E, W);  // W = Y E
-        for (int e = tid; e < D * D; e += blockDim.x)
-            E[e] = (e / D == e % D ? 1.0 : 0.0) + W[e] / (double)k;
+    for (int k = 13; k >= 1; --k) {  // G <- I + Y G / (k + 1)
+        matmul_lds(n, Y, G, W);
+        for (int e = tid; e < n * n; e += blockDim.x)
+            G[e] = (e / n == e % n ? 1.0 : 0.0) + W[e] / (double)(k + 1);
         __syncthreads();
     }
-    for (int r = 0; r < s_scale; ++r) {
-        matmul_lds(D, E, E, W);
-        for (int e = tid; e < D * D; e += blockDim.x) E[e] = W[e];
+    matmul_lds(n, Y, G, W);
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        Ph[e] = (e / n == e % n ? 1.0 : 0.0) + W[e];
+        G[e] *= h;
+    }
+    __syncthreads();
+    for (int r = 0; r < sc; ++r) {
+        matmul_lds(n, Ph, G, W);  // Phi Gamma
+        for (int e = tid; e < n * n; e += blockDim.x) G[e] += W[e];
+        __syncthreads();
+        matmul_lds(n, Ph, Ph, W);
+        for (int e = tid; e < n * n; e += blockDim.x) Ph[e] = W[e];
         __syncthreads();
     }
-    for (int e = tid; e < n * n; e += blockDim.x) Ad[e] = (T)E[(e / n) * D + e % n];
-    for (int e = tid; e < n * m; e += blockDim.x) Bd[e] = (T)E[(e / m) * D + n + e % m];
-    if (tid < n) wd[tid] = (T)E[tid * D + n + m];
+    for (int e = tid; e < n * n; e += blockDim.x) Ad[e] = (T)Ph[e];
+    for (int e = tid; e < n * m1; e += blockDim.x) {
+        const int i = e / m1, j = e % m1;
+        double v = 0.0;
+        for (int k = 0; k < n; ++k) v += G[i * n + k] * F[k * m1 + j];
+        if (j < m)
+            Bd[i * m + j] = (T)v;
+        else
+            wd[i] = (T)v;
+    }
 }
 
 constexpr int STEP_THREADS = 64;
@@ -259,40 +382,39 @@ __global__ __launch_bounds__(STEP_THREADS) void nlink_step_kernel(
     int N, const T *__restrict__ mass_in, const T *__restrict__ len_in, double b, double dt,
     int sub, const T *x_in, const T *__restrict__ u_in, T *x_out) {
     __shared__ double mass[NLINK_MAX], len[NLINK_MAX], tau[NLINK_MAX];
-    __shared__ double y[2 * NLINK_MAX], st[2 * NLINK_MAX], acc[2 * NLINK_MAX];
-    __shared__ double Msh[NLINK_MAX * NLINK_MAX], qdd[NLINK_MAX];
+    __shared__ double st[NS_MAX];
+    __shared__ double Msh[NLINK_MAX * NLINK_MAX], dg[NLINK_MAX], sh[NLINK_MAX], qdd[NLINK_MAX];
+    __shared__ double sphi[NLINK_MAX], cphi[NLINK_MAX];
     const int tid = threadIdx.x, n = 2 * N;
     if (tid < N) {
         mass[tid] = (double)mass_in[tid];
         len[tid] = (double)len_in[tid];
         tau[tid] = (double)u_in[tid];
     }
-    if (tid < n) y[tid] = (double)x_in[tid];
-    __syncthreads();
-    const double h = dt / sub;
+    // thread i < n keeps state i (y), its RK4 sum (acc) in registers
+    double y = tid < n ? (double)x_in[tid] : 0.0;
+    const double hs = dt / sub;
     const double wt[4] = {1.0, 2.0, 2.0, 1.0}, off[4] = {0.0, 0.5, 0.5, 1.0};
     for (int s = 0; s < sub; ++s) {
-        if (tid < n) {
-            st[tid] = y[tid];
-            acc[tid] = 0.0;
-        }
+        double acc = 0.0;
+        if (tid < n) st[tid] = y;
         __syncthreads();
+#pragma unroll
         for (int stage = 0; stage < 4; ++stage) {
-            forward_dynamics(N, mass, len, b, st, st + N, tau, Msh, qdd);
+            forward_dynamics(N, mass, len, b, st, st + N, tau, Msh, dg, sh, sphi, cphi, qdd);
             // k = [qd; qdd] at the stage state; next stage state y + off h k
             double k = 0.0;
             if (tid < n) {
                 k = tid < N ? st[N + tid] : qdd[tid - N];
-                acc[tid] += wt[stage] * k;
+                acc += wt[stage] * k;
             }
             __syncthreads();
-            if (tid < n && stage < 3) st[tid] = y[tid] + off[stage + 1] * h * k;
+            if (tid < n && stage < 3) st[tid] = y + off[stage + 1] * hs * k;
             __syncthreads();
         }
-        if (tid < n) y[tid] += h / 6.0 * acc[tid];
-        __syncthreads();
+        if (tid < n) y += hs / 6.0 * acc;
     }
-    if (tid < n) x_out[tid] = (T)y[tid];
+    if (tid < n) x_out[tid] = (T)y;
 }
 
 }  // namespace
