@@ -119,13 +119,27 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // its parents in place from the other one), costs [pop], elite knots [pm][k]
 // (the parents carried to the next tick), elite costs [k], elite indices
 // [k] (int64), best index (int64), and the parents as a structure of arrays
-// [pm][k] for gradient refinement.
+// [pm][k] for gradient refinement; for a linear problem without the state
+// box whose quadratic form (Sec. IV-B) fits in QP_REFINE_MAX_BYTES, that
+// form too: P [pm][pm], q [pm], c, and the unit-knot responses it is built
+// from (refinement then runs on the form instead of the adjoint).
 struct Workspace {
     int *has_elites, *best_slot;
     void *knots[2], *cost, *elite_rows, *elite_cost, *elite_soa;
     int64_t *elite_idx, *best_idx;
+    void *qP = nullptr, *qq = nullptr, *qc = nullptr, *qws = nullptr;  // quadratic form
     size_t bytes;
 };
+
+constexpr size_t QP_REFINE_MAX_BYTES = 8ull << 20;
+
+// the linear-quadratic case whose parents refine on the quadratic form
+bool quadratic_refine(const empc_problem *P) {
+    if (P->model != EMPC_LINEAR || P->qb || P->Q || P->R || P->Qf) return false;
+    const int pm = P->p * P->m;
+    if (pm > QP_REFINE_MAX_PM) return false;
+    return qp_form_bytes(P->n, P->T, pm) + (size_t)pm * pm * esize(P) <= QP_REFINE_MAX_BYTES;
+}
 
 Workspace layout(const empc_problem *P, const empc_ga *G, void *base) {
     const size_t es = esize(P), pm = (size_t)P->p * P->m, pop = G->pop, k = G->n_elite;
@@ -143,6 +157,12 @@ Workspace layout(const empc_problem *P, const empc_ga *G, void *base) {
     w.elite_idx = (int64_t *)(b + off); off += align256(k * sizeof(int64_t));
     w.best_idx = (int64_t *)(b + off); off += 256;
     w.elite_soa = b + off; off += align256(k * pm * es);
+    if (quadratic_refine(P)) {
+        w.qP = b + off; off += align256(pm * pm * es);
+        w.qq = b + off; off += align256(pm * es);
+        w.qc = b + off; off += 256;
+        w.qws = b + off; off += align256(qp_form_bytes(P->n, P->T, (int)pm));
+    }
     w.bytes = off;
     return w;
 }
@@ -195,19 +215,28 @@ hipError_t timed_rollout(const ProbView<T> &V, int model, const T *x0, const T *
     return launch_rollout<T>(V, model, x0, knots, ncand, ld, cost, s, next_events(), form);
 }
 
-// Gradient refinement of the parents after a selection: gather them, run
-// Adam, write the parent rows back, pick the best refined parent.
+// Gradient refinement of the parents after a selection: Adam on the
+// parents, which land in elite_soa ([pm][k], the layout of the parent rows:
+// the next generation's population reads them there); after the last
+// generation the parent rows for the next tick, u* and the best cost.
 template <typename T>
 hipError_t refine_parents(const empc_problem *P, const empc_ga *G, const Workspace &w,
                           const void *x0, const T *cur, double lr, int steps, bool last,
                           void *u_star, void *best_cost, hipStream_t s) {
     const ProbView<T> V = view_of<T>(*P);
     const int k = G->n_elite, pm = P->p * P->m;
-    hipError_t e = launch_gather_parents<T>(cur, G->pop, w.elite_idx, k, pm, (T *)w.elite_soa, s);
-    if (e != hipSuccess) return e;
-    e = launch_grad<T>(V, P->model, (const T *)x0, nullptr, k, k, nullptr, nullptr, steps, (T)lr,
-                       (T *)w.elite_soa, (T *)w.elite_cost, s);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (w.qP) {  // on the quadratic form of this tick (built before generation 0)
+        e = launch_qp_refine<T>(V, (const T *)w.qP, (const T *)w.qq, (const T *)w.qc, cur,
+                                G->pop, w.elite_idx, (T *)w.elite_soa, k, steps, (T)lr,
+                                (T *)w.elite_cost, s);
+    } else {
+        e = launch_gather_parents<T>(cur, G->pop, w.elite_idx, k, pm, (T *)w.elite_soa, s);
+        if (e == hipSuccess)
+            e = launch_grad<T>(V, P->model, (const T *)x0, nullptr, k, k, nullptr, nullptr,
+                               steps, (T)lr, (T *)w.elite_soa, (T *)w.elite_cost, s);
+    }
+    if (e != hipSuccess || !last) return e;
     return launch_finish_refine<T>((const T *)w.elite_soa, k, pm, P->m, (const T *)w.elite_cost,
                                    (T *)w.elite_rows, w.best_slot, last ? (T *)u_star : nullptr,
                                    last ? (T *)best_cost : nullptr, s);
@@ -221,6 +250,11 @@ empc_status solve_t(const empc_problem *P, const empc_ga *G, const Workspace &w,
     const int64_t pop = G->pop;
     const bool refine = adam_steps > 0;
     const Tuned tu = tuned_for(P, pop);
+    if (refine && w.qP) {  // the quadratic form at this tick's x0 (the model may change per tick)
+        const hipError_t e = launch_qp_form<T>(V, (const T *)x0, w.qws, (T *)w.qP, (T *)w.qq,
+                                               (T *)w.qc, s);
+        if (e != hipSuccess) return device_status(e, "quadratic form launch");
+    }
     for (int g = 0; g < G->generations; ++g) {
         const bool last = g == G->generations - 1;
         T *cur = (T *)w.knots[g & 1];
@@ -230,9 +264,10 @@ empc_status solve_t(const empc_problem *P, const empc_ga *G, const Workspace &w,
         // (with refinement the parents are always the refined parent rows)
         // (the optional shift moves the carried parents once, at generation 0)
         const PopVariant<T> var = pop_variant<T>(*G, x0, g == 0);
+        // (refined parents of the previous generation: elite_soa, same layout)
+        const T *rows = (g > 0 && refine) ? (const T *)w.elite_soa : (const T *)w.elite_rows;
         hipError_t e = (g == 0 || refine)
-                           ? launch_population<T>(V, *G, nullptr, 0, nullptr,
-                                                  (const T *)w.elite_rows, w.has_elites,
+                           ? launch_population<T>(V, *G, nullptr, 0, nullptr, rows, w.has_elites,
                                                   g == 0 ? 2 : 0, cur, pop, tick, (uint32_t)g, s,
                                                   var, tu.R)
                            : launch_population<T>(V, *G, prev, pop, w.elite_idx, nullptr,

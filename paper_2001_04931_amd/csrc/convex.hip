@@ -78,19 +78,25 @@ __device__ inline double row_weight(const ProbView<T> &P, int K) {
     return w;
 }
 
+// Partial Gram products over a slice of the stacked state rows (split K):
+// blockIdx.z = slice; Ppart[z][i][j] = sum over the slice's rows K of
+// w_K S[K][i] S[K][j].
+constexpr int GRAM_SPLIT = 8;
 template <typename T>
 __global__ __launch_bounds__(256) void qp_gram_kernel(ProbView<T> P, const double *__restrict__ S,
-                                                      T *__restrict__ Pout) {
+                                                      double *__restrict__ Ppart) {
     __shared__ double As[16][17], Bs[16][17];
     const int pm = P.p * P.m, K = P.Tn * P.n;
     const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
     const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+    const int kb = (int)((int64_t)K * blockIdx.z / GRAM_SPLIT);
+    const int ke = (int)((int64_t)K * (blockIdx.z + 1) / GRAM_SPLIT);
     double acc = 0.0;
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = kb; k0 < ke; k0 += 16) {
         // thread (ti, tj) stages row k0 + ti, columns i0 + tj / j0 + tj
         const int kr = k0 + ti;
         double a = 0.0, b = 0.0;
-        if (kr < K) {
+        if (kr < ke) {
             const double w = row_weight(P, kr);
             if (i0 + tj < pm) a = w * S[(int64_t)kr * pm + i0 + tj];
             if (j0 + tj < pm) b = S[(int64_t)kr * pm + j0 + tj];
@@ -103,41 +109,52 @@ __global__ __launch_bounds__(256) void qp_gram_kernel(ProbView<T> P, const doubl
         __syncthreads();
     }
     const int i = i0 + ti, j = j0 + tj;
-    if (i < pm && j < pm) {
-        const int m = P.m;
-        if (i % m == j % m) {
-            // input part: sum_k w_k(knot of i) w_k(knot of j) r_input
-            double s = 0.0;
-            for (int k = 0; k < P.Tn; ++k)
-                s += knot_weight(P.Tn, P.p, k, i / m) * knot_weight(P.Tn, P.p, k, j / m);
-            acc += s * (double)P.r[i % m];
-        }
-        Pout[(int64_t)i * pm + j] = (T)acc;
-    }
+    if (i < pm && j < pm) Ppart[((int64_t)blockIdx.z * pm + i) * pm + j] = acc;
 }
 
+// P = the partial products summed in slice order, plus the input part
+// sum_k w_k(knot of i) w_k(knot of j) r_input on matching inputs.
+template <typename T>
+__global__ __launch_bounds__(256) void qp_gram_sum_kernel(ProbView<T> P,
+                                                          const double *__restrict__ Ppart,
+                                                          T *__restrict__ Pout) {
+    const int pm = P.p * P.m, m = P.m;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)pm * pm) return;
+    const int i = (int)(e / pm), j = (int)(e % pm);
+    double acc = 0.0;
+#pragma unroll
+    for (int z = 0; z < GRAM_SPLIT; ++z) acc += Ppart[(int64_t)z * pm * pm + e];
+    if (i % m == j % m) {
+        double s = 0.0;
+        for (int k = 0; k < P.Tn; ++k)
+            s += knot_weight(P.Tn, P.p, k, i / m) * knot_weight(P.Tn, P.p, k, j / m);
+        acc += s * (double)P.r[i % m];
+    }
+    Pout[e] = (T)acc;
+}
+
+// q_i (block i < pm) and c (block pm): sums over the stacked state rows
+// K = k n + r, spread over the workgroup's threads and reduced in LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void qp_lin_kernel(ProbView<T> P, const double *__restrict__ S,
                                                      const double *__restrict__ v,
                                                      T *__restrict__ qout, T *__restrict__ cout) {
     __shared__ double part[256];
     const int pm = P.p * P.m, K = P.Tn * P.n, m = P.m;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x;
+    double s = 0.0;
     if (i < pm) {
-        double s = 0.0;
-        for (int kr = 0; kr < K; ++kr) {
+        for (int kr = threadIdx.x; kr < K; kr += blockDim.x) {
             const double g = P.xg ? (double)P.xg[kr % P.n] : 0.0;
             s += S[(int64_t)kr * pm + i] * row_weight(P, kr) * (v[kr] - g);
         }
-        if (P.ug) {
+        if (P.ug && threadIdx.x == 0) {
             double wsum = 0.0;
             for (int k = 0; k < P.Tn; ++k) wsum += knot_weight(P.Tn, P.p, k, i / m);
             s -= wsum * (double)P.r[i % m] * (double)P.ug[i % m];
         }
-        qout[i] = (T)s;
-    }
-    if (blockIdx.x == 0) {
-        double s = 0.0;
+    } else {
         for (int kr = threadIdx.x; kr < K; kr += blockDim.x) {
             const double e = v[kr] - (P.xg ? (double)P.xg[kr % P.n] : 0.0);
             s += row_weight(P, kr) * e * e;
@@ -145,14 +162,170 @@ __global__ __launch_bounds__(256) void qp_lin_kernel(ProbView<T> P, const double
         if (P.ug)
             for (int ii = threadIdx.x; ii < m; ii += blockDim.x)
                 s += (double)P.Tn * (double)P.r[ii] * (double)P.ug[ii] * (double)P.ug[ii];
-        part[threadIdx.x] = s;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) *cout = (T)part[0];
     }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (i < pm)
+            qout[i] = (T)part[0];
+        else
+            *cout = (T)part[0];
+    }
+}
+
+// Adam refinement of k parents on the quadratic J(z) = z^T P z + 2 q^T z + c
+// of a linear problem without the state box: its gradient 2 (P z + q) is
+// the rollout cost's gradient exactly (the value the adjoint builds step by
+// step), so an Adam step is one product with the symmetric P.  The Adam of
+// the adjoint kernel: moments from zero, bias correction, a clamp to the
+// knot bounds after every update, and the result kept only if its cost (by
+// the same quadratic) is below the entry cost.  The parents are read from
+// the population (parameter j of parent b at knots[j ld + idx[b]]) and
+// written, refined or not, to Z: [pm][k]; cost_io [k] takes the refined
+// costs.  One workgroup per parent, up to QP_MAX_PM parameters.  When P fits
+// in the workgroup's LDS (dynamic size pm^2 elements) it is staged there
+// once and every product reads it from LDS; otherwise from global memory.
+// LS: rows per lane of the product (pm <= 64 LS), a compile-time count so
+// the slot loops carry no runtime guards.
+constexpr int REF_THREADS = 256, REF_WAVES = REF_THREADS / 64;
+constexpr size_t REF_LDS_MAX = 96 * 1024;  // bytes of P staged in LDS at most
+template <typename T, int LS>
+__global__ __launch_bounds__(REF_THREADS) void qp_refine_kernel(
+    int pm, int m, int k, const T *__restrict__ Pg, const T *__restrict__ qv,
+    const T *__restrict__ cp, const T *__restrict__ umin, const T *__restrict__ umax, int steps,
+    T lr, const T *__restrict__ knots, int64_t ld, const int64_t *__restrict__ idx,
+    T *__restrict__ Z, T *__restrict__ cost_io, int p_in_lds) {
+    constexpr int REF_SLOTS = (64 * LS + REF_THREADS - 1) / REF_THREADS;
+    constexpr int NP = 64 * LS;  // parameters at most
+    extern __shared__ __align__(16) unsigned char ref_smem[];
+    __shared__ T zs[NP];
+    __shared__ double part[REF_WAVES][NP];
+    __shared__ double red[REF_WAVES];
+    const int tid = threadIdx.x, b = blockIdx.x, lane = tid & 63, wv = tid >> 6;
+    T *Pl = (T *)ref_smem;
+    const int64_t src = idx[b];
+    for (int i = tid; i < pm; i += REF_THREADS) zs[i] = knots[(int64_t)i * ld + src];
+    if (p_in_lds) {  // eight loads in flight per thread, then their stores
+        const int tot = pm * pm;
+        for (int e0 = tid; e0 < tot; e0 += 8 * REF_THREADS) {
+            T t8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * REF_THREADS;
+                t8[u] = e < tot ? Pg[e] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * REF_THREADS;
+                if (e < tot) Pl[e] = t8[u];
+            }
+        }
+    }
+    const T *Pm = p_in_lds ? Pl : Pg;
+    // this thread's parameters: linear term and bounds in registers
+    T qr[REF_SLOTS], lo[REF_SLOTS], hi[REF_SLOTS];
+#pragma unroll
+    for (int sl = 0; sl < REF_SLOTS; ++sl) {
+        const int i = tid + REF_THREADS * sl;
+        qr[sl] = i < pm ? qv[i] : (T)0;
+        lo[sl] = i < pm ? umin[i % m] : (T)0;
+        hi[sl] = i < pm ? umax[i % m] : (T)0;
+    }
+    const double c0 = (double)*cp;
+    __syncthreads();
+    // y = P z: wavefront w sums the columns j of its quarter of 0..pm-1
+    // for every row i = lane + 64 s (P symmetric: column j read as row j,
+    // contiguous over the lanes), the quarters added in LDS; then
+    // J = sum_i z_i (y_i + 2 q_i) + c over the workgroup.  Each thread
+    // returns y for its parameters i = tid + REF_THREADS s.
+    double y[REF_SLOTS];
+    const int jb = pm * wv / REF_WAVES, je = pm * (wv + 1) / REF_WAVES;
+    auto product = [&]() {
+        // partial sums in the problem's precision, four columns per pass
+        // so that their loads are in flight together
+        T acc[LS];
+#pragma unroll
+        for (int sl = 0; sl < LS; ++sl) acc[sl] = 0;
+#pragma unroll 4
+        for (int j = jb; j < je; ++j) {
+            const T zj = zs[j];
+            const T *row = Pm + (int64_t)j * pm;
+#pragma unroll
+            for (int sl = 0; sl < LS; ++sl) {
+                const int i = lane + 64 * sl;
+                acc[sl] += (i < pm ? row[i] : (T)0) * zj;
+            }
+        }
+#pragma unroll
+        for (int sl = 0; sl < LS; ++sl) {
+            const int i = lane + 64 * sl;
+            if (i < pm) part[wv][i] = (double)acc[sl];
+        }
+        __syncthreads();
+        double pj = 0.0;
+#pragma unroll
+        for (int sl = 0; sl < REF_SLOTS; ++sl) {
+            const int i = tid + REF_THREADS * sl;
+            double a = 0.0;
+            if (i < pm) {
+#pragma unroll
+                for (int w2 = 0; w2 < REF_WAVES; ++w2) a += part[w2][i];
+                pj += (double)zs[i] * (a + 2.0 * (double)qr[sl]);
+            }
+            y[sl] = a;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) pj += __shfl_xor(pj, o, 64);
+        if (lane == 0) red[wv] = pj;
+        __syncthreads();
+        double J = c0;
+#pragma unroll
+        for (int w2 = 0; w2 < REF_WAVES; ++w2) J += red[w2];
+        return J;
+    };
+    const T b1 = (T)0.9, b2 = (T)0.999, eps = (T)1e-8;
+    T b1t = 1, b2t = 1;
+    T m1[REF_SLOTS], m2[REF_SLOTS];
+#pragma unroll
+    for (int sl = 0; sl < REF_SLOTS; ++sl) m1[sl] = m2[sl] = 0;
+    double J0 = 0.0;
+    for (int t = 1; t <= steps; ++t) {
+        const double Jt = product();
+        if (t == 1) J0 = Jt;
+        b1t *= b1;
+        b2t *= b2;
+        T U[REF_SLOTS];
+#pragma unroll
+        for (int sl = 0; sl < REF_SLOTS; ++sl) {
+            const int i = tid + REF_THREADS * sl;
+            if (i < pm) {
+                const T g = (T)(2.0 * (y[sl] + (double)qr[sl]));
+                m1[sl] = b1 * m1[sl] + ((T)1 - b1) * g;
+                m2[sl] = b2 * m2[sl] + ((T)1 - b2) * g * g;
+                const T mh = m1[sl] / ((T)1 - b1t), vh = m2[sl] / ((T)1 - b2t);
+                T u = zs[i] - lr * mh / (sqrt(vh) + eps);
+                u = u < lo[sl] ? lo[sl] : u;
+                u = u > hi[sl] ? hi[sl] : u;
+                U[sl] = u;
+            }
+        }
+        __syncthreads();  // every read of z done
+#pragma unroll
+        for (int sl = 0; sl < REF_SLOTS; ++sl) {
+            const int i = tid + REF_THREADS * sl;
+            if (i < pm) zs[i] = U[sl];
+        }
+        __syncthreads();
+    }
+    const double Jn = product();
+    const bool keep = steps > 0 && Jn < J0;  // uniform over the workgroup
+    for (int i = tid; i < pm; i += REF_THREADS)
+        Z[(int64_t)i * k + b] = keep ? zs[i] : knots[(int64_t)i * ld + src];
+    if (keep && tid == 0) cost_io[b] = (T)Jn;
 }
 
 // sum over the workgroup (every thread gets it)
@@ -319,9 +492,16 @@ __global__ __launch_bounds__(QP_THREADS) void qp_box_kernel(
 
 }  // namespace
 
+// workspace of the form, in doubles: S [T n][pm], v [T n], the split-K
+// partial Gram products [GRAM_SPLIT][pm][pm]; the box solver adds H [pm][pm]
+static size_t form_doubles(int n, int T, int pm) {
+    const size_t S = (size_t)T * n * pm, v = (size_t)T * n;
+    const size_t G = (size_t)GRAM_SPLIT * pm * pm;
+    return (S + 31) / 32 * 32 + (v + 31) / 32 * 32 + (G + 31) / 32 * 32;
+}
+
 size_t qp_workspace_bytes(int n, int T, int pm) {
-    const size_t S = (size_t)T * n * pm, v = (size_t)T * n, H = (size_t)pm * pm;
-    return ((S + 31) / 32 * 32 + (v + 31) / 32 * 32 + H) * sizeof(double);
+    return (form_doubles(n, T, pm) + (size_t)pm * pm) * sizeof(double);
 }
 
 template <typename T>
@@ -330,19 +510,58 @@ hipError_t launch_qp_form(const ProbView<T> &P, const T *x0, void *ws, T *Pout, 
     const int pm = P.p * P.m, n = P.n;
     double *S = (double *)ws;
     double *v = S + ((size_t)P.Tn * n * pm + 31) / 32 * 32;
+    double *Gp = v + ((size_t)P.Tn * n + 31) / 32 * 32;
     hipLaunchKernelGGL(qp_traj_kernel<T>, dim3(pm + 1), dim3(TRAJ_THREADS), 0, s, P, x0, S, v);
     const unsigned tiles = (unsigned)((pm + 15) / 16);
-    hipLaunchKernelGGL(qp_gram_kernel<T>, dim3(tiles, tiles), dim3(256), 0, s, P, S, Pout);
-    hipLaunchKernelGGL(qp_lin_kernel<T>, dim3((pm + 255) / 256), dim3(256), 0, s, P, S, v, qout,
-                       cout);
+    hipLaunchKernelGGL(qp_gram_kernel<T>, dim3(tiles, tiles, GRAM_SPLIT), dim3(256), 0, s, P, S,
+                       Gp);
+    hipLaunchKernelGGL(qp_gram_sum_kernel<T>, dim3((unsigned)(((int64_t)pm * pm + 255) / 256)),
+                       dim3(256), 0, s, P, Gp, Pout);
+    hipLaunchKernelGGL(qp_lin_kernel<T>, dim3(pm + 1), dim3(256), 0, s, P, S, v, qout, cout);
     return hipGetLastError();
 }
+
+size_t qp_form_bytes(int n, int T, int pm) { return form_doubles(n, T, pm) * sizeof(double); }
+
+template <typename T>
+hipError_t launch_qp_refine(const ProbView<T> &P, const T *Pm, const T *q, const T *c,
+                            const T *knots, int64_t ld, const int64_t *idx, T *Z, int k,
+                            int steps, T lr, T *cost_io, hipStream_t s) {
+    const int pm = P.p * P.m;
+    const size_t bytes = (size_t)pm * pm * sizeof(T);
+    const int in_lds = bytes <= REF_LDS_MAX ? 1 : 0;
+    const size_t dyn = in_lds ? bytes : 0;
+    auto go = [&](auto kernel) {
+        if (dyn > 65536) {
+            const hipError_t e = hipFuncSetAttribute((const void *)kernel,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)dyn);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kernel, dim3(k), dim3(REF_THREADS), dyn, s, pm, P.m, k, Pm, q, c,
+                           P.umin, P.umax, steps, lr, knots, ld, idx, Z, cost_io, in_lds);
+        return hipGetLastError();
+    };
+    if (pm <= 64) return go(qp_refine_kernel<T, 1>);
+    if (pm <= 128) return go(qp_refine_kernel<T, 2>);
+    if (pm <= 256) return go(qp_refine_kernel<T, 4>);
+    if (pm <= 512) return go(qp_refine_kernel<T, 8>);
+    return go(qp_refine_kernel<T, 16>);
+}
+template hipError_t launch_qp_refine<float>(const ProbView<float> &, const float *, const float *,
+                                            const float *, const float *, int64_t,
+                                            const int64_t *, float *, int, int, float, float *,
+                                            hipStream_t);
+template hipError_t launch_qp_refine<double>(const ProbView<double> &, const double *,
+                                             const double *, const double *, const double *,
+                                             int64_t, const int64_t *, double *, int, int, double,
+                                             double *, hipStream_t);
 
 template <typename T>
 hipError_t launch_qp_solve(const ProbView<T> &P, const T *Pm, const T *q, const T *c, void *ws,
                            int max_iter, T *z, T *cost, int *info, hipStream_t s) {
     const int pm = P.p * P.m, n = P.n;
-    double *H = (double *)ws + ((size_t)P.Tn * n * pm + 31) / 32 * 32 + ((size_t)P.Tn * n + 31) / 32 * 32;
+    double *H = (double *)ws + form_doubles(n, P.Tn, pm);
     hipLaunchKernelGGL(qp_box_kernel<T>, dim3(1), dim3(QP_THREADS), 0, s, pm, P.m, P.umin, P.umax,
                        Pm, q, c, max_iter, H, z, cost, info);
     return hipGetLastError();

@@ -409,6 +409,13 @@ size_t qp_workspace_bytes(int n, int T, int pm);
 template <typename T>
 hipError_t launch_qp_form(const ProbView<T> &P, const T *x0, void *ws, T *Pout, T *qout, T *cout,
                           hipStream_t s);
+// the S, v part of the form's workspace (what launch_qp_form needs)
+size_t qp_form_bytes(int n, int T, int pm);
+constexpr int QP_REFINE_MAX_PM = 1024;  // parameters of the quadratic refinement
+template <typename T>
+hipError_t launch_qp_refine(const ProbView<T> &P, const T *Pm, const T *q, const T *c,
+                            const T *knots, int64_t ld, const int64_t *idx, T *Z, int k,
+                            int steps, T lr, T *cost_io, hipStream_t s);
 template <typename T>
 hipError_t launch_qp_solve(const ProbView<T> &P, const T *Pm, const T *q, const T *c, void *ws,
                            int max_iter, T *z, T *cost, int *info, hipStream_t s);

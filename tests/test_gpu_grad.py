@@ -212,3 +212,27 @@ def test_refined_solve_fp32_c2_not_worse(E):
     _, Jp = plain.solve(x0, 0)
     _, Jr = refined.solve(x0, 0, refine_steps=5, lr=0.01)
     assert float(Jr.item()) <= float(Jp.item()) * (1 + 1e-4)
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_refined_solve_quadratic_form_equals_adjoint_path(E, dtype):
+    # a linear problem without the state box refines its parents on the
+    # quadratic form 2 (P z + q); the same problem with a box of infinite
+    # bounds (no penalty, but not quadratic to the library) refines through
+    # the adjoint kernel: both give the same ticks (FP64 1e-9; FP32 through
+    # a few ticks within the FP32 tolerance of the cost)
+    prob = W.linear_chain(4, 25, 5, seed=8)
+    boxed = W.dataclasses.replace(prob, x_min=np.full(prob.n, -np.inf),
+                                  x_max=np.full(prob.n, np.inf), qb=np.ones(prob.n))
+    ga = W.GA(pop=256, n_elite=16, generations=4 if dtype == F64 else 1, sigma=0.1, seed=6)
+    sq = E.Solver(E.DeviceProblem(prob, dtype), ga)
+    sa = E.Solver(E.DeviceProblem(boxed, dtype), ga)
+    x = dev(W.draw_x0(prob.n, 8), dtype)
+    rtol = 1e-9 if dtype == F64 else 2e-4
+    for tick in range(3 if dtype == F64 else 1):
+        uq, Jq = sq.solve(x, tick, refine_steps=5, lr=0.01)
+        ua, Ja = sa.solve(x, tick, refine_steps=5, lr=0.01)
+        np.testing.assert_allclose(float(Jq.item()), float(Ja.item()), rtol=rtol)
+        if dtype == F64:
+            np.testing.assert_allclose(uq.cpu().numpy(), ua.cpu().numpy(), rtol=1e-9,
+                                       atol=1e-12)
