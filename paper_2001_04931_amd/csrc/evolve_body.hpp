@@ -137,12 +137,17 @@ __device__ __forceinline__ void population_tile(
     for (int rg = 0; rg < R; ++rg) {
         const int j0 = jt + 16 * rg + 4 * w;
         if (j0 >= pm) break;
+        // inputs of parameters j0 .. j0+3: one division, then wrap at m
+        int ii[4];
+        ii[0] = j0 % m;
+#pragma unroll
+        for (int r = 1; r < 4; ++r) ii[r] = ii[r - 1] + 1 == m ? 0 : ii[r - 1] + 1;
         T val[4];
         if (cold) {
             const U4 wc = ga_draw(gs, slot, gen, tick, 1, (uint32_t)(j0 / 4));
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = (j0 + r) % m;
+                const int i = ii[r];
                 val[r] = P.umin[i] + (P.umax[i] - P.umin[i]) * uni23<T>(word_of(wc, r));
             }
         } else {
@@ -166,12 +171,9 @@ __device__ __forceinline__ void population_tile(
                 const int64_t src1 = elite_rows ? (int64_t)p1 : s_eidx[p1];
                 const int64_t src2 = elite_rows ? (int64_t)p2 : s_eidx[p2];
                 bool flag[4];
-                int ii[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    ii[r] = (j0 + r) % m;
+                for (int r = 0; r < 4; ++r)
                     flag[r] = j0 + r < pm && ((s_flag[lane][ii[r] / 32] >> (ii[r] % 32)) & 1u);
-                }
                 T z[4] = {0, 0, 0, 0};
                 if (flag[0] || flag[1] || flag[2] || flag[3]) {
                     const U4 wn = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.NB + j0 / 4));
