@@ -122,7 +122,9 @@ typedef struct {
      * R (m*m), Qf (n*n) replacing q, r, qf respectively when non-NULL
      * (q, r may then be NULL); each stage adds (x-g)^T Q (x-g) +
      * (u-ug)^T R (u-ug), the end (x_T-g)^T Qf (x_T-g).  Such problems
-     * run on the vector-ALU rollout (n, m <= 16, else EMPC_EUNSUPPORTED);
+     * run on a vector-ALU rollout with 16 lanes per candidate (n <= 64,
+     * m <= 32, else EMPC_EUNSUPPORTED; for n, m <= 16 the tuner may pick
+     * one lane per candidate);
      * the adjoint, refinement, the convex solver and the batched plan
      * refuse them (EMPC_EUNSUPPORTED). */
     const void *Q;         /* LINEAR: n*n full stage state weight; NULL = q      */

@@ -334,7 +334,8 @@ empc_status autotune_t(const empc_problem *P, const empc_ga *G, int reps, int al
         e = launch_population<T>(V, *G, nullptr, 0, nullptr, nullptr, nullptr, 1, knots, pop, 0, 0, s);
     std::vector<int> forms;
     if (P->model == EMPC_LINEAR && (P->Q || P->R || P->Qf)) {
-        forms = {RF_VALU256, RF_VALU64};  // full weights run the VALU form only
+        // full weights: the 16-lane row form (the rule) or, small, the VALU form
+        if (P->n <= 16 && P->m <= 16) forms = {RF_VALU256, RF_VALU64};
     } else if (P->model == EMPC_LINEAR) {
         forms = {RF_ONE1, RF_ONE2, RF_ONE4};
         if (P->n > 16) forms.push_back(RF_SPLIT);
@@ -616,10 +617,11 @@ empc_status empc_autotune_set(const empc_problem *prob, const empc_ga *ga, int32
     if (groups != 0 && groups != 1 && groups != 2 && groups != 4)
         return fail(EMPC_EINVAL, "groups=%d must be 0, 1, 2 or 4", groups);
     const bool full = prob->Q || prob->R || prob->Qf;
-    if ((form == RF_VALU256 || form == RF_VALU64) && !full && (prob->n > 16 || prob->m > 16))
+    if ((form == RF_VALU256 || form == RF_VALU64) && (prob->n > 16 || prob->m > 16))
         return fail(EMPC_EUNSUPPORTED, "the vector-ALU form takes n, m <= 16");
     if (full && form != RF_RULE && form != RF_VALU256 && form != RF_VALU64)
-        return fail(EMPC_EUNSUPPORTED, "full weights run the vector-ALU form only");
+        return fail(EMPC_EUNSUPPORTED,
+                     "full weights run the 16-lane row form (the rule) or the vector-ALU form");
     if (form == RF_SPLIT && prob->n <= 16)
         return fail(EMPC_EUNSUPPORTED, "the M-split form needs more than 16 states");
     std::lock_guard<std::mutex> lock(g_tune_mu);

@@ -195,8 +195,8 @@ struct Limits {
     static constexpr int MAX_D_CHAIN = 40;
     static constexpr int MAX_ELITE = 256;
 };
-constexpr int VALU_FULL_NMAX = 16;  // largest n with full weights (VALU rollout)
-constexpr int VALU_FULL_MMAX = 16;  // largest m with full weights
+constexpr int VALU_FULL_NMAX = 64;  // largest n with full weights (16-lane row form)
+constexpr int VALU_FULL_MMAX = 32;  // largest m with full weights
 
 // Optional start / stop events stamped by a kernel's dispatch.
 // Workgroups are dispatched to the chip's 8 XCDs round-robin (linear
@@ -332,7 +332,7 @@ struct Events {
 // bits, and all chain forms; the VALU forms sum in another order.
 enum RolloutForm {
     RF_RULE = 0, RF_ONE1 = 1, RF_ONE2 = 2, RF_ONE4 = 3, RF_SPLIT = 4, RF_VALU256 = 5,
-    RF_VALU64 = 6, RF_CH64 = 11, RF_CH128 = 12, RF_CH256 = 13
+    RF_VALU64 = 6, RF_FROWS = 7, RF_CH64 = 11, RF_CH128 = 12, RF_CH256 = 13
 };
 
 template <typename T>

@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include "internal.hpp"
+#include "rollout_full.hpp"
 #include "rollout_valu.hpp"
 
 namespace empc {
@@ -632,9 +633,48 @@ static hipError_t go_valu_full_n(const ProbView<T> &P, const T *x0, const T *kno
     if (P.n <= 8) return go_valu_full_m<T, 8, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
     return go_valu_full_m<T, 16, BOX>(P, x0, knots, ncand, ld, cost, s, ev, threads);
 }
+template <typename T, int J, int JM, bool BOX>
+static hipError_t go_full_rows_box(const ProbView<T> &P, const T *x0, const T *knots,
+                                   int64_t ncand, int64_t ld, T *cost, hipStream_t s,
+                                   const Events &ev) {
+    const size_t bytes = (size_t)full_rows_lds(P.n, P.m, J).total * sizeof(T);
+    auto kernel = roll_linear_full_rows<T, J, JM, BOX>;
+    if (bytes > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void *)kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return launch_timed(kernel, dim3((unsigned)((ncand + 15) / 16)), dim3(256), bytes, s, ev, P,
+                        x0, knots, ld, ncand, cost);
+}
+template <typename T, int J, bool BOX>
+static hipError_t go_full_rows_m(const ProbView<T> &P, const T *x0, const T *knots,
+                                 int64_t ncand, int64_t ld, T *cost, hipStream_t s,
+                                 const Events &ev) {
+    if (P.m <= 16) return go_full_rows_box<T, J, 1, BOX>(P, x0, knots, ncand, ld, cost, s, ev);
+    return go_full_rows_box<T, J, 2, BOX>(P, x0, knots, ncand, ld, cost, s, ev);
+}
+template <typename T, bool BOX>
+static hipError_t go_full_rows(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
+                               int64_t ld, T *cost, hipStream_t s, const Events &ev) {
+    const int J = (P.n + 15) / 16;
+    if (J <= 1) return go_full_rows_m<T, 1, BOX>(P, x0, knots, ncand, ld, cost, s, ev);
+    if (J <= 2) return go_full_rows_m<T, 2, BOX>(P, x0, knots, ncand, ld, cost, s, ev);
+    if (J <= 3) return go_full_rows_m<T, 3, BOX>(P, x0, knots, ncand, ld, cost, s, ev);
+    return go_full_rows_m<T, 4, BOX>(P, x0, knots, ncand, ld, cost, s, ev);
+}
+
+// Full weights: the 16-lane row form (n <= 64, m <= 32) unless the VALU form
+// (one lane per candidate, n, m <= 16) was chosen.
 template <typename T>
 static hipError_t go_valu_full(const ProbView<T> &P, const T *x0, const T *knots, int64_t ncand,
                                int64_t ld, T *cost, hipStream_t s, const Events &ev, int form) {
+    const bool valu = (form == RF_VALU64 || form == RF_VALU256) && P.n <= 16 && P.m <= 16;
+    if (!valu) {
+        if (P.qb) return go_full_rows<T, true>(P, x0, knots, ncand, ld, cost, s, ev);
+        return go_full_rows<T, false>(P, x0, knots, ncand, ld, cost, s, ev);
+    }
     const int threads = form == RF_VALU64 ? 64 : 256;
     if (P.qb) return go_valu_full_n<T, true>(P, x0, knots, ncand, ld, cost, s, ev, threads);
     return go_valu_full_n<T, false>(P, x0, knots, ncand, ld, cost, s, ev, threads);

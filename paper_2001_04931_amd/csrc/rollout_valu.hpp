@@ -18,7 +18,8 @@
 // FULL: full symmetric weights Q, R, Qf (eq. 3 in general form); each stage
 // adds e^T Q e + e_u^T R e_u, the end e_T^T Qf e_T, from the matrices in LDS
 // (a diagonal given as a vector is expanded there).  Problems with full
-// weights always run this form, for n, m <= 16.
+// weights run this form (n, m <= 16) when the tuner picks it, else the
+// 16-lane row form of rollout_full.hpp.
 #pragma once
 #include <math.h>
 

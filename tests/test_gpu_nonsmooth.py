@@ -82,8 +82,19 @@ def test_full_weights_rollout(oracle_lib, E, dtype, d, which):
 
 
 @pytest.mark.parametrize("dtype", [F32, F64])
-def test_full_weights_with_box_and_step_charge(oracle_lib, E, dtype):
-    prob = boxed(full(W.linear_chain(3, 40, 5, seed=9), 9), 9, 0.15)
+@pytest.mark.parametrize("d", [10, 14, 21, 32])
+def test_full_weights_row_form_large(oracle_lib, E, dtype, d):
+    # 16 lanes per candidate: 20 to 64 states (1 to 4 rows per lane), 10 to
+    # 32 inputs (1 or 2 per lane), ragged candidate count, ld > ncand
+    prob = full(W.linear_chain(d, 30, 5, seed=d), d)
+    compare(oracle_lib, E, prob, ncand=16 * 6 + 5, ld=120, dtype=dtype, seed=d,
+            rtol=RTOL[dtype])
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+@pytest.mark.parametrize("d", [3, 14])
+def test_full_weights_with_box_and_step_charge(oracle_lib, E, dtype, d):
+    prob = boxed(full(W.linear_chain(d, 40, 5, seed=9), 9), 9, 0.15)
     if dtype == F32:  # every state outside: the charge counts every step
         prob.x_min, prob.x_max = prob.x_min + 50.0, prob.x_max + 50.0
     compare(oracle_lib, E, prob, ncand=300, ld=300, dtype=dtype, seed=9, rtol=RTOL[dtype])
@@ -111,6 +122,10 @@ def test_full_weights_both_launch_shapes_and_the_tuner(oracle_lib, E):
         E.empc_autotune_reset()
     np.testing.assert_array_equal(outs[0], outs[1])
     np.testing.assert_allclose(outs[0], want, rtol=1e-9)
+    # the rule (16-lane row form) against the same oracle costs
+    rows = torch.empty(1000, dtype=F64, device="cuda")
+    E.empc_rollout_cost(dp, as_dev(x0, F64), as_dev(knots, F64), 1000, 1000, rows)
+    np.testing.assert_allclose(rows.cpu().numpy(), want, rtol=1e-9)
 
 
 def test_full_weights_solve_fp64_over_ticks(oracle_lib, E):
@@ -129,7 +144,7 @@ def test_full_weights_solve_fp64_over_ticks(oracle_lib, E):
 
 def test_full_weights_limits(E):
     rng = np.random.default_rng(0)
-    big = W.linear_chain(9, 20, 4, seed=1)  # n = 18 > 16
+    big = W.linear_chain(33, 20, 4, seed=1)  # n = 66 > 64
     big.Q = spd(big.n, rng)
     dp = E.DeviceProblem(big, F32)
     x0 = torch.zeros(big.n, device="cuda")
