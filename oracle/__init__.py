@@ -46,7 +46,7 @@ class _OrProblem(ctypes.Structure):
                 ("q", _dp), ("r", _dp), ("qf", _dp), ("x_goal", _dp), ("u_goal", _dp),
                 ("u_min", _dp), ("u_max", _dp), ("x_min", _dp), ("x_max", _dp), ("qb", _dp),
                 ("sb", _dp), ("q_min", _dp), ("q_max", _dp), ("restitution", ctypes.c_double),
-                ("Q", _dp), ("R", _dp), ("Qf", _dp)]
+                ("Q", _dp), ("R", _dp), ("Qf", _dp), ("fric_c", _dp), ("fric_s", _dp)]
 
 
 class _OrGA(ctypes.Structure):
@@ -126,7 +126,8 @@ class OracleProblem:
                             ("u_goal", "u_goal"), ("u_min", "u_min"), ("u_max", "u_max"),
                             ("x_min", "x_min"), ("x_max", "x_max"), ("qb", "qb"),
                             ("sb", "sb"), ("q_min", "q_min"), ("q_max", "q_max"),
-                            ("Q", "Q"), ("R", "R"), ("Qf", "Qf")):
+                            ("Q", "Q"), ("R", "R"), ("Qf", "Qf"), ("fric_c", "fric_c"),
+                            ("fric_s", "fric_s")):
             v = getattr(prob, name, None)
             if v is not None:
                 v = _f64(v)
@@ -238,9 +239,10 @@ def next_population(prob, ga, elite_knots, cold, tick, gen, pop=None):
 
 def _smooth_diagonal(prob):
     """The adjoint covers diagonal weights and smooth dynamics only: full Q,
-    R, Qf and joint limits with impacts have no gradient here (the step
-    charge sb has derivative zero off the box faces and is allowed)."""
-    for name in ("Q", "R", "Qf", "q_min", "q_max"):
+    R, Qf, joint limits with impacts and dry friction have no gradient here
+    (the step charge sb has derivative zero off the box faces and is
+    allowed)."""
+    for name in ("Q", "R", "Qf", "q_min", "q_max", "fric_c", "fric_s"):
         if getattr(prob, name, None) is not None:
             raise ValueError("the adjoint does not cover %s" % name)
 

@@ -158,8 +158,21 @@ static void chain_step(const or_problem *P, const double *tail_mass, const doubl
         double G = 0.0;
         for (int r = j; r < d; ++r) G += P->len[r] * tail_mass[r] * sphi[r];
         G *= P->gravity;
-        double qdd = (u[j] - P->stiff[j] * q[j] - P->damp[j] * qd[j] - G) / inertia[j];
-        double qd_new = qd[j] + P->dt * qdd;
+        double f = u[j] - P->stiff[j] * q[j] - P->damp[j] * qd[j] - G;
+        double qd_new = qd[j] + P->dt * (f / inertia[j]);
+        if (P->fric_c) {
+            /* dry friction with stiction: a joint at rest stays at rest while
+             * |f| <= fric_s, else it breaks away against fric_c; a moving
+             * joint is slowed by fric_c, and if that (or f) turns it round
+             * while |f| <= fric_s it sticks */
+            double tc = P->fric_c[j], ts = P->fric_s[j], dti = P->dt / inertia[j];
+            if (qd[j] == 0.0) {
+                qd_new = fabs(f) <= ts ? 0.0 : qd_new - dti * tc * (f > 0.0 ? 1.0 : -1.0);
+            } else {
+                qd_new -= dti * tc * (qd[j] > 0.0 ? 1.0 : -1.0);
+                if (qd_new * qd[j] <= 0.0 && fabs(f) <= ts) qd_new = 0.0;
+            }
+        }
         double q_new = q[j] + P->dt * qd_new;
         /* joint limits with impacts: an if/else branch inside the
          * simulation of the kind Sec. V-A names (contact, impacts) */

@@ -87,6 +87,11 @@ typedef struct {
      * diagonal q, r, qf when given: (x-g)^T Q (x-g) + (u-ug)^T R (u-ug) per
      * stage and (x_T-g)^T Qf (x_T-g) at the end (eq. 3 with full Q, R).   */
     const double *Q, *R, *Qf;         /* n*n, m*m, n*n                          */
+    /* chain dry friction (d each, NULL = none): sliding torque fric_c,
+     * breakaway torque fric_s >= fric_c; a joint at rest stays at rest
+     * while the other torques stay within fric_s (stick-slip, a
+     * history-dependent branch).                                           */
+    const double *fric_c, *fric_s;
 } or_problem;
 
 /* Tunables of Alg. 1: numSims (pop), numParents (n_elite), sigma_noise. */

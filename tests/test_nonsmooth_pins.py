@@ -224,3 +224,113 @@ def test_impacts_refused_by_the_adjoint():
     prob = free_joint(0.5)
     with pytest.raises(ValueError):
         oracle.grad(prob, np.array([0.0, 1.0]), W.draw_knots(prob, 2, seed=0))
+
+
+# ---------------------------------------------------------------------------
+# dry friction with stiction (pendulum chain)
+
+
+def frictional_joint(tc, ts, T=40):
+    """One link, no stiffness, damping or gravity, dry friction."""
+    prob = W.pendulum_chain(1, T, 2, seed=0)
+    return W.dataclasses.replace(prob, stiffness=np.zeros(1), damping=np.zeros(1), gravity=0.0,
+                                 fric_c=np.array([tc]), fric_s=np.array([ts]))
+
+
+def inertia(prob):
+    return prob.mass[0] * prob.length[0] ** 2
+
+
+def test_friction_holds_a_joint_at_rest_below_breakaway():
+    prob = frictional_joint(0.2, 0.5)
+    x = np.array([0.3, 0.0])
+    for u in (0.49, -0.5, 0.0, 0.3):
+        y = x.copy()
+        for _ in range(10):
+            y = oracle.step(prob, y, np.array([u]))
+        np.testing.assert_array_equal(y, x)  # exactly at rest
+
+
+def test_friction_breakaway_and_sliding_closed_form():
+    # from rest under u > fric_s the joint accelerates at (u - fric_c) / I
+    prob = frictional_joint(0.2, 0.5)
+    dt, I = prob.dt, inertia(prob)
+    x = np.array([0.0, 0.0])
+    q = v = 0.0
+    for k in range(1, 15):
+        x = oracle.step(prob, x, np.array([0.8]))
+        v += dt * 0.8 / I - dt / I * 0.2
+        q += dt * v
+        np.testing.assert_allclose(x, (q, v), rtol=1e-12, atol=1e-15)
+
+
+def test_friction_slides_to_a_stop_and_sticks():
+    # no torque: the rate falls by dt fric_c / I per step, then stops and stays
+    prob = frictional_joint(0.3, 0.3)
+    dt, I = prob.dt, inertia(prob)
+    dv = dt * 0.3 / I
+    v0 = 7.5 * dv
+    x = np.array([0.0, v0])
+    q, v = 0.0, v0
+    for k in range(1, 20):
+        x = oracle.step(prob, x, np.zeros(1))
+        v = max(v - dv, 0.0)
+        q += dt * v
+        np.testing.assert_allclose(x, (q, v), rtol=1e-12, atol=1e-15)
+    assert x[1] == 0.0
+
+
+def test_friction_hysteresis_of_a_torque_cycle():
+    # the torque needed to start the joint (fric_s) exceeds the one that
+    # keeps it moving (fric_c): ramping the torque up, the joint first moves
+    # once u > fric_s; ramping back down it keeps moving below fric_s
+    prob = frictional_joint(0.2, 0.5)
+    x = np.array([0.0, 0.0])
+    up = np.linspace(0.0, 0.6, 61)
+    started = None
+    for i, u in enumerate(up):
+        x = oracle.step(prob, x, np.array([u]))
+        if started is None and x[1] != 0.0:
+            started = u
+    assert started is not None and started > 0.5
+    for u in np.linspace(0.6, 0.3, 31):
+        x = oracle.step(prob, x, np.array([u]))
+        assert x[1] > 0.0  # still moving at torques below the breakaway
+
+
+def test_zero_friction_changes_nothing():
+    prob = W.pendulum_chain(5, 40, 5, seed=5)
+    x0 = W.draw_x0(prob.n, 5)
+    knots = W.draw_knots(prob, 6, seed=5)
+    zero = W.dataclasses.replace(prob, fric_c=np.zeros(5), fric_s=np.zeros(5))
+    np.testing.assert_array_equal(oracle.rollout_cost(zero, x0, knots),
+                                  oracle.rollout_cost(prob, x0, knots))
+
+
+def test_oracle_struct_matches_its_header(tmp_path):
+    """Every field of the oracle's ctypes mirror sits where the C compiler
+    puts it."""
+    import ctypes
+    import os
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    py = oracle._OrProblem
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "empc_oracle.h"',
+             "int main(void) {", '  printf("size %zu\\n", sizeof(or_problem));']
+    for f, _ in py._fields_:
+        lines.append('  printf("%s %%zu\\n", offsetof(or_problem, %s));' % (f, f))
+    lines.append("  return 0;\n}\n")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "oracle"), str(src), "-o",
+                    str(exe)], check=True)
+    out = dict(ln.split() for ln in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                   check=True).stdout.splitlines())
+    assert int(out["size"]) == ctypes.sizeof(py)
+    for f, _ in py._fields_:
+        assert int(out[f]) == getattr(py, f).offset, f

@@ -76,6 +76,10 @@ class Problem:
     q_min: Optional[np.ndarray] = None
     q_max: Optional[np.ndarray] = None
     restitution: float = 0.0
+    # chain dry friction (None: none): sliding torque fric_c, breakaway
+    # torque fric_s >= fric_c per joint (stick-slip)
+    fric_c: Optional[np.ndarray] = None
+    fric_s: Optional[np.ndarray] = None
     # full symmetric weights of the linear model (None: the diagonals q, r, qf)
     Q: Optional[np.ndarray] = None
     R: Optional[np.ndarray] = None
