@@ -29,8 +29,8 @@ packed u* to the host.  Printed as one JSON line:
                single solves, the N-link robot relinearized every tick, the
                parameterized convex MPC, the 14-DoF loop's variants, and the
                non-smooth forms (full weights with a settling-band charge on
-               a 7-DoF chain; joint limits with impacts on the 36-link
-               chain).
+               a 7-DoF chain; joint limits with impacts and dry friction on
+               the 36-link chain).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--only NAME]
 """
@@ -568,7 +568,8 @@ def nonsmooth_workload(E, W, ticks=100, with_cpu=True):
     """Sec. V-A's flexibility on the GPU: full Q, R, Qf with a settling-band
     charge on the 7-DoF linear chain (vector-ALU rollout), and joint limits
     with impacts plus a settling-band charge on the 36-joint pendulum chain
-    (C3's shape), each in a closed loop whose plant has the same effects."""
+    with dry friction (C3's shape), each in a closed loop whose plant has
+    the same effects."""
     import torch
 
     out = {}
@@ -594,14 +595,14 @@ def nonsmooth_workload(E, W, ticks=100, with_cpu=True):
     flop = ga.pop * chain_flop_per_candidate(prob.m, prob.T)
     r = {"rollouts_per_s": rate, "latency_ms": lat_summary(lats), "ticks": ticks,
          "dtype": "f32", "final_best_cost": costs[-1],
-         "roofline": kernel_roofline(prof, flop, PEAK_FP32_VALU, "roll_chain_rows<limits, box>",
+         "roofline": kernel_roofline(prof, flop, PEAK_FP32_VALU, "roll_chain_rows<limits, friction, box>",
                                      bound="valu", sines_per_launch=ga.pop * prob.m * prob.T)}
     if with_cpu:
         one_gen = W.dataclasses.replace(ga, generations=1)
         jobs = [closed_loop_job(prob, one_gen, 1, s) for s in range(1 + host_cores())]
         r["cpu_baseline"], r["cpu_baseline_all_cores"] = oracle_baseline(
             jobs, "1 tick of 1 generation of 16384 candidates of the same chain, FP64")
-    out["nonsmooth_36link_limits_band"] = r
+    out["nonsmooth_36link_limits_friction_band"] = r
     return out
 
 

@@ -130,6 +130,17 @@ typedef struct {
     const void *Q;         /* LINEAR: n*n full stage state weight; NULL = q      */
     const void *R;         /* LINEAR: m*m full stage input weight; NULL = r      */
     const void *Qf;        /* LINEAR: n*n full terminal weight; NULL = qf        */
+    /* Dry friction with stiction (PENDULUM_CHAIN, d each, both or neither):
+     * a joint at rest stays at rest while the other torques on it stay
+     * within fric_s; it breaks away against fric_c, which then slows it, and
+     * it sticks where that (or a holding torque within fric_s) turns it
+     * round: stick-slip, a history-dependent branch of the kind Sec. V-A
+     * names.  0 <= fric_c <= fric_s is the caller's to keep (device arrays,
+     * not read on the host).  The adjoint, refinement and the batched plan
+     * refuse such problems (EMPC_EUNSUPPORTED); FP32 rollouts decide each
+     * branch in FP32. */
+    const void *fric_c;    /* CHAIN: d sliding friction torques; NULL = none     */
+    const void *fric_s;    /* CHAIN: d breakaway torques; NULL = none            */
 } empc_problem;
 
 /* Tunables of Alg. 1: numSims = pop, numParents = n_elite, sigma_noise. */

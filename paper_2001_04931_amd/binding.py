@@ -40,7 +40,7 @@ class EmpcProblem(ctypes.Structure):
                 ("q", _vp), ("r", _vp), ("qf", _vp), ("x_goal", _vp), ("u_goal", _vp),
                 ("u_min", _vp), ("u_max", _vp), ("x_min", _vp), ("x_max", _vp), ("qb", _vp),
                 ("sb", _vp), ("q_min", _vp), ("q_max", _vp), ("restitution", ctypes.c_double),
-                ("Q", _vp), ("R", _vp), ("Qf", _vp)]
+                ("Q", _vp), ("R", _vp), ("Qf", _vp), ("fric_c", _vp), ("fric_s", _vp)]
 
 
 class EmpcGA(ctypes.Structure):
@@ -383,12 +383,13 @@ class DeviceProblem:
     Ad, Bd, wd (linear) or stiffness, damping, mass, length, gravity, dt
     (chain), and q, r, qf, x_goal, u_goal, u_min, u_max, and optionally the
     state box x_min, x_max, qb with its step charge sb, chain joint limits
-    q_min, q_max with restitution, full weights Q, R, Qf (host arrays).
+    q_min, q_max with restitution, full weights Q, R, Qf, chain dry friction
+    fric_c, fric_s (host arrays).
     """
 
     _ARRAYS = ("Ad", "Bd", "wd", "stiffness", "damping", "mass", "length", "q", "r", "qf",
                "x_goal", "u_goal", "u_min", "u_max", "x_min", "x_max", "qb", "sb", "q_min",
-               "q_max", "Q", "R", "Qf")
+               "q_max", "Q", "R", "Qf", "fric_c", "fric_s")
     # may be None (NULL); the zero-droppable ones are also passed as NULL
     # when all zero (x_min / x_max are bounds: a zero bound is kept)
     _OPTIONAL = ("wd", "qf", "x_goal", "u_goal", "qb", "sb")

@@ -640,9 +640,9 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         if ((st = empc_validate_problem_internal(&probs[i]))) return st;
         if (probs[i].dtype != EMPC_F32)
             return empc_fail_internal(EMPC_EUNSUPPORTED, "batched solves run in FP32");
-        if (probs[i].Q || probs[i].R || probs[i].Qf || probs[i].q_min)
-            return empc_fail_internal(EMPC_EUNSUPPORTED,
-                                      "batched solves take diagonal weights and no joint limits");
+        if (probs[i].Q || probs[i].R || probs[i].Qf || probs[i].q_min || probs[i].fric_c)
+            return empc_fail_internal(EMPC_EUNSUPPORTED, "batched solves take diagonal weights, "
+                                                         "no joint limits and no dry friction");
     }
     if (!x0_packed || !u_star_packed || !best_cost)
         return empc_fail_internal(EMPC_EINVAL, "x0_packed, u_star_packed and best_cost are required");

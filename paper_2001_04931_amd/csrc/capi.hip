@@ -59,6 +59,9 @@ empc_status validate_problem(const empc_problem *P) {
         return fail(EMPC_EINVAL, "joint limits (q_min, q_max) belong to the pendulum chain");
     if (P->q_min && !(P->restitution >= 0.0 && P->restitution <= 1.0))
         return fail(EMPC_EINVAL, "restitution must lie in [0, 1]");
+    if (!P->fric_c != !P->fric_s) return fail(EMPC_EINVAL, "fric_c and fric_s go together");
+    if (P->fric_c && P->model != EMPC_PENDULUM_CHAIN)
+        return fail(EMPC_EINVAL, "dry friction (fric_c, fric_s) belongs to the pendulum chain");
     const bool full = P->Q || P->R || P->Qf;
     if (full && P->model != EMPC_LINEAR)
         return fail(EMPC_EINVAL, "full weights (Q, R, Qf) belong to the linear model");
@@ -87,6 +90,8 @@ empc_status validate_grad(const empc_problem *P) {
         return fail(EMPC_EUNSUPPORTED, "the adjoint takes diagonal weights (no Q, R, Qf)");
     if (P->q_min)
         return fail(EMPC_EUNSUPPORTED, "the adjoint has no derivative through impacts (q_min, q_max)");
+    if (P->fric_c)
+        return fail(EMPC_EUNSUPPORTED, "the adjoint has no derivative through dry friction");
     if (P->model == EMPC_LINEAR ? P->n > 64 : P->m > 64)
         return fail(EMPC_EUNSUPPORTED, "adjoint supports n <= 64 (linear) or d <= 64 (chain)");
     const size_t b = grad_smem_bytes(P->model, P->n, P->m, P->T, P->p, esize(P));
@@ -201,7 +206,8 @@ std::map<TuneKey, Tuned> g_tune;
 TuneKey tune_key(const empc_problem *P, int64_t ncand) {
     return TuneKey(P->model, P->dtype, P->n, P->m, P->T, P->p, ncand, P->qb ? 1 : 0,
                    P->x_goal ? 1 : 0, P->wd ? 1 : 0,
-                   ((P->Q || P->R || P->Qf) ? 1 : 0) | (P->q_min ? 2 : 0));
+                   ((P->Q || P->R || P->Qf) ? 1 : 0) | (P->q_min ? 2 : 0) |
+                       (P->fric_c ? 4 : 0));
 }
 Tuned tuned_for(const empc_problem *P, int64_t ncand) {
     std::lock_guard<std::mutex> lock(g_tune_mu);

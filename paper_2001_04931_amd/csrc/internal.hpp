@@ -26,6 +26,7 @@ struct ProbView {
     const T *qlo, *qhi;       // chain joint limits with impacts (NULL: none)
     T rest;                   // impact restitution
     const T *Qm, *Rm, *Qfm;   // full weights (NULL: the diagonals)
+    const T *fc, *fs;         // chain dry friction: sliding, breakaway (NULL: none)
 };
 
 template <typename T>
@@ -43,6 +44,7 @@ inline ProbView<T> view_of(const empc_problem &P) {
     v.sb = (const T *)P.sb;
     v.qlo = (const T *)P.q_min; v.qhi = (const T *)P.q_max; v.rest = (T)P.restitution;
     v.Qm = (const T *)P.Q; v.Rm = (const T *)P.R; v.Qfm = (const T *)P.Qf;
+    v.fc = (const T *)P.fric_c; v.fs = (const T *)P.fric_s;
     return v;
 }
 
@@ -75,6 +77,18 @@ __host__ __device__ inline void joint_limit(T &q, T &v, T lo, T hi, T e) {
         q = lo;
         if (v < (T)0) v = -e * v;
     }
+}
+// Dry friction with stiction on one joint's rate update: v the rate before
+// the step, vf = v + dti f the rate without friction (f the other torques,
+// dti = dt / I), tc the sliding and ts the breakaway torque.  At rest: stays
+// at rest while |f| <= ts, else breaks away against tc; moving: slowed by
+// tc, and held at zero where that (or f within ts) turns it round.
+template <typename T>
+__host__ __device__ inline T dry_friction(T v, T vf, T f, T dti, T tc, T ts) {
+    const T af = f < (T)0 ? -f : f;
+    if (v == (T)0) return af <= ts ? (T)0 : vf - dti * tc * (f > (T)0 ? (T)1 : (T)-1);
+    const T vn = vf - dti * tc * (v > (T)0 ? (T)1 : (T)-1);
+    return (vn * v <= (T)0 && af <= ts) ? (T)0 : vn;
 }
 template <typename T>
 __host__ __device__ inline T box_pen_grad(T x, T lo, T hi, T w) {

@@ -65,12 +65,15 @@ hipError_t launch_rollout(const ProbView<T> &P, int model, const T *x0, const T 
     if (model == EMPC_LINEAR)
         return launch_linear<T>(P, x0, knots, ncand, ld, cost, s, ev, form >= RF_CH64 ? RF_RULE : form);
     const int cf = form >= RF_CH64 ? form : RF_RULE;
-    const int feat = (P.qb ? CF_BOX : 0) | (P.qhi ? CF_LIMIT : 0);
+    const int feat = (P.qb ? CF_BOX : 0) | (P.qhi ? CF_LIMIT : 0) | (P.fc ? CF_FRIC : 0);
     switch (feat) {
-        case CF_BOX: return go_chain_forms<T, CF_BOX>(P, x0, knots, ncand, ld, cost, s, ev, cf);
-        case CF_LIMIT: return go_chain_forms<T, CF_LIMIT>(P, x0, knots, ncand, ld, cost, s, ev, cf);
-        case CF_BOX | CF_LIMIT:
-            return go_chain_forms<T, CF_BOX | CF_LIMIT>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+        case 1: return go_chain_forms<T, 1>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+        case 2: return go_chain_forms<T, 2>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+        case 3: return go_chain_forms<T, 3>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+        case 4: return go_chain_forms<T, 4>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+        case 5: return go_chain_forms<T, 5>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+        case 6: return go_chain_forms<T, 6>(P, x0, knots, ncand, ld, cost, s, ev, cf);
+        case 7: return go_chain_forms<T, 7>(P, x0, knots, ncand, ld, cost, s, ev, cf);
         default: return go_chain_forms<T, 0>(P, x0, knots, ncand, ld, cost, s, ev, cf);
     }
 }
@@ -127,8 +130,9 @@ __global__ void plant_kernel(ProbView<T> P, int model, const T *__restrict__ x,
             dist += P.len[i];
             inert += P.mass[i] * dist * dist;
         }
-        const T acc = (u[j] - P.stiff[j] * xs[j] - P.damp[j] * xs[d + j] - G) / inert;
-        T vn = xs[d + j] + P.dt * acc;
+        const T f = u[j] - P.stiff[j] * xs[j] - P.damp[j] * xs[d + j] - G;
+        T vn = xs[d + j] + P.dt * (f / inert);
+        if (P.fc) vn = dry_friction(xs[d + j], vn, f, P.dt / inert, P.fc[j], P.fs[j]);
         T qn = xs[j] + P.dt * vn;
         if (P.qhi) joint_limit(qn, vn, P.qlo[j], P.qhi[j], P.rest);
         x_next[d + j] = vn + (noise ? noise[d + j] : (T)0);

@@ -23,11 +23,12 @@ struct JointConst {
     T loq, hiq, lov, hiv;  // and its bounds
     T sq, sv;            // step charges outside the box (0: none)
     T qmn, qmx;          // joint limits (with impacts)
+    T fc, fs;            // dry friction: sliding, breakaway torque
 };
 
 // Compile-time features of the chain forms: the state box penalty with its
-// step charge, and joint limits with impacts.
-constexpr int CF_BOX = 1, CF_LIMIT = 2;
+// step charge, joint limits with impacts, dry friction with stiction.
+constexpr int CF_BOX = 1, CF_LIMIT = 2, CF_FRIC = 4;
 
 template <typename T>
 __device__ void chain_constants_lds(const ProbView<T> &P, JointConst<T> *jc) {
@@ -64,6 +65,8 @@ __device__ void chain_constants_lds(const ProbView<T> &P, JointConst<T> *jc) {
         c.sv = (box && P.sb) ? P.sb[d + j] : (T)0;
         c.qmn = P.qlo ? P.qlo[j] : (T)0;
         c.qmx = P.qhi ? P.qhi[j] : (T)0;
+        c.fc = P.fc ? P.fc[j] : (T)0;
+        c.fs = P.fs ? P.fs[j] : (T)0;
         jc[j] = c;
     }
 }
@@ -106,6 +109,7 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
     const int d = P.m;
     const T dt = P.dt;
     constexpr bool box = (FEAT & CF_BOX) != 0, limit = (FEAT & CF_LIMIT) != 0;
+    constexpr bool fric = (FEAT & CF_FRIC) != 0;
     const T rest = P.rest;
     T q[DMAX], v[DMAX], ua[DMAX], ub[DMAX];
 #pragma unroll
@@ -160,7 +164,8 @@ __device__ __forceinline__ void chain_candidate(const ProbView<T> &P, const Join
                 const T u = ((T)1 - c) * ua[j] + c * ub[j];
                 // qd += dt (u - k q - b qd - G) / I, with dt / I as one factor
                 const T f = u - cj.kst * q[j] - cj.dmp * v[j] - G;
-                v[j] = v[j] + cj.dtI * f;
+                const T vf = v[j] + cj.dtI * f;
+                v[j] = fric ? dry_friction(v[j], vf, f, cj.dtI, cj.fc, cj.fs) : vf;
                 q[j] = q[j] + dt * v[j];
                 if (limit) joint_limit(q[j], v[j], cj.qmn, cj.qmx, rest);
                 const T eq = cj.gq - q[j], ev = cj.gv - v[j], eu = cj.gu - u;
@@ -233,6 +238,8 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
     // state box penalty: weights, bounds and running sums; step charges and
     // the running counts of steps outside; joint limits
     constexpr bool box = (FEAT & CF_BOX) != 0, limit = (FEAT & CF_LIMIT) != 0;
+    constexpr bool fric = (FEAT & CF_FRIC) != 0;
+    T fcr[fric ? J : 1], fsr[fric ? J : 1];
     T bq[J], bv[J], loq[J], hiq[J], lov[J], hiv[J], Pq[J], Pv[J];
     T sq[box ? J : 1], sv[box ? J : 1], Nq[box ? J : 1], Nv[box ? J : 1];
     T qmn[limit ? J : 1], qmx[limit ? J : 1];
@@ -277,6 +284,10 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
         if (limit) {
             qmn[i] = in ? P.qlo[j] : (T)0;
             qmx[i] = in ? P.qhi[j] : (T)0;
+        }
+        if (fric) {
+            fcr[i] = in ? P.fc[j] : (T)0;
+            fsr[i] = in ? P.fs[j] : (T)0;
         }
     }
     const T dt = P.dt;
@@ -357,7 +368,8 @@ __device__ __forceinline__ void chain_row_candidate(const ProbView<T> &P, const 
             const T u = ua[i] + c * du[i];
             // qd += dt (u - k q - b qd - G) / I, with dt / I as one factor
             const T f = u - kst[i] * q[i] - dmp[i] * v[i] - G;
-            v[i] = v[i] + dtI[i] * f;
+            const T vf = v[i] + dtI[i] * f;
+            v[i] = fric ? dry_friction(v[i], vf, f, dtI[i], fcr[i], fsr[i]) : vf;
             q[i] = q[i] + dt * v[i];
             if (limit) joint_limit(q[i], v[i], qmn[i], qmx[i], rest);
             const T eq = gq[i] - q[i], ev = gv[i] - v[i];

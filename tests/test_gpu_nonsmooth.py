@@ -366,3 +366,105 @@ def test_joint_limits_refused_where_unsupported(E):
                             torch.zeros(8, 16, device="cuda"), 16, 16,
                             torch.empty(16, device="cuda"))
     assert ex.value.status == E.EMPC_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# dry friction with stiction (pendulum chain: lane and row forms, plant)
+
+
+def frictional(prob, seed, tc=0.05, ts=0.12):
+    rng = np.random.default_rng(seed)
+    d = prob.m
+    c = tc * rng.uniform(0.5, 1.5, d)
+    return W.dataclasses.replace(prob, fric_c=c, fric_s=c + ts * rng.uniform(0.5, 1.5, d))
+
+
+@pytest.mark.parametrize("d", [1, 3, 5, 8, 12, 20, 36])
+@pytest.mark.parametrize("extra", ["", "box", "limits"])
+def test_dry_friction_fp64(oracle_lib, E, d, extra):
+    prob = frictional(W.pendulum_chain(d, 40, 5, seed=d), d)
+    if extra == "box":
+        prob = boxed(prob, d, 0.3)
+    elif extra == "limits":
+        prob = limited(prob, d)
+    x0 = start_inside(prob, d) if extra == "limits" else W.draw_x0(prob.n, d)
+    x0[prob.m:prob.m + (d + 1) // 2] = 0.0  # some joints start at rest
+    knots = W.draw_knots(prob, 150, d + 1, ld=151)
+    got = gpu_costs(E, prob, x0, knots, 150, F64)
+    want = oracle_lib.rollout_cost(prob, x0, knots, 150)
+    np.testing.assert_allclose(got, want, rtol=1e-9, atol=0)
+    free = oracle_lib.rollout_cost(W.dataclasses.replace(prob, fric_c=None, fric_s=None), x0,
+                                   knots, 150)
+    assert np.any(np.abs(want - free) > 1e-6 * np.abs(free))  # the friction acted
+
+
+@pytest.mark.parametrize("d", [5, 20])
+def test_dry_friction_fp32_mostly_agree(oracle_lib, E, d):
+    # every stick / slip decision is taken in FP32: a torque within rounding
+    # of the breakaway torque may go the other way, so most (not all)
+    # candidates must agree
+    prob = frictional(W.pendulum_chain(d, 40, 5, seed=d), d).cast(np.float32)
+    x0 = W.draw_x0(prob.n, d).astype(np.float32).astype(np.float64)
+    knots = W.draw_knots(prob, 400, d + 1).astype(np.float32).astype(np.float64)
+    got = gpu_costs(E, prob, x0, knots, 400, F32)
+    want = oracle_lib.rollout_cost(prob, x0, knots, 400)
+    rel = np.abs(got - want) / np.abs(want)
+    assert np.mean(rel < 1e-4) >= 0.9, np.sort(rel)[-10:]
+    assert np.median(rel) < 1e-5
+
+
+def test_zero_friction_keeps_the_bits(E):
+    for d in (5, 20):
+        prob = W.pendulum_chain(d, 30, 5, seed=d).cast(np.float32)
+        x0 = W.draw_x0(prob.n, 1)
+        knots = W.draw_knots(prob, 64, 2)
+        a = gpu_costs(E, prob, x0, knots, 64, F32)
+        zero = W.dataclasses.replace(prob, fric_c=np.zeros(d), fric_s=np.zeros(d))
+        np.testing.assert_array_equal(gpu_costs(E, zero, x0, knots, 64, F32), a)
+
+
+def test_dry_friction_plant_and_solve_fp64(oracle_lib, E):
+    prob = frictional(W.pendulum_chain(4, 30, 5, seed=4), 4, tc=0.1, ts=0.2)
+    ga = W.GA(pop=200, n_elite=10, generations=4, sigma=0.2, seed=3)
+    dp = E.DeviceProblem(prob, F64)
+    solver = E.Solver(dp, ga)
+    osolver = oracle_lib.Solver(prob, ga)
+    x = W.draw_x0(prob.n, 4)
+    x[4:6] = 0.0
+    for tick in range(4):
+        u, J = solver.solve(as_dev(x, F64), tick)
+        uo, Jo, _ = osolver.solve(x, tick)
+        np.testing.assert_allclose(u.cpu().numpy(), uo, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(float(J.item()), Jo, rtol=1e-9)
+        for push in (0.05 * np.sign(uo + 1e-3), 3.0 * np.sign(uo + 1e-3)):
+            xr = x.copy()
+            xr[4:] = 0.0  # at rest: held below breakaway, breaking away above
+            xg = torch.empty(prob.n, dtype=F64, device="cuda")
+            E.empc_plant_step(dp, as_dev(xr, F64), as_dev(push, F64), None, xg)
+            xo = oracle_lib.step(prob, xr, push)
+            np.testing.assert_allclose(xg.cpu().numpy(), xo, rtol=1e-12, atol=1e-14)
+        x = oracle_lib.step(prob, x, uo)
+
+
+def test_dry_friction_refused_where_unsupported(E):
+    prob = frictional(W.pendulum_chain(3, 20, 4, seed=1), 1)
+    dp = E.DeviceProblem(prob, F32)
+    K = torch.zeros(prob.p * prob.m, 16, device="cuda")
+    with pytest.raises(E.EmpcError) as ex:
+        E.empc_grad(dp, torch.zeros(prob.n, device="cuda"), K, 16, 16, torch.empty_like(K),
+                    torch.empty(16, device="cuda"))
+    assert ex.value.status == E.EMPC_EUNSUPPORTED
+    with pytest.raises(E.EmpcError):
+        E.BatchSolver([dp], W.GA(pop=64, n_elite=4, generations=1, sigma=0.1, seed=0))
+    half = W.dataclasses.replace(prob, fric_s=None)
+    with pytest.raises(E.EmpcError) as ex:
+        E.empc_rollout_cost(E.DeviceProblem(half, F32), torch.zeros(prob.n, device="cuda"), K,
+                            16, 16, torch.empty(16, device="cuda"))
+    assert ex.value.status == E.EMPC_EINVAL
+    lin = W.linear_chain(2, 20, 4, seed=1)
+    lin.fric_c, lin.fric_s = np.ones(2), np.ones(2)
+    with pytest.raises(E.EmpcError) as ex:
+        E.empc_rollout_cost(E.DeviceProblem(lin, F32), torch.zeros(4, device="cuda"),
+                            torch.zeros(8, 16, device="cuda"), 16, 16,
+                            torch.empty(16, device="cuda"))
+    assert ex.value.status == E.EMPC_EINVAL

@@ -317,11 +317,13 @@ def config_nonsmooth_linear(seed: int = 0):
 
 def config_nonsmooth_chain(seed: int = 0):
     """The 36-joint pendulum chain of the C3 configuration with joint limits
-    of +-0.6 rad (impacts with restitution 0.5) and a charge of 0.1 per step
-    for every joint angle more than 0.05 rad from its goal."""
+    of +-0.6 rad (impacts with restitution 0.5), dry friction on every joint
+    (sliding 0.02, breakaway 0.05 N m) and a charge of 0.1 per step for
+    every joint angle more than 0.05 rad from its goal."""
     prob, ga = config_c3(seed)
     d = prob.m
     prob.q_min, prob.q_max, prob.restitution = np.full(d, -0.6), np.full(d, 0.6), 0.5
+    prob.fric_c, prob.fric_s = np.full(d, 0.02), np.full(d, 0.05)
     band = np.concatenate([np.full(d, 0.05), np.full(d, np.inf)])
     prob.x_min, prob.x_max = prob.x_goal - band, prob.x_goal + band
     prob.qb = np.zeros(prob.n)
