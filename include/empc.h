@@ -197,7 +197,11 @@ empc_status empc_generation(const empc_problem *prob, const empc_ga *ga, const v
                             int64_t *elite_idx, int64_t *best_idx, uint32_t tick, uint32_t gen,
                             void *stream);
 
-/* Bytes of the workspace that empc_solve needs for (prob, ga). */
+/* Bytes of the workspace that empc_solve and empc_solve_refined need for
+ * (prob, ga).  For a linear problem without the state box or full weights
+ * it includes room for the problem's quadratic form (Sec. IV-B, knots of
+ * Sec. IV-E) when that fits in 48 MiB: empc_solve_refined then refines on
+ * it. */
 size_t empc_workspace_bytes(const empc_problem *prob, const empc_ga *ga);
 
 /* One control tick of EMPC: ga->generations rounds of {population, rollout
@@ -213,7 +217,11 @@ empc_status empc_solve(const empc_problem *prob, const empc_ga *ga, void *worksp
 /* Gradient-refined tick: as empc_solve, but after every selection the
  * parents are refined by `adam_steps` Adam updates (empc_refine semantics,
  * learning rate lr) before they breed the next generation; u* and the best
- * cost come from the best refined parent.  Same workspace as empc_solve. */
+ * cost come from the best refined parent.  Same workspace as empc_solve.
+ * A linear problem whose workspace holds its quadratic form forms P, q, c
+ * once per call (at this x0) and takes the gradient 2 (P z + q), which is
+ * the rollout cost's gradient exactly, with acceptance on the quadratic's
+ * own costs; any other problem uses the adjoint (the limits of empc_grad). */
 empc_status empc_solve_refined(const empc_problem *prob, const empc_ga *ga, void *workspace,
                                size_t ws_bytes, const void *x0, uint32_t tick, double lr,
                                int32_t adam_steps, void *u_star, void *best_cost, void *stream);

@@ -136,7 +136,7 @@ struct Workspace {
     size_t bytes;
 };
 
-constexpr size_t QP_REFINE_MAX_BYTES = 8ull << 20;
+constexpr size_t QP_REFINE_MAX_BYTES = 48ull << 20;
 
 // the linear-quadratic case whose parents refine on the quadratic form
 bool quadratic_refine(const empc_problem *P) {
@@ -559,7 +559,9 @@ empc_status empc_solve_refined(const empc_problem *prob, const empc_ga *ga, void
     if ((st = validate_ga(ga))) return st;
     if (adam_steps < 1 || !(lr >= 0.0) || !isfinite(lr))
         return fail(EMPC_EINVAL, "need adam_steps >= 1 and a finite lr >= 0");
-    if ((st = validate_grad(prob))) return st;
+    // (the parents of a linear-quadratic problem refine on its quadratic
+    // form, whatever its size; the others need the adjoint's limits)
+    if (!quadratic_refine(prob) && (st = validate_grad(prob))) return st;
     if (!x0 || !u_star || !best_cost) return fail(EMPC_EINVAL, "x0, u_star and best_cost are required");
     const Workspace w = layout(prob, ga, workspace);
     if (!workspace || ws_bytes < w.bytes)

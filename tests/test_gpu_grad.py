@@ -236,3 +236,19 @@ def test_refined_solve_quadratic_form_equals_adjoint_path(E, dtype):
         if dtype == F64:
             np.testing.assert_allclose(uq.cpu().numpy(), ua.cpu().numpy(), rtol=1e-9,
                                        atol=1e-12)
+
+
+def test_refined_solve_fp64_beyond_the_adjoint_limit(oracle_lib, E):
+    # 36-DoF linear chain (72 states, above the adjoint's 64): its parents
+    # refine on the quadratic form; FP64 ticks follow the oracle's adjoint
+    prob = W.linear_chain(36, 20, 5, seed=36)
+    ga = W.GA(pop=128, n_elite=8, generations=2, sigma=0.1, seed=8)
+    s = E.Solver(E.DeviceProblem(prob, F64), ga)
+    o = oracle_lib.Solver(prob, ga, refine=True, lr=0.01, adam_steps=5)
+    x = W.draw_x0(prob.n, 36)
+    for tick in range(2):
+        u, J = s.solve(dev(x, F64), tick, refine_steps=5, lr=0.01)
+        uo, Jo, _ = o.solve(x, tick)
+        np.testing.assert_allclose(u.cpu().numpy(), uo, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(float(J.item()), Jo, rtol=1e-9)
+        x = oracle_lib.step(prob, x, uo)
