@@ -146,7 +146,9 @@ bool quadratic_refine(const empc_problem *P) {
     return qp_form_bytes(P->n, P->T, pm) + (size_t)pm * pm * esize(P) <= QP_REFINE_MAX_BYTES;
 }
 
-Workspace layout(const empc_problem *P, const empc_ga *G, void *base) {
+// qp: room for the quadratic form of refinement (the static solve, which
+// never refines, leaves it out)
+Workspace layout(const empc_problem *P, const empc_ga *G, void *base, bool qp = true) {
     const size_t es = esize(P), pm = (size_t)P->p * P->m, pop = G->pop, k = G->n_elite;
     char *b = (char *)base;
     size_t off = 0;
@@ -162,7 +164,7 @@ Workspace layout(const empc_problem *P, const empc_ga *G, void *base) {
     w.elite_idx = (int64_t *)(b + off); off += align256(k * sizeof(int64_t));
     w.best_idx = (int64_t *)(b + off); off += 256;
     w.elite_soa = b + off; off += align256(k * pm * es);
-    if (quadratic_refine(P)) {
+    if (qp && quadratic_refine(P)) {
         w.qP = b + off; off += align256(pm * pm * es);
         w.qq = b + off; off += align256(pm * es);
         w.qc = b + off; off += 256;
@@ -581,7 +583,7 @@ empc_status empc_solve_static(const empc_problem *prob, const empc_ga *ga, const
     if ((st = validate_ga(ga))) return st;
     if (cold != 0 && cold != 1) return fail(EMPC_EINVAL, "cold=%d must be 0 or 1", cold);
     if (!x0 || !u_star || !best_cost) return fail(EMPC_EINVAL, "x0, u_star and best_cost are required");
-    const size_t need = layout(prob, ga, nullptr).bytes;
+    const size_t need = layout(prob, ga, nullptr, false).bytes;
     if (need > EMPC_STATIC_SCRATCH_BYTES)
         return fail(EMPC_EUNSUPPORTED, "solve needs %zu bytes of workspace, above the static %zu",
                     need, (size_t)EMPC_STATIC_SCRATCH_BYTES);
@@ -589,7 +591,7 @@ empc_status empc_solve_static(const empc_problem *prob, const empc_ga *ga, const
     void *base = nullptr;
     if ((st = static_scratch(&base))) return st;
     hipStream_t s = (hipStream_t)stream;
-    const Workspace w = layout(prob, ga, base);
+    const Workspace w = layout(prob, ga, base, false);
     if (cold) {
         hipLaunchKernelGGL(clear_header_kernel, dim3(1), dim3(64), 0, s, w.has_elites);
         const hipError_t e = hipGetLastError();
