@@ -49,9 +49,12 @@ hipError_t launch_select(const ProbView<T> &P, const T *cost, const T *knots, in
                            P.m, elite_idx, best_idx, elite_rows, elite_cost, has_elites, best_slot,
                            u_star, best_cost);
     };
-    // 256 threads up to 1024 candidates, else 1024 threads (measured at
-    // 4096: 7.1 against 9.2 us; at 16384: 11.6 against 21.4 us)
-    if (pop <= 1024) {
+    // one wavefront's bitonic sort up to 256 candidates; 256 threads up to
+    // 1024 candidates, else 1024 threads (measured at 4096: 7.1 against
+    // 9.2 us; at 16384: 11.6 against 21.4 us)
+    if (pop <= 256) {
+        go(select_small_kernel<T, K>, 64);
+    } else if (pop <= 1024) {
         go(select_kernel<T, K, 4, 256>, 256);
     } else {
         const int64_t per = (pop + 1023) / 1024;

@@ -507,6 +507,113 @@ __device__ __forceinline__ void select_body(
         for (int i = tid; i < m; i += NTHR) u_star[i] = knots[(int64_t)i * ld + s_elite[bslot]];
 }
 
+// Selection for populations of at most 256 by one wavefront (no
+// histogram passes): lane l holds candidates l, l + 64, l + 128, l + 192 as (key,
+// index) pairs (past the population: the largest key and an index past the
+// population), a bitonic network sorts the 256 pairs ascending (partners
+// closer than 64 positions through lane shuffles, farther ones within the
+// lane's registers), so position p holds the p-th lowest (key, index) and
+// the parents are positions 0..k-1, the best one position 0.  Each parent's
+// slot in the ascending-index parent list is its rank by index among them.
+// The outputs are those of select_body, bit for bit (the same total order
+// decides).
+template <typename T, typename K>
+__global__ __launch_bounds__(64) void select_small_kernel(
+    const T *__restrict__ cost, int64_t pop, int k, const T *__restrict__ knots, int64_t ld,
+    int pm, int m, int64_t *__restrict__ elite_idx_out, int64_t *__restrict__ best_idx_out,
+    T *__restrict__ elite_rows, T *__restrict__ elite_cost, int *__restrict__ has_elites,
+    int *__restrict__ best_slot_out, T *__restrict__ u_star, T *__restrict__ best_cost) {
+    __shared__ int s_sidx[256];      // sorted indices (positions 0..k-1)
+    __shared__ int64_t s_elite[256];  // parents in ascending index order
+    __shared__ K s_ekey[256];
+    __shared__ int s_best_slot;
+    const int lane = threadIdx.x;
+    K key[4];
+    int idx[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = lane + 64 * r;
+        idx[r] = e;
+        key[r] = e < pop ? sort_key(cost[e]) : ~(K)0;
+    }
+    auto less = [](K ka, int ia, K kb, int ib) { return ka < kb || (ka == kb && ia < ib); };
+#pragma unroll
+    for (int size = 2; size <= 256; size <<= 1) {
+#pragma unroll
+        for (int stride = size / 2; stride > 0; stride >>= 1) {
+            if (stride >= 64) {  // partner in this lane: register r ^ (stride / 64)
+                const int rb = stride / 64;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r & rb) continue;
+                    const int e = lane + 64 * r, h = r | rb;
+                    const bool asc = (e & size) == 0;
+                    const bool swap = asc ? less(key[h], idx[h], key[r], idx[r])
+                                          : less(key[r], idx[r], key[h], idx[h]);
+                    if (swap) {
+                        const K tk = key[r];
+                        const int ti = idx[r];
+                        key[r] = key[h];
+                        idx[r] = idx[h];
+                        key[h] = tk;
+                        idx[h] = ti;
+                    }
+                }
+            } else {  // partner lane ^ stride, same register
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = lane + 64 * r;
+                    const K ok = __shfl_xor(key[r], stride, 64);
+                    const int oi = __shfl_xor(idx[r], stride, 64);
+                    const bool asc = (e & size) == 0, lower = (e & stride) == 0;
+                    // the lower position keeps the smaller pair when ascending
+                    const bool other_less = less(ok, oi, key[r], idx[r]);
+                    const bool take = (lower == asc) ? other_less : !other_less;
+                    if (take) {
+                        key[r] = ok;
+                        idx[r] = oi;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s_sidx[lane + 64 * r] = idx[r];
+    __syncthreads();
+    // parent at sorted position p < k goes to slot rank(p) = number of
+    // parents with a smaller index
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = lane + 64 * r;
+        if (p < k) {
+            int rank = 0;
+            for (int q = 0; q < k; ++q) rank += s_sidx[q] < idx[r] ? 1 : 0;
+            s_elite[rank] = idx[r];
+            s_ekey[rank] = key[r];
+            if (p == 0) s_best_slot = rank;
+        }
+    }
+    __syncthreads();
+    const int bslot = s_best_slot;
+    for (int s2 = lane; s2 < k; s2 += 64) {
+        if (elite_idx_out) elite_idx_out[s2] = s_elite[s2];
+        if (elite_cost) elite_cost[s2] = key_value(s_ekey[s2]);
+    }
+    if (elite_rows)  // parameter-major: elite_rows[j k + s]
+        for (int t = lane; t < k * pm; t += 64) {
+            const int j = t / k, s2 = t - j * k;
+            elite_rows[t] = knots[(int64_t)j * ld + s_elite[s2]];
+        }
+    if (lane == 0) {
+        if (best_idx_out) *best_idx_out = s_elite[bslot];
+        if (has_elites) *has_elites = 1;
+        if (best_slot_out) *best_slot_out = bslot;
+        if (best_cost) *best_cost = key_value(s_ekey[bslot]);
+    }
+    if (u_star)
+        for (int i = lane; i < m; i += 64) u_star[i] = knots[(int64_t)i * ld + s_elite[bslot]];
+}
+
 template <typename T, typename K, int CACHE, int NTHR>
 __global__ __launch_bounds__(NTHR) void select_kernel(
     const T *__restrict__ cost, int64_t pop, int k, const T *__restrict__ knots, int64_t ld,

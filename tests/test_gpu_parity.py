@@ -402,10 +402,10 @@ def test_selection_nan_after_inf(oracle_lib, E, dtype):
 
 @pytest.mark.parametrize("dtype", [F32, F64])
 def test_selection_small_populations(oracle_lib, E, dtype):
-    # populations of at most 256 run the 256-thread radix select with at
-    # most one key per thread (most threads hold none): heavy ties, NaN / inf
-    # / signed zeros, every k from 1 to pop on a few sizes, exact equality
-    # with the oracle
+    # populations of at most 256 run the one-wavefront bitonic sort (pads
+    # past the population, partners across lanes and within a lane): heavy
+    # ties, NaN / inf / signed zeros, every k from 1 to pop on a few sizes,
+    # exact equality with the oracle
     prob = W.linear_chain(2, 10, 3, seed=0)
     rng = np.random.default_rng(11)
     cases = [(pop, k) for pop in (2, 16, 63, 64, 65, 200, 256) for k in sorted({1, 2, pop // 3 or 1, pop})]
