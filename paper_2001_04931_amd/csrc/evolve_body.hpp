@@ -85,8 +85,8 @@ __device__ __forceinline__ void population_tile(
     int R = 1) {
     __shared__ int s_par[POP_SLOTS][2];
     __shared__ int64_t s_eidx[Limits::MAX_ELITE];
-    __shared__ uint32_t s_flag[POP_SLOTS][4];
-    __shared__ uint32_t s_xw[POP_SLOTS][4];
+    __shared__ __align__(16) uint32_t s_flag[POP_SLOTS][4];
+    __shared__ __align__(16) uint32_t s_xw[POP_SLOTS][4];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int m = P.m, pm = P.p * P.m;
@@ -153,44 +153,70 @@ __device__ __forceinline__ void population_tile(
         } else {
             const T *base = elite_rows ? elite_rows : knots_in;
             const int64_t step = elite_rows ? k : ld_in;
-            // parameter j of the parent stored at src; with the shift, the
+            // the parent's values of all four parameters are loaded first, so
+            // that the loads are in flight together and behind the draws;
+            // parameter j of the parent stored at src, and with the shift the
             // carried input one control step later, (1-d) U_a + d U_{a+1} for
-            // knot a < p-1 (d = (p-1)/(T-1), the knot spacing in steps inverted)
+            // knot a < p-1 (d = (p-1)/(T-1), the knot spacing in steps
+            // inverted).  Indices past the last parameter load parameter
+            // pm-1 and are never stored.
             const T d = P.p > 1 ? (T)(P.p - 1) / (T)(P.Tn - 1) : (T)0;
-            auto parent = [&](int64_t src, int j) -> T {
-                const T v = base[src + (int64_t)j * step];
-                if (!var.shift || j / m >= P.p - 1) return v;
-                return ((T)1 - d) * v + d * base[src + (int64_t)(j + m) * step];
-            };
-            if (elitism && s < k) {
-                const int64_t src = elite_rows ? s : s_eidx[s];
+            const bool elite_slot = elitism && s < k;
+            int64_t src[4];
+            bool flag[4] = {false, false, false, false};
+            if (elite_slot) {
+                const int64_t e = elite_rows ? s : s_eidx[s];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) val[r] = j0 + r < pm ? parent(src, j0 + r) : (T)0;
+                for (int r = 0; r < 4; ++r) src[r] = e;
             } else {
                 const int p1 = s_par[lane][0], p2 = s_par[lane][1];
                 const int64_t src1 = elite_rows ? (int64_t)p1 : s_eidx[p1];
                 const int64_t src2 = elite_rows ? (int64_t)p2 : s_eidx[p2];
-                bool flag[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    flag[r] = j0 + r < pm && ((s_flag[lane][ii[r] / 32] >> (ii[r] % 32)) & 1u);
-                T z[4] = {0, 0, 0, 0};
-                if (flag[0] || flag[1] || flag[2] || flag[3]) {
-                    const U4 wn = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.NB + j0 / 4));
-                    if (flag[0] || flag[1]) box_muller<T>(wn.x, wn.y, z[0], z[1]);
-                    if (flag[2] || flag[3]) box_muller<T>(wn.z, wn.w, z[2], z[3]);
-                }
+                typedef uint32_t w4 __attribute__((ext_vector_type(4)));
+                const w4 fw = *reinterpret_cast<const w4 *>(&s_flag[lane][0]);
+                const w4 xw = *reinterpret_cast<const w4 *>(&s_xw[lane][0]);
+                auto word = [](const w4 &v, int q) {
+                    return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+                };
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int j = j0 + r, jb = j % 128;
-                    if (j >= pm) {
-                        val[r] = 0;
-                        continue;
-                    }
-                    const bool from2 = (s_xw[lane][jb / 32] >> (jb % 32)) & 1u;
-                    val[r] = mutate_clamp<T>(parent(from2 ? src2 : src1, j), flag[r], sigma, z[r],
-                                             P.umin[ii[r]], P.umax[ii[r]]);
+                    flag[r] = j < pm && ((word(fw, ii[r] / 32) >> (ii[r] % 32)) & 1u);
+                    const bool from2 = (word(xw, jb / 32) >> (jb % 32)) & 1u;
+                    src[r] = from2 ? src2 : src1;
                 }
+            }
+            T pv[4], pn[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 + r < pm ? j0 + r : pm - 1;
+                pv[r] = base[src[r] + (int64_t)j * step];
+            }
+            if (var.shift) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = j0 + r < pm ? j0 + r : pm - 1;
+                    pn[r] = j / m < P.p - 1 ? base[src[r] + (int64_t)(j + m) * step] : pv[r];
+                }
+            }
+            T z[4] = {0, 0, 0, 0};
+            if (flag[0] || flag[1] || flag[2] || flag[3]) {
+                const U4 wn = ga_draw(gs, slot, gen, tick, 0, (uint32_t)(gs.NB + j0 / 4));
+                if (flag[0] || flag[1]) box_muller<T>(wn.x, wn.y, z[0], z[1]);
+                if (flag[2] || flag[3]) box_muller<T>(wn.z, wn.w, z[2], z[3]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 + r;
+                if (j >= pm) {
+                    val[r] = 0;
+                    continue;
+                }
+                T v = pv[r];
+                if (var.shift && j / m < P.p - 1) v = ((T)1 - d) * v + d * pn[r];
+                val[r] = elite_slot ? v
+                                    : mutate_clamp<T>(v, flag[r], sigma, z[r], P.umin[ii[r]],
+                                                      P.umax[ii[r]]);
             }
         }
 #pragma unroll
