@@ -301,14 +301,14 @@ def blended_roofline(lin, ch, seconds, **extra):
     return roofline(lin + ch, seconds, peak, "mfma+valu", linear_flop=lin, chain_flop=ch, **extra)
 
 
-def batched_run(E, W, probs, ga, mode, ticks, warm, event_ticks=50):
+def batched_run(E, W, probs, ga, mode, ticks, warm, event_ticks=50, allow_valu=False):
     """One BatchSolver over `probs`, one graph replay per tick.  Returns a
     summary (throughput, host latency, GPU tick time by HIP events)."""
     import torch
 
     dps = [E.DeviceProblem(p, torch.float32) for p in probs]
     t_tune = time.perf_counter()
-    bs = E.BatchSolver(dps, ga, autotune=mode == 0)
+    bs = E.BatchSolver(dps, ga, autotune=mode == 0, allow_valu=allow_valu)
     bs.set_mode(mode)
     t_tune = time.perf_counter() - t_tune
     for i, p in enumerate(probs):
@@ -350,7 +350,8 @@ def batched_run(E, W, probs, ga, mode, ticks, warm, event_ticks=50):
             "latency_ms": lat_summary(lats), "ticks": ticks, "problems": n,
             "within_2ms": float(np.mean(lats <= 2.0)), "gpu_tick_ms": gpu_ms, "wall_s": wall,
             "plan_and_autotune_s": round(t_tune, 3),
-            "mode": "persistent work queue" if mode else "per-class launches, autotuned",
+            "mode": "persistent work queue" if mode else (
+                "per-class launches, autotuned" + (", VALU form allowed" if allow_valu else "")),
             "classes": None if classes is None else [
                 "%s%s x%d: shape %d of us %s, stream %d" % (
                     "lin" if c["model"] == "linear" else "chain", list(c["shape"]),
@@ -385,7 +386,7 @@ def c5_oracle_jobs(probs, ga, cores):
 def c5_workload(E, W, ticks, warm, with_cpu=True):
     """The headline: 512 uneven problems, one graph replay per tick."""
     probs, ga = c5_problems(W)
-    r = batched_run(E, W, probs, ga, 0, ticks, warm)
+    r = batched_run(E, W, probs, ga, 0, ticks, warm, allow_valu=True)
     lin, ch = c5_flop(probs, ga)
     r["roofline"] = blended_roofline(lin, ch, r["gpu_tick_ms"] * 1e-3,
                                      unit_of_work="one tick (graph replay), all 512 problems",

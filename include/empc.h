@@ -393,7 +393,8 @@ empc_status empc_batch_destroy(empc_batch *plan);
  * (linear: one wavefront per 16-candidate tile with 4, 2 or 1 wavefronts per
  * workgroup, or the M-split form with one wavefront per state tile; chain:
  * workgroup sizes), and every shape of a class runs the same per-candidate
- * arithmetic, so the shape changes the time, never a result.
+ * arithmetic, so the shape changes the time, never a result (the VALU form
+ * that empc_batch_allow_valu offers is the one exception).
  * empc_batch_create picks shapes by a fixed rule.  empc_batch_autotune(plan,
  * reps, stream) times every shape of every class on the plan's own problems
  * (one untimed and `reps` timed launches each, on `stream`, after one
@@ -412,12 +413,21 @@ empc_status empc_batch_destroy(empc_batch *plan);
  * empc_batch_class_times(plan, cls, us[4]) gives the mean launch time in
  *   microseconds the autotuner measured for each shape (-1: not measured).
  * empc_batch_set_variant(plan, cls, variant) sets a class's shape by hand
- *   (EMPC_EINVAL if out of range). */
+ *   (EMPC_EINVAL if out of range).
+ * empc_batch_allow_valu(plan, allow) offers (allow != 0) or withdraws the
+ *   vector-ALU form, one lane per candidate, as shape 3 of every linear class
+ *   of at most 16 states whose inputs are at most 16 and whose problems share
+ *   the form's padded state count (4, 8 or 16); a problem solved in that form
+ *   gives the bits of its single solve with the form pinned (RF_VALU64), not
+ *   those of the matrix-core shapes (its cost is summed in another order),
+ *   which is why the plan starts without it.  Withdrawing it puts a class
+ *   that uses it back on shape 0.  Host call; EMPC_EINVAL for a NULL plan. */
 empc_status empc_batch_autotune(empc_batch *plan, int32_t reps, void *stream);
 int32_t empc_batch_classes(const empc_batch *plan);
 empc_status empc_batch_class_info(const empc_batch *plan, int32_t cls, int32_t *info);
 empc_status empc_batch_class_times(const empc_batch *plan, int32_t cls, float *us);
 empc_status empc_batch_set_variant(empc_batch *plan, int32_t cls, int32_t variant);
+empc_status empc_batch_allow_valu(empc_batch *plan, int32_t allow);
 
 /* Launch form of a batch plan's ticks.  Mode 0 (the default): per
  * generation, one population launch, one rollout launch per class (on side

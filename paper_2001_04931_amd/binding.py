@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
                                        ctypes.c_int),
             "empc_batch_set_variant": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
             "empc_batch_set_mode": ([_vp, ctypes.c_int32], ctypes.c_int),
+            "empc_batch_allow_valu": ([_vp, ctypes.c_int32], ctypes.c_int),
             "empc_qp_workspace_bytes": ([P], sz),
             "empc_qp_form": ([P, _vp, _vp, sz, _vp, _vp, _vp, _vp], ctypes.c_int),
             "empc_qp_solve": ([P, _vp, _vp, _vp, _vp, sz, ctypes.c_int32, _vp, _vp, _vp, _vp],
@@ -128,7 +129,7 @@ def exported_symbols():
             "empc_batch_workspace_bytes", "empc_batch_create", "empc_solve_batched",
             "empc_batch_destroy", "empc_batch_autotune", "empc_batch_classes",
             "empc_batch_class_info", "empc_batch_class_times", "empc_batch_set_variant",
-            "empc_batch_set_mode",
+            "empc_batch_set_mode", "empc_batch_allow_valu",
             "empc_qp_workspace_bytes", "empc_qp_form", "empc_qp_solve",
             "empc_nlink_linearize", "empc_nlink_step", "empc_profile_begin",
             "empc_profile_end"]
@@ -510,7 +511,7 @@ class BatchSolver:
     packed outputs.  The device tick counter starts at 0 and advances by one
     per solve()."""
 
-    def __init__(self, dprobs, ga, autotune=True, tune_reps=5):
+    def __init__(self, dprobs, ga, autotune=True, tune_reps=5, allow_valu=False):
         self.dprobs = list(dprobs)
         self.ga = make_ga(ga)
         n = len(self.dprobs)
@@ -528,6 +529,8 @@ class BatchSolver:
         self.best_cost = torch.zeros(n, dtype=torch.float32, device=dev)
         self.plan = empc_batch_create(arr, n, self.ga, self.workspace, self.x0, self.u_star,
                                       self.best_cost)
+        if allow_valu:
+            self.allow_valu(True)
         if autotune:
             self.autotune(tune_reps)
 
@@ -541,6 +544,13 @@ class BatchSolver:
 
     def set_variant(self, cls, variant):
         empc_batch_set_variant(self.plan, cls, variant)
+
+    def allow_valu(self, allow=True):
+        """Offer the vector-ALU form as a launch shape of the linear classes
+        of at most 16 states and inputs (its cost is summed in another order
+        than the matrix-core shapes', so results may differ in the last
+        bits); call autotune() afterwards to let it be picked."""
+        _check(lib().empc_batch_allow_valu(self.plan, 1 if allow else 0))
 
     def set_mode(self, mode):
         """0: a launch per kernel class (default); 1: the persistent

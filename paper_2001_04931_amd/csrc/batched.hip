@@ -67,6 +67,19 @@ __global__ __launch_bounds__(64 * WPB) void batch_roll_linear(const BatchSlot<T>
                                  (w % gridDim.x) * WPB + (threadIdx.x >> 6));
 }
 
+// linear problems of at most 16 states and 16 inputs, the vector-ALU form:
+// one lane per candidate, 64 per workgroup, through the single-problem VALU
+// kernel's device body (so a problem rounds as its single solve in that form
+// does)
+template <int NM, int MM, bool BOX>
+__global__ __launch_bounds__(64) void batch_roll_linear_valu(const BatchSlot<float> *__restrict__ slots,
+                                                             const int *__restrict__ items,
+                                                             int64_t pop, int g) {
+    const BatchSlot<float> &S = slots[items[blockIdx.y]];
+    valu_block<float, NM, MM, BOX, false>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
+                                          (int64_t)blockIdx.x * 64 + threadIdx.x);
+}
+
 // linear problems of more than 16 states: the M-split form, one workgroup
 // of NT wavefronts per tile, as in the single-problem rollout
 template <typename T, int NT, int NU, bool BOX>
@@ -270,19 +283,24 @@ struct BatchClass {
     int count;
     double work;  // cost estimate (rule-based, or measured by the autotuner)
     int stream;   // side stream its rollout runs on
-    int variant;  // launch shape, one of class_variants(); all round identically
+    int variant;  // launch shape, one of class_variants()
     float tuned_us[4] = {-1, -1, -1, -1};  // autotuner: mean launch time per shape
+    int vnm = 0;         // linear, NT = 1: the VALU form's padded state count
+                         // shared by every problem of the class (0: none)
+    int allow_valu = 0;  // the plan offers the VALU form (empc_batch_allow_valu)
 };
 
-// Launch shapes a class can use.  Every shape of a class runs the same
-// per-candidate device code in the same order, so the choice changes the
-// time, never a result.
+// Launch shapes a class can use.  The matrix-core shapes of a class run the
+// same per-candidate device code in the same order, so the choice among them
+// changes the time, never a result; the VALU form sums the cost in another
+// order, so it is offered only when the plan allows it.
 //   linear:   0..2  one wavefront per tile, 4 / 2 / 1 wavefronts per
-//                   workgroup; 3  the M-split form (NT > 1 only)
+//                   workgroup; 3  the M-split form (NT > 1), or the VALU form
+//                   with 64 threads (NT = 1, allowed and vnm > 0)
 //   chain, lane per candidate (DMAX <= 8): 0..2  256 / 128 / 64 threads
 //   chain, row per candidate:              0..2  4 / 2 / 1 wavefronts
 int class_variants(const BatchClass &c) {
-    if (c.model == EMPC_LINEAR) return c.a > 1 ? 4 : 3;
+    if (c.model == EMPC_LINEAR) return (c.a > 1 || (c.allow_valu && c.vnm > 0)) ? 4 : 3;
     return 3;
 }
 
@@ -339,6 +357,32 @@ static void go_batch_linear(int box, int variant, const BatchSlot<float> *slots,
     if (box) return go_batch_linear_box<NT, NU, true>(variant, slots, items, count, pop, g, s);
     go_batch_linear_box<NT, NU, false>(variant, slots, items, count, pop, g, s);
 }
+template <int NM, int MM>
+static void go_batch_valu_mm(int box, const BatchSlot<float> *slots, const int *items, int count,
+                             int64_t pop, int g, hipStream_t s) {
+    const dim3 grid((unsigned)((pop + 63) / 64), (unsigned)count);
+    if (box)
+        hipLaunchKernelGGL((batch_roll_linear_valu<NM, MM, true>), grid, dim3(64), 0, s, slots,
+                           items, pop, g);
+    else
+        hipLaunchKernelGGL((batch_roll_linear_valu<NM, MM, false>), grid, dim3(64), 0, s, slots,
+                           items, pop, g);
+}
+template <int NM>
+static void go_batch_valu_nm(int nu, int box, const BatchSlot<float> *slots, const int *items,
+                             int count, int64_t pop, int g, hipStream_t s) {
+    // the input bucket of the class fixes the padded input count as the
+    // single-problem launch picks it from m (at most 4, 8, 16)
+    if (nu == 1) return go_batch_valu_mm<NM, 4>(box, slots, items, count, pop, g, s);
+    if (nu == 2) return go_batch_valu_mm<NM, 8>(box, slots, items, count, pop, g, s);
+    go_batch_valu_mm<NM, 16>(box, slots, items, count, pop, g, s);
+}
+static void go_batch_valu(const BatchClass &c, const BatchSlot<float> *slots, const int *items,
+                          int64_t pop, int g, hipStream_t s) {
+    if (c.vnm == 4) return go_batch_valu_nm<4>(c.b, c.box, slots, items, c.count, pop, g, s);
+    if (c.vnm == 8) return go_batch_valu_nm<8>(c.b, c.box, slots, items, c.count, pop, g, s);
+    go_batch_valu_nm<16>(c.b, c.box, slots, items, c.count, pop, g, s);
+}
 template <int NT>
 static void go_batch_linear_nu(int nu, int box, int variant, const BatchSlot<float> *slots,
                                const int *items, int count, int64_t pop, int g, hipStream_t s) {
@@ -390,6 +434,7 @@ static void launch_class(const BatchClass &c, int variant, const BatchSlot<float
                          const int *d_items, int64_t pop, int g, hipStream_t s) {
     const int *items = d_items + c.first;
     if (c.model == EMPC_LINEAR) {
+        if (c.a == 1 && variant == 3) return go_batch_valu(c, slots, items, pop, g, s);
         switch (c.a) {
             case 1: go_batch_linear_nu<1>(c.b, c.box, variant, slots, items, c.count, pop, g, s); break;
             case 2: go_batch_linear_nu<2>(c.b, c.box, variant, slots, items, c.count, pop, g, s); break;
@@ -713,6 +758,14 @@ empc_status empc_batch_create(const empc_problem *probs, int32_t nprob, const em
         c.first = (int)items.size();
         c.count = (int)kv.second.size();
         c.work = 0;
+        if (c.model == EMPC_LINEAR && c.a == 1 && c.b <= 4) {
+            // the VALU form's padded state count, as the single-problem
+            // launch picks it from n; offered only if every problem shares it
+            auto nm_of = [](int n) { return n <= 4 ? 4 : n <= 8 ? 8 : 16; };
+            c.vnm = nm_of(probs[kv.second[0]].n);
+            for (int i : kv.second)
+                if (nm_of(probs[i].n) != c.vnm) c.vnm = 0;
+        }
         for (int i : kv.second) {  // per candidate-step: MFMAs (linear), joints (chain)
             const empc_problem &P = probs[i];
             c.work += (double)P.T * (P.model == EMPC_LINEAR ? 4.0 * c.a * c.a * 8.0 : 3.0 * P.m);
@@ -917,6 +970,15 @@ empc_status empc_batch_destroy(empc_batch *b) {
     (void)hipFree(b->d_code);
     (void)hipFree(b->d_counters);
     delete b;
+    return EMPC_OK;
+}
+
+empc_status empc_batch_allow_valu(empc_batch *b, int32_t allow) {
+    if (!b) return empc_fail_internal(EMPC_EINVAL, "batch is NULL");
+    for (BatchClass &c : b->classes) {
+        c.allow_valu = allow ? 1 : 0;
+        if (c.variant >= class_variants(c)) c.variant = 0;
+    }
     return EMPC_OK;
 }
 

@@ -149,10 +149,12 @@ __device__ __forceinline__ void valu_candidate(const ProbView<T> &P, const T *sA
 
 // One candidate per thread; the model and weights staged in LDS, zero-padded
 // to NM x NM and NM x MM so every loop is unrolled with no bounds tests.
-template <typename T, int NM, int MM, bool BOX, bool FULL = false>
-__global__ __launch_bounds__(256) void roll_linear_valu(ProbView<T> P, const T *__restrict__ x0,
-                                                        const T *__restrict__ knots, int64_t ld,
-                                                        int64_t ncand, T *__restrict__ cost) {
+// Every thread of the workgroup takes part in the staging (candidate `cand`
+// of the workgroup's problem; none past ncand).
+template <typename T, int NM, int MM, bool BOX, bool FULL>
+__device__ __forceinline__ void valu_block(const ProbView<T> &P, const T *__restrict__ x0,
+                                           const T *__restrict__ knots, int64_t ld, int64_t ncand,
+                                           T *__restrict__ cost, int64_t cand) {
     __shared__ T sA[NM * NM], sB[NM * MM];
     __shared__ T sw[NM], sq[NM], sqf[NM], sxg[NM], sr[MM], sug[MM];
     __shared__ T slo[BOX ? NM : 1], shi[BOX ? NM : 1], sqb[BOX ? NM : 1], ssb[BOX ? NM : 1];
@@ -199,10 +201,17 @@ __global__ __launch_bounds__(256) void roll_linear_valu(ProbView<T> P, const T *
         sug[i] = (i < m && P.ug) ? P.ug[i] : (T)0;
     }
     __syncthreads();
-    const int64_t cand = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (cand >= ncand) return;
     valu_candidate<T, NM, MM, BOX, FULL>(P, sA, sB, sw, sq, sqf, sxg, sr, sug, slo, shi, sqb, ssb,
                                          sQ, sR, sQf, x0, knots, ld, cost, cand);
+}
+
+template <typename T, int NM, int MM, bool BOX, bool FULL = false>
+__global__ __launch_bounds__(256) void roll_linear_valu(ProbView<T> P, const T *__restrict__ x0,
+                                                        const T *__restrict__ knots, int64_t ld,
+                                                        int64_t ncand, T *__restrict__ cost) {
+    valu_block<T, NM, MM, BOX, FULL>(P, x0, knots, ld, ncand, cost,
+                                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 }  // namespace empc

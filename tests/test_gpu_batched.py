@@ -146,6 +146,56 @@ def test_batch_launch_shapes_round_identically(E):
         bs.close()
 
 
+def test_batch_valu_form_equals_single_valu_solves(E):
+    """The vector-ALU shape of the small linear classes, offered only when
+    the plan allows it, gives each problem the bits of its single solve with
+    the VALU form pinned (64 threads); withdrawing it puts the classes back
+    on a matrix-core shape.  A class whose problems pad to different state
+    counts is not offered the form."""
+    probs = [p for p in mixed_problems(3) if p.model == W.LINEAR and p.n <= 16]
+    assert sorted(p.n for p in probs) == [4, 14]
+    ga = W.GA(pop=200, n_elite=8, generations=2, sigma=0.1, seed=0x5151)
+    dps = [E.DeviceProblem(p, F32) for p in probs]
+    bs = E.BatchSolver(dps, ga, autotune=False)
+    assert all(c["variants"] == 3 for c in bs.classes())
+    bs.allow_valu(True)
+    for ci, c in enumerate(bs.classes()):
+        assert c["variants"] == 4
+        bs.set_variant(ci, 3)
+    x0s = [W.draw_x0(p.n, 50 + i).astype(np.float32) for i, p in enumerate(probs)]
+    for i, x in enumerate(x0s):
+        bs.set_x0(i, x)
+    singles = []
+    try:
+        for i, dp in enumerate(dps):
+            g = W.dataclasses.replace(ga, seed=ga.seed ^ (i << 32))
+            E.empc_autotune_set(dp, E.make_ga(g), E.RF_VALU64, 0)
+            singles.append(E.Solver(dp, g))
+        for tick in range(3):
+            bs.solve()
+            torch.cuda.synchronize()
+            for i, s in enumerate(singles):
+                u, J = s.solve(torch.tensor(x0s[i], device="cuda"), tick)
+                torch.cuda.synchronize()
+                assert torch.equal(bs.u_of(i), u), (tick, i)
+                assert torch.equal(bs.best_cost[i:i + 1], J), (tick, i)
+    finally:
+        E.empc_autotune_reset()
+    bs.allow_valu(False)
+    assert all(c["variant"] == 0 and c["variants"] == 3 for c in bs.classes())
+    with pytest.raises(E.EmpcError):
+        bs.set_variant(0, 3)
+    bs.close()
+    # n = 4 and n = 6 share a class (one state tile, one input slice) but pad
+    # to 4 and 8 states in the VALU form
+    mixed = [W.linear_chain(2, 30, 5, seed=1).cast(np.float32),
+             W.linear_chain(3, 30, 5, seed=2).cast(np.float32)]
+    bm = E.BatchSolver([E.DeviceProblem(p, F32) for p in mixed], ga, autotune=False)
+    bm.allow_valu(True)
+    assert [c["variants"] for c in bm.classes()] == [3]
+    bm.close()
+
+
 def test_batch_autotune_keeps_state_and_results(E):
     """Autotuning between two ticks leaves the warm-start state alone: the
     second tick equals that of an untuned plan."""
