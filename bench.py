@@ -56,10 +56,11 @@ PEAK_FP32_VALU = 78.6e12   # MI355X FP32 vector peak without packed math, FLOP/s
 PEAK_FP64 = 78.6e12        # MI355X FP64 (vector and matrix), FLOP/s
 CSRC = os.path.join(ROOT, "paper_2001_04931_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rollout_linear_c2_traffic.md")
-ROLLOUT_SRC = os.path.join(CSRC, "rollout_linear.hpp")
+ROLLOUT_SRCS = [os.path.join(CSRC, f) for f in ("rollout_linear.hpp", "internal.hpp")]
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_tick_c5_traffic.md")
 BATCH_SRCS = [os.path.join(CSRC, f) for f in ("batched.hip", "rollout_linear.hpp",
-                                               "rollout_chain.hpp", "evolve_body.hpp")]
+                                               "rollout_chain.hpp", "evolve_body.hpp",
+                                               "rollout_valu.hpp", "internal.hpp")]
 
 
 # ---------------------------------------------------------------------------
@@ -118,7 +119,7 @@ def _counted_bytes(summary, sources, hash_key, bytes_key):
 
 def traffic_entry():
     """HBM bytes per C2 rollout launch (FETCH_SIZE + WRITE_SIZE, scaled)."""
-    return _counted_bytes(TRAFFIC_FILE, [ROLLOUT_SRC], "rollout_src_sha256", "bytes_per_launch")
+    return _counted_bytes(TRAFFIC_FILE, ROLLOUT_SRCS, "rollout_src_sha256", "bytes_per_launch")
 
 
 def batch_traffic_entry():
@@ -583,7 +584,10 @@ def nonsmooth_workload(E, W, ticks=100, with_cpu=True):
     flop = ga.pop * full_weight_flop_per_candidate(prob.n, prob.m, prob.T)
     r = {"rollouts_per_s": rate, "latency_ms": lat_summary(lats), "ticks": ticks,
          "dtype": "f32", "autotuned": tuned, "final_best_cost": costs[-1],
-         "roofline": kernel_roofline(prof, flop, PEAK_FP32_VALU, "roll_linear_valu<full>",
+         "roofline": kernel_roofline(prof, flop, PEAK_FP32_VALU,
+                                     "roll_linear_valu<full>"
+                                     if tuned["rollout_form"] in (E.RF_VALU256, E.RF_VALU64)
+                                     else "roll_linear_full_rows",
                                      bound="valu")}
     if with_cpu:
         jobs = [closed_loop_job(prob, W.dataclasses.replace(ga, generations=5), 1, s, 1e-3)
