@@ -25,7 +25,7 @@
  *    EMPC_EDEVICE.  empc_last_error() describes the last failure of the
  *    calling thread.  Nothing throws across this ABI.
  *  - Costs that are NaN rank after every finite or infinite cost.
- *  - Limits of this build: n <= 80, m <= 40 for LINEAR; d = m <= 40 joints
+ *  - Limits of the library: n <= 80, m <= 40 for LINEAR; d = m <= 40 joints
  *    (n = 2d) for PENDULUM_CHAIN; 1 <= p <= T; n_elite <= 256;
  *    pop <= 2^24.  Larger problems return EMPC_EUNSUPPORTED.
  */
@@ -43,7 +43,7 @@ typedef enum {
     EMPC_OK = 0,
     EMPC_EINVAL = 1,       /* invalid argument; nothing was launched             */
     EMPC_EDEVICE = 2,      /* HIP runtime error or earlier asynchronous fault    */
-    EMPC_EUNSUPPORTED = 3, /* valid problem outside this build's limits          */
+    EMPC_EUNSUPPORTED = 3, /* valid problem outside the library's limits        */
     EMPC_EWORKSPACE = 4    /* workspace NULL or smaller than required            */
 } empc_status;
 

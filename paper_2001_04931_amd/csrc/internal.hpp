@@ -434,7 +434,7 @@ template <typename T>
 hipError_t launch_qp_solve(const ProbView<T> &P, const T *Pm, const T *q, const T *c, void *ws,
                            int max_iter, T *z, T *cost, int *info, hipStream_t s);
 
-// N-link planar robot (nlink.hip): links per robot of this build
+// N-link planar robot (nlink.hip): links per robot the library supports
 constexpr int NLINK_MAX = 16;
 template <typename T>
 hipError_t launch_nlink_linearize(int N, const T *mass, const T *len, double b, double dt,

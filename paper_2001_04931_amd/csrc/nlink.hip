@@ -459,7 +459,7 @@ empc_status check_robot(const empc_nlink *R, double dt) {
         return empc_fail_internal(EMPC_EINVAL, "unknown dtype");
     if (R->links < 1) return empc_fail_internal(EMPC_EINVAL, "links must be >= 1");
     if (R->links > NLINK_MAX)
-        return empc_fail_internal(EMPC_EUNSUPPORTED, "more links than this build supports (16)");
+        return empc_fail_internal(EMPC_EUNSUPPORTED, "more links than the library supports (16)");
     if (!R->mass || !R->length) return empc_fail_internal(EMPC_EINVAL, "mass and length are required");
     if (!isfinite(R->damping)) return empc_fail_internal(EMPC_EINVAL, "damping must be finite");
     if (!(dt > 0.0) || !isfinite(dt)) return empc_fail_internal(EMPC_EINVAL, "dt must be finite and > 0");
