@@ -202,30 +202,42 @@ __global__ __launch_bounds__(REF_THREADS) void qp_refine_kernel(
     constexpr int REF_SLOTS = (64 * LS + REF_THREADS - 1) / REF_THREADS;
     constexpr int NP = 64 * LS;  // parameters at most
     extern __shared__ __align__(16) unsigned char ref_smem[];
-    __shared__ T zs[NP];
+    // the knots in two buffers: an Adam step writes the other one, so one
+    // barrier separates it from the next product's reads
+    __shared__ T zbuf[2][NP];
+    int cur = 0;
     __shared__ double part[REF_WAVES][NP];
     __shared__ double red[REF_WAVES];
     const int tid = threadIdx.x, b = blockIdx.x, lane = tid & 63, wv = tid >> 6;
     T *Pl = (T *)ref_smem;
     const int64_t src = idx[b];
-    for (int i = tid; i < pm; i += REF_THREADS) zs[i] = knots[(int64_t)i * ld + src];
-    if (p_in_lds) {  // eight loads in flight per thread, then their stores
+    for (int i = tid; i < pm; i += REF_THREADS) zbuf[0][i] = knots[(int64_t)i * ld + src];
+    if (p_in_lds) {
+        // P is copied as a flat array: 16-byte pieces, sixteen loads in
+        // flight per thread, then their stores (a 140 x 140 FP32 form takes
+        // two such rounds per thread); the scalar tail, and every element
+        // when P is not 16-byte aligned, one at a time
+        typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
+        constexpr int W = 16 / sizeof(T);
         const int tot = pm * pm;
-        for (int e0 = tid; e0 < tot; e0 += 8 * REF_THREADS) {
-            T t8[8];
+        const int nv = (reinterpret_cast<uintptr_t>(Pg) & 15) == 0 ? tot / W : 0;
+        const v16 *Pv = reinterpret_cast<const v16 *>(Pg);
+        v16 *Lv = reinterpret_cast<v16 *>(Pl);
+        for (int e0 = tid; e0 < nv; e0 += 16 * REF_THREADS) {
+            v16 t16[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 const int e = e0 + u * REF_THREADS;
-                t8[u] = e < tot ? Pg[e] : (T)0;
+                if (e < nv) t16[u] = Pv[e];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 const int e = e0 + u * REF_THREADS;
-                if (e < tot) Pl[e] = t8[u];
+                if (e < nv) Lv[e] = t16[u];
             }
         }
+        for (int e = nv * W + tid; e < tot; e += REF_THREADS) Pl[e] = Pg[e];
     }
-    const T *Pm = p_in_lds ? Pl : Pg;
     // this thread's parameters: linear term and bounds in registers
     T qr[REF_SLOTS], lo[REF_SLOTS], hi[REF_SLOTS];
 #pragma unroll
@@ -239,27 +251,37 @@ __global__ __launch_bounds__(REF_THREADS) void qp_refine_kernel(
     __syncthreads();
     // y = P z: wavefront w sums the columns j of its quarter of 0..pm-1
     // for every row i = lane + 64 s (P symmetric: column j read as row j,
-    // contiguous over the lanes), the quarters added in LDS; then
-    // J = sum_i z_i (y_i + 2 q_i) + c over the workgroup.  Each thread
-    // returns y for its parameters i = tid + REF_THREADS s.
+    // contiguous over the lanes), the quarters added in LDS; then, when
+    // asked for (the first and the last product: the Adam steps in between
+    // need only the gradient), J = sum_i z_i (y_i + 2 q_i) + c over the
+    // workgroup.  Each thread returns y for its parameters
+    // i = tid + REF_THREADS s.
     double y[REF_SLOTS];
     const int jb = pm * wv / REF_WAVES, je = pm * (wv + 1) / REF_WAVES;
-    auto product = [&]() {
-        // partial sums in the problem's precision, four columns per pass
+    auto product = [&](bool want_J) {
+        // partial sums in the problem's precision, eight columns per pass
         // so that their loads are in flight together
         T acc[LS];
 #pragma unroll
         for (int sl = 0; sl < LS; ++sl) acc[sl] = 0;
-#pragma unroll 4
-        for (int j = jb; j < je; ++j) {
-            const T zj = zs[j];
-            const T *row = Pm + (int64_t)j * pm;
+        // P from LDS or from global memory, each loop on its own pointer so
+        // that the LDS one compiles to LDS reads
+        auto columns = [&](const T *Pp) {
+#pragma unroll 8
+            for (int j = jb; j < je; ++j) {
+                const T zj = zbuf[cur][j];
+                const T *row = Pp + (int64_t)j * pm;
 #pragma unroll
-            for (int sl = 0; sl < LS; ++sl) {
-                const int i = lane + 64 * sl;
-                acc[sl] += (i < pm ? row[i] : (T)0) * zj;
+                for (int sl = 0; sl < LS; ++sl) {
+                    const int i = lane + 64 * sl;
+                    acc[sl] += (i < pm ? row[i] : (T)0) * zj;
+                }
             }
-        }
+        };
+        if (p_in_lds)
+            columns(Pl);
+        else
+            columns(Pg);
 #pragma unroll
         for (int sl = 0; sl < LS; ++sl) {
             const int i = lane + 64 * sl;
@@ -274,10 +296,11 @@ __global__ __launch_bounds__(REF_THREADS) void qp_refine_kernel(
             if (i < pm) {
 #pragma unroll
                 for (int w2 = 0; w2 < REF_WAVES; ++w2) a += part[w2][i];
-                pj += (double)zs[i] * (a + 2.0 * (double)qr[sl]);
+                pj += (double)zbuf[cur][i] * (a + 2.0 * (double)qr[sl]);
             }
             y[sl] = a;
         }
+        if (!want_J) return 0.0;  // uniform over the workgroup
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) pj += __shfl_xor(pj, o, 64);
         if (lane == 0) red[wv] = pj;
@@ -294,7 +317,7 @@ __global__ __launch_bounds__(REF_THREADS) void qp_refine_kernel(
     for (int sl = 0; sl < REF_SLOTS; ++sl) m1[sl] = m2[sl] = 0;
     double J0 = 0.0;
     for (int t = 1; t <= steps; ++t) {
-        const double Jt = product();
+        const double Jt = product(t == 1);
         if (t == 1) J0 = Jt;
         b1t *= b1;
         b2t *= b2;
@@ -307,24 +330,26 @@ __global__ __launch_bounds__(REF_THREADS) void qp_refine_kernel(
                 m1[sl] = b1 * m1[sl] + ((T)1 - b1) * g;
                 m2[sl] = b2 * m2[sl] + ((T)1 - b2) * g * g;
                 const T mh = m1[sl] / ((T)1 - b1t), vh = m2[sl] / ((T)1 - b2t);
-                T u = zs[i] - lr * mh / (sqrt(vh) + eps);
+                T u = zbuf[cur][i] - lr * mh / (sqrt(vh) + eps);
                 u = u < lo[sl] ? lo[sl] : u;
                 u = u > hi[sl] ? hi[sl] : u;
                 U[sl] = u;
             }
         }
-        __syncthreads();  // every read of z done
+        // every read of the current buffer lies before this step's product
+        // barrier or is this thread's own; the next product reads the other
 #pragma unroll
         for (int sl = 0; sl < REF_SLOTS; ++sl) {
             const int i = tid + REF_THREADS * sl;
-            if (i < pm) zs[i] = U[sl];
+            if (i < pm) zbuf[cur ^ 1][i] = U[sl];
         }
+        cur ^= 1;
         __syncthreads();
     }
-    const double Jn = product();
+    const double Jn = product(true);
     const bool keep = steps > 0 && Jn < J0;  // uniform over the workgroup
     for (int i = tid; i < pm; i += REF_THREADS)
-        Z[(int64_t)i * k + b] = keep ? zs[i] : knots[(int64_t)i * ld + src];
+        Z[(int64_t)i * k + b] = keep ? zbuf[cur][i] : knots[(int64_t)i * ld + src];
     if (keep && tid == 0) cost_io[b] = (T)Jn;
 }
 
