@@ -326,8 +326,10 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
                 lv += box_pen_grad(vT, L.lov, L.hiv, L.bv);
             }
         }
-        T *segbuf[2] = {sm + G.oSeg, sm + G.oSeg + (size_t)S * n};
-        if (wave == 1) recompute(G.nchk - 1, segbuf[(G.nchk - 1) & 1]);
+        // the two segment buffers (offsets from the LDS base, not a table
+        // of pointers, so that their accesses compile to LDS operations)
+        auto segbuf = [&](int b) { return sm + G.oSeg + (b ? (size_t)S * n : (size_t)0); };
+        if (wave == 1) recompute(G.nchk - 1, segbuf((G.nchk - 1) & 1));
         __syncthreads();
         // dJ/du_k goes to knots a and b of step k with weights 1-c and c;
         // summed in registers while the knot pair stays, then added to sG
@@ -341,10 +343,10 @@ __global__ __launch_bounds__(128) void adjoint_kernel(ProbView<T> P, GradPlan G,
         };
         for (int sg = G.nchk - 1; sg >= 0; --sg) {
             if (wave == 1) {
-                if (sg > 0) recompute(sg - 1, segbuf[(sg - 1) & 1]);
+                if (sg > 0) recompute(sg - 1, segbuf((sg - 1) & 1));
             } else {
                 const int k0 = sg * S, k1 = min(k0 + S, Tn);
-                const T *sSeg = segbuf[sg & 1];
+                const T *sSeg = segbuf(sg & 1);
                 for (int k = k1 - 1; k >= k0; --k) {
                     const Knot kn = knot_at(Tn, P.p, k);
                     const T c = sC[k];

@@ -184,7 +184,9 @@ __device__ void angle_table(int N, const double *q, double *sphi, double *cphi) 
     __syncthreads();
 }
 
-__device__ void forward_dynamics(int N, const double *mass, const double *len, double b,
+// (inlined into its callers, so that its LDS arrays are addressed as LDS)
+__device__ __forceinline__ void forward_dynamics(int N, const double *mass, const double *len,
+                                                 double b,
                                  const double *q, const double *qd, const double *tau,
                                  double *Msh, double *dg, double *sh, double *sphi,
                                  double *cphi, double *qdd) {
@@ -394,22 +396,23 @@ __global__ __launch_bounds__(STEP_THREADS) void nlink_step_kernel(
     // thread i < n keeps state i (y), its RK4 sum (acc) in registers
     double y = tid < n ? (double)x_in[tid] : 0.0;
     const double hs = dt / sub;
-    const double wt[4] = {1.0, 2.0, 2.0, 1.0}, off[4] = {0.0, 0.5, 0.5, 1.0};
     for (int s = 0; s < sub; ++s) {
         double acc = 0.0;
         if (tid < n) st[tid] = y;
         __syncthreads();
-#pragma unroll
+        // the four stages share one inlined copy of the dynamics; weights
+        // 1, 2, 2, 1 and next-stage offsets 0.5, 0.5, 1
+#pragma unroll 1
         for (int stage = 0; stage < 4; ++stage) {
             forward_dynamics(N, mass, len, b, st, st + N, tau, Msh, dg, sh, sphi, cphi, qdd);
             // k = [qd; qdd] at the stage state; next stage state y + off h k
             double k = 0.0;
             if (tid < n) {
                 k = tid < N ? st[N + tid] : qdd[tid - N];
-                acc += wt[stage] * k;
+                acc += (stage == 0 || stage == 3 ? 1.0 : 2.0) * k;
             }
             __syncthreads();
-            if (tid < n && stage < 3) st[tid] = y + off[stage + 1] * hs * k;
+            if (tid < n && stage < 3) st[tid] = y + (stage == 2 ? 1.0 : 0.5) * hs * k;
             __syncthreads();
         }
         if (tid < n) y += hs / 6.0 * acc;
