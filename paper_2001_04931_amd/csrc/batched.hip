@@ -37,7 +37,7 @@ __global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<
         for (int c = threadIdx.x; c < ncounters; c += blockDim.x) counters[c] = 0;
     const int2 e = popmap[blockIdx.x];  // (problem, tile within the problem)
     const BatchSlot<T> &S = slots[e.x];
-    const ProbView<T> P = S.P;
+    const ProbView<T> P = global_view(S.P);
     GaStreams gs;
     gs.k0 = seed_lo;
     gs.k1 = S.key_hi;
@@ -47,14 +47,16 @@ __global__ __launch_bounds__(POP_THREADS) void batch_population(const BatchSlot<
     const bool cold = first && *S.has_elites == 0;
     const int64_t nts = pop_tiles_s(pop);
     PopVariant<T> var;
-    var.x0 = S.x0;
+    var.x0 = global_ptr(S.x0);
     var.sigma_min = sigma_min;
     var.sigma_dist = sigma_dist;
     var.shift = first ? shift : 0;
-    population_tile<T>(P, gs, pop, k, elitism, sigma, first ? nullptr : S.knots[(g + 1) & 1], pop,
-                       first ? nullptr : S.elite_idx, first ? S.elite_rows : nullptr, cold,
-                       S.knots[g & 1], pop, *tick, (uint32_t)g, e.y % nts, (int)(e.y / nts), var,
-                       R);
+    population_tile<T>(P, gs, pop, k, elitism, sigma,
+                       first ? nullptr : global_ptr(S.knots[(g + 1) & 1]), pop,
+                       first ? nullptr : global_ptr(S.elite_idx),
+                       first ? global_ptr(S.elite_rows) : nullptr, cold,
+                       global_ptr(S.knots[g & 1]), pop, *tick, (uint32_t)g, e.y % nts,
+                       (int)(e.y / nts), var, R);
 }
 
 template <typename T, int NT, int NU, int WPB, bool BOX>
@@ -63,8 +65,9 @@ __global__ __launch_bounds__(64 * WPB) void batch_roll_linear(const BatchSlot<T>
                                                               int64_t pop, int g) {
     const int64_t w = xcd_swizzle_2d();
     const BatchSlot<T> &S = slots[items[w / gridDim.x]];
-    linear_tile<T, NT, NU, true, BOX>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
-                                 (w % gridDim.x) * WPB + (threadIdx.x >> 6));
+    linear_tile<T, NT, NU, true, BOX>(global_view(S.P), global_ptr(S.x0),
+                                      global_ptr(S.knots[g & 1]), pop, pop, global_ptr(S.cost),
+                                      (w % gridDim.x) * WPB + (threadIdx.x >> 6));
 }
 
 // linear problems of at most 16 states and 16 inputs, the vector-ALU form:
@@ -76,8 +79,9 @@ __global__ __launch_bounds__(64) void batch_roll_linear_valu(const BatchSlot<flo
                                                              const int *__restrict__ items,
                                                              int64_t pop, int g) {
     const BatchSlot<float> &S = slots[items[blockIdx.y]];
-    valu_block<float, NM, MM, BOX, false>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
-                                          (int64_t)blockIdx.x * 64 + threadIdx.x);
+    valu_block<float, NM, MM, BOX, false>(global_view(S.P), global_ptr(S.x0),
+                                          global_ptr(S.knots[g & 1]), pop, pop,
+                                          global_ptr(S.cost), (int64_t)blockIdx.x * 64 + threadIdx.x);
 }
 
 // linear problems of more than 16 states: the M-split form, one workgroup
@@ -87,8 +91,9 @@ __global__ __launch_bounds__(64 * NT) void batch_roll_linear_split(
     const BatchSlot<T> *__restrict__ slots, const int *__restrict__ items, int64_t pop, int g) {
     const int64_t w = xcd_swizzle_2d();
     const BatchSlot<T> &S = slots[items[w / gridDim.x]];
-    linear_tile_split<T, NT, NU, true, BOX>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
-                                       w % gridDim.x);
+    linear_tile_split<T, NT, NU, true, BOX>(global_view(S.P), global_ptr(S.x0),
+                                            global_ptr(S.knots[g & 1]), pop, pop,
+                                            global_ptr(S.cost), w % gridDim.x);
 }
 
 template <typename T, int DMAX, bool BOX>
@@ -97,11 +102,13 @@ __global__ __launch_bounds__(256) void batch_roll_chain(const BatchSlot<T> *__re
                                                         int g) {
     __shared__ JointConst<T> jc[DMAX];
     const BatchSlot<T> &S = slots[items[blockIdx.y]];
-    chain_constants_lds(S.P, jc);
+    const ProbView<T> P = global_view(S.P);
+    chain_constants_lds(P, jc);
     __syncthreads();
     const int64_t cand = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (cand >= pop) return;
-    chain_candidate<T, DMAX, BOX>(S.P, jc, S.x0, S.knots[g & 1], pop, S.cost, cand);
+    chain_candidate<T, DMAX, BOX>(P, jc, global_ptr(S.x0), global_ptr(S.knots[g & 1]), pop,
+                                  global_ptr(S.cost), cand);
 }
 
 // chains of more than 8 joints: one candidate per 16-lane row, as in the
@@ -115,8 +122,9 @@ __global__ __launch_bounds__(64 * WPB) void batch_roll_chain_rows(const BatchSlo
     const BatchSlot<T> &S = slots[items[w / gridDim.x]];
     const int64_t cand0 = (w % gridDim.x) * (4 * WPB);
     if (cand0 + (threadIdx.x >> 6) * 4 >= pop) return;  // whole wavefront past the end
-    chain_row_candidate<T, J, BOX>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
-                              cand0 + (threadIdx.x >> 4), threadIdx.x & 15);
+    chain_row_candidate<T, J, BOX>(global_view(S.P), global_ptr(S.x0),
+                                   global_ptr(S.knots[g & 1]), pop, pop, global_ptr(S.cost),
+                                   cand0 + (threadIdx.x >> 4), threadIdx.x & 15);
 }
 
 // one workgroup per problem: problem items[blockIdx.x] (items NULL: blockIdx.x)
@@ -125,10 +133,11 @@ __global__ __launch_bounds__(SEL_THREADS) void batch_select(const BatchSlot<T> *
                                                             const int *__restrict__ items,
                                                             int64_t pop, int k, int g, int last) {
     const BatchSlot<T> &S = slots[items ? items[blockIdx.x] : (int)blockIdx.x];
-    select_body<T, K, CACHE, SEL_THREADS>(S.cost, pop, k, S.knots[g & 1], pop, S.P.p * S.P.m, S.P.m,
-                             S.elite_idx, S.best_idx, last ? S.elite_rows : nullptr, S.elite_cost,
-                             S.has_elites, nullptr, last ? S.u_star : nullptr,
-                             last ? S.best_cost : nullptr);
+    select_body<T, K, CACHE, SEL_THREADS>(
+        global_ptr(S.cost), pop, k, global_ptr(S.knots[g & 1]), pop, S.P.p * S.P.m, S.P.m,
+        global_ptr(S.elite_idx), global_ptr(S.best_idx), last ? global_ptr(S.elite_rows) : nullptr,
+        global_ptr(S.elite_cost), global_ptr(S.has_elites), nullptr,
+        last ? global_ptr(S.u_star) : nullptr, last ? global_ptr(S.best_cost) : nullptr);
 }
 
 __global__ void batch_tick_advance(uint32_t *tick) {

@@ -200,6 +200,33 @@ struct BatchSlot {
     T *best_cost;      // 1
 };
 
+// Pointers that a kernel reads from memory (a batch slot's fields) are of
+// unknown address space to the compiler, so accesses through them compile
+// to flat instructions, which also count against the LDS wait counter (an
+// LDS wait then drains every global load in flight).  All of a slot's
+// memory is device global memory: re-made from its integer value as a
+// global pointer (a cast the optimizer keeps), each becomes global loads
+// and stores.
+template <typename T>
+__device__ __forceinline__ T *global_ptr(T *p) {
+    typedef __attribute__((address_space(1))) T gT;
+    return (T *)(gT *)(uintptr_t)p;
+}
+template <typename T>
+__device__ __forceinline__ ProbView<T> global_view(ProbView<T> v) {
+    v.Ad = global_ptr(v.Ad); v.Bd = global_ptr(v.Bd); v.wd = global_ptr(v.wd);
+    v.stiff = global_ptr(v.stiff); v.damp = global_ptr(v.damp);
+    v.mass = global_ptr(v.mass); v.len = global_ptr(v.len);
+    v.q = global_ptr(v.q); v.r = global_ptr(v.r); v.qf = global_ptr(v.qf);
+    v.xg = global_ptr(v.xg); v.ug = global_ptr(v.ug);
+    v.umin = global_ptr(v.umin); v.umax = global_ptr(v.umax);
+    v.xlo = global_ptr(v.xlo); v.xhi = global_ptr(v.xhi); v.qb = global_ptr(v.qb);
+    v.sb = global_ptr(v.sb); v.qlo = global_ptr(v.qlo); v.qhi = global_ptr(v.qhi);
+    v.Qm = global_ptr(v.Qm); v.Rm = global_ptr(v.Rm); v.Qfm = global_ptr(v.Qfm);
+    v.fc = global_ptr(v.fc); v.fs = global_ptr(v.fs);
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (one per kernel family), defined in the .hip files.
 // All return a hipError_t from the launch.
