@@ -180,7 +180,9 @@ __host__ __device__ inline int pcode(int kind, int a, int b) { return kind * 256
 
 template <int NT, int NU>
 __device__ __forceinline__ void p_linear(const BatchSlot<float> &S, int64_t pop, int g, int unit) {
-    linear_tile<float, NT, NU, true, false>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost, unit);
+    linear_tile<float, NT, NU, true, false>(global_view(S.P), global_ptr(S.x0),
+                                            global_ptr(S.knots[g & 1]), pop, pop,
+                                            global_ptr(S.cost), unit);
 }
 template <int NT>
 __device__ __forceinline__ bool p_linear_nu(int nu, const BatchSlot<float> &S, int64_t pop, int g,
@@ -201,18 +203,22 @@ __device__ __forceinline__ void p_rows(const BatchSlot<float> &S, int64_t pop, i
     for (int pass = 0; pass < 4; ++pass) {
         const int64_t c0 = (int64_t)unit * 16 + pass * 4;
         if (c0 >= pop) break;  // wave-uniform
-        chain_row_candidate<float, J, false>(S.P, S.x0, S.knots[g & 1], pop, pop, S.cost,
-                                             c0 + (lane >> 4), lane & 15);
+        chain_row_candidate<float, J, false>(global_view(S.P), global_ptr(S.x0),
+                                             global_ptr(S.knots[g & 1]), pop, pop,
+                                             global_ptr(S.cost), c0 + (lane >> 4), lane & 15);
     }
 }
 template <int DMAX>
 __device__ __forceinline__ void p_lane(const BatchSlot<float> &S, JointConst<float> *jc,
                                        int64_t pop, int g, int unit) {
     __syncthreads();  // the previous item's readers of jc are done
-    chain_constants_lds(S.P, jc);
+    const ProbView<float> P = global_view(S.P);
+    chain_constants_lds(P, jc);
     __syncthreads();
     const int64_t cand = (int64_t)unit * 64 + (threadIdx.x & 63);
-    if (cand < pop) chain_candidate<float, DMAX, false>(S.P, jc, S.x0, S.knots[g & 1], pop, S.cost, cand);
+    if (cand < pop)
+        chain_candidate<float, DMAX, false>(P, jc, global_ptr(S.x0), global_ptr(S.knots[g & 1]),
+                                            pop, global_ptr(S.cost), cand);
 }
 
 template <int TIER>
@@ -267,9 +273,11 @@ __global__ __launch_bounds__(64, persist_waves<TIER>()) void batch_persist(Persi
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
         select_body<float, uint32_t, CACHE, 64, 1>(
-            S.cost, A.pop, A.k, S.knots[A.g & 1], A.pop, S.P.p * S.P.m, S.P.m, S.elite_idx,
-            S.best_idx, A.last ? S.elite_rows : nullptr, S.elite_cost, S.has_elites, nullptr,
-            A.last ? S.u_star : nullptr, A.last ? S.best_cost : nullptr);
+            global_ptr(S.cost), A.pop, A.k, global_ptr(S.knots[A.g & 1]), A.pop, S.P.p * S.P.m,
+            S.P.m, global_ptr(S.elite_idx), global_ptr(S.best_idx),
+            A.last ? global_ptr(S.elite_rows) : nullptr, global_ptr(S.elite_cost),
+            global_ptr(S.has_elites), nullptr, A.last ? global_ptr(S.u_star) : nullptr,
+            A.last ? global_ptr(S.best_cost) : nullptr);
         if (A.last) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             unsigned pd = 0;
